@@ -1,0 +1,130 @@
+/*
+ * mr.h -- C ABI of libmr: the per-CTU coding-tree search of multi-resolution
+ * encoding (arxiv 2301.12191, "Multi-resolution encoding and optimization for
+ * next generation video compression") on AMD Instinct MI355X (gfx950).
+ *
+ * What the library computes, for one frame pair (current, reference) of 8-bit
+ * luma:
+ *   - the picture is covered by 64x64 CTUs; each CTU is coded by a quad-tree
+ *     of CUs 64, 32, 16, 8 (HEVC background section: CTB sizes and the CU
+ *     quad-tree from 64x64 down to 8x8);
+ *   - every CU is scored as inter (integer full-search motion estimation,
+ *     SAD plus sqrt(lambda) times the MV bits; cost-function subsection, SAD
+ *     equation) and as intra DC and planar (HEVC background section), each by
+ *     the Hadamard SATD of its residual (cost-function subsection, SATD
+ *     equation: sum |H| / 2 over 4x4 Hadamard tiles);
+ *   - a bottom-up rate-distortion decision picks the partition and modes
+ *     (HEVC background section: RDO over the quad-tree), optionally bounded
+ *     per 8x8 unit by depths derived from a reference representation
+ *     (related-work section: depth-bound reuse and arbitrary-ratio block
+ *     matching; analysis-share appendix: scale factor; analysis-refinement
+ *     appendix: refine-intra level 1, depth n and n+1).
+ *
+ * Integer arithmetic, bit-exact:
+ *   s = round(sqrt(lambda) * 65536), lambda = 0.57 * 2^((QP - 12) / 3)
+ *   J = D * 65536 + s * R  (int64), D = SATD, R = bits:
+ *     inter: 1 + se(4 mx) + se(4 my); planar: 3; DC: 4; split flag: 1 bit
+ *     for a node inside the picture with depth < 3.
+ *   ME cost: SAD * 65536 + s * (se(4 dx) + se(4 dy)), candidates
+ *   dx, dy in [-R, R], reference samples clamped to the picture, first strict
+ *   minimum in raster order (dy outer, dx inner).
+ *   Pictures whose size is not a multiple of 8 are padded by edge replication
+ *   to W8 x H8; CTU nodes crossing that edge are split without a flag.
+ *
+ * Conventions:
+ *   - every function returns an mr_status (0 = MR_OK, negative = error); no
+ *     exceptions or aborts cross the ABI;
+ *   - argument errors are detected on the host before any launch (MR_EINVAL)
+ *     and leave outputs untouched;
+ *   - compute calls are asynchronous on the caller's HIP stream (a
+ *     hipStream_t passed as void*, NULL = the default stream); outputs are
+ *     valid once the caller synchronises that stream;
+ *   - all buffers are owned by the caller unless stated otherwise; pointers
+ *     marked "device" must be device-accessible memory of the current device.
+ */
+#ifndef MR_H_
+#define MR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MR_OK = 0,
+  MR_EINVAL = -1,   /* invalid argument (checked before any launch) */
+  MR_ENOMEM = -2,   /* device or host allocation failed */
+  MR_EAGAIN = -3,   /* ladder: queue full or memory budget exhausted, retry later */
+  MR_EDEPEND = -4,  /* ladder: reference job missing and not implied */
+  MR_EHIP = -5,     /* a HIP runtime call failed */
+  MR_ETIMEOUT = -6, /* ladder: poll timed out with no completion */
+  MR_ESTATE = -7    /* call not valid in the object's current state */
+} mr_status;
+
+/* One 8-bit luma picture: device pointer, width x height samples, row stride
+ * in bytes (stride >= width).  1 <= width, height <= 8192. */
+typedef struct {
+  const uint8_t* luma;
+  int32_t width, height, stride;
+} mr_frame;
+
+/* qp: 0..51.  search_range R: 0..128 (integer-pel, candidates [-R, R]^2). */
+typedef struct {
+  int32_t qp;
+  int32_t search_range;
+} mr_search_params;
+
+/* Outputs (device, caller-allocated).  With U = ceil(H/8) rows and
+ * V = ceil(W/8) columns of 8x8 units, and T = ceil(H/64) x ceil(W/64) CTUs in
+ * raster order:
+ *   depth[U][V]   u8: depth 0..3 of the CU covering the unit (CU size 64 >> d)
+ *   mode[U][V]    u8: 0 inter, 1 planar, 2 DC
+ *   mv[U][V][2]  i16: (mx, my) best integer MV of that CU (also for intra CUs)
+ *   ctu_cost[T], ctu_dist[T], ctu_bits[T] i64: J, D and R of each CTU, with
+ *     J == D * 65536 + s * R. */
+typedef struct {
+  uint8_t* depth;
+  uint8_t* mode;
+  int16_t* mv;
+  int64_t* ctu_cost;
+  int64_t* ctu_dist;
+  int64_t* ctu_bits;
+} mr_search_out;
+
+/* Coding-tree search of one frame pair.  cur and ref must have equal width
+ * and height.  bounds: NULL for full search, else device [U][V][2] u8
+ * {lo, hi} with 0 <= lo <= 3, 0 <= hi <= 3 (as written by mr_depth_bounds):
+ * a node at depth d covering units S may stop (be a leaf) iff
+ * d >= min_S lo or it may not split, and may split iff d < 3 and
+ * d < max_S hi.  Scratch memory is allocated stream-ordered on hip_stream.
+ * Errors: MR_EINVAL (null pointers, sizes, qp, R), MR_ENOMEM, MR_EHIP. */
+int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
+                  const uint8_t* bounds, mr_search_out* out, void* hip_stream);
+
+/* Depth bounds of a dependent representation (dep_w x dep_h) from the depth
+ * map of its reference representation (ref_w x ref_h, as written by
+ * mr_ctu_search), for multi-resolution reuse.  For dependent unit (ux, uy):
+ *   xr = min(((8 ux + 4) * ref_w) / dep_w, ref_w - 1), yr likewise;
+ *   d_r = ref_depth[yr / 8][xr / 8];
+ *   d_s = smallest d in 0..3 with (64 >> d) * ref_w <= (64 >> d_r) * dep_w
+ *         (3 if none): the co-located CU size scaled to the dependent;
+ *   bounds_out[uy][ux] = {max(0, d_s - delta_lo), min(3, d_s + delta_hi)}.
+ * delta_lo = 0, delta_hi = 1 evaluates depths n and n+1 (refine-intra level 1
+ * of the analysis-refinement appendix); (0, 0) forces the scaled depth;
+ * (3, 0) searches only depths <= the co-located one (related-work section).
+ * ref_depth: device [ceil(ref_h/8)][ceil(ref_w/8)] u8 (values 0..3);
+ * bounds_out: device [ceil(dep_h/8)][ceil(dep_w/8)][2] u8.
+ * Errors: MR_EINVAL (null pointers, sizes <= 0 or > 8192, deltas outside 0..3). */
+int mr_depth_bounds(const uint8_t* ref_depth, int32_t ref_w, int32_t ref_h, int32_t dep_w,
+                    int32_t dep_h, int32_t delta_lo, int32_t delta_hi, uint8_t* bounds_out,
+                    void* hip_stream);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* mr_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MR_H_ */

@@ -1,0 +1,56 @@
+// Internal layouts shared by the host runtime and the HIP kernels of libmr.
+#pragma once
+#include <stdint.h>
+
+namespace mr {
+
+constexpr int kCtu = 64;
+constexpr int kNodes = 85;          // 1 + 4 + 16 + 64 quad-tree nodes per CTU
+constexpr int kMaxBands = 8;        // dy bands a CTU's search window may be split into
+constexpr int kWaveSteps = 64;      // search tasks per wavefront step (one per lane)
+constexpr int kRankBits = 11;       // rank field of the 32-bit arg-min key
+constexpr uint32_t kCinv = 1050000u;  // cost field of candidates outside the window
+constexpr uint64_t kKeyNone = ~0ull;
+
+// Node index: depth offsets 0, 1, 5, 21, raster order inside a depth.
+__host__ __device__ inline int node_index(int d, int lx, int ly) {
+  return (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
+}
+
+// Per-job search layout.  The (2R+1)^2 window is covered by tasks of
+// 4 horizontal shifts (a quad) x D vertical shifts (a group); tasks are
+// grouped into wavefront steps of 64 and steps into dy bands.
+struct SearchLayout {
+  int32_t R, D, Q, G;           // range, group height, quads, groups
+  int32_t nbands, total_steps;
+  int32_t band_g0[kMaxBands + 1];    // first group of each band (+ end)
+  int32_t band_step0[kMaxBands + 1]; // first global step of each band (+ end)
+  int32_t win_rows_max, win_dwords;  // LDS window rows (largest band), dwords per row
+};
+
+// One frame pair's search job as seen by the kernels.
+struct JobDesc {
+  const uint8_t* cur;      // device luma
+  const uint8_t* ref;
+  int32_t w, h, stride;
+  int32_t w8, h8, ctus_w, ctus_h;
+  int32_t R, D, Q, nbands;
+  int32_t win_dwords;
+  int32_t band_g0[kMaxBands + 1];
+  int32_t band_step0[kMaxBands + 1];
+  int64_t s;               // sqrt(lambda) in Q16
+  const uint32_t* curpack; // [ctus][64 blocks][16 dwords]
+  uint64_t* keys;          // [ctus][85] arg-min keys J_me * 2^17 + candidate index
+  const uint32_t* qtab;    // [steps][64 lanes][4D]
+  const uint64_t* dtab;    // [steps][2048]
+  const uint8_t* bounds;   // [U][V][2] or null
+  uint8_t* elig;           // [ctus][85] 1 = node may be a leaf (inside and allowed)
+  uint8_t* depth;          // outputs
+  uint8_t* mode;
+  int16_t* mv;
+  int64_t* ctu_cost;
+  int64_t* ctu_dist;
+  int64_t* ctu_bits;
+};
+
+}  // namespace mr

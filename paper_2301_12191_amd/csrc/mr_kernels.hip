@@ -1,0 +1,645 @@
+// HIP kernels of libmr for gfx950 (CDNA4): the per-CTU coding-tree search.
+//
+// Pipeline per frame pair (one job):
+//   prep   : pack the current CTUs into 8x8-block-linear dwords (coded picture,
+//            edge-replicated), reset the arg-min keys, mark leaf-eligible nodes
+//            (inside the picture and allowed by the depth bounds);
+//   search : integer full-search ME.  One workgroup per (CTU, dy band) stages
+//            the reference window in LDS; each lane owns 4 horizontal x D
+//            vertical candidate shifts, computes the 64 8x8 SADs per candidate
+//            with v_sad_u8 (current block read through SGPRs, reference
+//            dwords re-aligned with v_alignbyte), sums them into 16/32/64 SADs
+//            and keeps an exact first-minimum arg-min for all 85 CUs;
+//   leaf   : SATD (4x4 Hadamard) of the inter residual at the best MV and of
+//            the intra DC / planar residuals, leaf mode choice, bottom-up
+//            quad-tree decision with optional depth bounds, outputs.
+// All arithmetic is integer and matches the CPU definition bit for bit.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mr_internal.h"
+
+namespace mr {
+
+typedef const __attribute__((address_space(4))) uint32_t* sptr32;  // scalar (uniform) loads
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Z-order (Morton) position -> (x, y) for 6-bit indices.
+__device__ __forceinline__ int zx(int z) { return (z & 1) | ((z >> 1) & 2) | ((z >> 2) & 4); }
+__device__ __forceinline__ int zy(int z) { return ((z >> 1) & 1) | ((z >> 2) & 2) | ((z >> 3) & 4); }
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWMASK, 0xF, false);
+}
+
+// Minimum over the 64 lanes of a wavefront (all lanes active); wave-uniform result.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+  v = min(v, dpp_mov<0xB1, 0xF>(v, v));          // quad_perm [1,0,3,2]
+  v = min(v, dpp_mov<0x4E, 0xF>(v, v));          // quad_perm [2,3,0,1]
+  v = min(v, dpp_mov<0x141, 0xF>(v, v));         // row_half_mirror
+  v = min(v, dpp_mov<0x140, 0xF>(v, v));         // row_mirror
+  v = min(v, dpp_mov<0x142, 0xA>(0xFFFFFFFFu, v));  // row_bcast:15
+  v = min(v, dpp_mov<0x143, 0xC>(0xFFFFFFFFu, v));  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// ---------------------------------------------------------------------------------- prep
+// One workgroup (256 threads) per CTU.
+__device__ void prep_ctu(const JobDesc& jb, int ctu) {
+  const int tid = threadIdx.x;
+  const int cx = (ctu % jb.ctus_w) * kCtu, cy = (ctu / jb.ctus_w) * kCtu;
+  // 64 blocks x 16 dwords: thread -> (block, 4 dwords = 2 rows x 2 dwords)
+  {
+    const int bz = tid >> 2, part = tid & 3;
+    const int bx = zx(bz), by = zy(bz);
+    uint32_t* dst = (uint32_t*)jb.curpack + (size_t)ctu * 1024 + bz * 16 + part * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = part * 2 + (i >> 1), c = i & 1;
+      const int y = min(cy + by * 8 + r, jb.h - 1);
+      const uint8_t* row = jb.cur + (size_t)y * jb.stride;
+      const int x0 = cx + bx * 8 + c * 4;
+      uint32_t v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) v |= (uint32_t)row[min(x0 + b, jb.w - 1)] << (8 * b);
+      dst[i] = v;
+    }
+  }
+  if (tid < kNodes) {
+    const int d = tid == 0 ? 0 : tid < 5 ? 1 : tid < 21 ? 2 : 3;
+    const int local = tid - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
+    const int n = kCtu >> d, lx = local % (1 << d), ly = local / (1 << d);
+    const int x0 = cx + lx * n, y0 = cy + ly * n;
+    uint8_t e = 0;
+    if (x0 + n <= jb.w8 && y0 + n <= jb.h8) {
+      e = 1;
+      if (jb.bounds) {
+        const int uw = jb.w8 >> 3;
+        int min_lo = 3, max_hi = 0;
+        for (int uy = y0 >> 3; uy < (y0 + n) >> 3; ++uy)
+          for (int ux = x0 >> 3; ux < (x0 + n) >> 3; ++ux) {
+            const uint8_t* b = jb.bounds + 2 * ((size_t)uy * uw + ux);
+            min_lo = min(min_lo, (int)b[0]);
+            max_hi = max(max_hi, (int)b[1]);
+          }
+        const bool split_ok = d < 3 && d < max_hi;
+        e = (d >= min_lo || !split_ok) ? 1 : 0;
+      }
+    }
+    jb.elig[(size_t)ctu * kNodes + tid] = e;
+    jb.keys[(size_t)ctu * kNodes + tid] = kKeyNone;
+  }
+}
+
+
+// -------------------------------------------------------------------------------- search
+__device__ void stage_window(const JobDesc& jb, int cx, int cy, int g0, int rows, uint32_t* win) {
+  const int Wd = jb.win_dwords;
+  const int ybase = cy - jb.R + g0 * jb.D, xbase = cx - jb.R;
+  const bool dword_ok = ((jb.stride & 3) == 0) && ((((uintptr_t)jb.ref) & 3) == 0) &&
+                        ((xbase & 3) == 0);
+  const int total = rows * Wd;
+  for (int i = threadIdx.x; i < total; i += blockDim.x) {
+    const int row = i / Wd, c4 = (i - row * Wd) * 4;
+    const int y = clampi(ybase + row, 0, jb.h - 1);
+    const uint8_t* rp = jb.ref + (size_t)y * jb.stride;
+    const int x = xbase + c4;
+    uint32_t v;
+    if (dword_ok && x >= 0 && x + 3 < jb.w) {
+      v = *(const uint32_t*)(rp + x);
+    } else {
+      v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[clampi(x + b, 0, jb.w - 1)] << (8 * b);
+    }
+    win[i] = v;
+  }
+}
+
+// Merge a wave's reduced 32-bit keys (one CU per lane) into its 64-bit bests.
+__device__ __forceinline__ void merge_keys(uint32_t vk, const uint64_t* __restrict__ dt,
+                                           uint64_t& best) {
+  if (vk != 0xFFFFFFFFu) {
+    const uint64_t K = ((uint64_t)(vk >> kRankBits) << 33) + dt[vk & ((1u << kRankBits) - 1)];
+    best = K < best ? K : best;
+  }
+}
+
+template <int D>
+__device__ void search_item(const JobDesc& jb, int ctu, int band, uint32_t* win) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int Q = jb.Q, Wd = jb.win_dwords;
+  const int cx = (ctu % jb.ctus_w) * kCtu, cy = (ctu / jb.ctus_w) * kCtu;
+  const int g0 = jb.band_g0[band], g1 = jb.band_g0[band + 1];
+  stage_window(jb, cx, cy, g0, (g1 - g0) * D + 63, win);
+  __syncthreads();
+
+  const int ntasks = (g1 - g0) * Q;
+  const int step0 = jb.band_step0[band], nsteps = jb.band_step0[band + 1] - step0;
+  const uint8_t* __restrict__ elig = jb.elig + (size_t)ctu * kNodes;
+  const sptr32 cur = (sptr32)(jb.curpack + (size_t)ctu * 1024);
+  uint64_t best8 = kKeyNone, bestB = kKeyNone;
+
+  for (int st = wave; st < nsteps; st += nwaves) {
+    const int gstep = step0 + st;
+    int task = st * kWaveSteps + lane;
+    if (task >= ntasks) task = ntasks - 1;  // idle lane: its table entries are invalid
+    const int g = task / Q, qd = task - g * Q;
+    uint32_t kq[D][4];
+    {
+      const uint4* qp = (const uint4*)(jb.qtab + ((size_t)gstep * kWaveSteps + lane) * (4 * D));
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const uint4 t = qp[j];
+        kq[j][0] = t.x, kq[j][1] = t.y, kq[j][2] = t.z, kq[j][3] = t.w;
+      }
+    }
+    const uint32_t* lbase = win + g * D * Wd + qd;
+    uint32_t s16[D][4], s32[D][4], s64[D][4];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s64[j][k] = 0;
+    uint32_t vk8 = 0xFFFFFFFFu, vkB = 0xFFFFFFFFu;
+
+    for (int reg = 0; reg < 16; ++reg) {
+#pragma unroll
+      for (int sub = 0; sub < 4; ++sub) {
+        const int bz = reg * 4 + sub;
+        const int bx = zx(bz), by = zy(bz);
+        uint32_t cw[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cw[i] = cur[bz * 16 + i];
+        uint32_t acc[D][4];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[j][k] = 0;
+        const uint32_t* rb = lbase + by * 8 * Wd + 2 * bx;
+#pragma unroll
+        for (int w = 0; w < D + 7; ++w) {
+          const uint32_t* rp = rb + w * Wd;
+          const uint32_t d0 = rp[0], d1 = rp[1], d2 = rp[2];
+          uint32_t a0[4], a1[4];
+          a0[0] = d0, a1[0] = d1;
+#pragma unroll
+          for (int k = 1; k < 4; ++k) {
+            a0[k] = __builtin_amdgcn_alignbyte(d1, d0, k);
+            a1[k] = __builtin_amdgcn_alignbyte(d2, d1, k);
+          }
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            const int r = w - j;
+            if (r < 0 || r > 7) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              acc[j][k] = __builtin_amdgcn_sad_u8(a0[k], cw[2 * r], acc[j][k]);
+              acc[j][k] = __builtin_amdgcn_sad_u8(a1[k], cw[2 * r + 1], acc[j][k]);
+            }
+          }
+        }
+        if (elig[21 + by * 8 + bx]) {
+          uint32_t m = 0xFFFFFFFFu;
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m = min(m, acc[j][k] * 2048u + kq[j][k]);
+          { const uint32_t mk = wave_min(m); vk8 = lane == bz ? mk : vk8; }
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s16[j][k] = sub == 0 ? acc[j][k] : s16[j][k] + acc[j][k];
+      }
+      {  // 16x16 CU of this region
+        const int lx = zx(reg), ly = zy(reg);
+        if (elig[5 + ly * 4 + lx]) {
+          uint32_t m = 0xFFFFFFFFu;
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m = min(m, s16[j][k] * 2048u + kq[j][k]);
+          { const uint32_t mk = wave_min(m); vkB = lane == reg ? mk : vkB; }
+        }
+        if ((reg & 3) == 0) {
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s32[j][k] = 0;
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s32[j][k] += s16[j][k];
+      }
+      if ((reg & 3) == 3) {  // 32x32 CU
+        const int qz = reg >> 2, lx = qz & 1, ly = qz >> 1;
+        if (elig[1 + ly * 2 + lx]) {
+          uint32_t m = 0xFFFFFFFFu;
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m = min(m, s32[j][k] * 2048u + kq[j][k]);
+          { const uint32_t mk = wave_min(m); vkB = lane == 16 + qz ? mk : vkB; }
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s64[j][k] += s32[j][k];
+      }
+    }
+    if (elig[0]) {  // 64x64 CU
+      uint32_t m = 0xFFFFFFFFu;
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m = min(m, s64[j][k] * 2048u + kq[j][k]);
+      { const uint32_t mk = wave_min(m); vkB = lane == 20 ? mk : vkB; }
+    }
+    const uint64_t* dt = jb.dtab + (size_t)gstep * 2048;
+    merge_keys(vk8, dt, best8);
+    if (lane < 21) merge_keys(vkB, dt, bestB);
+  }
+
+  // Publish: lane i holds the 8x8 CU of Z-order block i; lanes 0..20 the larger CUs.
+  unsigned long long* keys = (unsigned long long*)jb.keys + (size_t)ctu * kNodes;
+  if (best8 != kKeyNone) atomicMin(&keys[21 + zy(lane) * 8 + zx(lane)], (unsigned long long)best8);
+  if (lane < 21 && bestB != kKeyNone) {
+    int node;
+    if (lane < 16) node = 5 + zy(lane) * 4 + zx(lane);
+    else if (lane < 20) node = 1 + ((lane - 16) >> 1) * 2 + ((lane - 16) & 1);
+    else node = 0;
+    atomicMin(&keys[node], (unsigned long long)bestB);
+  }
+}
+
+
+// ---------------------------------------------------------------------------------- leaf
+// SATD of a 4x4 residual: sum |H d H^T| / 2 via butterflies.
+__device__ __forceinline__ uint32_t satd4x4(int d[16]) {
+  int t[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {  // rows
+    const int a0 = d[4 * i] + d[4 * i + 1], a1 = d[4 * i] - d[4 * i + 1];
+    const int a2 = d[4 * i + 2] + d[4 * i + 3], a3 = d[4 * i + 2] - d[4 * i + 3];
+    t[4 * i] = a0 + a2, t[4 * i + 1] = a1 + a3, t[4 * i + 2] = a0 - a2, t[4 * i + 3] = a1 - a3;
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {  // columns
+    const int a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
+    const int a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
+    s += abs(a0 + a2) + abs(a1 + a3) + abs(a0 - a2) + abs(a1 - a3);
+  }
+  return s >> 1;
+}
+
+__device__ __forceinline__ int se_bits_dev(int v) {
+  const uint32_t k = v > 0 ? 2u * (uint32_t)v - 1u : 2u * (uint32_t)(-v);
+  return 2 * (31 - __builtin_clz(k + 1u)) + 1;
+}
+
+// Offsets of each node's reference arrays in LDS: left column 2N+1, top row 2N.
+__device__ __forceinline__ int ref_offset(int node) {
+  if (node == 0) return 0;
+  if (node < 5) return 257 + (node - 1) * 129;
+  if (node < 21) return 257 + 4 * 129 + (node - 5) * 65;
+  return 257 + 4 * 129 + 16 * 65 + (node - 21) * 33;
+}
+constexpr int kRefTotal = 257 + 4 * 129 + 16 * 65 + 64 * 33;  // 3925
+
+struct LeafShared {
+  uint8_t cur[64 * 64];
+  int16_t refs[kRefTotal];
+  int16_t mvx[kNodes], mvy[kNodes];
+  int32_t dc[kNodes];
+  uint32_t satd[kNodes][3];
+  uint32_t part0[4][3];          // per-wave partial sums for the 64x64 node
+  int64_t jt[kNodes], dt[kNodes], rt[kNodes];
+  uint8_t leaf[kNodes];          // decision: 1 = leaf, 0 = split
+  uint8_t kind[kNodes];          // 0 absent, 1 crosses edge, 2 inside
+  uint8_t elig[kNodes];
+  uint8_t mode[kNodes];
+  int64_t lj[kNodes], ld[kNodes], lr[kNodes];
+  uint8_t split_ok[kNodes], leaf_ok[kNodes];
+};
+
+__device__ __forceinline__ uint32_t shfl_sum(uint32_t v, int width) {
+  for (int o = 1; o < width; o <<= 1) v += __shfl_xor((int)v, o, 64);
+  return v;
+}
+
+__device__ void leaf_ctu(const JobDesc& jb, int ctu, LeafShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cx = (ctu % jb.ctus_w) * kCtu, cy = (ctu / jb.ctus_w) * kCtu;
+  const int W8 = jb.w8, H8 = jb.h8;
+  const int span = 2 * jb.R + 1;
+
+  // Current CTU (coded picture, edge-replicated).
+  for (int i = tid; i < 64 * 64; i += blockDim.x) {
+    const int y = min(cy + (i >> 6), jb.h - 1), x = min(cx + (i & 63), jb.w - 1);
+    sh.cur[i] = jb.cur[(size_t)y * jb.stride + x];
+  }
+  if (tid < kNodes) {
+    const int node = tid;
+    const int d = node == 0 ? 0 : node < 5 ? 1 : node < 21 ? 2 : 3;
+    const int local = node - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
+    const int n = kCtu >> d, x0 = cx + (local % (1 << d)) * n, y0 = cy + (local / (1 << d)) * n;
+    sh.kind[node] = (x0 >= W8 || y0 >= H8) ? 0 : ((x0 + n > W8 || y0 + n > H8) ? 1 : 2);
+    const uint8_t e = jb.elig[(size_t)ctu * kNodes + node];
+    sh.elig[node] = e;
+    int mx = 0, my = 0;
+    if (e) {
+      const uint64_t key = jb.keys[(size_t)ctu * kNodes + node];
+      const int idx = (int)(key & 0x1FFFF);
+      my = idx / span - jb.R;
+      mx = idx - (my + jb.R) * span - jb.R;
+    }
+    sh.mvx[node] = (int16_t)mx, sh.mvy[node] = (int16_t)my;
+    // bounds admissibility (same rule the prep kernel applied)
+    bool split_ok = d < 3, leaf_ok = true;
+    if (jb.bounds && sh.kind[node] == 2) {
+      const int uw = W8 >> 3;
+      int min_lo = 3, max_hi = 0;
+      for (int uy = y0 >> 3; uy < (y0 + n) >> 3; ++uy)
+        for (int ux = x0 >> 3; ux < (x0 + n) >> 3; ++ux) {
+          const uint8_t* b = jb.bounds + 2 * ((size_t)uy * uw + ux);
+          min_lo = min(min_lo, (int)b[0]);
+          max_hi = max(max_hi, (int)b[1]);
+        }
+      split_ok = d < 3 && d < max_hi;
+      leaf_ok = d >= min_lo || !split_ok;
+    }
+    sh.split_ok[node] = split_ok, sh.leaf_ok[node] = leaf_ok;
+  }
+  // Raw neighbour samples, -1 where unavailable (outside the coded picture).
+  for (int i = tid; i < kRefTotal; i += blockDim.x) {
+    int node, off;
+    if (i < 257) node = 0, off = i;
+    else if (i < 257 + 4 * 129) node = 1 + (i - 257) / 129, off = (i - 257) % 129;
+    else if (i < 257 + 4 * 129 + 16 * 65) node = 5 + (i - 773) / 65, off = (i - 773) % 65;
+    else node = 21 + (i - 1813) / 33, off = (i - 1813) % 33;
+    const int d = node == 0 ? 0 : node < 5 ? 1 : node < 21 ? 2 : 3;
+    const int local = node - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
+    const int n = kCtu >> d, x0 = cx + (local % (1 << d)) * n, y0 = cy + (local / (1 << d)) * n;
+    int x, y;
+    if (off <= 2 * n) x = x0 - 1, y = y0 - 1 + off;        // left column p[-1][off-1]
+    else x = x0 + (off - 2 * n - 1), y = y0 - 1;            // top row p[off-2n-1][-1]
+    int v = -1;
+    if (x >= 0 && y >= 0 && x < W8 && y < H8)
+      v = jb.cur[(size_t)min(y, jb.h - 1) * jb.stride + min(x, jb.w - 1)];
+    sh.refs[i] = (int16_t)v;
+  }
+  __syncthreads();
+  // Substitution per node (sequential scan), then the DC value.
+  if (tid < kNodes && sh.elig[tid]) {
+    const int node = tid;
+    const int d = node == 0 ? 0 : node < 5 ? 1 : node < 21 ? 2 : 3;
+    const int n = kCtu >> d;
+    int16_t* L = sh.refs + ref_offset(node);  // L[0..2n] = p[-1][-1..2n-1]
+    int16_t* T = L + 2 * n + 1;               // T[0..2n-1] = p[0..2n-1][-1]
+    bool any = false;
+    for (int i = 0; i <= 2 * n; ++i) any |= L[i] >= 0;
+    for (int i = 0; i < 2 * n; ++i) any |= T[i] >= 0;
+    if (!any) {
+      for (int i = 0; i <= 2 * n; ++i) L[i] = 128;
+      for (int i = 0; i < 2 * n; ++i) T[i] = 128;
+    } else {
+      if (L[2 * n] < 0) {
+        int v = -1;
+        for (int i = 2 * n - 1; i >= 0 && v < 0; --i) v = L[i];
+        for (int i = 0; i < 2 * n && v < 0; ++i) v = T[i];
+        L[2 * n] = (int16_t)v;
+      }
+      for (int i = 2 * n - 1; i >= 0; --i)
+        if (L[i] < 0) L[i] = L[i + 1];
+      for (int i = 0; i < 2 * n; ++i)
+        if (T[i] < 0) T[i] = i == 0 ? L[0] : T[i - 1];
+    }
+    int s = n;
+    for (int i = 0; i < n; ++i) s += T[i] + L[i + 1];
+    sh.dc[node] = s >> (31 - __builtin_clz((unsigned)n) + 1);
+  }
+  __syncthreads();
+
+  // SATD of every 4x4 tile under every eligible node: thread = tile in Z-order.
+  {
+    const int t = tid;  // 0..255
+    const int tx = (t & 1) | ((t >> 1) & 2) | ((t >> 2) & 4) | ((t >> 3) & 8);
+    const int ty = ((t >> 1) & 1) | ((t >> 2) & 2) | ((t >> 3) & 4) | ((t >> 4) & 8);
+    int c[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) c[i] = sh.cur[(ty * 4 + (i >> 2)) * 64 + tx * 4 + (i & 3)];
+#pragma unroll
+    for (int d = 3; d >= 0; --d) {
+      const int n = kCtu >> d, lg = 6 - d;
+      const int lx = (tx * 4) >> lg, ly = (ty * 4) >> lg;
+      const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
+      uint32_t v0 = 0, v1 = 0, v2 = 0;
+      if (sh.elig[node]) {
+        const int mx = sh.mvx[node], my = sh.mvy[node];
+        int r[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int x = clampi(cx + tx * 4 + (i & 3) + mx, 0, jb.w - 1);
+          const int y = clampi(cy + ty * 4 + (i >> 2) + my, 0, jb.h - 1);
+          r[i] = c[i] - (int)jb.ref[(size_t)y * jb.stride + x];
+        }
+        v0 = satd4x4(r);
+        const int16_t* L = sh.refs + ref_offset(node);
+        const int16_t* T = L + 2 * n + 1;
+        const int px0 = tx * 4 - lx * n, py0 = ty * 4 - ly * n;  // position inside the CU
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int px = px0 + (i & 3), py = py0 + (i >> 2);
+          const int p = ((n - 1 - px) * L[py + 1] + (px + 1) * T[n] + (n - 1 - py) * T[px] +
+                         (py + 1) * L[n + 1] + n) >> (lg + 1);
+          r[i] = c[i] - p;
+        }
+        v1 = satd4x4(r);
+        const int dcv = sh.dc[node];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r[i] = c[i] - dcv;
+        v2 = satd4x4(r);
+      }
+      // Tiles of a node are consecutive threads: 4^(3-d+1) of them.
+      const int width = 4 << (2 * (3 - d));  // 4, 16, 64, 256
+      const int w = width > 64 ? 64 : width;
+      v0 = shfl_sum(v0, w), v1 = shfl_sum(v1, w), v2 = shfl_sum(v2, w);
+      if (d > 0) {
+        if ((lane & (w - 1)) == 0) sh.satd[node][0] = v0, sh.satd[node][1] = v1, sh.satd[node][2] = v2;
+      } else if (lane == 0) {
+        sh.part0[wave][0] = v0, sh.part0[wave][1] = v1, sh.part0[wave][2] = v2;
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t s = jb.s;
+  if (tid < kNodes) {
+    const int node = tid;
+    if (node == 0) {
+      for (int m = 0; m < 3; ++m)
+        sh.satd[0][m] = sh.part0[0][m] + sh.part0[1][m] + sh.part0[2][m] + sh.part0[3][m];
+    }
+  }
+  __syncthreads();
+  if (tid < kNodes && sh.elig[tid]) {
+    const int node = tid;
+    const int64_t r_inter = 1 + se_bits_dev(4 * sh.mvx[node]) + se_bits_dev(4 * sh.mvy[node]);
+    int64_t j = (int64_t)sh.satd[node][0] * 65536 + s * r_inter, dd = sh.satd[node][0], rr = r_inter;
+    uint8_t m = 0;
+    const int64_t jp = (int64_t)sh.satd[node][1] * 65536 + s * 3;
+    if (jp < j) j = jp, dd = sh.satd[node][1], rr = 3, m = 1;
+    const int64_t jd = (int64_t)sh.satd[node][2] * 65536 + s * 4;
+    if (jd < j) j = jd, dd = sh.satd[node][2], rr = 4, m = 2;
+    sh.lj[node] = j, sh.ld[node] = dd, sh.lr[node] = rr, sh.mode[node] = m;
+  }
+  __syncthreads();
+  // Bottom-up decision, one depth level at a time.
+  for (int d = 3; d >= 0; --d) {
+    const int cnt = 1 << (2 * d), base = d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21;
+    if (tid < cnt) {
+      const int node = base + tid;
+      const int lx = tid % (1 << d), ly = tid / (1 << d);
+      int64_t J = 0, Dd = 0, Rr = 0;
+      uint8_t leaf = 0;
+      const int k = sh.kind[node];
+      int64_t cj = 0, cd = 0, cr = 0;
+      if (k != 0 && d < 3) {
+        const int cb = d == 0 ? 1 : d == 1 ? 5 : 21;
+        for (int q = 0; q < 4; ++q) {
+          const int c = cb + (2 * ly + (q >> 1)) * (2 << d) + 2 * lx + (q & 1);
+          cj += sh.jt[c], cd += sh.dt[c], cr += sh.rt[c];
+        }
+      }
+      if (k == 1) {
+        J = cj, Dd = cd, Rr = cr;
+      } else if (k == 2) {
+        const bool split_ok = sh.split_ok[node], leaf_ok = sh.leaf_ok[node];
+        const int flag = d < 3 ? 1 : 0;
+        int64_t lj = INT64_MAX;
+        if (leaf_ok) lj = sh.lj[node] + s * flag;
+        if (split_ok && (!leaf_ok || cj + s < lj)) {
+          J = cj + s, Dd = cd, Rr = cr + 1;
+        } else {
+          J = lj, Dd = sh.ld[node], Rr = sh.lr[node] + flag, leaf = 1;
+        }
+      }
+      sh.jt[node] = J, sh.dt[node] = Dd, sh.rt[node] = Rr, sh.leaf[node] = leaf;
+    }
+    __syncthreads();
+  }
+  // Outputs: one thread per 8x8 unit of the CTU.
+  if (tid < 64) {
+    const int ux = tid & 7, uy = tid >> 3;
+    const int x = cx + ux * 8, y = cy + uy * 8;
+    if (x < W8 && y < H8) {
+      int node = 0, d = 0;
+      for (; d < 3; ++d) {
+        node = (d == 0 ? 0 : d == 1 ? 1 : 5) + (uy >> (3 - d)) * (1 << d) + (ux >> (3 - d));
+        if (sh.leaf[node]) break;
+      }
+      if (d == 3) node = 21 + uy * 8 + ux;
+      const size_t u = (size_t)(y >> 3) * (W8 >> 3) + (x >> 3);
+      jb.depth[u] = (uint8_t)d;
+      jb.mode[u] = sh.mode[node];
+      jb.mv[2 * u] = sh.mvx[node];
+      jb.mv[2 * u + 1] = sh.mvy[node];
+    }
+  }
+  if (tid == 0) {
+    jb.ctu_cost[ctu] = sh.jt[0];
+    jb.ctu_dist[ctu] = sh.dt[0];
+    jb.ctu_bits[ctu] = sh.rt[0];
+  }
+}
+
+
+// ------------------------------------------------------------------------- depth bounds
+__global__ __launch_bounds__(256) void depth_bounds_kernel(const uint8_t* __restrict__ ref_depth,
+                                                           int ref_w, int ref_h, int dep_w,
+                                                           int dep_h, int dlo, int dhi,
+                                                           uint8_t* __restrict__ out) {
+  const int duw = (dep_w + 7) >> 3, duh = (dep_h + 7) >> 3;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= duw * duh) return;
+  const int ux = i % duw, uy = i / duw;
+  const int64_t xr = min((int64_t)(8 * ux + 4) * ref_w / dep_w, (int64_t)ref_w - 1);
+  const int64_t yr = min((int64_t)(8 * uy + 4) * ref_h / dep_h, (int64_t)ref_h - 1);
+  const int dr = ref_depth[(yr >> 3) * ((ref_w + 7) >> 3) + (xr >> 3)] & 3;
+  int ds = 3;
+  for (int d = 3; d >= 0; --d)
+    if ((int64_t)(64 >> d) * ref_w <= (int64_t)(64 >> dr) * dep_w) ds = d;
+  out[2 * i] = (uint8_t)max(0, ds - dlo);
+  out[2 * i + 1] = (uint8_t)min(3, ds + dhi);
+}
+
+}  // namespace mr
+
+// Single-job kernels (descriptor passed by value) and their launch wrappers.
+namespace mr {
+
+__global__ __launch_bounds__(256) void prep_kernel1(JobDesc jb) {
+  if ((int)blockIdx.x >= jb.ctus_w * jb.ctus_h) return;
+  prep_ctu(jb, blockIdx.x);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void search_kernel1(JobDesc jb) {
+  extern __shared__ uint32_t win[];
+  if ((int)blockIdx.x >= jb.ctus_w * jb.ctus_h || (int)blockIdx.y >= jb.nbands) return;
+  search_item<D>(jb, blockIdx.x, blockIdx.y, win);
+}
+
+__global__ __launch_bounds__(256) void leaf_kernel1(JobDesc jb) {
+  __shared__ LeafShared sh;
+  if ((int)blockIdx.x >= jb.ctus_w * jb.ctus_h) return;
+  leaf_ctu(jb, blockIdx.x, sh);
+}
+
+hipError_t launch_prep1(const JobDesc& jb, hipStream_t st) {
+  hipLaunchKernelGGL(prep_kernel1, dim3(jb.ctus_w * jb.ctus_h), dim3(256), 0, st, jb);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t allow_lds(size_t lds_bytes) {
+  static size_t allowed = 64 * 1024;
+  if (lds_bytes <= allowed) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute((const void*)search_kernel1<D>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes);
+  if (e == hipSuccess) allowed = lds_bytes;
+  return e;
+}
+
+hipError_t launch_search1(const JobDesc& jb, size_t lds_bytes, hipStream_t st) {
+  const dim3 grid(jb.ctus_w * jb.ctus_h, jb.nbands);
+  hipError_t e = jb.D == 2 ? allow_lds<2>(lds_bytes)
+                           : (jb.D == 4 ? allow_lds<4>(lds_bytes) : allow_lds<8>(lds_bytes));
+  if (e != hipSuccess) return e;
+  switch (jb.D) {
+    case 2: hipLaunchKernelGGL(search_kernel1<2>, grid, dim3(256), lds_bytes, st, jb); break;
+    case 4: hipLaunchKernelGGL(search_kernel1<4>, grid, dim3(256), lds_bytes, st, jb); break;
+    case 8: hipLaunchKernelGGL(search_kernel1<8>, grid, dim3(256), lds_bytes, st, jb); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf1(const JobDesc& jb, hipStream_t st) {
+  hipLaunchKernelGGL(leaf_kernel1, dim3(jb.ctus_w * jb.ctus_h), dim3(256), 0, st, jb);
+  return hipGetLastError();
+}
+
+hipError_t launch_depth_bounds(const uint8_t* ref_depth, int ref_w, int ref_h, int dep_w,
+                               int dep_h, int dlo, int dhi, uint8_t* out, hipStream_t st) {
+  const int n = ((dep_w + 7) >> 3) * ((dep_h + 7) >> 3);
+  hipLaunchKernelGGL(depth_bounds_kernel, dim3((n + 255) / 256), dim3(256), 0, st, ref_depth,
+                     ref_w, ref_h, dep_w, dep_h, dlo, dhi, out);
+  return hipGetLastError();
+}
+
+}  // namespace mr

@@ -1,0 +1,105 @@
+"""Host-side checks of libmr (no GPU): symbols, argument validation, host arithmetic."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mr_[a-z_0-9]+)\s*\(", text,
+                                flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def libmr():
+    from paper_2301_12191_amd import mr
+    return mr.lib()
+
+
+def test_library_exports_every_declared_symbol(libmr):
+    names = _declared_functions()
+    assert "mr_ctu_search" in names and "mr_depth_bounds" in names
+    for n in names:
+        assert hasattr(libmr, n), n
+
+
+def test_status_strings(libmr):
+    from paper_2301_12191_amd import mr
+    for code in range(-7, 1):
+        assert mr.mr_status_str(code).startswith("MR_")
+    assert "unknown" in mr.mr_status_str(-99)
+
+
+def _fake_frame(mr, w=64, h=64, stride=None, ptr=0x1000):
+    return mr.mr_frame(ctypes.c_void_p(ptr), w, h, stride if stride is not None else w)
+
+
+def _fake_out(mr):
+    p = ctypes.c_void_p(0x2000)
+    return mr.mr_search_out(p, p, p, p, p, p)
+
+
+@pytest.mark.parametrize("case", ["qp_low", "qp_high", "range_neg", "range_big", "null_cur",
+                                  "size_mismatch", "stride_small", "zero_width", "huge",
+                                  "null_out_field"])
+def test_search_rejects_invalid_arguments_before_launch(libmr, case):
+    from paper_2301_12191_amd import mr
+    cur, ref = _fake_frame(mr), _fake_frame(mr)
+    prm = mr.mr_search_params(30, 16)
+    out = _fake_out(mr)
+    if case == "qp_low":
+        prm.qp = -1
+    elif case == "qp_high":
+        prm.qp = 52
+    elif case == "range_neg":
+        prm.search_range = -1
+    elif case == "range_big":
+        prm.search_range = 129
+    elif case == "null_cur":
+        cur.luma = None
+    elif case == "size_mismatch":
+        ref = _fake_frame(mr, 64, 72)
+    elif case == "stride_small":
+        cur, ref = _fake_frame(mr, 64, 64, 32), _fake_frame(mr, 64, 64, 32)
+    elif case == "zero_width":
+        cur, ref = _fake_frame(mr, 0, 64), _fake_frame(mr, 0, 64)
+    elif case == "huge":
+        cur, ref = _fake_frame(mr, 8193, 64), _fake_frame(mr, 8193, 64)
+    elif case == "null_out_field":
+        out.mv = None
+    rc = libmr.mr_ctu_search(ctypes.byref(cur), ctypes.byref(ref), ctypes.byref(prm), None,
+                             ctypes.byref(out), None)
+    assert rc == mr.MR_EINVAL
+
+
+def test_search_rejects_null_structs(libmr):
+    from paper_2301_12191_amd import mr
+    cur = _fake_frame(mr)
+    prm = mr.mr_search_params(30, 16)
+    out = _fake_out(mr)
+    assert libmr.mr_ctu_search(None, ctypes.byref(cur), ctypes.byref(prm), None,
+                               ctypes.byref(out), None) == mr.MR_EINVAL
+    assert libmr.mr_ctu_search(ctypes.byref(cur), ctypes.byref(cur), None, None,
+                               ctypes.byref(out), None) == mr.MR_EINVAL
+    assert libmr.mr_ctu_search(ctypes.byref(cur), ctypes.byref(cur), ctypes.byref(prm), None,
+                               None, None) == mr.MR_EINVAL
+
+
+@pytest.mark.parametrize("args", [
+    (0, 64, 64, 128, 128, 0, 1), (1, 0, 64, 128, 128, 0, 1), (1, 64, 64, 0, 128, 0, 1),
+    (1, 64, 64, 128, 128, -1, 1), (1, 64, 64, 128, 128, 0, 4), (1, 9000, 64, 128, 128, 0, 1)])
+def test_depth_bounds_rejects_invalid_arguments(libmr, args):
+    from paper_2301_12191_amd import mr
+    ptr, rw, rh, dw, dh, lo, hi = args
+    rc = libmr.mr_depth_bounds(ctypes.c_void_p(0x1000 if ptr else 0), rw, rh, dw, dh, lo, hi,
+                               ctypes.c_void_p(0x2000), None)
+    assert rc == mr.MR_EINVAL
