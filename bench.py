@@ -1,0 +1,186 @@
+"""Benchmark of the per-CTU coding-tree search on one MI355X.
+
+Default workload (the headline number): 1920x1080 8-bit luma, 8 consecutive
+frame pairs (frame k searched against frame k-1), full search with R = 64 and
+QP 27, synthetic content (24 moving textured rectangles, MVs up to 48 px,
+global pan up to 4 px/frame, sigma-2 noise).  One step = all 8 pairs through
+the whole hot path (prep, motion search + arg-min, SATD / intra / quad-tree
+decision) = 4080 CTUs.  Frames are resident in HBM before timing starts.
+
+Beside it the JSON line carries:
+  roofline     : the search kernel (dominant) as algorithmic absolute
+                 differences per second against the packed-byte SAD peak;
+  pruned       : multi-resolution pruning on a 3840x2160 source: 960x540
+                 reference (QP 32, R 32) bounds 1920x1080 (QP 27, R 64) and
+                 3840x2160 (QP 22, R 128), refine depths n..n+1; speedup of
+                 pruned over full search and the exact RD-cost increase;
+  cpu_baseline : the CPU oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-pruned]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Packed-byte SAD peak: 256 CUs x 64 lanes x 2.4 GHz x 4 absolute differences per v_sad_u8.
+PEAK_ABSDIFF = 256 * 64 * 2.4e9 * 4
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pruned", action="store_true")
+    ap.add_argument("--cpu-ctus", type=int, default=768,
+                    help="CTUs of one 1080p pair the CPU oracle times (bounded sample)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the coding-tree "
+              "search has no cross-GPU step in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2301_12191_amd import mr
+
+    assert torch.cuda.is_available(), "no GPU"
+    mr.lib()
+    dev = torch.device("cuda:0")
+
+    # ---------------------------------------------------------------- headline workload
+    W, H, R, QP, NP = 1920, 1080, 64, 27, 8
+    log("rendering 1920x1080 x 9 frames")
+    scene = synth.Scene(synth.SEED_BASE + 1, W, H, 24, 48, 4)
+    frames = [torch.from_numpy(scene.render(t)).to(dev) for t in range(NP + 1)]
+    jobs = [dict(cur=frames[k + 1], ref=frames[k], qp=QP, search_range=R) for k in range(NP)]
+    stream = torch.cuda.current_stream()
+    batch = mr.Batch(jobs)  # one persistent search launch over all 8 pairs per step
+    ctus_per_pair = jobs[0]["out"]["cost"].numel()
+    ctus_per_step = ctus_per_pair * NP
+
+    def step():
+        batch.launch(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mr.mr_profile_read(reset=True)
+    mr.mr_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mr.mr_profile_enable(False)
+    prof = mr.mr_profile_read(reset=True)
+    elapsed = t1 - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = ctus_per_step * args.steps / elapsed
+    log(f"{ms_per_step:.3f} ms/step, {value:.0f} CTUs/s; stages {prof}")
+
+    W8, H8 = (W + 7) // 8 * 8, (H + 7) // 8 * 8
+    absdiff_per_launch = (2 * R + 1) ** 2 * W8 * H8 * NP  # one search launch covers 8 pairs
+    search_ms, search_n = prof["search"]
+    search_avg_s = search_ms / 1e3 / max(1, search_n)
+    achieved = absdiff_per_launch / search_avg_s
+    roofline = {
+        "bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_ABSDIFF / 1e12, 3),
+        "unit": "T absdiff/s", "frac": round(achieved / PEAK_ABSDIFF, 4), "traffic": None,
+        "kernel": "search_kernel (persistent, 8 pairs per launch)", "avg_launch_ms": round(search_avg_s * 1e3, 4),
+        "absdiff_per_launch": absdiff_per_launch,
+        "stage_avg_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()},
+    }
+
+    # ------------------------------------------------------------- pruned vs full search
+    pruned = None
+    if not args.no_pruned:
+        log("rendering 3840x2160 source pair")
+        src = synth.Scene(synth.SEED_BASE + 2, 3840, 2160, 24, 96, 8)
+        s0, s1 = src.render(0), src.render(1)
+        rungs = {}
+        for (w, h, n) in [(960, 540, 4), (1920, 1080, 2), (3840, 2160, 1)]:
+            rungs[w] = (torch.from_numpy(synth.box_downscale(s0, n, w, h)).to(dev),
+                        torch.from_numpy(synth.box_downscale(s1, n, w, h)).to(dev))
+        r540, c540 = rungs[960]
+        ref_out = mr.mr_ctu_search(c540, r540, 32, 32)
+        deps = [(1920, 1080, 27, 64), (3840, 2160, 22, 128)]
+        bounds = {w: mr.mr_depth_bounds(ref_out["depth"], 960, 540, w, h, 0, 1)
+                  for (w, h, _, _) in deps}
+        torch.cuda.synchronize()
+        res = {"full_ms": 0.0, "pruned_ms": 0.0, "J_full": 0, "J_pruned": 0, "per_rung": {}}
+        reps = 3
+        for (w, h, qp, rr) in deps:
+            ref_t, cur_t = rungs[w]
+            of, op = mr.alloc_outputs(w, h, dev), mr.alloc_outputs(w, h, dev)
+            times = {}
+            for name, b, o in (("full", None, of), ("pruned", bounds[w], op)):
+                mr.mr_ctu_search(cur_t, ref_t, qp, rr, bounds=b, out=o)  # warm
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                for _ in range(reps):
+                    mr.mr_ctu_search(cur_t, ref_t, qp, rr, bounds=b, out=o)
+                torch.cuda.synchronize()
+                times[name] = (time.perf_counter() - ta) * 1e3 / reps
+            jf, jp = int(of["cost"].sum().item()), int(op["cost"].sum().item())
+            res["full_ms"] += times["full"]
+            res["pruned_ms"] += times["pruned"]
+            res["J_full"] += jf
+            res["J_pruned"] += jp
+            res["per_rung"][f"{w}x{h}"] = {
+                "full_ms": round(times["full"], 3), "pruned_ms": round(times["pruned"], 3),
+                "speedup": round(times["full"] / times["pruned"], 4),
+                "rd_cost_increase_pct": round(100.0 * (jp - jf) / jf, 6)}
+        pruned = {
+            "workload": "3840x2160 source; 960x540 QP32 R32 reference bounds 1920x1080 QP27 R64 "
+                        "and 3840x2160 QP22 R128 (depths n..n+1)",
+            "speedup": round(res["full_ms"] / res["pruned_ms"], 4),
+            "rd_cost_increase_pct": round(100.0 * (res["J_pruned"] - res["J_full"]) / res["J_full"], 6),
+            "full_ms": round(res["full_ms"], 3), "pruned_ms": round(res["pruned_ms"], 3),
+            "per_rung": res["per_rung"]}
+        log(f"pruned: {pruned}")
+
+    # ------------------------------------------------------------------- CPU oracle leg
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        cur_np, ref_np = frames[1].cpu().numpy(), frames[0].cpu().numpy()
+        n = min(args.cpu_ctus, ctus_per_pair)
+        threads = min(16, os.cpu_count() or 1)
+        log(f"CPU oracle: {n} CTUs on {threads} threads")
+        ta = time.perf_counter()
+        oracle.ctu_search(cur_np, ref_np, QP, R, ctu_list=list(range(n)), n_threads=threads)
+        dt = time.perf_counter() - ta
+        cpu = {"value": round(n / dt, 3), "unit": "CTUs/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n} CTUs (raster order) of one 1920x1080 pair, R 64, QP 27; "
+                         f"{dt:.1f} s"}
+
+    line = {
+        "metric": "CTUs/s full vs ref-pruned CU search (bit-exact); p50/p99 frame latency",
+        "value": round(value, 1), "unit": "CTUs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "1920x1080 luma, 8 frame pairs, full search R64 QP27",
+                   "ctus_per_step": ctus_per_step, "frames": NP + 1, "search_range": R,
+                   "qp": QP},
+        "roofline": roofline, "cpu_baseline": cpu, "pruned": pruned,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -102,6 +102,41 @@ typedef struct {
 int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
                   const uint8_t* bounds, mr_search_out* out, void* hip_stream);
 
+/* One frame pair of a batch (same meaning as the mr_ctu_search arguments). */
+typedef struct {
+  mr_frame cur, ref;
+  mr_search_params params;
+  const uint8_t* bounds; /* device [U][V][2] or NULL */
+  mr_search_out out;
+} mr_search_job;
+
+/* Batched coding-tree search: the CTUs of all jobs (frames of any sizes,
+ * ranges and QPs) go through one persistent work-queue search launch fed by a
+ * flattened item list ordered longest-first, between one prep and one leaf
+ * launch over the flattened CTUs.  Results are identical to calling
+ * mr_ctu_search per job.  Host-blocking while it uploads the job list, then
+ * asynchronous on hip_stream.  Errors: MR_EINVAL (n_jobs < 1 or any job
+ * invalid; nothing is launched), MR_ENOMEM, MR_EHIP. */
+int mr_ctu_search_batch(const mr_search_job* jobs, int32_t n_jobs, void* hip_stream);
+
+/* A reusable batch: plans tiles, tables and work items once, owns its device
+ * scratch, and records prep -> search -> leaf as a HIP graph that
+ * mr_batch_launch replays.  Caller-owned frames, bounds and outputs must stay
+ * valid while launches that use them are in flight.
+ *   mr_batch_create : plan + allocate + capture (host-blocking).
+ *   mr_batch_set_jobs: swap in new frame / bounds / output pointers for jobs
+ *     of the same count, sizes, QPs, ranges and bounds presence (else
+ *     MR_EINVAL); waits for this batch's previous launch to finish.
+ *   mr_batch_launch : replay on hip_stream (with stage profiling enabled, the
+ *     three kernels are launched directly between timing events instead).
+ *   mr_batch_destroy: waits for the last launch, frees everything (NULL ok).
+ * Errors: MR_EINVAL, MR_ENOMEM, MR_EHIP. */
+typedef struct mr_batch mr_batch;
+int mr_batch_create(const mr_search_job* jobs, int32_t n_jobs, mr_batch** out);
+int mr_batch_set_jobs(mr_batch* b, const mr_search_job* jobs, int32_t n_jobs);
+int mr_batch_launch(mr_batch* b, void* hip_stream);
+int mr_batch_destroy(mr_batch* b);
+
 /* Depth bounds of a dependent representation (dep_w x dep_h) from the depth
  * map of its reference representation (ref_w x ref_h, as written by
  * mr_ctu_search), for multi-resolution reuse.  For dependent unit (ux, uy):
@@ -119,6 +154,36 @@ int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_para
 int mr_depth_bounds(const uint8_t* ref_depth, int32_t ref_w, int32_t ref_h, int32_t dep_w,
                     int32_t dep_h, int32_t delta_lo, int32_t delta_hi, uint8_t* bounds_out,
                     void* hip_stream);
+
+/* Tile override for one search range R (an autotuner knob): the search
+ * kernel gives each lane 4 horizontal x d vertical candidate shifts (d = 2, 4
+ * or 8) and splits the search window into nbands dy bands (1..8), one
+ * workgroup per (CTU, band).  d = 0 removes the override (built-in choice).
+ * Results are identical for every setting; only speed changes.
+ * Errors: MR_EINVAL (R outside 0..128, d not 0/2/4/8, nbands outside 1..8). */
+int mr_set_tiles(int32_t search_range, int32_t d, int32_t nbands);
+
+/* Stage timing, a profiling aid for benchmarks.  While enabled, every
+ * mr_ctu_search call records HIP events on its stream around its three
+ * kernels: 0 prep (pack current CTUs, reset keys), 1 search (motion search
+ * and arg-min), 2 leaf (SATD, intra, quad-tree decision).  mr_profile_read
+ * waits for the recorded events, adds their elapsed times (milliseconds) and
+ * counts per stage into *out and, if reset != 0, forgets them.
+ * Errors: MR_EINVAL (out NULL), MR_EHIP. */
+typedef struct {
+  double ms[3];
+  int64_t launches[3];
+} mr_profile;
+
+int mr_profile_enable(int on);
+int mr_profile_read(mr_profile* out, int reset);
+
+/* Host helpers (no device work): s = round(sqrt(lambda) * 65536) for qp 0..51
+ * (-1 outside), and the length in bits of the signed Exp-Golomb code se(v)
+ * (v maps to codeNum 2v-1 for v > 0, -2v otherwise; ue(k) has
+ * 2 floor(log2(k+1)) + 1 bits), as used by every cost above. */
+int64_t mr_sqrt_lambda_q16(int32_t qp);
+int32_t mr_se_bits(int32_t v);
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* mr_status_str(int status);

@@ -11,6 +11,12 @@ constexpr int kWaveSteps = 64;      // search tasks per wavefront step (one per 
 constexpr int kRankBits = 11;       // rank field of the 32-bit arg-min key
 constexpr uint32_t kCinv = 1050000u;  // cost field of candidates outside the window
 constexpr uint64_t kKeyNone = ~0ull;
+constexpr int kMaxStrip = 4;        // CTUs (wavefronts) per search workgroup
+
+// Search work item of a batch: x = job, y = row << 16 | first CTU column << 4 | band.
+__host__ __device__ inline uint32_t pack_item_y(int row, int col0, int band) {
+  return ((uint32_t)row << 16) | ((uint32_t)col0 << 4) | (uint32_t)band;
+}
 
 // Node index: depth offsets 0, 1, 5, 21, raster order inside a depth.
 __host__ __device__ inline int node_index(int d, int lx, int ly) {
@@ -28,14 +34,17 @@ struct SearchLayout {
   int32_t win_rows_max, win_dwords;  // LDS window rows (largest band), dwords per row
 };
 
-// One frame pair's search job as seen by the kernels.
+// One frame pair's search job as seen by the kernels (stored in device memory;
+// a batch is an array of these).
 struct JobDesc {
   const uint8_t* cur;      // device luma
   const uint8_t* ref;
   int32_t w, h, stride;
   int32_t w8, h8, ctus_w, ctus_h;
   int32_t R, D, Q, nbands;
-  int32_t win_dwords;
+  int32_t win_dwords;      // LDS window row length in dwords: Q + 16 * strip
+  int32_t strip;           // CTUs per search workgroup (one wavefront each)
+  int32_t ctu_start;       // first flattened CTU index of this job in its batch
   int32_t band_g0[kMaxBands + 1];
   int32_t band_step0[kMaxBands + 1];
   int64_t s;               // sqrt(lambda) in Q16

@@ -22,6 +22,7 @@
 namespace mr {
 
 typedef const __attribute__((address_space(4))) uint32_t* sptr32;  // scalar (uniform) loads
+typedef const __attribute__((address_space(4))) JobDesc* cjob;     // job descriptor, scalar loads
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -47,23 +48,23 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
 
 // ---------------------------------------------------------------------------------- prep
 // One workgroup (256 threads) per CTU.
-__device__ void prep_ctu(const JobDesc& jb, int ctu) {
+__device__ void prep_ctu(cjob jb, int ctu) {
   const int tid = threadIdx.x;
-  const int cx = (ctu % jb.ctus_w) * kCtu, cy = (ctu / jb.ctus_w) * kCtu;
+  const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
   // 64 blocks x 16 dwords: thread -> (block, 4 dwords = 2 rows x 2 dwords)
   {
     const int bz = tid >> 2, part = tid & 3;
     const int bx = zx(bz), by = zy(bz);
-    uint32_t* dst = (uint32_t*)jb.curpack + (size_t)ctu * 1024 + bz * 16 + part * 4;
+    uint32_t* dst = (uint32_t*)jb->curpack + (size_t)ctu * 1024 + bz * 16 + part * 4;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = part * 2 + (i >> 1), c = i & 1;
-      const int y = min(cy + by * 8 + r, jb.h - 1);
-      const uint8_t* row = jb.cur + (size_t)y * jb.stride;
+      const int y = min(cy + by * 8 + r, jb->h - 1);
+      const uint8_t* row = jb->cur + (size_t)y * jb->stride;
       const int x0 = cx + bx * 8 + c * 4;
       uint32_t v = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) v |= (uint32_t)row[min(x0 + b, jb.w - 1)] << (8 * b);
+      for (int b = 0; b < 4; ++b) v |= (uint32_t)row[min(x0 + b, jb->w - 1)] << (8 * b);
       dst[i] = v;
     }
   }
@@ -73,14 +74,14 @@ __device__ void prep_ctu(const JobDesc& jb, int ctu) {
     const int n = kCtu >> d, lx = local % (1 << d), ly = local / (1 << d);
     const int x0 = cx + lx * n, y0 = cy + ly * n;
     uint8_t e = 0;
-    if (x0 + n <= jb.w8 && y0 + n <= jb.h8) {
+    if (x0 + n <= jb->w8 && y0 + n <= jb->h8) {
       e = 1;
-      if (jb.bounds) {
-        const int uw = jb.w8 >> 3;
+      if (jb->bounds) {
+        const int uw = jb->w8 >> 3;
         int min_lo = 3, max_hi = 0;
         for (int uy = y0 >> 3; uy < (y0 + n) >> 3; ++uy)
           for (int ux = x0 >> 3; ux < (x0 + n) >> 3; ++ux) {
-            const uint8_t* b = jb.bounds + 2 * ((size_t)uy * uw + ux);
+            const uint8_t* b = jb->bounds + 2 * ((size_t)uy * uw + ux);
             min_lo = min(min_lo, (int)b[0]);
             max_hi = max(max_hi, (int)b[1]);
           }
@@ -88,31 +89,31 @@ __device__ void prep_ctu(const JobDesc& jb, int ctu) {
         e = (d >= min_lo || !split_ok) ? 1 : 0;
       }
     }
-    jb.elig[(size_t)ctu * kNodes + tid] = e;
-    jb.keys[(size_t)ctu * kNodes + tid] = kKeyNone;
+    jb->elig[(size_t)ctu * kNodes + tid] = e;
+    jb->keys[(size_t)ctu * kNodes + tid] = kKeyNone;
   }
 }
 
 
 // -------------------------------------------------------------------------------- search
-__device__ void stage_window(const JobDesc& jb, int cx, int cy, int g0, int rows, uint32_t* win) {
-  const int Wd = jb.win_dwords;
-  const int ybase = cy - jb.R + g0 * jb.D, xbase = cx - jb.R;
-  const bool dword_ok = ((jb.stride & 3) == 0) && ((((uintptr_t)jb.ref) & 3) == 0) &&
-                        ((xbase & 3) == 0);
+// Stage rows [y0, y0 + rows) x dword columns [0, Wd) of the reference, with
+// coordinates clamped to the picture, into the LDS window (x origin x0).
+__device__ void stage_window(cjob jb, int x0, int y0, int rows, uint32_t* win) {
+  const int Wd = jb->win_dwords, w = jb->w, h = jb->h, stride = jb->stride;
+  const uint8_t* ref = jb->ref;
+  const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0) && ((x0 & 3) == 0);
   const int total = rows * Wd;
   for (int i = threadIdx.x; i < total; i += blockDim.x) {
     const int row = i / Wd, c4 = (i - row * Wd) * 4;
-    const int y = clampi(ybase + row, 0, jb.h - 1);
-    const uint8_t* rp = jb.ref + (size_t)y * jb.stride;
-    const int x = xbase + c4;
+    const uint8_t* rp = ref + (size_t)clampi(y0 + row, 0, h - 1) * stride;
+    const int x = x0 + c4;
     uint32_t v;
-    if (dword_ok && x >= 0 && x + 3 < jb.w) {
+    if (dword_ok && x >= 0 && x + 3 < w) {
       v = *(const uint32_t*)(rp + x);
     } else {
       v = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[clampi(x + b, 0, jb.w - 1)] << (8 * b);
+      for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[clampi(x + b, 0, w - 1)] << (8 * b);
     }
     win[i] = v;
   }
@@ -127,29 +128,29 @@ __device__ __forceinline__ void merge_keys(uint32_t vk, const uint64_t* __restri
   }
 }
 
+// One wavefront: all steps of one (CTU, band); `win` points at this CTU's
+// column 0 of the staged window (dx = -R).
 template <int D>
-__device__ void search_item(const JobDesc& jb, int ctu, int band, uint32_t* win) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  const int Q = jb.Q, Wd = jb.win_dwords;
-  const int cx = (ctu % jb.ctus_w) * kCtu, cy = (ctu / jb.ctus_w) * kCtu;
-  const int g0 = jb.band_g0[band], g1 = jb.band_g0[band + 1];
-  stage_window(jb, cx, cy, g0, (g1 - g0) * D + 63, win);
-  __syncthreads();
-
+__device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win) {
+  const int lane = threadIdx.x & 63;
+  const int Q = jb->Q, Wd = jb->win_dwords;
+  const int g0 = jb->band_g0[band], g1 = jb->band_g0[band + 1];
   const int ntasks = (g1 - g0) * Q;
-  const int step0 = jb.band_step0[band], nsteps = jb.band_step0[band + 1] - step0;
-  const uint8_t* __restrict__ elig = jb.elig + (size_t)ctu * kNodes;
-  const sptr32 cur = (sptr32)(jb.curpack + (size_t)ctu * 1024);
+  const int step0 = jb->band_step0[band], nsteps = jb->band_step0[band + 1] - step0;
+  const uint8_t* __restrict__ elig = jb->elig + (size_t)ctu * kNodes;
+  const sptr32 cur = (sptr32)(jb->curpack + (size_t)ctu * 1024);
+  const uint32_t* __restrict__ qtab = jb->qtab;
+  const uint64_t* __restrict__ dtab = jb->dtab;
   uint64_t best8 = kKeyNone, bestB = kKeyNone;
 
-  for (int st = wave; st < nsteps; st += nwaves) {
+  for (int st = 0; st < nsteps; ++st) {
     const int gstep = step0 + st;
     int task = st * kWaveSteps + lane;
     if (task >= ntasks) task = ntasks - 1;  // idle lane: its table entries are invalid
     const int g = task / Q, qd = task - g * Q;
     uint32_t kq[D][4];
     {
-      const uint4* qp = (const uint4*)(jb.qtab + ((size_t)gstep * kWaveSteps + lane) * (4 * D));
+      const uint4* qp = (const uint4*)(qtab + ((size_t)gstep * kWaveSteps + lane) * (4 * D));
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         const uint4 t = qp[j];
@@ -206,7 +207,8 @@ __device__ void search_item(const JobDesc& jb, int ctu, int band, uint32_t* win)
           for (int j = 0; j < D; ++j)
 #pragma unroll
             for (int k = 0; k < 4; ++k) m = min(m, acc[j][k] * 2048u + kq[j][k]);
-          { const uint32_t mk = wave_min(m); vk8 = lane == bz ? mk : vk8; }
+          const uint32_t mk = wave_min(m);
+          vk8 = lane == bz ? mk : vk8;
         }
 #pragma unroll
         for (int j = 0; j < D; ++j)
@@ -221,7 +223,8 @@ __device__ void search_item(const JobDesc& jb, int ctu, int band, uint32_t* win)
           for (int j = 0; j < D; ++j)
 #pragma unroll
             for (int k = 0; k < 4; ++k) m = min(m, s16[j][k] * 2048u + kq[j][k]);
-          { const uint32_t mk = wave_min(m); vkB = lane == reg ? mk : vkB; }
+          const uint32_t mk = wave_min(m);
+          vkB = lane == reg ? mk : vkB;
         }
         if ((reg & 3) == 0) {
 #pragma unroll
@@ -242,7 +245,8 @@ __device__ void search_item(const JobDesc& jb, int ctu, int band, uint32_t* win)
           for (int j = 0; j < D; ++j)
 #pragma unroll
             for (int k = 0; k < 4; ++k) m = min(m, s32[j][k] * 2048u + kq[j][k]);
-          { const uint32_t mk = wave_min(m); vkB = lane == 16 + qz ? mk : vkB; }
+          const uint32_t mk = wave_min(m);
+          vkB = lane == 16 + qz ? mk : vkB;
         }
 #pragma unroll
         for (int j = 0; j < D; ++j)
@@ -256,15 +260,16 @@ __device__ void search_item(const JobDesc& jb, int ctu, int band, uint32_t* win)
       for (int j = 0; j < D; ++j)
 #pragma unroll
         for (int k = 0; k < 4; ++k) m = min(m, s64[j][k] * 2048u + kq[j][k]);
-      { const uint32_t mk = wave_min(m); vkB = lane == 20 ? mk : vkB; }
+      const uint32_t mk = wave_min(m);
+      vkB = lane == 20 ? mk : vkB;
     }
-    const uint64_t* dt = jb.dtab + (size_t)gstep * 2048;
+    const uint64_t* dt = dtab + (size_t)gstep * 2048;
     merge_keys(vk8, dt, best8);
     if (lane < 21) merge_keys(vkB, dt, bestB);
   }
 
   // Publish: lane i holds the 8x8 CU of Z-order block i; lanes 0..20 the larger CUs.
-  unsigned long long* keys = (unsigned long long*)jb.keys + (size_t)ctu * kNodes;
+  unsigned long long* keys = (unsigned long long*)jb->keys + (size_t)ctu * kNodes;
   if (best8 != kKeyNone) atomicMin(&keys[21 + zy(lane) * 8 + zx(lane)], (unsigned long long)best8);
   if (lane < 21 && bestB != kKeyNone) {
     int node;
@@ -274,7 +279,6 @@ __device__ void search_item(const JobDesc& jb, int ctu, int band, uint32_t* win)
     atomicMin(&keys[node], (unsigned long long)bestB);
   }
 }
-
 
 // ---------------------------------------------------------------------------------- leaf
 // SATD of a 4x4 residual: sum |H d H^T| / 2 via butterflies.
@@ -331,16 +335,16 @@ __device__ __forceinline__ uint32_t shfl_sum(uint32_t v, int width) {
   return v;
 }
 
-__device__ void leaf_ctu(const JobDesc& jb, int ctu, LeafShared& sh) {
+__device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cx = (ctu % jb.ctus_w) * kCtu, cy = (ctu / jb.ctus_w) * kCtu;
-  const int W8 = jb.w8, H8 = jb.h8;
-  const int span = 2 * jb.R + 1;
+  const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
+  const int W8 = jb->w8, H8 = jb->h8;
+  const int span = 2 * jb->R + 1;
 
   // Current CTU (coded picture, edge-replicated).
   for (int i = tid; i < 64 * 64; i += blockDim.x) {
-    const int y = min(cy + (i >> 6), jb.h - 1), x = min(cx + (i & 63), jb.w - 1);
-    sh.cur[i] = jb.cur[(size_t)y * jb.stride + x];
+    const int y = min(cy + (i >> 6), jb->h - 1), x = min(cx + (i & 63), jb->w - 1);
+    sh.cur[i] = jb->cur[(size_t)y * jb->stride + x];
   }
   if (tid < kNodes) {
     const int node = tid;
@@ -348,24 +352,24 @@ __device__ void leaf_ctu(const JobDesc& jb, int ctu, LeafShared& sh) {
     const int local = node - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
     const int n = kCtu >> d, x0 = cx + (local % (1 << d)) * n, y0 = cy + (local / (1 << d)) * n;
     sh.kind[node] = (x0 >= W8 || y0 >= H8) ? 0 : ((x0 + n > W8 || y0 + n > H8) ? 1 : 2);
-    const uint8_t e = jb.elig[(size_t)ctu * kNodes + node];
+    const uint8_t e = jb->elig[(size_t)ctu * kNodes + node];
     sh.elig[node] = e;
     int mx = 0, my = 0;
     if (e) {
-      const uint64_t key = jb.keys[(size_t)ctu * kNodes + node];
+      const uint64_t key = jb->keys[(size_t)ctu * kNodes + node];
       const int idx = (int)(key & 0x1FFFF);
-      my = idx / span - jb.R;
-      mx = idx - (my + jb.R) * span - jb.R;
+      my = idx / span - jb->R;
+      mx = idx - (my + jb->R) * span - jb->R;
     }
     sh.mvx[node] = (int16_t)mx, sh.mvy[node] = (int16_t)my;
     // bounds admissibility (same rule the prep kernel applied)
     bool split_ok = d < 3, leaf_ok = true;
-    if (jb.bounds && sh.kind[node] == 2) {
+    if (jb->bounds && sh.kind[node] == 2) {
       const int uw = W8 >> 3;
       int min_lo = 3, max_hi = 0;
       for (int uy = y0 >> 3; uy < (y0 + n) >> 3; ++uy)
         for (int ux = x0 >> 3; ux < (x0 + n) >> 3; ++ux) {
-          const uint8_t* b = jb.bounds + 2 * ((size_t)uy * uw + ux);
+          const uint8_t* b = jb->bounds + 2 * ((size_t)uy * uw + ux);
           min_lo = min(min_lo, (int)b[0]);
           max_hi = max(max_hi, (int)b[1]);
         }
@@ -389,7 +393,7 @@ __device__ void leaf_ctu(const JobDesc& jb, int ctu, LeafShared& sh) {
     else x = x0 + (off - 2 * n - 1), y = y0 - 1;            // top row p[off-2n-1][-1]
     int v = -1;
     if (x >= 0 && y >= 0 && x < W8 && y < H8)
-      v = jb.cur[(size_t)min(y, jb.h - 1) * jb.stride + min(x, jb.w - 1)];
+      v = jb->cur[(size_t)min(y, jb->h - 1) * jb->stride + min(x, jb->w - 1)];
     sh.refs[i] = (int16_t)v;
   }
   __syncthreads();
@@ -443,9 +447,9 @@ __device__ void leaf_ctu(const JobDesc& jb, int ctu, LeafShared& sh) {
         int r[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          const int x = clampi(cx + tx * 4 + (i & 3) + mx, 0, jb.w - 1);
-          const int y = clampi(cy + ty * 4 + (i >> 2) + my, 0, jb.h - 1);
-          r[i] = c[i] - (int)jb.ref[(size_t)y * jb.stride + x];
+          const int x = clampi(cx + tx * 4 + (i & 3) + mx, 0, jb->w - 1);
+          const int y = clampi(cy + ty * 4 + (i >> 2) + my, 0, jb->h - 1);
+          r[i] = c[i] - (int)jb->ref[(size_t)y * jb->stride + x];
         }
         v0 = satd4x4(r);
         const int16_t* L = sh.refs + ref_offset(node);
@@ -476,7 +480,7 @@ __device__ void leaf_ctu(const JobDesc& jb, int ctu, LeafShared& sh) {
     }
   }
   __syncthreads();
-  const int64_t s = jb.s;
+  const int64_t s = jb->s;
   if (tid < kNodes) {
     const int node = tid;
     if (node == 0) {
@@ -543,16 +547,16 @@ __device__ void leaf_ctu(const JobDesc& jb, int ctu, LeafShared& sh) {
       }
       if (d == 3) node = 21 + uy * 8 + ux;
       const size_t u = (size_t)(y >> 3) * (W8 >> 3) + (x >> 3);
-      jb.depth[u] = (uint8_t)d;
-      jb.mode[u] = sh.mode[node];
-      jb.mv[2 * u] = sh.mvx[node];
-      jb.mv[2 * u + 1] = sh.mvy[node];
+      jb->depth[u] = (uint8_t)d;
+      jb->mode[u] = sh.mode[node];
+      jb->mv[2 * u] = sh.mvx[node];
+      jb->mv[2 * u + 1] = sh.mvy[node];
     }
   }
   if (tid == 0) {
-    jb.ctu_cost[ctu] = sh.jt[0];
-    jb.ctu_dist[ctu] = sh.dt[0];
-    jb.ctu_bits[ctu] = sh.rt[0];
+    jb->ctu_cost[ctu] = sh.jt[0];
+    jb->ctu_dist[ctu] = sh.dt[0];
+    jb->ctu_bits[ctu] = sh.rt[0];
   }
 }
 
@@ -578,59 +582,145 @@ __global__ __launch_bounds__(256) void depth_bounds_kernel(const uint8_t* __rest
 
 }  // namespace mr
 
-// Single-job kernels (descriptor passed by value) and their launch wrappers.
+// Kernels over a batch of jobs (an array of JobDesc in device memory) and their
+// launch wrappers.  prep and leaf run one workgroup per CTU of the flattened
+// batch; search is one persistent work-queue kernel over (job, strip, band) items.
 namespace mr {
 
-__global__ __launch_bounds__(256) void prep_kernel1(JobDesc jb) {
-  if ((int)blockIdx.x >= jb.ctus_w * jb.ctus_h) return;
-  prep_ctu(jb, blockIdx.x);
+// Job owning flattened CTU `flat` (jobs sorted by ctu_start).
+__device__ int find_job(cjob jobs, int n_jobs, int flat) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].ctu_start <= flat) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
+__global__ void store_job_kernel(JobDesc jb, JobDesc* dst) {
+  if (threadIdx.x == 0) *dst = jb;
+}
+
+__global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus,
+                                                   uint32_t* counter) {
+  const cjob jobs = (cjob)jobs_;
+  const int flat = blockIdx.x;
+  if (flat == 0 && threadIdx.x == 0) *counter = 0;  // work-queue head of the search kernel
+  if (flat >= n_ctus) return;
+  const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
+  prep_ctu(jobs + j, flat - jobs[j].ctu_start);
+}
+
+// Persistent search: each workgroup pops items until the queue is empty.  An
+// item is a strip of up to `strip` horizontally adjacent CTUs (one wavefront
+// each) and one dy band; the strip's reference window band is staged once in
+// LDS and shared by its wavefronts.  items == null: one job, items implicit.
 template <int D>
-__global__ __launch_bounds__(256) void search_kernel1(JobDesc jb) {
+__device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const uint2* items_,
+                                                  int n_items, uint32_t* counter, uint32_t* win) {
+  __shared__ int s_item;
+  const cjob jobs = (cjob)jobs_;
+  const sptr32 items = (sptr32)items_;
+  const int wave = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= n_items) break;  // every wavefront of the workgroup sees the same value
+    int job, row, col0, band;
+    if (items_) {
+      const uint32_t vx = items[2 * it], vy = items[2 * it + 1];
+      job = (int)vx, row = (int)(vy >> 16), col0 = (int)((vy >> 4) & 0xFFF), band = (int)(vy & 15);
+    } else {
+      const int nb = jobs[0].nbands, sw = jobs[0].strip;
+      const int spr = (jobs[0].ctus_w + sw - 1) / sw;
+      job = 0, band = it % nb;
+      const int strip = it / nb;
+      row = strip / spr, col0 = (strip % spr) * sw;
+    }
+    const cjob jb = jobs + job;
+    const int g0 = jb->band_g0[band], g1 = jb->band_g0[band + 1];
+    stage_window(jb, col0 * kCtu - jb->R, row * kCtu - jb->R + g0 * D, (g1 - g0) * D + 63, win);
+    __syncthreads();
+    const int col = col0 + wave;
+    if (col < jb->ctus_w) search_wave<D>(jb, row * jb->ctus_w + col, band, win + 16 * wave);
+    __syncthreads();  // the window is restaged for the next item
+  }
+}
+
+// D = 2, 4: three wavefronts per SIMD (register budget 168); D = 8 keeps its
+// larger register file at one or two.
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void search_kernel(
+    const JobDesc* jobs_, const uint2* items_, int n_items, uint32_t* counter) {
   extern __shared__ uint32_t win[];
-  if ((int)blockIdx.x >= jb.ctus_w * jb.ctus_h || (int)blockIdx.y >= jb.nbands) return;
-  search_item<D>(jb, blockIdx.x, blockIdx.y, win);
+  search_persistent<D>(jobs_, items_, n_items, counter, win);
 }
 
-__global__ __launch_bounds__(256) void leaf_kernel1(JobDesc jb) {
+__global__ __launch_bounds__(256) void search_kernel_d8(const JobDesc* jobs_, const uint2* items_,
+                                                        int n_items, uint32_t* counter) {
+  extern __shared__ uint32_t win[];
+  search_persistent<8>(jobs_, items_, n_items, counter, win);
+}
+
+__global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus) {
   __shared__ LeafShared sh;
-  if ((int)blockIdx.x >= jb.ctus_w * jb.ctus_h) return;
-  leaf_ctu(jb, blockIdx.x, sh);
+  const cjob jobs = (cjob)jobs_;
+  const int flat = blockIdx.x;
+  if (flat >= n_ctus) return;
+  const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
+  leaf_ctu(jobs + j, flat - jobs[j].ctu_start, sh);
 }
 
-hipError_t launch_prep1(const JobDesc& jb, hipStream_t st) {
-  hipLaunchKernelGGL(prep_kernel1, dim3(jb.ctus_w * jb.ctus_h), dim3(256), 0, st, jb);
+hipError_t launch_store_job(const JobDesc& jb, JobDesc* dst, hipStream_t st) {
+  hipLaunchKernelGGL(store_job_kernel, dim3(1), dim3(64), 0, st, jb, dst);
   return hipGetLastError();
 }
 
-template <int D>
-static hipError_t allow_lds(size_t lds_bytes) {
-  static size_t allowed = 64 * 1024;
-  if (lds_bytes <= allowed) return hipSuccess;
-  const hipError_t e = hipFuncSetAttribute((const void*)search_kernel1<D>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes);
-  if (e == hipSuccess) allowed = lds_bytes;
-  return e;
+hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* counter,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(prep_kernel, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus, counter);
+  return hipGetLastError();
 }
 
-hipError_t launch_search1(const JobDesc& jb, size_t lds_bytes, hipStream_t st) {
-  const dim3 grid(jb.ctus_w * jb.ctus_h, jb.nbands);
-  hipError_t e = jb.D == 2 ? allow_lds<2>(lds_bytes)
-                           : (jb.D == 4 ? allow_lds<4>(lds_bytes) : allow_lds<8>(lds_bytes));
-  if (e != hipSuccess) return e;
-  switch (jb.D) {
-    case 2: hipLaunchKernelGGL(search_kernel1<2>, grid, dim3(256), lds_bytes, st, jb); break;
-    case 4: hipLaunchKernelGGL(search_kernel1<4>, grid, dim3(256), lds_bytes, st, jb); break;
-    case 8: hipLaunchKernelGGL(search_kernel1<8>, grid, dim3(256), lds_bytes, st, jb); break;
+static const void* search_fn(int D) {
+  switch (D) {
+    case 2: return (const void*)search_kernel<2>;
+    case 4: return (const void*)search_kernel<4>;
+    case 8: return (const void*)search_kernel_d8;
+    default: return nullptr;
+  }
+}
+
+int search_occupancy(int D, int strip, size_t lds_bytes) {
+  const void* fn = search_fn(D);
+  if (!fn) return 0;
+  if (lds_bytes > 64 * 1024 &&
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
+          hipSuccess)
+    return 0;
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64 * strip, lds_bytes) !=
+      hipSuccess)
+    return 0;
+  return blocks;
+}
+
+hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, int D, int strip,
+                         int n_wg, size_t lds_bytes, uint32_t* counter, hipStream_t st) {
+  const dim3 grid(n_wg), block(64 * strip);
+  switch (D) {
+    case 2: hipLaunchKernelGGL(search_kernel<2>, grid, block, lds_bytes, st, jobs, items, n_items, counter); break;
+    case 4: hipLaunchKernelGGL(search_kernel<4>, grid, block, lds_bytes, st, jobs, items, n_items, counter); break;
+    case 8: hipLaunchKernelGGL(search_kernel_d8, grid, block, lds_bytes, st, jobs, items, n_items, counter); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_leaf1(const JobDesc& jb, hipStream_t st) {
-  hipLaunchKernelGGL(leaf_kernel1, dim3(jb.ctus_w * jb.ctus_h), dim3(256), 0, st, jb);
+hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st) {
+  hipLaunchKernelGGL(leaf_kernel, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus);
   return hipGetLastError();
 }
 

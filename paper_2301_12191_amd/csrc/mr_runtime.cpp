@@ -1,5 +1,5 @@
 // Host runtime of libmr: argument checks, search layouts, rank-ordered key
-// tables, stream-ordered scratch and the C ABI entry points for one frame pair.
+// tables, batch plans, and the single-pair C ABI entry points.
 #include "mr_runtime.h"
 
 #include <algorithm>
@@ -21,52 +21,70 @@ int se_bits(int v) {
   return 2 * (31 - __builtin_clz(k + 1u)) + 1;
 }
 
-static constexpr size_t kLdsBudget = 64 * 1024;  // two search workgroups per CU
+// ------------------------------------------------------------------------ tiles
+namespace {
+std::mutex g_tile_mu;
+TileConfig g_tile_override[129];  // D == 0: none
+}  // namespace
 
-TileConfig default_tiles(int R, int n_ctus) {
-  TileConfig tc;
-  tc.D = R < 20 ? 2 : (R < 48 ? 4 : 8);
-  const int span = 2 * R + 1, Q = (span + 3) / 4, G = (span + tc.D - 1) / tc.D;
-  const size_t row_bytes = (size_t)(Q + 16) * 4;
-  int nb = 1;
-  while (nb < kMaxBands && nb < G) {
-    const int B = (G + nb - 1) / nb;
-    if ((size_t)(B * tc.D + 63) * row_bytes <= kLdsBudget) break;
-    ++nb;
-  }
-  // Small jobs: split the window further so the grid has enough workgroups.
-  while (nb < kMaxBands && (int64_t)n_ctus * nb < 1024 && (G + nb) / (nb + 1) >= 2) ++nb;
-  tc.nbands = nb;
-  return tc;
+int set_tile_override(int R, const TileConfig& tc) {
+  if (R < 0 || R > 128 || !(tc.D == 0 || tc.D == 2 || tc.D == 4 || tc.D == 8)) return MR_EINVAL;
+  if (tc.D != 0 && (tc.nbands < 0 || tc.nbands > kMaxBands || tc.strip < 0 ||
+                    tc.strip > kMaxStrip))
+    return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile_override[R] = tc.D ? tc : TileConfig{0, 0, 0};
+  return MR_OK;
 }
 
-SearchLayout make_layout(int R, const TileConfig& tc) {
+bool get_tile_override(int R, TileConfig* tc) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  if (!g_tile_override[R].D) return false;
+  *tc = g_tile_override[R];
+  return true;
+}
+
+static int default_D(int R) { return R < 20 ? 2 : 4; }
+
+SearchLayout make_layout(int R, int D, int nbands) {
   SearchLayout L;
   std::memset(&L, 0, sizeof(L));
   const int span = 2 * R + 1;
   L.R = R;
-  L.D = tc.D;
+  L.D = D;
   L.Q = (span + 3) / 4;
-  L.G = (span + tc.D - 1) / tc.D;
-  L.nbands = std::max(1, std::min(std::min(tc.nbands, kMaxBands), L.G));
-  L.band_step0[0] = 0;
-  L.win_rows_max = 0;
+  L.G = (span + D - 1) / D;
+  L.nbands = std::max(1, std::min(std::min(nbands, kMaxBands), L.G));
   for (int b = 0; b <= L.nbands; ++b) L.band_g0[b] = (int)((int64_t)b * L.G / L.nbands);
   for (int b = 0; b < L.nbands; ++b) {
     const int B = L.band_g0[b + 1] - L.band_g0[b];
-    const int tasks = B * L.Q;
-    L.band_step0[b + 1] = L.band_step0[b] + (tasks + kWaveSteps - 1) / kWaveSteps;
-    L.win_rows_max = std::max(L.win_rows_max, B * L.D + 63);
+    L.band_step0[b + 1] = L.band_step0[b] + (B * L.Q + kWaveSteps - 1) / kWaveSteps;
+    L.win_rows_max = std::max(L.win_rows_max, B * D + 63);
   }
   L.total_steps = L.band_step0[L.nbands];
-  L.win_dwords = L.Q + 16;
+  L.win_dwords = L.Q;  // + 16 * strip, added per job
   return L;
 }
 
-size_t search_lds_bytes(const SearchLayout& L) {
-  return (size_t)L.win_rows_max * L.win_dwords * 4;
+size_t window_bytes(const SearchLayout& L, int strip) {
+  return (size_t)L.win_rows_max * (L.Q + 16 * strip) * 4;
 }
 
+int choose_bands(int R, int D, int strip, int ctus_w, int ctus_h, size_t lds_budget,
+                 int min_items) {
+  const int span = 2 * R + 1, G = (span + D - 1) / D;
+  int nb = 1;
+  while (nb < kMaxBands && nb < G && window_bytes(make_layout(R, D, nb), strip) > lds_budget) ++nb;
+  const int64_t strips = (int64_t)((ctus_w + strip - 1) / strip) * ctus_h;
+  while (min_items > 0 && nb < kMaxBands && strips * nb < min_items && (G + nb) / (nb + 1) >= 2)
+    ++nb;
+  return nb;
+}
+
+// LDS budget per search workgroup: three workgroups per CU.
+static constexpr size_t kLdsBudget = 53 * 1024;
+
+// ----------------------------------------------------------------------- tables
 namespace {
 
 struct TableKey {
@@ -84,6 +102,11 @@ struct Cand {
   int slot;  // lane * 4D + j * 4 + k
 };
 
+// For every wavefront step: each lane's 4D candidates get the constant
+// q = C * 2048 + rank, C = (MV cost) >> 16, rank = position of the candidate
+// among the step's valid candidates sorted by (MV cost & 0xFFFF, raster index).
+// Then (SAD + C) * 2048 + rank orders the step's candidates exactly as
+// (SAD * 65536 + MV cost, raster index).  dtab[rank] = (cost & 0xFFFF) << 17 | index.
 void build_tables(int qp, const SearchLayout& L, std::vector<uint32_t>& q,
                   std::vector<uint64_t>& dt) {
   const int R = L.R, D = L.D, span = 2 * R + 1, per_lane = 4 * D;
@@ -169,61 +192,16 @@ int get_key_tables(int qp, const SearchLayout& L, KeyTables* out) {
   return MR_OK;
 }
 
+// ------------------------------------------------------------------------ plans
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-size_t job_scratch_bytes(int n_ctus) {
-  return up256((size_t)n_ctus * 4096) + up256((size_t)n_ctus * kNodes * 8) +
-         up256((size_t)n_ctus * kNodes);
-}
-
-void fill_job(JobDesc* jb, const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
-              const uint8_t* bounds, const mr_search_out* out, const SearchLayout& L,
-              const KeyTables& kt, void* scratch) {
-  std::memset(jb, 0, sizeof(*jb));
-  jb->cur = cur->luma;
-  jb->ref = ref->luma;
-  jb->w = cur->width;
-  jb->h = cur->height;
-  jb->stride = cur->stride;
-  jb->w8 = (cur->width + 7) / 8 * 8;
-  jb->h8 = (cur->height + 7) / 8 * 8;
-  jb->ctus_w = (jb->w8 + kCtu - 1) / kCtu;
-  jb->ctus_h = (jb->h8 + kCtu - 1) / kCtu;
-  jb->R = L.R;
-  jb->D = L.D;
-  jb->Q = L.Q;
-  jb->nbands = L.nbands;
-  jb->win_dwords = L.win_dwords;
-  for (int b = 0; b <= kMaxBands; ++b) {
-    jb->band_g0[b] = L.band_g0[b];
-    jb->band_step0[b] = L.band_step0[b];
-  }
-  jb->s = sqrt_lambda_q16(p->qp);
-  const int n_ctus = jb->ctus_w * jb->ctus_h;
-  uint8_t* sp = (uint8_t*)scratch;
-  jb->curpack = (const uint32_t*)sp;
-  sp += up256((size_t)n_ctus * 4096);
-  jb->keys = (uint64_t*)sp;
-  sp += up256((size_t)n_ctus * kNodes * 8);
-  jb->elig = sp;
-  jb->qtab = kt.qtab;
-  jb->dtab = kt.dtab;
-  jb->bounds = bounds;
-  jb->depth = out->depth;
-  jb->mode = out->mode;
-  jb->mv = out->mv;
-  jb->ctu_cost = out->ctu_cost;
-  jb->ctu_dist = out->ctu_dist;
-  jb->ctu_bits = out->ctu_bits;
-}
 
 static bool frame_ok(const mr_frame* f) {
   return f && f->luma && f->width >= 1 && f->height >= 1 && f->width <= 8192 &&
          f->height <= 8192 && f->stride >= f->width;
 }
 
-int validate_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
-                    const mr_search_out* out) {
+int validate_job(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
+                 const mr_search_out* out) {
   if (!frame_ok(cur) || !frame_ok(ref) || !p || !out) return MR_EINVAL;
   if (cur->width != ref->width || cur->height != ref->height || cur->stride != ref->stride)
     return MR_EINVAL;
@@ -232,6 +210,173 @@ int validate_search(const mr_frame* cur, const mr_frame* ref, const mr_search_pa
       !out->ctu_bits)
     return MR_EINVAL;
   return MR_OK;
+}
+
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
+              const mr_search_params* const* p, const uint8_t* const* bounds,
+              const mr_search_out* const* out, int n_jobs, bool materialize_items, Plan* P) {
+  if (n_jobs < 1 || n_jobs > (1 << 20)) return MR_EINVAL;
+  for (int j = 0; j < n_jobs; ++j) {
+    const int rc = validate_job(cur[j], ref[j], p[j], out[j]);
+    if (rc != MR_OK) return rc;
+  }
+  // Batch-wide D and strip from the job with the most search work.
+  int heavy = 0;
+  double heavy_work = -1;
+  int max_ctus_w = 1;
+  for (int j = 0; j < n_jobs; ++j) {
+    const double r = 2.0 * p[j]->search_range + 1;
+    const double work = r * r * (double)cur[j]->width * cur[j]->height;
+    if (work > heavy_work) heavy_work = work, heavy = j;
+    max_ctus_w = std::max(max_ctus_w, ((cur[j]->width + 7) / 8 * 8 + 63) / 64);
+  }
+  TileConfig tc{0, 0, 0};
+  const bool ov = get_tile_override(p[heavy]->search_range, &tc);
+  P->D = ov ? tc.D : default_D(p[heavy]->search_range);
+  P->strip = (ov && tc.strip) ? tc.strip : std::min(kMaxStrip, max_ctus_w);
+  P->n_jobs = n_jobs;
+  P->jobs.assign(n_jobs, JobDesc{});
+  P->job_off.assign(n_jobs, 0);
+  P->items.clear();
+  P->n_ctus = 0;
+  P->scratch_bytes = 0;
+  P->lds_bytes = 0;
+  int64_t total_items = 0;
+  const int min_items = n_jobs == 1 ? 3 * device_cu_count() : 0;
+  struct Work {
+    int64_t cost;
+    uint32_t job, y;
+  };
+  std::vector<Work> work;
+  for (int j = 0; j < n_jobs; ++j) {
+    JobDesc& jb = P->jobs[j];
+    std::memset(&jb, 0, sizeof(jb));
+    const int R = p[j]->search_range;
+    jb.cur = cur[j]->luma;
+    jb.ref = ref[j]->luma;
+    jb.w = cur[j]->width;
+    jb.h = cur[j]->height;
+    jb.stride = cur[j]->stride;
+    jb.w8 = (jb.w + 7) / 8 * 8;
+    jb.h8 = (jb.h + 7) / 8 * 8;
+    jb.ctus_w = (jb.w8 + kCtu - 1) / kCtu;
+    jb.ctus_h = (jb.h8 + kCtu - 1) / kCtu;
+    int nb = choose_bands(R, P->D, P->strip, jb.ctus_w, jb.ctus_h, kLdsBudget, min_items);
+    TileConfig tj;
+    if (get_tile_override(R, &tj) && tj.D == P->D && tj.nbands) nb = tj.nbands;
+    const SearchLayout L = make_layout(R, P->D, nb);
+    KeyTables kt;
+    const int rc = get_key_tables(p[j]->qp, L, &kt);
+    if (rc != MR_OK) return rc;
+    jb.R = R;
+    jb.D = P->D;
+    jb.Q = L.Q;
+    jb.nbands = L.nbands;
+    jb.strip = P->strip;
+    jb.win_dwords = L.Q + 16 * P->strip;
+    jb.ctu_start = P->n_ctus;
+    for (int b = 0; b <= kMaxBands; ++b) {
+      jb.band_g0[b] = L.band_g0[b];
+      jb.band_step0[b] = L.band_step0[b];
+    }
+    jb.s = sqrt_lambda_q16(p[j]->qp);
+    jb.qtab = kt.qtab;
+    jb.dtab = kt.dtab;
+    jb.bounds = bounds[j];
+    jb.depth = out[j]->depth;
+    jb.mode = out[j]->mode;
+    jb.mv = out[j]->mv;
+    jb.ctu_cost = out[j]->ctu_cost;
+    jb.ctu_dist = out[j]->ctu_dist;
+    jb.ctu_bits = out[j]->ctu_bits;
+    const int n_ctus = jb.ctus_w * jb.ctus_h;
+    P->job_off[j] = P->scratch_bytes;
+    P->scratch_bytes += up256((size_t)n_ctus * 4096) + up256((size_t)n_ctus * kNodes * 8) +
+                        up256((size_t)n_ctus * kNodes);
+    P->n_ctus += n_ctus;
+    P->lds_bytes = std::max(P->lds_bytes, window_bytes(L, P->strip));
+    const int spr = (jb.ctus_w + P->strip - 1) / P->strip;
+    total_items += (int64_t)spr * jb.ctus_h * L.nbands;
+    if (materialize_items) {
+      for (int b = 0; b < L.nbands; ++b) {
+        const int steps = L.band_step0[b + 1] - L.band_step0[b];
+        const int rows = (L.band_g0[b + 1] - L.band_g0[b]) * P->D + 63;
+        const int64_t cost = (int64_t)steps * 4096 + rows;  // compute + staging
+        for (int row = 0; row < jb.ctus_h; ++row)
+          for (int sidx = 0; sidx < spr; ++sidx)
+            work.push_back(Work{cost, (uint32_t)j, pack_item_y(row, sidx * P->strip, b)});
+      }
+    }
+  }
+  if (total_items > ((int64_t)1 << 30)) return MR_EINVAL;
+  P->n_items = (int)total_items;
+  if (materialize_items) {
+    // Longest items first (LPT): heavy search ranges start early, small ones fill the tail.
+    std::stable_sort(work.begin(), work.end(),
+                     [](const Work& a, const Work& b) { return a.cost > b.cost; });
+    P->items.resize(work.size());
+    for (size_t i = 0; i < work.size(); ++i) P->items[i] = make_uint2(work[i].job, work[i].y);
+  }
+  const int occ = std::max(1, search_occupancy(P->D, P->strip, P->lds_bytes));
+  P->n_wg = (int)std::min<int64_t>(P->n_items, (int64_t)occ * device_cu_count());
+  return MR_OK;
+}
+
+void bind_scratch(Plan& P, uint8_t* base) {
+  for (int j = 0; j < P.n_jobs; ++j) {
+    JobDesc& jb = P.jobs[j];
+    const int n_ctus = jb.ctus_w * jb.ctus_h;
+    uint8_t* sp = base + P.job_off[j];
+    jb.curpack = (const uint32_t*)sp;
+    sp += up256((size_t)n_ctus * 4096);
+    jb.keys = (uint64_t*)sp;
+    sp += up256((size_t)n_ctus * kNodes * 8);
+    jb.elig = sp;
+  }
+}
+
+// -------------------------------------------------------------------- profiling
+namespace {
+struct ProfileState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<StageEvents> pending;
+  double ms[3] = {0, 0, 0};
+  int64_t n[3] = {0, 0, 0};
+};
+ProfileState g_prof;
+}  // namespace
+
+bool profile_on() {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  return g_prof.on;
+}
+
+int profile_begin(StageEvents* ev, hipStream_t st) {
+  for (auto& x : ev->e)
+    if (hipEventCreate(&x) != hipSuccess) return MR_EHIP;
+  return hipEventRecord(ev->e[0], st) == hipSuccess ? MR_OK : MR_EHIP;
+}
+
+void profile_mark(StageEvents* ev, int k, hipStream_t st) { (void)hipEventRecord(ev->e[k], st); }
+
+void profile_push(const StageEvents& ev) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.pending.push_back(ev);
 }
 
 }  // namespace mr
@@ -256,25 +401,74 @@ const char* mr_status_str(int status) {
 
 int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
                   const uint8_t* bounds, mr_search_out* out, void* hip_stream) {
-  int rc = validate_search(cur, ref, p, out);
-  if (rc != MR_OK) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
-  const int w8 = (cur->width + 7) / 8 * 8, h8 = (cur->height + 7) / 8 * 8;
-  const int n_ctus = ((w8 + 63) / 64) * ((h8 + 63) / 64);
-  const SearchLayout L = make_layout(p->search_range, default_tiles(p->search_range, n_ctus));
-  KeyTables kt;
-  rc = get_key_tables(p->qp, L, &kt);
+  Plan P;
+  const mr_search_out* o = out;
+  int rc = make_plan(&cur, &ref, &p, &bounds, &o, 1, false, &P);
   if (rc != MR_OK) return rc;
-  void* scratch = nullptr;
-  if (hipMallocAsync(&scratch, job_scratch_bytes(n_ctus), st) != hipSuccess) return MR_ENOMEM;
-  JobDesc jb;
-  fill_job(&jb, cur, ref, p, bounds, out, L, kt, scratch);
-  hipError_t e = launch_prep1(jb, st);
-  if (e == hipSuccess) e = launch_search1(jb, search_lds_bytes(L), st);
-  if (e == hipSuccess) e = launch_leaf1(jb, st);
+  // Scratch: job descriptor, queue counter, per-job buffers.
+  const size_t head = up256(sizeof(JobDesc)) + 256;
+  uint8_t* scratch = nullptr;
+  if (hipMallocAsync((void**)&scratch, head + P.scratch_bytes, st) != hipSuccess) return MR_ENOMEM;
+  bind_scratch(P, scratch + head);
+  JobDesc* jobs_d = (JobDesc*)scratch;
+  uint32_t* counter = (uint32_t*)(scratch + up256(sizeof(JobDesc)));
+  StageEvents ev{};
+  const bool prof = profile_on() && profile_begin(&ev, st) == MR_OK;
+  hipError_t e = launch_store_job(P.jobs[0], jobs_d, st);
+  if (e == hipSuccess) e = launch_prep(jobs_d, 1, P.n_ctus, counter, st);
+  if (prof) profile_mark(&ev, 1, st);
+  if (e == hipSuccess)
+    e = launch_search(jobs_d, nullptr, P.n_items, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
+  if (prof) profile_mark(&ev, 2, st);
+  if (e == hipSuccess) e = launch_leaf(jobs_d, 1, P.n_ctus, st);
+  if (prof) {
+    profile_mark(&ev, 3, st);
+    profile_push(ev);
+  }
   const hipError_t ef = hipFreeAsync(scratch, st);
   if (e != hipSuccess || ef != hipSuccess) return MR_EHIP;
   return MR_OK;
+}
+
+int64_t mr_sqrt_lambda_q16(int32_t qp) { return qp < 0 || qp > 51 ? -1 : sqrt_lambda_q16(qp); }
+
+int32_t mr_se_bits(int32_t v) {
+  return (v > (1 << 29) || v < -(1 << 29)) ? -1 : se_bits(v);
+}
+
+int mr_set_tiles(int32_t search_range, int32_t d, int32_t nbands) {
+  if (d != 0 && (nbands < 1 || nbands > kMaxBands)) return MR_EINVAL;
+  return set_tile_override(search_range, TileConfig{d, nbands, 0});
+}
+
+int mr_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  return MR_OK;
+}
+
+int mr_profile_read(mr_profile* out, int reset) {
+  if (!out) return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  int rc = MR_OK;
+  for (auto& ev : g_prof.pending) {
+    if (hipEventSynchronize(ev.e[3]) != hipSuccess) rc = MR_EHIP;
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev.e[k], ev.e[k + 1]) != hipSuccess) rc = MR_EHIP;
+      g_prof.ms[k] += ms;
+      g_prof.n[k] += 1;
+    }
+    for (auto& x : ev.e) (void)hipEventDestroy(x);
+  }
+  g_prof.pending.clear();
+  for (int k = 0; k < 3; ++k) {
+    out->ms[k] = g_prof.ms[k];
+    out->launches[k] = g_prof.n[k];
+    if (reset) g_prof.ms[k] = 0, g_prof.n[k] = 0;
+  }
+  return rc;
 }
 
 int mr_depth_bounds(const uint8_t* ref_depth, int32_t ref_w, int32_t ref_h, int32_t dep_w,

@@ -1,4 +1,4 @@
-// Host-side runtime of libmr: search layouts, key tables, job descriptors.
+// Host-side runtime of libmr: search layouts, key tables, plans of job batches.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -15,39 +15,73 @@ int64_t sqrt_lambda_q16(int qp);
 // Bits of the signed Exp-Golomb code of v.
 int se_bits(int v);
 
-// Tile choice of the search kernel for one job.
+// Tile choice of the search kernel.
 struct TileConfig {
-  int D;        // vertical shifts per lane (2, 4 or 8)
-  int nbands;   // dy bands the window is split into (1..kMaxBands)
+  int D;       // vertical shifts per lane (2, 4 or 8)
+  int nbands;  // dy bands the window is split into (1..kMaxBands); 0 = derive
+  int strip;   // CTUs per workgroup (1..kMaxStrip); 0 = derive
 };
-TileConfig default_tiles(int R, int n_ctus);
-SearchLayout make_layout(int R, const TileConfig& tc);
+// Tile override for one search range (autotuner / user knob); D == 0 clears it.
+int set_tile_override(int R, const TileConfig& tc);
+bool get_tile_override(int R, TileConfig* tc);
 
-// Device tables of the rank-ordered arg-min keys for (qp, R, tiles); cached per device.
+SearchLayout make_layout(int R, int D, int nbands);
+// Bands for a job: smallest count whose window fits the LDS budget, raised until
+// the job alone has at least min_items items (when min_items > 0).
+int choose_bands(int R, int D, int strip, int ctus_w, int ctus_h, size_t lds_budget,
+                 int min_items);
+size_t window_bytes(const SearchLayout& L, int strip);
+
+// Device tables of the rank-ordered arg-min keys for (qp, layout); cached per device.
 struct KeyTables {
   const uint32_t* qtab;
   const uint64_t* dtab;
 };
 int get_key_tables(int qp, const SearchLayout& L, KeyTables* out);
 
-// Scratch bytes a job needs (curpack + keys + elig), 256-byte aligned pieces.
-size_t job_scratch_bytes(int n_ctus);
+int validate_job(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
+                 const mr_search_out* out);
 
-// Fill a JobDesc from validated arguments and a scratch block.
-void fill_job(JobDesc* jb, const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
-              const uint8_t* bounds, const mr_search_out* out, const SearchLayout& L,
-              const KeyTables& kt, void* scratch);
+// A planned batch: job descriptors (scratch pointers relative to a base until
+// bound), the search items in longest-first order, and launch geometry.
+struct Plan {
+  int D = 4, strip = 4;
+  int n_jobs = 0, n_ctus = 0, n_items = 0, n_wg = 0;
+  size_t lds_bytes = 0;
+  std::vector<JobDesc> jobs;
+  std::vector<uint2> items;           // empty when implicit (single job)
+  std::vector<size_t> job_off;        // per-job scratch offset
+  size_t scratch_bytes = 0;           // per-job scratch total (curpack, keys, elig)
+};
 
-int validate_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
-                    const mr_search_out* out);
+// Build a plan.  tiles: batch-wide D / strip (0 = choose); materialize_items:
+// false only for a single job (the kernel derives items from the job).
+int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
+              const mr_search_params* const* p, const uint8_t* const* bounds,
+              const mr_search_out* const* out, int n_jobs, bool materialize_items, Plan* P);
+// Point each job's scratch fields into `base` (device memory of P.scratch_bytes).
+void bind_scratch(Plan& P, uint8_t* base);
+
+int device_cu_count();
 
 // Kernel launches (defined with the kernels).
-hipError_t launch_prep1(const JobDesc& jb, hipStream_t st);
-hipError_t launch_search1(const JobDesc& jb, size_t lds_bytes, hipStream_t st);
-hipError_t launch_leaf1(const JobDesc& jb, hipStream_t st);
+hipError_t launch_store_job(const JobDesc& jb, JobDesc* dst, hipStream_t st);
+hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* counter,
+                       hipStream_t st);
+hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, int D, int strip,
+                         int n_wg, size_t lds_bytes, uint32_t* counter, hipStream_t st);
+hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st);
 hipError_t launch_depth_bounds(const uint8_t* ref_depth, int ref_w, int ref_h, int dep_w,
                                int dep_h, int dlo, int dhi, uint8_t* out, hipStream_t st);
+int search_occupancy(int D, int strip, size_t lds_bytes);
 
-size_t search_lds_bytes(const SearchLayout& L);
+// Stage profiling (mr_profile_*).
+bool profile_on();
+struct StageEvents {
+  hipEvent_t e[4];
+};
+int profile_begin(StageEvents* ev, hipStream_t st);
+void profile_mark(StageEvents* ev, int k, hipStream_t st);
+void profile_push(const StageEvents& ev);
 
 }  // namespace mr

@@ -41,6 +41,15 @@ class mr_search_out(ctypes.Structure):
                 ("ctu_bits", ctypes.c_void_p)]
 
 
+class mr_search_job(ctypes.Structure):
+    _fields_ = [("cur", mr_frame), ("ref", mr_frame), ("params", mr_search_params),
+                ("bounds", ctypes.c_void_p), ("out", mr_search_out)]
+
+
+class mr_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 3), ("launches", ctypes.c_int64 * 3)]
+
+
 def lib():
     """Load libmr.so (raises if it was not built)."""
     global _lib
@@ -57,6 +66,22 @@ def lib():
                                     ctypes.POINTER(mr_search_out), vp]
         L.mr_depth_bounds.restype = ctypes.c_int
         L.mr_depth_bounds.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
+        L.mr_ctu_search_batch.restype = ctypes.c_int
+        L.mr_ctu_search_batch.argtypes = [ctypes.POINTER(mr_search_job), i32, vp]
+        L.mr_batch_create.restype = ctypes.c_int
+        L.mr_batch_create.argtypes = [ctypes.POINTER(mr_search_job), i32, ctypes.POINTER(vp)]
+        L.mr_batch_set_jobs.restype = ctypes.c_int
+        L.mr_batch_set_jobs.argtypes = [vp, ctypes.POINTER(mr_search_job), i32]
+        L.mr_batch_launch.restype = ctypes.c_int
+        L.mr_batch_launch.argtypes = [vp, vp]
+        L.mr_batch_destroy.restype = ctypes.c_int
+        L.mr_batch_destroy.argtypes = [vp]
+        L.mr_set_tiles.restype = ctypes.c_int
+        L.mr_set_tiles.argtypes = [i32, i32, i32]
+        L.mr_profile_enable.restype = ctypes.c_int
+        L.mr_profile_enable.argtypes = [ctypes.c_int]
+        L.mr_profile_read.restype = ctypes.c_int
+        L.mr_profile_read.argtypes = [ctypes.POINTER(mr_profile), ctypes.c_int]
         _lib = L
     return _lib
 
@@ -130,6 +155,77 @@ def mr_ctu_search(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: i
     return out
 
 
+def _out_struct(out):
+    return mr_search_out(_dev_ptr(out["depth"], torch.uint8, "depth"),
+                         _dev_ptr(out["mode"], torch.uint8, "mode"),
+                         _dev_ptr(out["mv"], torch.int16, "mv"),
+                         _dev_ptr(out["cost"], torch.int64, "cost"),
+                         _dev_ptr(out["dist"], torch.int64, "dist"),
+                         _dev_ptr(out["bits"], torch.int64, "bits"))
+
+
+def _job_array(jobs):
+    """jobs: list of dicts {cur, ref, qp, search_range, bounds (optional), out (optional)}."""
+    arr = (mr_search_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        cur = j["cur"]
+        if j.get("out") is None:
+            j["out"] = alloc_outputs(cur.shape[1], cur.shape[0], cur.device)
+        b = j.get("bounds")
+        arr[i] = mr_search_job(_frame(cur, "cur"), _frame(j["ref"], "ref"),
+                               mr_search_params(j["qp"], j["search_range"]),
+                               None if b is None else _dev_ptr(b, torch.uint8, "bounds"),
+                               _out_struct(j["out"]))
+    return arr
+
+
+def mr_ctu_search_batch(jobs, stream=None):
+    """Batched search (see mr_ctu_search_batch in include/mr.h); fills each job's "out"."""
+    arr = _job_array(jobs)
+    rc = lib().mr_ctu_search_batch(arr, len(jobs), _stream_handle(stream))
+    if rc != MR_OK:
+        raise MRError(rc, "mr_ctu_search_batch")
+    return [j["out"] for j in jobs]
+
+
+class Batch:
+    """mr_batch_* handle: planned once, replayed as a captured graph."""
+
+    def __init__(self, jobs):
+        self._h = ctypes.c_void_p()
+        self.jobs = jobs
+        arr = _job_array(jobs)
+        rc = lib().mr_batch_create(arr, len(jobs), ctypes.byref(self._h))
+        if rc != MR_OK:
+            raise MRError(rc, "mr_batch_create")
+
+    def set_jobs(self, jobs):
+        arr = _job_array(jobs)
+        rc = lib().mr_batch_set_jobs(self._h, arr, len(jobs))
+        if rc != MR_OK:
+            raise MRError(rc, "mr_batch_set_jobs")
+        self.jobs = jobs
+
+    def launch(self, stream=None):
+        rc = lib().mr_batch_launch(self._h, _stream_handle(stream))
+        if rc != MR_OK:
+            raise MRError(rc, "mr_batch_launch")
+        return [j["out"] for j in self.jobs]
+
+    def close(self):
+        if self._h:
+            rc = lib().mr_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            if rc != MR_OK:
+                raise MRError(rc, "mr_batch_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def mr_depth_bounds(ref_depth: torch.Tensor, ref_w: int, ref_h: int, dep_w: int, dep_h: int,
                     delta_lo: int, delta_hi: int, out: torch.Tensor | None = None, stream=None):
     """Depth bounds of a dependent representation (see mr_depth_bounds in include/mr.h)."""
@@ -142,3 +238,28 @@ def mr_depth_bounds(ref_depth: torch.Tensor, ref_w: int, ref_h: int, dep_w: int,
     if rc != MR_OK:
         raise MRError(rc, "mr_depth_bounds")
     return out
+
+
+STAGES = ("prep", "search", "leaf")
+
+
+def mr_profile_enable(on: bool) -> None:
+    rc = lib().mr_profile_enable(1 if on else 0)
+    if rc != MR_OK:
+        raise MRError(rc, "mr_profile_enable")
+
+
+def mr_profile_read(reset: bool = True) -> dict:
+    """{stage: (total_ms, launches)} of the calls made while profiling was enabled."""
+    p = mr_profile()
+    rc = lib().mr_profile_read(ctypes.byref(p), 1 if reset else 0)
+    if rc != MR_OK:
+        raise MRError(rc, "mr_profile_read")
+    return {name: (p.ms[i], p.launches[i]) for i, name in enumerate(STAGES)}
+
+
+def mr_set_tiles(search_range: int, d: int, nbands: int = 1) -> None:
+    """Override the search kernel's tile choice for one search range (d = 0 clears)."""
+    rc = lib().mr_set_tiles(search_range, d, nbands)
+    if rc != MR_OK:
+        raise MRError(rc, "mr_set_tiles")

@@ -103,3 +103,44 @@ def test_depth_bounds_rejects_invalid_arguments(libmr, args):
     rc = libmr.mr_depth_bounds(ctypes.c_void_p(0x1000 if ptr else 0), rw, rh, dw, dh, lo, hi,
                                ctypes.c_void_p(0x2000), None)
     assert rc == mr.MR_EINVAL
+
+
+def test_batch_rejects_invalid_jobs_before_launch(libmr):
+    from paper_2301_12191_amd import mr
+    assert libmr.mr_ctu_search_batch(None, 1, None) == mr.MR_EINVAL
+    arr = (mr.mr_search_job * 2)()
+    for i in range(2):
+        arr[i] = mr.mr_search_job(_fake_frame(mr), _fake_frame(mr), mr.mr_search_params(30, 16),
+                                  None, _fake_out(mr))
+    assert libmr.mr_ctu_search_batch(arr, 0, None) == mr.MR_EINVAL
+    arr[1].params.qp = 99
+    assert libmr.mr_ctu_search_batch(arr, 2, None) == mr.MR_EINVAL
+    h = ctypes.c_void_p()
+    assert libmr.mr_batch_create(arr, 2, ctypes.byref(h)) == mr.MR_EINVAL
+    assert not h.value
+    assert libmr.mr_batch_create(arr, 2, None) == mr.MR_EINVAL
+    assert libmr.mr_batch_launch(None, None) == mr.MR_EINVAL
+    assert libmr.mr_batch_set_jobs(None, arr, 2) == mr.MR_EINVAL
+    assert libmr.mr_batch_destroy(None) == mr.MR_OK
+
+
+def test_tile_override_validation(libmr):
+    from paper_2301_12191_amd import mr
+    assert libmr.mr_set_tiles(200, 4, 1) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles(64, 3, 1) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles(64, 4, 0) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles(64, 4, 9) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles(64, 0, 1) == mr.MR_OK
+
+
+def test_host_lambda_and_bits_match_the_oracle():
+    """libmr's host-side sqrt(lambda) table and MV bit counts equal the oracle's (all QPs)."""
+    import oracle
+    from paper_2301_12191_amd import mr
+    L = mr.lib()
+    L.mr_sqrt_lambda_q16.restype = ctypes.c_int64
+    L.mr_se_bits.restype = ctypes.c_int
+    for qp in range(52):
+        assert L.mr_sqrt_lambda_q16(qp) == oracle.sqrt_lambda_q16(qp), qp
+    for v in range(-1100, 1101):
+        assert L.mr_se_bits(v) == oracle.se_bits(v), v
