@@ -42,6 +42,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (3 times) and exit: "
+                         "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--cpu-ctus", type=int, default=768,
                     help="CTUs of one 1080p pair the CPU oracle times (bounded sample)")
     args = ap.parse_args()
@@ -57,6 +60,16 @@ def main():
     from paper_2301_12191_amd import mr
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.calibrate_copy} MiB x 3")
+        return
     mr.lib()
     dev = torch.device("cuda:0")
 

@@ -622,7 +622,7 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
   __shared__ int s_item;
   const cjob jobs = (cjob)jobs_;
   const sptr32 items = (sptr32)items_;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
     __syncthreads();
