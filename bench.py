@@ -80,6 +80,8 @@ def main():
     frames = [torch.from_numpy(scene.render(t)).to(dev) for t in range(NP + 1)]
     jobs = [dict(cur=frames[k + 1], ref=frames[k], qp=QP, search_range=R) for k in range(NP)]
     stream = torch.cuda.current_stream()
+    tune = mr.mr_autotune(jobs, reps=2)  # tile shape for this batch (installed as override)
+    log(f"autotune: {tune}")
     batch = mr.Batch(jobs)  # one persistent search launch over all 8 pairs per step
     ctus_per_pair = jobs[0]["out"]["cost"].numel()
     ctus_per_step = ctus_per_pair * NP
@@ -116,6 +118,8 @@ def main():
         "kernel": "search_kernel (persistent, 8 pairs per launch)", "avg_launch_ms": round(search_avg_s * 1e3, 4),
         "absdiff_per_launch": absdiff_per_launch,
         "stage_avg_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()},
+        "tiles": {"d": tune["d"], "nbands": tune["nbands"], "strip": tune["strip"],
+                  "autotune_shapes": tune["tried"]},
     }
 
     # ------------------------------------------------------------- pruned vs full search

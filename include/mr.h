@@ -162,6 +162,25 @@ int mr_depth_bounds(const uint8_t* ref_depth, int32_t ref_w, int32_t ref_h, int3
  * Results are identical for every setting; only speed changes.
  * Errors: MR_EINVAL (R outside 0..128, d not 0/2/4/8, nbands outside 1..8). */
 int mr_set_tiles(int32_t search_range, int32_t d, int32_t nbands);
+/* Same with the strip width (CTUs per workgroup, 1..4; 0 = built-in). */
+int mr_set_tiles3(int32_t search_range, int32_t d, int32_t nbands, int32_t strip);
+
+/* Autotuner.  Times tile shapes of the search kernel on the given batch (the
+ * jobs a later mr_batch_create / mr_ctu_search_batch will run) and installs
+ * the fastest as the tile override of the batch's dominant search range (the
+ * job with the most candidate work).  Coarse-to-fine: d in {2, 4, 8} at the
+ * built-in band count, then nbands 1..8 for the best d, then strip (CTUs per
+ * workgroup) in {1, 2, 4}.  Each shape is run once to warm up and then `reps`
+ * times (1..20) with HIP events around the search kernel; the minimum counts.
+ * Blocking; overwrites the jobs' outputs.  *out receives the choice.
+ * Errors: MR_EINVAL, MR_ENOMEM, MR_EHIP. */
+typedef struct {
+  int32_t search_range, d, nbands, strip;
+  double search_ms;  /* best measured search-kernel time */
+  double default_ms; /* time of the built-in choice */
+  int32_t tried;     /* shapes measured */
+} mr_tune_result;
+int mr_autotune(const mr_search_job* jobs, int32_t n_jobs, int32_t reps, mr_tune_result* out);
 
 /* Stage timing, a profiling aid for benchmarks.  While enabled, every
  * mr_ctu_search call records HIP events on its stream around its three

@@ -226,6 +226,20 @@ int device_cu_count() {
   return cached[dev];
 }
 
+size_t device_lds_max() {
+  static size_t cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        n <= 0)
+      n = 64 * 1024;
+    cached[dev] = (size_t)n;
+  }
+  return cached[dev];
+}
+
 int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
               const mr_search_params* const* p, const uint8_t* const* bounds,
               const mr_search_out* const* out, int n_jobs, bool materialize_items, Plan* P) {
@@ -323,6 +337,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     }
   }
   if (total_items > ((int64_t)1 << 30)) return MR_EINVAL;
+  if (P->lds_bytes > device_lds_max()) return MR_EINVAL;  // a forced tile shape too large
   P->n_items = (int)total_items;
   if (materialize_items) {
     // Longest items first (LPT): heavy search ranges start early, small ones fill the tail.
@@ -440,6 +455,12 @@ int32_t mr_se_bits(int32_t v) {
 int mr_set_tiles(int32_t search_range, int32_t d, int32_t nbands) {
   if (d != 0 && (nbands < 1 || nbands > kMaxBands)) return MR_EINVAL;
   return set_tile_override(search_range, TileConfig{d, nbands, 0});
+}
+
+int mr_set_tiles3(int32_t search_range, int32_t d, int32_t nbands, int32_t strip) {
+  if (d != 0 && (nbands < 1 || nbands > kMaxBands || strip < 0 || strip > kMaxStrip))
+    return MR_EINVAL;
+  return set_tile_override(search_range, TileConfig{d, nbands, strip});
 }
 
 int mr_profile_enable(int on) {

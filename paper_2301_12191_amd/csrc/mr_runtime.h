@@ -63,6 +63,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
 void bind_scratch(Plan& P, uint8_t* base);
 
 int device_cu_count();
+size_t device_lds_max();
 
 // Kernel launches (defined with the kernels).
 hipError_t launch_store_job(const JobDesc& jb, JobDesc* dst, hipStream_t st);

@@ -46,6 +46,13 @@ class mr_search_job(ctypes.Structure):
                 ("bounds", ctypes.c_void_p), ("out", mr_search_out)]
 
 
+class mr_tune_result(ctypes.Structure):
+    _fields_ = [("search_range", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("nbands", ctypes.c_int32), ("strip", ctypes.c_int32),
+                ("search_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("tried", ctypes.c_int32)]
+
+
 class mr_profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 3), ("launches", ctypes.c_int64 * 3)]
 
@@ -76,6 +83,11 @@ def lib():
         L.mr_batch_launch.argtypes = [vp, vp]
         L.mr_batch_destroy.restype = ctypes.c_int
         L.mr_batch_destroy.argtypes = [vp]
+        L.mr_autotune.restype = ctypes.c_int
+        L.mr_autotune.argtypes = [ctypes.POINTER(mr_search_job), i32, i32,
+                                  ctypes.POINTER(mr_tune_result)]
+        L.mr_set_tiles3.restype = ctypes.c_int
+        L.mr_set_tiles3.argtypes = [i32, i32, i32, i32]
         L.mr_set_tiles.restype = ctypes.c_int
         L.mr_set_tiles.argtypes = [i32, i32, i32]
         L.mr_profile_enable.restype = ctypes.c_int
@@ -263,3 +275,19 @@ def mr_set_tiles(search_range: int, d: int, nbands: int = 1) -> None:
     rc = lib().mr_set_tiles(search_range, d, nbands)
     if rc != MR_OK:
         raise MRError(rc, "mr_set_tiles")
+
+
+def mr_set_tiles3(search_range: int, d: int, nbands: int, strip: int) -> None:
+    rc = lib().mr_set_tiles3(search_range, d, nbands, strip)
+    if rc != MR_OK:
+        raise MRError(rc, "mr_set_tiles3")
+
+
+def mr_autotune(jobs, reps: int = 3) -> dict:
+    """Tune the search tile shape on a batch (see mr_autotune in include/mr.h)."""
+    arr = _job_array(jobs)
+    res = mr_tune_result()
+    rc = lib().mr_autotune(arr, len(jobs), reps, ctypes.byref(res))
+    if rc != MR_OK:
+        raise MRError(rc, "mr_autotune")
+    return {f: getattr(res, f) for f, _ in mr_tune_result._fields_}

@@ -154,3 +154,21 @@ def test_tile_overrides_do_not_change_results(mr, R, D, nb):
         mr.mr_set_tiles(R, 0, 1)
     torch.cuda.synchronize()
     _same(got, base, f"R{R} D{D} nb{nb}")
+
+
+def test_autotune_installs_a_shape_and_keeps_results(mr):
+    import torch
+    sc = synth.Scene(91, 640, 360, 10, 16, 3)
+    f = [torch.from_numpy(sc.render(t)).cuda() for t in range(3)]
+    jobs = [dict(cur=f[k + 1], ref=f[k], qp=35, search_range=24) for k in range(2)]
+    before = [_np(o) for o in mr.mr_ctu_search_batch([dict(j) for j in jobs])]
+    try:
+        res = mr.mr_autotune([dict(j) for j in jobs], reps=1)
+        assert res["search_range"] == 24 and res["d"] in (2, 4, 8) and res["tried"] >= 4
+        assert 0 < res["search_ms"] <= res["default_ms"]
+        after = [_np(o) for o in mr.mr_ctu_search_batch([dict(j) for j in jobs])]
+        torch.cuda.synchronize()
+        for a, b in zip(before, after):
+            _same(a, b, "after autotune")
+    finally:
+        mr.mr_set_tiles(24, 0, 1)
