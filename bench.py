@@ -112,9 +112,21 @@ def main():
     search_ms, search_n = prof["search"]
     search_avg_s = search_ms / 1e3 / max(1, search_n)
     achieved = absdiff_per_launch / search_avg_s
+    # HBM bytes per launch from the committed counter record (FETCH_SIZE / WRITE_SIZE of the
+    # search kernel, scaled by a plain copy's counters); null once the kernel source changed.
+    traffic = None
+    try:
+        import hashlib
+        rec = json.load(open(os.path.join(ROOT, "profiles", "search_1080p_r64_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2301_12191_amd", "csrc", "mr_kernels.hip"), "rb").read()
+        if rec.get("kernels_source_sha256") == hashlib.sha256(src).hexdigest():
+            traffic = rec["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
     roofline = {
         "bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_ABSDIFF / 1e12, 3),
-        "unit": "T absdiff/s", "frac": round(achieved / PEAK_ABSDIFF, 4), "traffic": None,
+        "unit": "T absdiff/s", "frac": round(achieved / PEAK_ABSDIFF, 4), "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch",
         "kernel": "search_kernel (persistent, 8 pairs per launch)", "avg_launch_ms": round(search_avg_s * 1e3, 4),
         "absdiff_per_launch": absdiff_per_launch,
         "stage_avg_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()},
