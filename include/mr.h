@@ -137,6 +137,85 @@ int mr_batch_set_jobs(mr_batch* b, const mr_search_job* jobs, int32_t n_jobs);
 int mr_batch_launch(mr_batch* b, void* hip_stream);
 int mr_batch_destroy(mr_batch* b);
 
+/* ---------------------------------------------------------------- serving
+ * A ladder server: frame-pair jobs of the rungs of an ABR ladder arrive over
+ * time (the thesis's multi-encoding schemes: one master representation,
+ * dependent tiers bounded by its analysis; concurrent tiers are its future
+ * work).  Frames stay resident in device memory (registered with
+ * mr_ladder_put_frame, caller-owned).  A job (stream, frame, rung) searches
+ * frame `frame` against `frame - 1` of that stream and rung.  A rung with
+ * ref_rung >= 0 is a dependent: its job waits until the job of the reference
+ * rung for the same (stream, frame) is done, then its depth search is bounded
+ * by mr_depth_bounds(delta_lo, delta_hi) of that job's depth map.  Submitting
+ * a dependent whose reference job does not exist creates it (an implied job)
+ * if the reference rung's frames are resident, else fails with MR_EDEPEND.
+ * A request loop (one host thread, two device streams of default priority)
+ * admits ready jobs in arrival order while their device footprint (scratch +
+ * outputs + bounds) fits hbm_budget_bytes and fewer than max_inflight jobs
+ * run, batches up to max_batch_jobs of them into one persistent search launch,
+ * keeps up to two batches in flight, and releases dependents as references
+ * complete (continuous batching).  Done reference jobs stay resident for later
+ * dependents until their memory is needed.  Results equal mr_ctu_search on
+ * the same frames (with the same bounds). */
+typedef struct {
+  int32_t width, height, qp, search_range;
+  int32_t ref_rung; /* index of the rung whose depths bound this one, -1 = none */
+} mr_rung;
+
+typedef struct {
+  int32_t n_rungs;       /* 1..8 */
+  mr_rung rungs[8];
+  int32_t delta_lo, delta_hi;  /* bound policy of dependents (0..3 each) */
+  uint64_t hbm_budget_bytes;   /* admission budget, > 0 */
+  int32_t max_inflight;        /* 1..65536 admitted, unfinished jobs */
+  int32_t max_queue;           /* 1..1<<20 submitted, unfinished jobs (else MR_EAGAIN) */
+  int32_t max_batch_jobs;      /* 1..4096 jobs per device launch */
+} mr_ladder_config;
+
+typedef struct {
+  int32_t stream_id; /* >= 0 */
+  int32_t frame_idx; /* >= 1 */
+  int32_t rung;
+} mr_job;
+
+typedef struct {
+  uint64_t job_id;
+  int32_t status;    /* MR_OK, or the failure (MR_EDEPEND if its reference failed) */
+  int32_t stream_id, frame_idx, rung;
+  int32_t implied;   /* 1: created by the server as a reference */
+  int32_t n_ctus;
+  int64_t t_arrive_ns, t_start_ns, t_done_ns;  /* steady clock */
+  mr_search_out out; /* device, owned by the ladder until mr_ladder_release */
+} mr_completion;
+
+typedef struct {
+  int64_t submitted, implied, completed, failed, rejected, batches, ctus_done;
+  double p50_ms, p99_ms, mean_ms, max_ms; /* arrival -> completion of completed jobs */
+  double ctus_per_s;                      /* ctus_done / (last done - first start) */
+  uint64_t bytes_in_use, peak_bytes;
+} mr_ladder_stats;
+
+typedef struct mr_ladder mr_ladder;
+
+/* Errors: MR_EINVAL (config), MR_ENOMEM, MR_EHIP. */
+int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out);
+/* Register a resident frame (device luma of the rung's size, stride >= width).
+ * Errors: MR_EINVAL (null, rung or ids out of range). Re-registering replaces. */
+int mr_ladder_put_frame(mr_ladder* l, int32_t stream_id, int32_t frame_idx, int32_t rung,
+                        const uint8_t* luma, int32_t stride);
+/* Errors: MR_EINVAL (ids, frames not resident), MR_EDEPEND, MR_EAGAIN (queue
+ * full, or the job alone exceeds the budget), MR_ESTATE (closed). */
+int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id);
+/* Up to max completions, waiting up to timeout_us for the first one
+ * (0 = do not wait).  MR_ETIMEOUT if none arrived. */
+int mr_ladder_poll(mr_ladder* l, mr_completion* out, int32_t max, int32_t timeout_us,
+                   int32_t* n_out);
+/* Give a completed job's outputs back (MR_ESTATE if not completed yet). */
+int mr_ladder_release(mr_ladder* l, uint64_t job_id);
+int mr_ladder_get_stats(mr_ladder* l, mr_ladder_stats* out);
+/* Waits for in-flight work, frees everything the ladder owns (NULL ok). */
+int mr_ladder_close(mr_ladder* l);
+
 /* Depth bounds of a dependent representation (dep_w x dep_h) from the depth
  * map of its reference representation (ref_w x ref_h, as written by
  * mr_ctu_search), for multi-resolution reuse.  For dependent unit (ux, uy):

@@ -1,0 +1,396 @@
+// Ladder server (mr_ladder_*): the GPU executor of the serving scheduler and
+// its request-loop thread.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "mr_runtime.h"
+#include "mr_sched.h"
+
+using namespace mr;
+
+namespace {
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct FrameRef {
+  const uint8_t* luma;
+  int stride;
+};
+
+struct JobOut {
+  uint8_t* mem = nullptr;  // one allocation: outputs then bounds
+  mr_search_out out{};
+  uint8_t* bounds = nullptr;
+  hipStream_t stream = nullptr;  // stream that wrote it
+};
+
+struct BatchState {
+  hipEvent_t done = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+class GpuExecutor : public Executor {
+ public:
+  GpuExecutor(const SchedConfig& cfg, int dlo, int dhi) : cfg_(cfg), dlo_(dlo), dhi_(dhi) {}
+
+  int init() {
+    if (hipGetDevice(&device_) != hipSuccess) return MR_EHIP;
+    for (auto& s : streams_)
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return MR_EHIP;
+    return MR_OK;
+  }
+
+  ~GpuExecutor() override {
+    for (auto& s : streams_)
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+  }
+
+  int device() const { return device_; }
+
+  int64_t now_ns() override {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+  }
+
+  void put_frame(int stream, int frame, int rung, const uint8_t* luma, int stride) {
+    std::lock_guard<std::mutex> lk(mu_);
+    frames_[std::make_tuple(stream, frame, rung)] = FrameRef{luma, stride};
+  }
+
+  bool frames_resident(int stream, int frame, int rung) override {
+    std::lock_guard<std::mutex> lk(mu_);
+    return frames_.count(std::make_tuple(stream, frame, rung)) &&
+           frames_.count(std::make_tuple(stream, frame - 1, rung));
+  }
+
+  static size_t out_bytes(const RungCfg& r, bool bounded, size_t* off) {
+    const size_t U = (r.height + 7) / 8, V = (r.width + 7) / 8;
+    const size_t T = ((U * 8 + 63) / 64) * ((V * 8 + 63) / 64);
+    size_t o = 0;
+    off[0] = o, o += up256(U * V);          // depth
+    off[1] = o, o += up256(U * V);          // mode
+    off[2] = o, o += up256(U * V * 4);      // mv
+    off[3] = o, o += up256(T * 8);          // cost
+    off[4] = o, o += up256(T * 8);          // dist
+    off[5] = o, o += up256(T * 8);          // bits
+    off[6] = o, o += bounded ? up256(U * V * 2) : 0;
+    return o;
+  }
+
+  size_t footprint(const SchedJob& j) override {
+    const RungCfg& r = cfg_.rungs[j.rung];
+    size_t off[7];
+    const size_t T = (((r.height + 7) / 8 * 8 + 63) / 64) * (((r.width + 7) / 8 * 8 + 63) / 64);
+    return out_bytes(r, r.ref_rung >= 0, off) + T * (4096 + 85 * 9) + 4096;
+  }
+
+  int launch(const std::vector<SchedJob*>& jobs, void** handle) override {
+    hipStream_t st = streams_[next_++ & 1];
+    const int n = (int)jobs.size();
+    std::vector<mr_frame> cur(n), ref(n);
+    std::vector<mr_search_params> prm(n);
+    std::vector<const uint8_t*> bnd(n, nullptr);
+    std::vector<mr_search_out> outs(n);
+    for (int i = 0; i < n; ++i) {
+      SchedJob& j = *jobs[i];
+      const RungCfg& r = cfg_.rungs[j.rung];
+      FrameRef fc, fr;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        fc = frames_[std::make_tuple(j.stream, j.frame, j.rung)];
+        fr = frames_[std::make_tuple(j.stream, j.frame - 1, j.rung)];
+      }
+      cur[i] = mr_frame{fc.luma, r.width, r.height, fc.stride};
+      ref[i] = mr_frame{fr.luma, r.width, r.height, fr.stride};
+      prm[i] = mr_search_params{r.qp, r.search_range};
+      JobOut* o = new JobOut();
+      size_t off[7];
+      const size_t bytes = out_bytes(r, j.ref_job != 0, off);
+      if (hipMallocAsync((void**)&o->mem, bytes, st) != hipSuccess) {
+        delete o;
+        return MR_ENOMEM;
+      }
+      o->stream = st;
+      o->out = mr_search_out{o->mem + off[0], o->mem + off[1], (int16_t*)(o->mem + off[2]),
+                             (int64_t*)(o->mem + off[3]), (int64_t*)(o->mem + off[4]),
+                             (int64_t*)(o->mem + off[5])};
+      j.exec_state = o;
+      const int U = (r.height + 7) / 8, V = (r.width + 7) / 8;
+      j.n_ctus = ((U * 8 + 63) / 64) * ((V * 8 + 63) / 64);
+      if (j.ref_job) {
+        o->bounds = o->mem + off[6];
+        const RungCfg& rr = cfg_.rungs[r.ref_rung];
+        const JobOut* ro = (const JobOut*)ref_state_(j.ref_job);
+        if (!ro) return MR_EDEPEND;
+        if (launch_depth_bounds(ro->out.depth, rr.width, rr.height, r.width, r.height, dlo_, dhi_,
+                                o->bounds, st) != hipSuccess)
+          return MR_EHIP;
+        bnd[i] = o->bounds;
+      }
+      outs[i] = o->out;
+    }
+    std::vector<const mr_frame*> pc(n), pr(n);
+    std::vector<const mr_search_params*> pp(n);
+    std::vector<const mr_search_out*> po(n);
+    for (int i = 0; i < n; ++i) pc[i] = &cur[i], pr[i] = &ref[i], pp[i] = &prm[i], po[i] = &outs[i];
+    Plan P;
+    int rc = make_plan(pc.data(), pr.data(), pp.data(), bnd.data(), po.data(), n, true, &P);
+    if (rc != MR_OK) return rc;
+    const size_t off_items = up256(sizeof(JobDesc) * n);
+    const size_t off_ctr = off_items + up256(sizeof(uint2) * P.items.size());
+    const size_t off_scr = off_ctr + 256;
+    uint8_t* mem = nullptr;
+    if (hipMallocAsync((void**)&mem, off_scr + P.scratch_bytes, st) != hipSuccess) return MR_ENOMEM;
+    bind_scratch(P, mem + off_scr);
+    hipError_t e = hipMemcpyAsync(mem, P.jobs.data(), sizeof(JobDesc) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(mem + off_items, P.items.data(), sizeof(uint2) * P.items.size(),
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_prep((JobDesc*)mem, n, P.n_ctus, (uint32_t*)(mem + off_ctr), st);
+    if (e == hipSuccess)
+      e = launch_search((JobDesc*)mem, (const uint2*)(mem + off_items), P.n_items, P.D, P.strip,
+                        P.n_wg, P.lds_bytes, (uint32_t*)(mem + off_ctr), st);
+    if (e == hipSuccess) e = launch_leaf((JobDesc*)mem, n, P.n_ctus, st);
+    const hipError_t ef = hipFreeAsync(mem, st);
+    BatchState* b = new BatchState();
+    b->stream = st;
+    if (e == hipSuccess) e = ef;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(b->done, st);
+    if (e != hipSuccess) {
+      if (b->done) (void)hipEventDestroy(b->done);
+      delete b;
+      return MR_EHIP;
+    }
+    *handle = b;
+    return MR_OK;
+  }
+
+  int query(void* handle) override {
+    const hipError_t e = hipEventQuery(((BatchState*)handle)->done);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return -1;
+  }
+
+  void finish(void* handle, const std::vector<SchedJob*>& jobs) override {
+    BatchState* b = (BatchState*)handle;
+    (void)hipEventDestroy(b->done);
+    delete b;
+    for (SchedJob* j : jobs) j->status = MR_OK;
+  }
+
+  void free_job(SchedJob& j) override {
+    JobOut* o = (JobOut*)j.exec_state;
+    if (!o) return;
+    (void)hipFreeAsync(o->mem, o->stream);
+    delete o;
+  }
+
+  // Lookup of a job's executor state through the scheduler (set by the ladder).
+  std::function<void*(uint64_t)> ref_state_;
+
+  void sync() {
+    for (auto& s : streams_) (void)hipStreamSynchronize(s);
+  }
+
+ private:
+  SchedConfig cfg_;
+  int dlo_, dhi_;
+  int device_ = 0;
+  hipStream_t streams_[2] = {nullptr, nullptr};
+  unsigned next_ = 0;
+  std::mutex mu_;
+  std::map<std::tuple<int, int, int>, FrameRef> frames_;
+};
+
+}  // namespace
+
+struct mr_ladder {
+  SchedConfig cfg;
+  std::unique_ptr<GpuExecutor> ex;
+  std::unique_ptr<Scheduler> sched;
+  std::mutex mu;                 // guards sched
+  std::condition_variable cv_work, cv_done;
+  std::thread worker;
+  std::atomic<bool> stop{false};
+  bool closed = false;
+};
+
+static void ladder_loop(mr_ladder* l) {
+  (void)hipSetDevice(l->ex->device());
+  std::unique_lock<std::mutex> lk(l->mu);
+  while (!l->stop.load()) {
+    const int done = l->sched->step();
+    if (done) l->cv_done.notify_all();
+    if (l->sched->idle()) {
+      l->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    } else {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    }
+  }
+  // Drain: wait for batches in flight so their outputs are complete.
+  while (l->sched->batches_in_flight() > 0) {
+    l->sched->step();
+    lk.unlock();
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
+    lk.lock();
+  }
+  l->cv_done.notify_all();
+}
+
+extern "C" {
+
+int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
+  if (!out) return MR_EINVAL;
+  *out = nullptr;
+  if (!cfg || cfg->n_rungs < 1 || cfg->n_rungs > 8 || cfg->delta_lo < 0 || cfg->delta_lo > 3 ||
+      cfg->delta_hi < 0 || cfg->delta_hi > 3 || cfg->hbm_budget_bytes == 0 ||
+      cfg->max_inflight < 1 || cfg->max_inflight > 65536 || cfg->max_queue < 1 ||
+      cfg->max_queue > (1 << 20) || cfg->max_batch_jobs < 1 || cfg->max_batch_jobs > 4096)
+    return MR_EINVAL;
+  SchedConfig sc;
+  for (int r = 0; r < cfg->n_rungs; ++r) {
+    const mr_rung& g = cfg->rungs[r];
+    if (g.width < 1 || g.height < 1 || g.width > 8192 || g.height > 8192 || g.qp < 0 ||
+        g.qp > 51 || g.search_range < 0 || g.search_range > 128 || g.ref_rung < -1 ||
+        g.ref_rung >= cfg->n_rungs || g.ref_rung == r)
+      return MR_EINVAL;
+    sc.rungs.push_back(RungCfg{g.width, g.height, g.qp, g.search_range, g.ref_rung});
+  }
+  // Reference chains must end (no cycles).
+  for (int r = 0; r < cfg->n_rungs; ++r) {
+    int x = r, hops = 0;
+    while (x >= 0 && hops <= cfg->n_rungs) x = sc.rungs[x].ref_rung, ++hops;
+    if (x >= 0) return MR_EINVAL;
+  }
+  sc.budget_bytes = cfg->hbm_budget_bytes;
+  sc.max_inflight = cfg->max_inflight;
+  sc.max_queue = cfg->max_queue;
+  sc.max_batch_jobs = cfg->max_batch_jobs;
+  mr_ladder* l = new mr_ladder();
+  l->cfg = sc;
+  l->ex.reset(new GpuExecutor(sc, cfg->delta_lo, cfg->delta_hi));
+  if (l->ex->init() != MR_OK) {
+    delete l;
+    return MR_EHIP;
+  }
+  l->sched.reset(new Scheduler(sc, l->ex.get()));
+  Scheduler* s = l->sched.get();
+  l->ex->ref_state_ = [s](uint64_t id) -> void* {
+    const SchedJob* j = s->job(id);
+    return j ? j->exec_state : nullptr;
+  };
+  l->worker = std::thread(ladder_loop, l);
+  *out = l;
+  return MR_OK;
+}
+
+int mr_ladder_put_frame(mr_ladder* l, int32_t stream_id, int32_t frame_idx, int32_t rung,
+                        const uint8_t* luma, int32_t stride) {
+  if (!l || !luma || stream_id < 0 || frame_idx < 0 || rung < 0 ||
+      rung >= (int)l->cfg.rungs.size() || stride < l->cfg.rungs[rung].width)
+    return MR_EINVAL;
+  l->ex->put_frame(stream_id, frame_idx, rung, luma, stride);
+  return MR_OK;
+}
+
+int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id) {
+  if (!l || !job) return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(l->mu);
+  if (l->closed) return MR_ESTATE;
+  const int rc = l->sched->submit(job->stream_id, job->frame_idx, job->rung, job_id);
+  if (rc == MR_OK) l->cv_work.notify_all();
+  return rc;
+}
+
+int mr_ladder_poll(mr_ladder* l, mr_completion* out, int32_t max, int32_t timeout_us,
+                   int32_t* n_out) {
+  if (!l || !out || max < 1 || timeout_us < 0 || !n_out) return MR_EINVAL;
+  *n_out = 0;
+  std::unique_lock<std::mutex> lk(l->mu);
+  std::vector<uint64_t> ids = l->sched->take_completions(max);
+  if (ids.empty() && timeout_us > 0) {
+    const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(timeout_us);
+    while (ids.empty() && std::chrono::steady_clock::now() < until) {
+      l->cv_done.wait_until(lk, until);
+      ids = l->sched->take_completions(max);
+    }
+  }
+  if (ids.empty()) return MR_ETIMEOUT;
+  for (size_t i = 0; i < ids.size(); ++i) {
+    const SchedJob* j = l->sched->job(ids[i]);
+    mr_completion& c = out[i];
+    std::memset(&c, 0, sizeof(c));
+    c.job_id = j->id;
+    c.status = j->status;
+    c.stream_id = j->stream, c.frame_idx = j->frame, c.rung = j->rung;
+    c.implied = j->implied ? 1 : 0;
+    c.n_ctus = j->n_ctus;
+    c.t_arrive_ns = j->t_arrive, c.t_start_ns = j->t_start, c.t_done_ns = j->t_done;
+    if (j->exec_state) c.out = ((JobOut*)j->exec_state)->out;
+  }
+  *n_out = (int32_t)ids.size();
+  return MR_OK;
+}
+
+int mr_ladder_release(mr_ladder* l, uint64_t job_id) {
+  if (!l) return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(l->mu);
+  return l->sched->release(job_id);
+}
+
+int mr_ladder_get_stats(mr_ladder* l, mr_ladder_stats* out) {
+  if (!l || !out) return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(l->mu);
+  const SchedStats s = l->sched->stats();
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = s.submitted, out->implied = s.implied, out->completed = s.completed;
+  out->failed = s.failed, out->rejected = s.rejected, out->batches = s.batches;
+  out->ctus_done = s.ctus_done;
+  out->p50_ms = s.p50_ms, out->p99_ms = s.p99_ms, out->mean_ms = s.mean_ms, out->max_ms = s.max_ms;
+  const double span = (s.last_done_ns - s.first_start_ns) * 1e-9;
+  out->ctus_per_s = span > 0 ? s.ctus_done / span : 0.0;
+  out->bytes_in_use = s.bytes_in_use, out->peak_bytes = s.peak_bytes;
+  return MR_OK;
+}
+
+int mr_ladder_close(mr_ladder* l) {
+  if (!l) return MR_OK;
+  {
+    std::lock_guard<std::mutex> lk(l->mu);
+    l->closed = true;
+  }
+  l->stop.store(true);
+  l->cv_work.notify_all();
+  if (l->worker.joinable()) l->worker.join();
+  l->ex->sync();
+  // Free every job's outputs still held.
+  {
+    std::lock_guard<std::mutex> lk(l->mu);
+    for (uint64_t id = 1;; ++id) {
+      const SchedJob* j = l->sched->job(id);
+      if (!j) break;
+      if (j->exec_state) l->ex->free_job(const_cast<SchedJob&>(*j));
+    }
+  }
+  l->ex->sync();
+  delete l;
+  return MR_OK;
+}
+
+}  // extern "C"

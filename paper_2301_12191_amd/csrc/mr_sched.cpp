@@ -1,0 +1,243 @@
+// Serving scheduler (see mr_sched.h).
+#include "mr_sched.h"
+
+#include <algorithm>
+
+#include "mr.h"
+
+namespace mr {
+
+Scheduler::Scheduler(const SchedConfig& cfg, Executor* ex) : cfg_(cfg), ex_(ex) {}
+
+static bool is_reference_rung(const SchedConfig& cfg, int rung) {
+  for (const RungCfg& r : cfg.rungs)
+    if (r.ref_rung == rung) return true;
+  return false;
+}
+
+SchedJob* Scheduler::find_ref(int stream, int frame, int ref_rung) {
+  auto it = latest_.find(std::make_tuple(stream, frame, ref_rung));
+  if (it == latest_.end()) return nullptr;
+  auto jt = jobs_.find(it->second);
+  if (jt == jobs_.end()) return nullptr;
+  SchedJob* r = jt->second.get();
+  if (r->state == kFailed) return nullptr;
+  if (r->state == kDone && !r->exec_state) return nullptr;  // outputs already freed
+  return r;
+}
+
+int Scheduler::submit(int stream, int frame, int rung, uint64_t* id) {
+  if (id) *id = 0;
+  if (stream < 0 || frame < 1 || rung < 0 || rung >= (int)cfg_.rungs.size()) return MR_EINVAL;
+  if (!ex_->frames_resident(stream, frame, rung)) return MR_EINVAL;
+  int open = 0;
+  for (const auto& kv : jobs_)
+    if (kv.second->state != kDone && kv.second->state != kFailed) ++open;
+  if (open >= cfg_.max_queue) {
+    ++st_.rejected;
+    return MR_EAGAIN;
+  }
+  SchedJob* ref = nullptr;
+  const int rr = cfg_.rungs[rung].ref_rung;
+  if (rr >= 0) {
+    ref = find_ref(stream, frame, rr);
+    if (!ref) {
+      if (!ex_->frames_resident(stream, frame, rr)) return MR_EDEPEND;
+      uint64_t rid = 0;
+      const int rc = submit(stream, frame, rr, &rid);  // the implied reference job
+      if (rc != MR_OK) return rc == MR_EINVAL ? MR_EDEPEND : rc;
+      ref = jobs_[rid].get();
+      ref->implied = true;
+      ++st_.implied;
+    }
+  }
+  auto j = std::make_unique<SchedJob>();
+  j->id = next_id_++;
+  j->stream = stream, j->frame = frame, j->rung = rung;
+  j->t_arrive = ex_->now_ns();
+  j->footprint = ex_->footprint(*j);
+  if (j->footprint > cfg_.budget_bytes) {
+    ++st_.rejected;
+    return MR_EAGAIN;  // can never be admitted under this budget
+  }
+  if (ref) {
+    j->ref_job = ref->id;
+    ref->pending_dependents++;
+    j->state = ref->depth_ready ? kReady : kQueued;
+  } else {
+    j->state = kReady;
+  }
+  const uint64_t jid = j->id;
+  latest_[std::make_tuple(stream, frame, rung)] = jid;
+  jobs_[jid] = std::move(j);
+  queue_.push_back(jid);
+  ++st_.submitted;
+  if (id) *id = jid;
+  return MR_OK;
+}
+
+void Scheduler::maybe_free(SchedJob& j) {
+  if (!j.exec_state) return;
+  if (j.state != kDone && j.state != kFailed) return;
+  if (!j.released || j.pending_dependents > 0) return;
+  // A done reference job stays resident (its depth map serves later
+  // dependents) until admission needs its memory; see step().
+  if (j.state == kDone && is_reference_rung(cfg_, j.rung)) return;
+  ex_->free_job(j);
+  j.exec_state = nullptr;
+  if (j.admitted) st_.bytes_in_use -= j.footprint, j.admitted = false;
+}
+
+void Scheduler::complete(SchedJob& j, int status, int64_t t) {
+  j.t_done = t;
+  j.status = status;
+  j.state = status == MR_OK ? kDone : kFailed;
+  j.depth_ready = status == MR_OK;
+  --inflight_;
+  if (status == MR_OK) {
+    ++st_.completed;
+    st_.ctus_done += j.n_ctus;
+    st_.last_done_ns = std::max(st_.last_done_ns, t);
+    latencies_ms_.push_back((t - j.t_arrive) * 1e-6);
+  } else {
+    ++st_.failed;
+  }
+  completions_.push_back(j.id);
+  if (j.ref_job) {
+    auto it = jobs_.find(j.ref_job);
+    if (it != jobs_.end()) {
+      it->second->pending_dependents--;
+      maybe_free(*it->second);
+    }
+  }
+}
+
+int Scheduler::step() {
+  int done = 0;
+  const int64_t now = ex_->now_ns();
+  // 1. Retire finished batches.
+  for (size_t b = 0; b < running_.size();) {
+    const int q = ex_->query(running_[b].handle);
+    if (q == 0) {
+      ++b;
+      continue;
+    }
+    ex_->finish(running_[b].handle, running_[b].jobs);
+    const int64_t t = ex_->now_ns();
+    for (SchedJob* j : running_[b].jobs) {
+      complete(*j, q < 0 ? MR_EHIP : j->status, t);
+      ++done;
+    }
+    running_.erase(running_.begin() + b);
+  }
+  // 2. Dependents of finished references become ready (or fail with them).
+  for (uint64_t id : queue_) {
+    SchedJob& j = *jobs_[id];
+    if (j.state != kQueued) continue;
+    const SchedJob& r = *jobs_[j.ref_job];
+    if (r.state == kDone) j.state = kReady;
+    if (r.state == kFailed) {
+      j.state = kRunning;  // transient; completed below
+      ++inflight_;
+      complete(j, MR_EDEPEND, now);
+      ++done;
+    }
+  }
+  queue_.erase(std::remove_if(queue_.begin(), queue_.end(),
+                              [&](uint64_t id) { return jobs_[id]->state == kFailed; }),
+               queue_.end());
+  // 3. Admit ready jobs in arrival order (head of line blocks: no starvation of
+  //    large jobs) and launch them as one batch.
+  if ((int)running_.size() >= cfg_.max_batches_in_flight) return done;
+  std::vector<SchedJob*> batch;
+  for (uint64_t id : queue_) {
+    SchedJob& j = *jobs_[id];
+    if (j.state == kQueued) continue;  // waiting for its reference
+    if ((int)batch.size() >= cfg_.max_batch_jobs || inflight_ >= cfg_.max_inflight) break;
+    if (st_.bytes_in_use + j.footprint > cfg_.budget_bytes) {
+      // Evict resident reference jobs nobody needs any more (oldest first).
+      for (auto& kv : jobs_) {
+        SchedJob& r = *kv.second;
+        if (st_.bytes_in_use + j.footprint <= cfg_.budget_bytes) break;
+        if (r.exec_state && r.state == kDone && r.released && r.pending_dependents == 0) {
+          ex_->free_job(r);
+          r.exec_state = nullptr;
+          if (r.admitted) st_.bytes_in_use -= r.footprint, r.admitted = false;
+        }
+      }
+      if (st_.bytes_in_use + j.footprint > cfg_.budget_bytes) break;
+    }
+    j.admitted = true;
+    st_.bytes_in_use += j.footprint;
+    st_.peak_bytes = std::max(st_.peak_bytes, st_.bytes_in_use);
+    ++inflight_;
+    batch.push_back(&j);
+  }
+  if (batch.empty()) return done;
+  for (SchedJob* j : batch) j->state = kRunning;
+  queue_.erase(std::remove_if(queue_.begin(), queue_.end(),
+                              [&](uint64_t id) { return jobs_[id]->state == kRunning; }),
+               queue_.end());
+  void* handle = nullptr;
+  const int rc = ex_->launch(batch, &handle);
+  const int64_t t = ex_->now_ns();
+  if (rc != MR_OK) {
+    for (SchedJob* j : batch) {
+      complete(*j, rc, t);
+      ++done;
+    }
+    return done;
+  }
+  for (SchedJob* j : batch) j->t_start = t;
+  if (!st_.first_start_ns) st_.first_start_ns = t;
+  ++st_.batches;
+  running_.push_back(Batch{handle, batch});
+  return done;
+}
+
+std::vector<uint64_t> Scheduler::take_completions(int max) {
+  std::vector<uint64_t> out;
+  while (!completions_.empty() && (int)out.size() < max) {
+    out.push_back(completions_.front());
+    completions_.pop_front();
+  }
+  return out;
+}
+
+const SchedJob* Scheduler::job(uint64_t id) const {
+  auto it = jobs_.find(id);
+  return it == jobs_.end() ? nullptr : it->second.get();
+}
+
+int Scheduler::release(uint64_t id) {
+  auto it = jobs_.find(id);
+  if (it == jobs_.end()) return MR_EINVAL;
+  SchedJob& j = *it->second;
+  if (j.state != kDone && j.state != kFailed) return MR_ESTATE;
+  j.released = true;
+  maybe_free(j);
+  return MR_OK;
+}
+
+bool Scheduler::idle() const { return queue_.empty() && running_.empty(); }
+
+SchedStats Scheduler::stats() const {
+  SchedStats s = st_;
+  if (!latencies_ms_.empty()) {
+    std::vector<double> v = latencies_ms_;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+      const size_t k = (size_t)std::min<double>(v.size() - 1, std::max(0.0, p * v.size() - 1e-9));
+      return v[k];
+    };
+    s.p50_ms = pct(0.50);
+    s.p99_ms = pct(0.99);
+    double sum = 0;
+    for (double x : v) sum += x;
+    s.mean_ms = sum / v.size();
+    s.max_ms = v.back();
+  }
+  return s;
+}
+
+}  // namespace mr

@@ -1,0 +1,114 @@
+// Serving scheduler of the ladder server: job state machine, reference-depth
+// dependencies, memory-footprint admission, continuous batching and latency
+// statistics.  Pure host C++ (no HIP): the device work goes through an
+// Executor, so the state machine is testable on the CPU with a fake one.
+#pragma once
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <tuple>
+#include <vector>
+
+namespace mr {
+
+enum JobState { kQueued = 0, kReady = 1, kRunning = 2, kDone = 3, kFailed = 4 };
+
+struct RungCfg {
+  int width, height, qp, search_range, ref_rung;  // ref_rung -1: a root (no dependency)
+};
+
+struct SchedConfig {
+  std::vector<RungCfg> rungs;
+  uint64_t budget_bytes = 0;  // footprint of admitted, not yet released jobs
+  int max_inflight = 64;      // jobs admitted (running or done-unreleased excluded)
+  int max_queue = 4096;       // submitted, not yet completed
+  int max_batch_jobs = 64;    // jobs per device launch
+  int max_batches_in_flight = 2;
+};
+
+struct SchedJob {
+  uint64_t id = 0;
+  int stream = 0, frame = 0, rung = 0;
+  JobState state = kQueued;
+  int status = 0;
+  bool implied = false;            // created by the server for a dependent
+  bool released = false;           // caller released the outputs
+  uint64_t ref_job = 0;            // job whose depth map bounds this one (0 none)
+  int pending_dependents = 0;      // dependents that still need this job's depth map
+  bool depth_ready = false;        // reference depth map available (job done)
+  size_t footprint = 0;            // device bytes while admitted
+  bool admitted = false;
+  int64_t t_arrive = 0, t_start = 0, t_done = 0;
+  int64_t cost_sum = 0;
+  int n_ctus = 0;
+  void* exec_state = nullptr;      // executor-owned per-job data (outputs)
+};
+
+// Device side of the server.  All calls come from the scheduler's thread.
+class Executor {
+ public:
+  virtual ~Executor() = default;
+  virtual int64_t now_ns() = 0;
+  // Bytes a job occupies on the device while admitted (scratch + outputs + bounds).
+  virtual size_t footprint(const SchedJob& j) = 0;
+  // Are both frames (frame and frame-1) of (stream, rung) resident?
+  virtual bool frames_resident(int stream, int frame, int rung) = 0;
+  // Launch a batch; jobs' references (ref_job) are done.  Returns 0 or an mr_status.
+  virtual int launch(const std::vector<SchedJob*>& jobs, void** handle) = 0;
+  // 1 done, 0 still running, < 0 failed.
+  virtual int query(void* handle) = 0;
+  // After query() != 0: fill per-job results (cost_sum, status) and free batch resources.
+  virtual void finish(void* handle, const std::vector<SchedJob*>& jobs) = 0;
+  // Free a job's outputs (released and no longer needed by dependents).
+  virtual void free_job(SchedJob& j) = 0;
+};
+
+struct SchedStats {
+  int64_t submitted = 0, implied = 0, completed = 0, failed = 0, rejected = 0;
+  int64_t batches = 0, ctus_done = 0;
+  int64_t first_start_ns = 0, last_done_ns = 0;
+  double p50_ms = 0, p99_ms = 0, mean_ms = 0, max_ms = 0;
+  uint64_t bytes_in_use = 0, peak_bytes = 0;
+};
+
+class Scheduler {
+ public:
+  Scheduler(const SchedConfig& cfg, Executor* ex);
+  // Validate and enqueue; may create the implied reference job.  Returns an mr_status.
+  int submit(int stream, int frame, int rung, uint64_t* id);
+  // One loop iteration: retire finished batches, release dependents, admit and
+  // launch.  Returns the number of jobs completed in this call.
+  int step();
+  // Completed jobs not yet handed out (ids in completion order).
+  std::vector<uint64_t> take_completions(int max);
+  const SchedJob* job(uint64_t id) const;
+  int release(uint64_t id);
+  bool idle() const;  // nothing queued or running
+  SchedStats stats() const;
+  int batches_in_flight() const { return (int)running_.size(); }
+
+ private:
+  struct Batch {
+    void* handle;
+    std::vector<SchedJob*> jobs;
+  };
+  SchedJob* find_ref(int stream, int frame, int ref_rung);
+  void maybe_free(SchedJob& j);
+  void complete(SchedJob& j, int status, int64_t t);
+  SchedConfig cfg_;
+  Executor* ex_;
+  uint64_t next_id_ = 1;
+  std::map<uint64_t, std::unique_ptr<SchedJob>> jobs_;
+  std::map<std::tuple<int, int, int>, uint64_t> latest_;  // (stream, frame, rung) -> job
+  std::deque<uint64_t> queue_;                           // submitted, not launched (FIFO)
+  std::vector<Batch> running_;
+  std::deque<uint64_t> completions_;
+  std::vector<double> latencies_ms_;
+  SchedStats st_;
+  int inflight_ = 0;
+};
+
+}  // namespace mr

@@ -291,3 +291,154 @@ def mr_autotune(jobs, reps: int = 3) -> dict:
     if rc != MR_OK:
         raise MRError(rc, "mr_autotune")
     return {f: getattr(res, f) for f, _ in mr_tune_result._fields_}
+
+
+# ------------------------------------------------------------------ ladder server
+class mr_rung(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("qp", ctypes.c_int32),
+                ("search_range", ctypes.c_int32), ("ref_rung", ctypes.c_int32)]
+
+
+class mr_ladder_config(ctypes.Structure):
+    _fields_ = [("n_rungs", ctypes.c_int32), ("rungs", mr_rung * 8), ("delta_lo", ctypes.c_int32),
+                ("delta_hi", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("max_batch_jobs", ctypes.c_int32)]
+
+
+class mr_job(ctypes.Structure):
+    _fields_ = [("stream_id", ctypes.c_int32), ("frame_idx", ctypes.c_int32),
+                ("rung", ctypes.c_int32)]
+
+
+class mr_completion(ctypes.Structure):
+    _fields_ = [("job_id", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("stream_id", ctypes.c_int32), ("frame_idx", ctypes.c_int32),
+                ("rung", ctypes.c_int32), ("implied", ctypes.c_int32), ("n_ctus", ctypes.c_int32),
+                ("t_arrive_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("out", mr_search_out)]
+
+
+class mr_ladder_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("implied", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("ctus_done", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("ctus_per_s", ctypes.c_double),
+                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64)]
+
+
+def _ladder_lib():
+    L = lib()
+    if not getattr(L, "_ladder_bound", False):
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        L.mr_ladder_open.argtypes = [ctypes.POINTER(mr_ladder_config), ctypes.POINTER(vp)]
+        L.mr_ladder_put_frame.argtypes = [vp, i32, i32, i32, vp, i32]
+        L.mr_ladder_submit.argtypes = [vp, ctypes.POINTER(mr_job), ctypes.POINTER(ctypes.c_uint64)]
+        L.mr_ladder_poll.argtypes = [vp, ctypes.POINTER(mr_completion), i32, i32,
+                                     ctypes.POINTER(i32)]
+        L.mr_ladder_release.argtypes = [vp, ctypes.c_uint64]
+        L.mr_ladder_get_stats.argtypes = [vp, ctypes.POINTER(mr_ladder_stats)]
+        L.mr_ladder_close.argtypes = [vp]
+        for f in ("mr_ladder_open", "mr_ladder_put_frame", "mr_ladder_submit", "mr_ladder_poll",
+                  "mr_ladder_release", "mr_ladder_get_stats", "mr_ladder_close"):
+            getattr(L, f).restype = ctypes.c_int
+        L._ladder_bound = True
+    return L
+
+
+def _tensor_view(ptr, shape, dtype, device):
+    """Non-owning torch view of ladder-owned device memory (valid until release)."""
+    n = torch.empty((), dtype=dtype).element_size()
+    for d in shape:
+        n *= d
+
+    class _Holder:
+        __cuda_array_interface__ = {"shape": (n,), "typestr": "|u1", "data": (ptr, False),
+                                    "version": 2}
+    return torch.as_tensor(_Holder(), device=device).view(dtype).view(shape)
+
+
+class Ladder:
+    """mr_ladder_* handle: continuous-batching server of ladder frame-pair jobs."""
+
+    def __init__(self, rungs, delta_lo=0, delta_hi=1, budget_bytes=8 << 30, max_inflight=256,
+                 max_queue=8192, max_batch_jobs=64):
+        L = _ladder_lib()
+        cfg = mr_ladder_config()
+        cfg.n_rungs = len(rungs)
+        for i, r in enumerate(rungs):
+            cfg.rungs[i] = mr_rung(r["width"], r["height"], r["qp"], r["search_range"],
+                                   r.get("ref_rung", -1))
+        cfg.delta_lo, cfg.delta_hi = delta_lo, delta_hi
+        cfg.hbm_budget_bytes = budget_bytes
+        cfg.max_inflight, cfg.max_queue, cfg.max_batch_jobs = max_inflight, max_queue, max_batch_jobs
+        self.rungs = rungs
+        self._h = ctypes.c_void_p()
+        self._frames = {}
+        rc = L.mr_ladder_open(ctypes.byref(cfg), ctypes.byref(self._h))
+        if rc != MR_OK:
+            raise MRError(rc, "mr_ladder_open")
+
+    def put_frame(self, stream_id, frame_idx, rung, luma: torch.Tensor):
+        self._frames[(stream_id, frame_idx, rung)] = luma  # keep resident
+        rc = _ladder_lib().mr_ladder_put_frame(self._h, stream_id, frame_idx, rung,
+                                               _dev_ptr(luma, torch.uint8, "luma"), luma.stride(0))
+        if rc != MR_OK:
+            raise MRError(rc, "mr_ladder_put_frame")
+
+    def submit(self, stream_id, frame_idx, rung) -> int:
+        jid = ctypes.c_uint64()
+        rc = _ladder_lib().mr_ladder_submit(self._h, ctypes.byref(mr_job(stream_id, frame_idx, rung)),
+                                            ctypes.byref(jid))
+        if rc != MR_OK:
+            raise MRError(rc, "mr_ladder_submit")
+        return jid.value
+
+    def poll(self, max_n=64, timeout_us=0):
+        arr = (mr_completion * max_n)()
+        n = ctypes.c_int32()
+        rc = _ladder_lib().mr_ladder_poll(self._h, arr, max_n, timeout_us, ctypes.byref(n))
+        if rc == MR_ETIMEOUT:
+            return []
+        if rc != MR_OK:
+            raise MRError(rc, "mr_ladder_poll")
+        return [arr[i] for i in range(n.value)]
+
+    def outputs(self, c, device="cuda"):
+        """torch views of a completion's device outputs (valid until release)."""
+        r = self.rungs[c.rung]
+        uh, uw = unit_shape(r["width"], r["height"])
+        th, tw = ctu_shape(r["width"], r["height"])
+        return dict(depth=_tensor_view(c.out.depth, (uh, uw), torch.uint8, device),
+                    mode=_tensor_view(c.out.mode, (uh, uw), torch.uint8, device),
+                    mv=_tensor_view(c.out.mv, (uh, uw, 2), torch.int16, device),
+                    cost=_tensor_view(c.out.ctu_cost, (th, tw), torch.int64, device),
+                    dist=_tensor_view(c.out.ctu_dist, (th, tw), torch.int64, device),
+                    bits=_tensor_view(c.out.ctu_bits, (th, tw), torch.int64, device))
+
+    def release(self, job_id):
+        rc = _ladder_lib().mr_ladder_release(self._h, job_id)
+        if rc != MR_OK:
+            raise MRError(rc, "mr_ladder_release")
+
+    def stats(self) -> dict:
+        s = mr_ladder_stats()
+        rc = _ladder_lib().mr_ladder_get_stats(self._h, ctypes.byref(s))
+        if rc != MR_OK:
+            raise MRError(rc, "mr_ladder_get_stats")
+        return {f: getattr(s, f) for f, _ in mr_ladder_stats._fields_}
+
+    def close(self):
+        if self._h:
+            rc = _ladder_lib().mr_ladder_close(self._h)
+            self._h = ctypes.c_void_p()
+            if rc != MR_OK:
+                raise MRError(rc, "mr_ladder_close")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

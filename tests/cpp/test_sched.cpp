@@ -1,0 +1,249 @@
+// CPU test of the serving scheduler's state machine with a fake executor:
+// dependencies and implied references, footprint admission, queue limits,
+// failure propagation, resident references and eviction, continuous batching,
+// latency statistics.  Exit code 0 = all checks passed.
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "mr.h"
+#include "mr_sched.h"
+
+using namespace mr;
+
+static int g_fail = 0;
+#define CHECK(c)                                                      \
+  do {                                                                \
+    if (!(c)) {                                                       \
+      std::fprintf(stderr, "CHECK failed line %d: %s\n", __LINE__, #c); \
+      ++g_fail;                                                       \
+    }                                                                 \
+  } while (0)
+
+struct FakeBatch {
+  int64_t done_at;
+  bool fail;
+};
+
+struct FakeExec : Executor {
+  int64_t t = 0;                       // fake clock (ns), advanced by the test
+  int64_t batch_ns = 1000000;          // every batch takes 1 ms
+  std::set<std::tuple<int, int, int>> frames;
+  std::map<int, size_t> fp;            // per-rung footprint
+  std::vector<std::vector<uint64_t>> launched;
+  int freed = 0;
+  bool fail_next = false;
+  std::set<FakeBatch*> live;
+  ~FakeExec() override {
+    for (FakeBatch* b : live) delete b;
+  }
+  int64_t now_ns() override { return t; }
+  size_t footprint(const SchedJob& j) override { return fp[j.rung]; }
+  bool frames_resident(int s, int f, int r) override {
+    return frames.count(std::make_tuple(s, f, r)) && frames.count(std::make_tuple(s, f - 1, r));
+  }
+  int launch(const std::vector<SchedJob*>& jobs, void** h) override {
+    std::vector<uint64_t> ids;
+    for (SchedJob* j : jobs) {
+      ids.push_back(j->id);
+      j->exec_state = (void*)1;
+      j->n_ctus = 10;
+    }
+    launched.push_back(ids);
+    FakeBatch* fb = new FakeBatch{t + batch_ns, fail_next};
+    live.insert(fb);
+    *h = fb;
+    fail_next = false;
+    return MR_OK;
+  }
+  int query(void* h) override {
+    FakeBatch* b = (FakeBatch*)h;
+    if (t < b->done_at) return 0;
+    return b->fail ? -1 : 1;
+  }
+  void finish(void* h, const std::vector<SchedJob*>& jobs) override {
+    live.erase((FakeBatch*)h);
+    delete (FakeBatch*)h;
+    for (SchedJob* j : jobs) j->status = MR_OK;
+  }
+  void free_job(SchedJob& j) override {
+    ++freed;
+    j.exec_state = nullptr;
+  }
+};
+
+static SchedConfig ladder_cfg(uint64_t budget) {
+  SchedConfig c;
+  // rung 0: 960x540 root; rungs 1, 2 depend on it
+  c.rungs = {{960, 540, 32, 32, -1}, {1920, 1080, 27, 64, 0}, {3840, 2160, 22, 128, 0}};
+  c.budget_bytes = budget;
+  c.max_inflight = 64;
+  c.max_queue = 16;
+  c.max_batch_jobs = 8;
+  return c;
+}
+
+static void add_frames(FakeExec& ex, int stream, int nframes, int rungs) {
+  for (int f = 0; f < nframes; ++f)
+    for (int r = 0; r < rungs; ++r) ex.frames.insert(std::make_tuple(stream, f, r));
+}
+
+static void run_until_idle(Scheduler& s, FakeExec& ex, int max_steps = 1000) {
+  for (int i = 0; i < max_steps && !s.idle(); ++i) {
+    s.step();
+    ex.t += 100000;  // 0.1 ms per loop iteration
+  }
+}
+
+static void test_dependency_and_implied_reference() {
+  FakeExec ex;
+  ex.fp = {{0, 100}, {1, 400}, {2, 1600}};
+  add_frames(ex, 0, 3, 3);
+  Scheduler s(ladder_cfg(1 << 20), &ex);
+  uint64_t d = 0;
+  CHECK(s.submit(0, 1, 1, &d) == MR_OK);  // dependent first: implies rung-0 job
+  CHECK(s.stats().implied == 1 && s.stats().submitted == 2);
+  const SchedJob* dj = s.job(d);
+  CHECK(dj && dj->ref_job != 0 && dj->state == kQueued);
+  const SchedJob* rj = s.job(dj->ref_job);
+  CHECK(rj && rj->implied && rj->rung == 0 && rj->state == kReady);
+  s.step();
+  CHECK(ex.launched.size() == 1 && ex.launched[0].size() == 1 && ex.launched[0][0] == rj->id);
+  ex.t += 2000000;
+  s.step();  // reference completes; dependent becomes ready and launches
+  CHECK(rj->state == kDone);
+  CHECK(ex.launched.size() == 2 && ex.launched[1][0] == d);
+  run_until_idle(s, ex);
+  CHECK(dj->state == kDone && dj->t_start >= rj->t_done);
+  // a second dependent of the same (stream, frame) reuses the resident reference
+  uint64_t d2 = 0;
+  CHECK(s.submit(0, 1, 2, &d2) == MR_OK);
+  CHECK(s.job(d2)->ref_job == rj->id && s.job(d2)->state == kReady);
+  CHECK(s.stats().implied == 1);
+}
+
+static void test_missing_reference_frames() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  ex.frames = {{0, 0, 1}, {0, 1, 1}};  // only rung-1 frames
+  Scheduler s(ladder_cfg(1000), &ex);
+  uint64_t id = 7;
+  CHECK(s.submit(0, 1, 1, &id) == MR_EDEPEND && id == 0);
+  CHECK(s.submit(0, 5, 1, &id) == MR_EINVAL);   // frames not resident
+  CHECK(s.submit(-1, 1, 0, &id) == MR_EINVAL);
+  CHECK(s.submit(0, 0, 0, &id) == MR_EINVAL);   // frame 0 has no predecessor
+  CHECK(s.submit(0, 1, 3, &id) == MR_EINVAL);
+}
+
+static void test_budget_admission_and_rejection() {
+  FakeExec ex;
+  ex.fp = {{0, 600}, {1, 400}, {2, 5000}};
+  add_frames(ex, 0, 4, 3);
+  add_frames(ex, 1, 4, 3);
+  Scheduler s(ladder_cfg(1000), &ex);
+  uint64_t a, b, c;
+  CHECK(s.submit(0, 1, 0, &a) == MR_OK);
+  CHECK(s.submit(1, 1, 0, &b) == MR_OK);
+  CHECK(s.submit(0, 2, 2, &c) == MR_EAGAIN);  // 5000 bytes can never fit 1000
+  CHECK(s.stats().rejected == 1);
+  s.step();
+  // only one 600-byte job fits at a time
+  CHECK(ex.launched.size() == 1 && ex.launched[0].size() == 1 && ex.launched[0][0] == a);
+  CHECK(s.stats().bytes_in_use == 600);
+  ex.t += 2000000;
+  s.step();
+  // a is done but not released: b still cannot fit (600 + 600 > 1000)
+  CHECK(ex.launched.size() == 1);
+  CHECK(s.release(a) == MR_OK);
+  // a is a reference rung with no pending dependents: it stays resident until
+  // b needs the memory, then it is evicted
+  s.step();
+  CHECK(ex.launched.size() == 2 && ex.launched[1][0] == b);
+  CHECK(ex.freed == 1 && s.stats().bytes_in_use == 600);
+  CHECK(s.release(b + 100) == MR_EINVAL);
+  CHECK(s.release(b) == MR_ESTATE);  // still running
+}
+
+static void test_queue_limit() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  SchedConfig cfg = ladder_cfg(1 << 20);
+  cfg.max_queue = 3;
+  for (int st = 0; st < 5; ++st) add_frames(ex, st, 2, 3);
+  Scheduler s(cfg, &ex);
+  uint64_t id;
+  for (int st = 0; st < 3; ++st) CHECK(s.submit(st, 1, 0, &id) == MR_OK);
+  CHECK(s.submit(4, 1, 0, &id) == MR_EAGAIN);
+  run_until_idle(s, ex);
+  CHECK(s.submit(4, 1, 0, &id) == MR_OK);  // room again once jobs completed
+}
+
+static void test_reference_failure_fails_dependents() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  add_frames(ex, 0, 2, 3);
+  Scheduler s(ladder_cfg(1 << 20), &ex);
+  uint64_t d1, d2;
+  CHECK(s.submit(0, 1, 1, &d1) == MR_OK);
+  CHECK(s.submit(0, 1, 2, &d2) == MR_OK);
+  CHECK(s.stats().implied == 1);  // both dependents share the one implied reference
+  ex.fail_next = true;  // the reference batch fails
+  run_until_idle(s, ex);
+  const SchedJob* r = s.job(s.job(d1)->ref_job);
+  CHECK(r->state == kFailed && r->status == MR_EHIP);
+  CHECK(s.job(d1)->state == kFailed && s.job(d1)->status == MR_EDEPEND);
+  CHECK(s.job(d2)->state == kFailed && s.job(d2)->status == MR_EDEPEND);
+  if (!(s.stats().failed == 3 && s.stats().completed == 0))
+    std::fprintf(stderr, "failed=%lld completed=%lld\n", (long long)s.stats().failed,
+                 (long long)s.stats().completed);
+  CHECK(s.stats().failed == 3 && s.stats().completed == 0);
+  CHECK(ex.launched.size() == 1);
+}
+
+static void test_continuous_batching_and_latency() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  for (int st = 0; st < 8; ++st) add_frames(ex, st, 2, 3);
+  SchedConfig cfg = ladder_cfg(1 << 20);
+  cfg.max_batch_jobs = 4;
+  cfg.max_batches_in_flight = 2;
+  cfg.max_queue = 64;
+  Scheduler s(cfg, &ex);
+  uint64_t id;
+  for (int st = 0; st < 3; ++st) CHECK(s.submit(st, 1, 0, &id) == MR_OK);
+  s.step();  // batch 1 (3 jobs) on the device
+  for (int st = 3; st < 8; ++st) CHECK(s.submit(st, 1, 0, &id) == MR_OK);
+  s.step();  // arrivals during batch 1 form batch 2 while batch 1 runs
+  CHECK(ex.launched.size() == 2 && ex.launched[0].size() == 3 && ex.launched[1].size() == 4);
+  CHECK(s.batches_in_flight() == 2);
+  CHECK(s.submit(0, 1, 1, &id) == MR_OK);  // dependent of stream 0's reference
+  s.step();
+  CHECK(ex.launched.size() == 2);  // at most 2 batches in flight
+  run_until_idle(s, ex);
+  // after batch 1: stream 7's job and the (now ready) dependent share batch 3
+  CHECK(ex.launched.size() == 3 && ex.launched[2].size() == 2);
+  const SchedStats st = s.stats();
+  CHECK(st.completed == 9 && st.ctus_done == 90 && st.batches == 3);
+  CHECK(st.p50_ms > 0.9 && st.p99_ms >= st.p50_ms && st.max_ms >= st.p99_ms);
+  std::vector<uint64_t> c = s.take_completions(100);
+  CHECK(c.size() == 9);
+  CHECK(s.take_completions(100).empty());
+}
+
+int main() {
+  test_dependency_and_implied_reference();
+  test_missing_reference_frames();
+  test_budget_admission_and_rejection();
+  test_queue_limit();
+  test_reference_failure_fails_dependents();
+  test_continuous_batching_and_latency();
+  if (g_fail) {
+    std::fprintf(stderr, "%d checks failed\n", g_fail);
+    return 1;
+  }
+  std::printf("scheduler: all checks passed\n");
+  return 0;
+}

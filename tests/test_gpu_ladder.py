@@ -1,0 +1,150 @@
+"""Ladder server on the GPU: each job's result in the mix equals its result alone."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("depth", "mode", "mv", "cost", "dist", "bits")
+
+# Three rungs from one source: 320x180 is the reference of the two others.
+RUNGS = [dict(width=320, height=180, qp=32, search_range=16, ref_rung=-1),
+         dict(width=640, height=360, qp=30, search_range=24, ref_rung=0),
+         dict(width=960, height=540, qp=27, search_range=32, ref_rung=0)]
+FACTORS = [6, 3, 2]
+
+
+@pytest.fixture(scope="module")
+def mr():
+    import torch
+    from paper_2301_12191_amd import mr as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def _frames(n_streams, n_frames):
+    import torch
+    fr = {}
+    for s in range(n_streams):
+        src = synth.Scene(synth.SEED_BASE + 4 + 1000 * s, 1920, 1080, 12, 30, 4)
+        for f in range(n_frames):
+            img = src.render(f)
+            for r, (cfg, k) in enumerate(zip(RUNGS, FACTORS)):
+                fr[(s, f, r)] = torch.from_numpy(
+                    synth.box_downscale(img, k, cfg["width"], cfg["height"])).cuda()
+    return fr
+
+
+def _alone(mr, fr, s, f, r, ref_depth_cache):
+    """The job run by itself through mr_ctu_search (+ mr_depth_bounds for dependents)."""
+    import torch
+    cfg = RUNGS[r]
+    bounds = None
+    if cfg["ref_rung"] >= 0:
+        rr = cfg["ref_rung"]
+        if (s, f) not in ref_depth_cache:
+            rc = RUNGS[rr]
+            ref_depth_cache[(s, f)] = mr.mr_ctu_search(fr[(s, f, rr)], fr[(s, f - 1, rr)], rc["qp"],
+                                                       rc["search_range"])["depth"]
+        bounds = mr.mr_depth_bounds(ref_depth_cache[(s, f)], RUNGS[rr]["width"],
+                                    RUNGS[rr]["height"], cfg["width"], cfg["height"], 0, 1)
+    out = mr.mr_ctu_search(fr[(s, f, r)], fr[(s, f - 1, r)], cfg["qp"], cfg["search_range"],
+                           bounds=bounds)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _run_mix(mr, fr, jobs, **kw):
+    import torch
+    lad = mr.Ladder(RUNGS, **kw)
+    try:
+        for (s, f, r), t in fr.items():
+            lad.put_frame(s, f, r, t)
+        ids = {}
+        for (s, f, r) in jobs:
+            ids[lad.submit(s, f, r)] = (s, f, r)
+        got, seen = {}, 0
+        deadline = 2000
+        while seen < len(ids) and deadline > 0:
+            for c in lad.poll(64, 100000):
+                key = (c.stream_id, c.frame_idx, c.rung)
+                assert c.status == 0, (key, c.status)
+                assert c.t_arrive_ns <= c.t_start_ns <= c.t_done_ns
+                if c.job_id in ids:
+                    seen += 1
+                    torch.cuda.synchronize()
+                    got[key] = {k: v.cpu().numpy() for k, v in lad.outputs(c).items()}
+                lad.release(c.job_id)
+            deadline -= 1
+        st = lad.stats()
+    finally:
+        lad.close()
+    assert seen == len(ids)
+    return got, st
+
+
+def test_mix_equals_alone(mr):
+    fr = _frames(3, 3)
+    rng = np.random.default_rng(0)
+    jobs = [(int(s), int(f), int(r)) for s in range(3) for f in (1, 2) for r in range(3)]
+    rng.shuffle(jobs)  # dependents often arrive before their reference
+    got, st = _run_mix(mr, fr, jobs)
+    assert st["completed"] == len(jobs) + st["implied"] and st["failed"] == 0
+    cache = {}
+    for key in jobs:
+        exp = _alone(mr, fr, *key, cache)
+        for k in FIELDS:
+            assert np.array_equal(got[key][k], exp[k]), (key, k)
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_dependent_only_submissions_imply_reference(mr):
+    fr = _frames(2, 2)
+    jobs = [(0, 1, 2), (1, 1, 1), (0, 1, 1)]
+    got, st = _run_mix(mr, fr, jobs)
+    assert st["implied"] == 2 and st["completed"] == 5
+    cache = {}
+    for key in jobs:
+        exp = _alone(mr, fr, *key, cache)
+        for k in FIELDS:
+            assert np.array_equal(got[key][k], exp[k]), (key, k)
+
+
+def test_tiny_budget_admits_one_job_at_a_time(mr):
+    fr = _frames(2, 2)
+    jobs = [(s, 1, r) for s in range(2) for r in range(3)]
+    # 1 MB holds one 960x540 job (~0.73 MB of scratch and outputs) at a time
+    got, st = _run_mix(mr, fr, jobs, budget_bytes=1 << 20, max_batch_jobs=8)
+    assert st["completed"] == 6 and 0 < st["peak_bytes"] <= 1 << 20
+    assert st["batches"] >= 3  # the budget forces small batches
+    cache = {}
+    for key in jobs:
+        exp = _alone(mr, fr, *key, cache)
+        for k in FIELDS:
+            assert np.array_equal(got[key][k], exp[k]), (key, k)
+
+
+def test_ladder_errors(mr):
+    import torch
+    fr = _frames(1, 2)
+    lad = mr.Ladder(RUNGS)
+    try:
+        for (s, f, r), t in fr.items():
+            if r != 0:  # reference rung frames missing
+                lad.put_frame(s, f, r, t)
+        with pytest.raises(mr.MRError) as e:
+            lad.submit(0, 1, 1)
+        assert e.value.code == mr.MR_EDEPEND
+        with pytest.raises(mr.MRError) as e:
+            lad.submit(0, 1, 5)
+        assert e.value.code == mr.MR_EINVAL
+        with pytest.raises(mr.MRError) as e:
+            lad.submit(3, 1, 1)  # frames of stream 3 not resident
+        assert e.value.code == mr.MR_EINVAL
+        assert lad.poll(4, 1000) == []
+    finally:
+        lad.close()
+    with pytest.raises(mr.MRError):
+        mr.Ladder([dict(width=64, height=64, qp=30, search_range=8, ref_rung=0)])  # self-reference
