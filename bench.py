@@ -42,6 +42,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
+    ap.add_argument("--no-ladder", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="duration of Poisson arrivals in the serving leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit: "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -182,6 +186,103 @@ def main():
             "per_rung": res["per_rung"]}
         log(f"pruned: {pruned}")
 
+    # ------------------------------------------------------- six-rung ladder, one launch
+    ladder = None
+    if not args.no_ladder:
+        nf = 16
+        log(f"rendering 3840x2160 x {nf + 1} ladder source frames")
+        src = synth.Scene(synth.SEED_BASE + 3, 3840, 2160, 24, 96, 8)
+        lj = []
+        srcs = [src.render(t) for t in range(nf + 1)]
+        for (w, h, n, qp) in synth.LADDER:
+            rr = synth.search_range_for_width(w)
+            rung = [torch.from_numpy(synth.box_downscale(f, n, w, h)).to(dev) for f in srcs]
+            for k in range(1, nf + 1):
+                lj.append(dict(cur=rung[k], ref=rung[k - 1], qp=qp, search_range=rr))
+        del srcs
+        ltune = mr.mr_autotune(lj, reps=1)
+        lb = mr.Batch(lj)
+        lb.launch(stream)
+        torch.cuda.synchronize()
+        reps = 3
+        mr.mr_profile_read(reset=True)
+        mr.mr_profile_enable(True)
+        ta = time.perf_counter()
+        for _ in range(reps):
+            lb.launch(stream)
+        torch.cuda.synchronize()
+        lt = (time.perf_counter() - ta) / reps
+        mr.mr_profile_enable(False)
+        lp = mr.mr_profile_read(reset=True)
+        lctus = sum(j["out"]["cost"].numel() for j in lj)
+        labs = sum((2 * j["search_range"] + 1) ** 2 * ((j["cur"].shape[1] + 7) // 8 * 8) *
+                   ((j["cur"].shape[0] + 7) // 8 * 8) for j in lj)
+        lsearch = lp["search"][0] / 1e3 / max(1, lp["search"][1])
+        ladder = {"workload": "6 rungs 426x240..3840x2160 x 16 pairs, QP 37/35/32/30/27/22, "
+                              "R 16/24/32/48/64/128, one persistent launch",
+                  "jobs": len(lj), "ctus": lctus, "ms_per_batch": round(lt * 1e3, 3),
+                  "ctus_per_s": round(lctus / lt, 1),
+                  "search_frac_of_peak": round(labs / lsearch / PEAK_ABSDIFF, 4),
+                  "tiles": {"d": ltune["d"], "nbands": ltune["nbands"], "strip": ltune["strip"]}}
+        lb.close()
+        del lj, lb
+        torch.cuda.synchronize()
+        log(f"ladder: {ladder}")
+
+    # ---------------------------------------------------------------------- serving leg
+    serving = None
+    if not args.no_serving:
+        import random
+        n_streams, n_content, nfr = 64, 8, 3
+        log(f"rendering serving content ({n_content} sources x {nfr} frames, 6 rungs)")
+        rungs = [dict(width=w, height=h, qp=qp, search_range=synth.search_range_for_width(w),
+                      ref_rung=(-1 if w == 960 else 2)) for (w, h, n, qp) in synth.LADDER]
+        content = {}
+        for c in range(n_content):
+            sc = synth.Scene(synth.SEED_BASE + 4 + 1000 * c, 3840, 2160, 24, 96, 8)
+            for f in range(nfr):
+                img = sc.render(f)
+                for r, (w, h, n, qp) in enumerate(synth.LADDER):
+                    content[(c, f, r)] = torch.from_numpy(synth.box_downscale(img, n, w, h)).to(dev)
+        lad = mr.Ladder(rungs, delta_lo=0, delta_hi=1, budget_bytes=16 << 30, max_inflight=512,
+                        max_queue=1 << 16, max_batch_jobs=64)
+        for st in range(n_streams):
+            for f in range(nfr):
+                for r in range(len(rungs)):
+                    lad.put_frame(st, f, r, content[(st % n_content, f, r)])
+        rng = random.Random(synth.SEED_BASE + 4)
+        t_next, t0s = 0.0, time.perf_counter()
+        submitted = done = 0
+        horizon = args.serve_seconds
+        while True:
+            now = time.perf_counter() - t0s
+            while t_next <= now and t_next < horizon:
+                lad.submit(rng.randrange(n_streams), rng.randrange(1, nfr), rng.randrange(len(rungs)))
+                submitted += 1
+                t_next += rng.expovariate(240.0)
+            for c in lad.poll(256, 200):
+                lad.release(c.job_id)
+                done += 1
+            st = lad.stats()
+            if t_next >= horizon and st["completed"] + st["failed"] >= st["submitted"]:
+                break
+            if now > horizon + 60:
+                break
+        st = lad.stats()
+        lad.close()
+        serving = {"workload": "64 streams, 6-rung ladder frames resident, Poisson arrivals mean "
+                               "240 jobs/s, rung uniform, 960x540 reference bounds the others "
+                               "(depths n..n+1)",
+                   "seconds": horizon, "jobs_submitted": st["submitted"] - st["implied"],
+                   "implied_reference_jobs": st["implied"], "completed": st["completed"],
+                   "failed": st["failed"], "batches": st["batches"],
+                   "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                   "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                   "ctus_per_s": round(st["ctus_per_s"], 1)}
+        log(f"serving: {serving}")
+        del content
+        torch.cuda.synchronize()
+
     # ------------------------------------------------------------------- CPU oracle leg
     cpu = None
     if not args.no_cpu:
@@ -206,7 +307,8 @@ def main():
         "config": {"workload": "1920x1080 luma, 8 frame pairs, full search R64 QP27",
                    "ctus_per_step": ctus_per_step, "frames": NP + 1, "search_range": R,
                    "qp": QP},
-        "roofline": roofline, "cpu_baseline": cpu, "pruned": pruned,
+        "roofline": roofline, "cpu_baseline": cpu, "pruned": pruned, "ladder": ladder,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 
