@@ -249,7 +249,7 @@ int mr_set_tiles3(int32_t search_range, int32_t d, int32_t nbands, int32_t strip
  * the fastest as the tile override of the batch's dominant search range (the
  * job with the most candidate work).  Coarse-to-fine: d in {2, 4, 8} at the
  * built-in band count, then nbands 1..8 for the best d, then strip (CTUs per
- * workgroup) in {1, 2, 4}.  Each shape is run once to warm up and then `reps`
+ * workgroup) in {1, 2, 3, 4}.  Each shape is run once to warm up and then `reps`
  * times (1..20) with HIP events around the search kernel; the minimum counts.
  * Blocking; overwrites the jobs' outputs.  *out receives the choice.
  * Errors: MR_EINVAL, MR_ENOMEM, MR_EHIP. */

@@ -12,6 +12,7 @@ constexpr int kRankBits = 11;       // rank field of the 32-bit arg-min key
 constexpr uint32_t kCinv = 1050000u;  // cost field of candidates outside the window
 constexpr uint64_t kKeyNone = ~0ull;
 constexpr int kMaxStrip = 4;        // CTUs (wavefronts) per search workgroup
+constexpr int kCurRingBytes = 512;  // per wavefront: two 16x16 regions of the current CTU
 
 // Search work item of a batch: x = job, y = row << 16 | first CTU column << 4 | band.
 __host__ __device__ inline uint32_t pack_item_y(int row, int col0, int band) {
@@ -54,6 +55,7 @@ struct JobDesc {
   const uint64_t* dtab;    // [steps][2048]
   const uint8_t* bounds;   // [U][V][2] or null
   uint8_t* elig;           // [ctus][85] 1 = node may be a leaf (inside and allowed)
+  uint32_t* eligbits;      // [ctus][4] the same as a bit mask (bit n of word n / 32)
   uint8_t* depth;          // outputs
   uint8_t* mode;
   int16_t* mv;

@@ -91,6 +91,13 @@ __device__ void prep_ctu(cjob jb, int ctu) {
     }
     jb->elig[(size_t)ctu * kNodes + tid] = e;
     jb->keys[(size_t)ctu * kNodes + tid] = kKeyNone;
+    // Eligibility as a bit mask: nodes 0..63 in the first wavefront, 64..84 in the second.
+    const unsigned long long bits = __ballot(e != 0);
+    if ((tid & 63) == 0) {
+      uint32_t* eb = jb->eligbits + (size_t)ctu * 4;
+      if (tid == 0) eb[0] = (uint32_t)bits, eb[1] = (uint32_t)(bits >> 32);
+      else eb[2] = (uint32_t)bits, eb[3] = 0;
+    }
   }
 }
 
@@ -129,16 +136,20 @@ __device__ __forceinline__ void merge_keys(uint32_t vk, const uint64_t* __restri
 }
 
 // One wavefront: all steps of one (CTU, band); `win` points at this CTU's
-// column 0 of the staged window (dx = -R).
+// column 0 of the staged window (dx = -R); `ring` is this wavefront's
+// 512-byte LDS ring for the current CTU (two 16x16 regions of 64 dwords).
 template <int D>
-__device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win) {
+__device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win, uint32_t* ring) {
   const int lane = threadIdx.x & 63;
   const int Q = jb->Q, Wd = jb->win_dwords;
   const int g0 = jb->band_g0[band], g1 = jb->band_g0[band + 1];
   const int ntasks = (g1 - g0) * Q;
   const int step0 = jb->band_step0[band], nsteps = jb->band_step0[band + 1] - step0;
-  const uint8_t* __restrict__ elig = jb->elig + (size_t)ctu * kNodes;
-  const sptr32 cur = (sptr32)(jb->curpack + (size_t)ctu * 1024);
+  // Leaf-eligible nodes as an 85-bit mask in SGPRs (bit n of word n >> 5).
+  const sptr32 eb = (sptr32)(jb->eligbits + (size_t)ctu * 4);
+  const uint32_t em0 = eb[0], em1 = eb[1], em2 = eb[2];
+  // Current CTU, 8x8-block-linear in Z-order: region r = dwords [64 r, 64 r + 64).
+  const uint32_t* __restrict__ cur = jb->curpack + (size_t)ctu * 1024;
   const uint32_t* __restrict__ qtab = jb->qtab;
   const uint64_t* __restrict__ dtab = jb->dtab;
   uint64_t best8 = kKeyNone, bestB = kKeyNone;
@@ -164,15 +175,26 @@ __device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) s64[j][k] = 0;
     uint32_t vk8 = 0xFFFFFFFFu, vkB = 0xFFFFFFFFu;
+    // Region 0 of the current CTU into the ring; later regions are fetched one
+    // region ahead (global load now, LDS write after the region's compute).
+    ring[lane] = cur[lane];
+    uint32_t pre = cur[64 + lane];
 
     for (int reg = 0; reg < 16; ++reg) {
+      const uint32_t* rcur = ring + (reg & 1) * 64;
 #pragma unroll
       for (int sub = 0; sub < 4; ++sub) {
         const int bz = reg * 4 + sub;
         const int bx = zx(bz), by = zy(bz);
         uint32_t cw[16];
+        {
+          const uint4* cp = (const uint4*)(rcur + sub * 16);  // same address in every lane
 #pragma unroll
-        for (int i = 0; i < 16; ++i) cw[i] = cur[bz * 16 + i];
+          for (int i = 0; i < 4; ++i) {
+            const uint4 t = cp[i];
+            cw[4 * i] = t.x, cw[4 * i + 1] = t.y, cw[4 * i + 2] = t.z, cw[4 * i + 3] = t.w;
+          }
+        }
         uint32_t acc[D][4];
 #pragma unroll
         for (int j = 0; j < D; ++j)
@@ -201,7 +223,9 @@ __device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win) {
             }
           }
         }
-        if (elig[21 + by * 8 + bx]) {
+        const int n8 = 21 + by * 8 + bx;  // 21..84
+        const uint32_t ew = n8 < 32 ? em0 : (n8 < 64 ? em1 : em2);
+        if ((ew >> (n8 & 31)) & 1u) {
           uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
           for (int j = 0; j < D; ++j)
@@ -215,9 +239,14 @@ __device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) s16[j][k] = sub == 0 ? acc[j][k] : s16[j][k] + acc[j][k];
       }
-      {  // 16x16 CU of this region
+      // Next-but-one region into the slot this region used.
+      if (reg < 15) {
+        ring[((reg + 1) & 1) * 64 + lane] = pre;
+        if (reg < 14) pre = cur[(reg + 2) * 64 + lane];
+      }
+      {  // 16x16 CU of this region (nodes 5..20)
         const int lx = zx(reg), ly = zy(reg);
-        if (elig[5 + ly * 4 + lx]) {
+        if ((em0 >> (5 + ly * 4 + lx)) & 1u) {
           uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
           for (int j = 0; j < D; ++j)
@@ -237,9 +266,9 @@ __device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) s32[j][k] += s16[j][k];
       }
-      if ((reg & 3) == 3) {  // 32x32 CU
+      if ((reg & 3) == 3) {  // 32x32 CU (nodes 1..4)
         const int qz = reg >> 2, lx = qz & 1, ly = qz >> 1;
-        if (elig[1 + ly * 2 + lx]) {
+        if ((em0 >> (1 + ly * 2 + lx)) & 1u) {
           uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
           for (int j = 0; j < D; ++j)
@@ -254,7 +283,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win) {
           for (int k = 0; k < 4; ++k) s64[j][k] += s32[j][k];
       }
     }
-    if (elig[0]) {  // 64x64 CU
+    if (em0 & 1u) {  // 64x64 CU (node 0)
       uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
       for (int j = 0; j < D; ++j)
@@ -618,7 +647,8 @@ __global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_j
 // LDS and shared by its wavefronts.  items == null: one job, items implicit.
 template <int D>
 __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const uint2* items_,
-                                                  int n_items, uint32_t* counter, uint32_t* win) {
+                                                  int n_items, uint32_t* counter, uint32_t* win,
+                                                  int win_dwords_max) {
   __shared__ int s_item;
   const cjob jobs = (cjob)jobs_;
   const sptr32 items = (sptr32)items_;
@@ -641,10 +671,13 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
     }
     const cjob jb = jobs + job;
     const int g0 = jb->band_g0[band], g1 = jb->band_g0[band + 1];
-    stage_window(jb, col0 * kCtu - jb->R, row * kCtu - jb->R + g0 * D, (g1 - g0) * D + 63, win);
+    const int rows = (g1 - g0) * D + 63;
+    stage_window(jb, col0 * kCtu - jb->R, row * kCtu - jb->R + g0 * D, rows, win);
     __syncthreads();
     const int col = col0 + wave;
-    if (col < jb->ctus_w) search_wave<D>(jb, row * jb->ctus_w + col, band, win + 16 * wave);
+    // This wavefront's current-CTU ring follows the largest window of the launch.
+    uint32_t* ring = win + win_dwords_max + wave * (kCurRingBytes / 4);
+    if (col < jb->ctus_w) search_wave<D>(jb, row * jb->ctus_w + col, band, win + 16 * wave, ring);
     __syncthreads();  // the window is restaged for the next item
   }
 }
@@ -653,15 +686,16 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
 // larger register file at one or two.
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void search_kernel(
-    const JobDesc* jobs_, const uint2* items_, int n_items, uint32_t* counter) {
+    const JobDesc* jobs_, const uint2* items_, int n_items, uint32_t* counter, int win_dwords_max) {
   extern __shared__ uint32_t win[];
-  search_persistent<D>(jobs_, items_, n_items, counter, win);
+  search_persistent<D>(jobs_, items_, n_items, counter, win, win_dwords_max);
 }
 
 __global__ __launch_bounds__(256) void search_kernel_d8(const JobDesc* jobs_, const uint2* items_,
-                                                        int n_items, uint32_t* counter) {
+                                                        int n_items, uint32_t* counter,
+                                                        int win_dwords_max) {
   extern __shared__ uint32_t win[];
-  search_persistent<8>(jobs_, items_, n_items, counter, win);
+  search_persistent<8>(jobs_, items_, n_items, counter, win, win_dwords_max);
 }
 
 __global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus) {
@@ -710,10 +744,12 @@ int search_occupancy(int D, int strip, size_t lds_bytes) {
 hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, int D, int strip,
                          int n_wg, size_t lds_bytes, uint32_t* counter, hipStream_t st) {
   const dim3 grid(n_wg), block(64 * strip);
+  // LDS: window (lds_bytes minus the rings) then one ring per wavefront.
+  const int win_dwords_max = (int)((lds_bytes - (size_t)kCurRingBytes * strip) / 4);
   switch (D) {
-    case 2: hipLaunchKernelGGL(search_kernel<2>, grid, block, lds_bytes, st, jobs, items, n_items, counter); break;
-    case 4: hipLaunchKernelGGL(search_kernel<4>, grid, block, lds_bytes, st, jobs, items, n_items, counter); break;
-    case 8: hipLaunchKernelGGL(search_kernel_d8, grid, block, lds_bytes, st, jobs, items, n_items, counter); break;
+    case 2: hipLaunchKernelGGL(search_kernel<2>, grid, block, lds_bytes, st, jobs, items, n_items, counter, win_dwords_max); break;
+    case 4: hipLaunchKernelGGL(search_kernel<4>, grid, block, lds_bytes, st, jobs, items, n_items, counter, win_dwords_max); break;
+    case 8: hipLaunchKernelGGL(search_kernel_d8, grid, block, lds_bytes, st, jobs, items, n_items, counter, win_dwords_max); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -67,7 +67,7 @@ SearchLayout make_layout(int R, int D, int nbands) {
 }
 
 size_t window_bytes(const SearchLayout& L, int strip) {
-  return (size_t)L.win_rows_max * (L.Q + 16 * strip) * 4;
+  return (size_t)L.win_rows_max * (L.Q + 16 * strip) * 4 + (size_t)kCurRingBytes * strip;
 }
 
 int choose_bands(int R, int D, int strip, int ctus_w, int ctus_h, size_t lds_budget,
@@ -81,8 +81,9 @@ int choose_bands(int R, int D, int strip, int ctus_w, int ctus_h, size_t lds_bud
   return nb;
 }
 
-// LDS budget per search workgroup: three workgroups per CU.
-static constexpr size_t kLdsBudget = 53 * 1024;
+// LDS budget per search workgroup: three workgroups per CU (the window plus
+// a 512-byte current-CTU ring per wavefront).
+static constexpr size_t kLdsBudget = 51 * 1024;
 
 // ----------------------------------------------------------------------- tables
 namespace {
@@ -320,7 +321,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     const int n_ctus = jb.ctus_w * jb.ctus_h;
     P->job_off[j] = P->scratch_bytes;
     P->scratch_bytes += up256((size_t)n_ctus * 4096) + up256((size_t)n_ctus * kNodes * 8) +
-                        up256((size_t)n_ctus * kNodes);
+                        up256((size_t)n_ctus * kNodes) + up256((size_t)n_ctus * 16);
     P->n_ctus += n_ctus;
     P->lds_bytes = std::max(P->lds_bytes, window_bytes(L, P->strip));
     const int spr = (jb.ctus_w + P->strip - 1) / P->strip;
@@ -361,6 +362,8 @@ void bind_scratch(Plan& P, uint8_t* base) {
     jb.keys = (uint64_t*)sp;
     sp += up256((size_t)n_ctus * kNodes * 8);
     jb.elig = sp;
+    sp += up256((size_t)n_ctus * kNodes);
+    jb.eligbits = (uint32_t*)sp;
   }
 }
 

@@ -113,7 +113,7 @@ extern "C" int mr_autotune(const mr_search_job* jobs, int32_t n_jobs, int32_t re
     rc = measure(TileConfig{bestD, nb, 0}, &ms);
     if (rc == MR_OK && ms < best_ms) best_ms = ms, best = TileConfig{bestD, nb, 0};
   }
-  for (int sw : {1, 2, 4}) {
+  for (int sw : {1, 2, 3, 4}) {
     if (rc != MR_OK || !best.D) break;
     double ms;
     TileConfig tc = best;
