@@ -205,3 +205,44 @@ def test_2160p_r128_sampled(mr):
     ctus = [0, 59, 1000, 2039]
     _compare(got, oracle.ctu_search(cur, ref, 22, 128, ctu_list=ctus), 3840, 2160, ctus=ctus,
              label="2160p R128")
+
+
+def test_padded_stride_and_unaligned_pointer(mr):
+    """Frames inside larger buffers: stride > width and a base address not 4-byte aligned
+    (the window staging falls back to byte loads); results equal the packed frames'."""
+    import torch
+    W, H = 150, 94
+    ref, cur = _pair(41, W, H, 5, 9, 2)
+    exp = oracle.ctu_search(cur, ref, 31, 11)
+    for stride, off in ((W + 10, 0), (W + 3, 1), (W + 64, 3)):
+        bufc = torch.zeros(H * stride + 64, dtype=torch.uint8)
+        bufr = torch.zeros(H * stride + 64, dtype=torch.uint8)
+        vc = bufc[off:off + H * stride].view(H, stride)
+        vr = bufr[off:off + H * stride].view(H, stride)
+        vc[:, :W] = torch.from_numpy(cur)
+        vr[:, :W] = torch.from_numpy(ref)
+        gc, gr = bufc.cuda(), bufr.cuda()
+        fc = gc[off:off + H * stride].view(H, stride)[:, :W]
+        fr = gr[off:off + H * stride].view(H, stride)[:, :W]
+        o = mr.alloc_outputs(W, H)
+        prm = mr.mr_search_params(31, 11)
+        outs = mr.mr_search_out(*[mr._dev_ptr(o[k], t, k) for k, t in
+                                  (("depth", torch.uint8), ("mode", torch.uint8),
+                                   ("mv", torch.int16), ("cost", torch.int64),
+                                   ("dist", torch.int64), ("bits", torch.int64))])
+        import ctypes
+        f1 = mr.mr_frame(ctypes.c_void_p(fc.data_ptr()), W, H, stride)
+        f2 = mr.mr_frame(ctypes.c_void_p(fr.data_ptr()), W, H, stride)
+        rc = mr.lib().mr_ctu_search(ctypes.byref(f1), ctypes.byref(f2), ctypes.byref(prm), None,
+                                    ctypes.byref(outs), None)
+        assert rc == 0
+        torch.cuda.synchronize()
+        _compare({k: v.cpu().numpy() for k, v in o.items()}, exp, W, H,
+                 label=f"stride {stride} offset {off}")
+
+
+def test_maximum_width(mr):
+    """8192-wide picture (the ABI maximum), 72 rows, R 4: full parity."""
+    W, H = 8192, 72
+    ref, cur = _pair(43, W, H, 10, 4, 1)
+    _compare(_gpu(mr, cur, ref, 34, 4), oracle.ctu_search(cur, ref, 34, 4), W, H, label="8192 wide")
