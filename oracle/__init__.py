@@ -56,9 +56,11 @@ def lib():
         L.orc_intra_predict.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, vp]
         L.orc_cu_motion_search.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, vp,
                                            vp, vp]
-        L.orc_ctu_nodes.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp]
-        L.orc_ctu_search.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp,
-                                     vp, vp, i32, i32]
+        L.orc_ctu_nodes.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, i32, i32,
+                                    i32, vp]
+        L.orc_ctu_search.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, i32, i32, i32, vp,
+                                     vp, vp, vp, vp, vp, vp, i32, i32]
+        L.orc_mv_centre.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, vp, vp]
         L.orc_depth_bounds.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp]
         _lib = L
     return _lib
@@ -101,20 +103,49 @@ def cu_motion_search(cur, ref, x0, y0, n, R, qp):
     return mx.value, my.value, sad.value
 
 
-def ctu_nodes(cur, ref, qp, R, ctu_x, ctu_y) -> np.ndarray:
+class Seed:
+    """Reference MVs for a seeded search: the [ceil(ref_h/8), ceil(ref_w/8), 2] int16 MV map of
+    a ref_w x ref_h search of the same content, and the refinement half-width r."""
+
+    def __init__(self, ref_mv, ref_w: int, ref_h: int, r: int):
+        self.ref_mv = np.ascontiguousarray(ref_mv, dtype=np.int16)
+        assert self.ref_mv.shape == ((ref_h + 7) // 8, (ref_w + 7) // 8, 2)
+        self.ref_w, self.ref_h, self.r = int(ref_w), int(ref_h), int(r)
+
+    def args(self):
+        return (_p(self.ref_mv), self.ref_w, self.ref_h, self.r)
+
+
+_NO_SEED = (None, 0, 0, 0)
+
+
+def mv_centre(seed: Seed, cur_w, cur_h, R, x0, y0, n):
+    """Search centre (cx, cy) of the n x n CU at (x0, y0) for a seeded search."""
+    cx, cy = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().orc_mv_centre(*seed.args()[:3], cur_w, cur_h, R, seed.r, x0, y0, n,
+                             ctypes.byref(cx), ctypes.byref(cy))
+    if rc != 0:
+        raise ValueError("orc_mv_centre: invalid arguments")
+    return cx.value, cy.value
+
+
+def ctu_nodes(cur, ref, qp, R, ctu_x, ctu_y, seed: Seed | None = None) -> np.ndarray:
     """(85, 11) int64 per-node leaf evaluation of one CTU (fields: NODE_FIELDS)."""
     c = np.ascontiguousarray(cur, dtype=np.uint8)
     r = np.ascontiguousarray(ref, dtype=np.uint8)
     rec = np.zeros((85, len(NODE_FIELDS)), dtype=np.int64)
+    sa = seed.args() if seed is not None else _NO_SEED
     rc = lib().orc_ctu_nodes(_p(c), _p(r), c.shape[1], c.shape[0], c.shape[1], qp, R, ctu_x,
-                             ctu_y, _p(rec))
+                             ctu_y, *sa, _p(rec))
     if rc != 0:
         raise ValueError("orc_ctu_nodes: invalid arguments")
     return rec
 
 
-def ctu_search(cur, ref, qp, R, bounds=None, ctu_list=None, n_threads=0):
-    """Coding-tree search of a frame pair (all CTUs or a listed subset).
+def ctu_search(cur, ref, qp, R, bounds=None, ctu_list=None, n_threads=0,
+               seed: Seed | None = None):
+    """Coding-tree search of a frame pair (all CTUs or a listed subset); seeded when ``seed``
+    is given.
 
     Returns a dict of numpy arrays: depth, mode ([H8/8, W8/8] u8), mv ([H8/8, W8/8, 2] i16),
     cost, dist, bits ([ceil(H/64), ceil(W/64)] i64).  Units of CTUs outside the list keep 0.
@@ -135,7 +166,8 @@ def ctu_search(cur, ref, qp, R, bounds=None, ctu_list=None, n_threads=0):
     lst = None
     if ctu_list is not None:
         lst = np.ascontiguousarray(np.asarray(ctu_list, dtype=np.int32))
-    rc = lib().orc_ctu_search(_p(c), _p(r), W, H, W, qp, R, _p(b), _p(out["depth"]),
+    sa = seed.args() if seed is not None else _NO_SEED
+    rc = lib().orc_ctu_search(_p(c), _p(r), W, H, W, qp, R, _p(b), *sa, _p(out["depth"]),
                               _p(out["mode"]), _p(out["mv"]), _p(out["cost"]), _p(out["dist"]),
                               _p(out["bits"]), _p(lst), 0 if lst is None else len(lst),
                               n_threads)

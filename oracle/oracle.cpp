@@ -36,6 +36,16 @@
  *     scale-factor option in the analysis-share appendix; refine-intra level 1
  *     "depth n and n+1" in the analysis-refinement appendix).
  *
+ *   - Seeded search (motion-vector reuse with refinement, the x265 refine-mv
+ *     option of the analysis-refinement appendix; the reuse of reference MVs
+ *     at scaled resolutions in the related-work section).  READING (the
+ *     thesis's MV-refinement table is empty): every CU takes the MV of the
+ *     reference unit co-located with its centre, scales it by the width and
+ *     height ratios (rounded half away from zero), clamps it to
+ *     [-(R - r), R - r] and searches the (2r+1)^2 displacements around it
+ *     with the same cost and tie order as the full search.  r = R is the
+ *     full search.
+ *
  * No blocking, fusion or reordering: SAD is summed directly per CU and per
  * candidate; the DP is a plain recursion.
  */
@@ -194,13 +204,15 @@ struct Node {
   int evaluated;
 };
 
-// Integer full-search ME for one CU: exhaustive over dy = -R..R (outer),
-// dx = -R..R (inner); J = SAD * 65536 + s * (se(4dx) + se(4dy)); first strict minimum.
-void cu_motion_search(const Pic& cur, const Pic& ref, int x0, int y0, int n, int R, int64_t s,
-                      int* bmx, int* bmy, int64_t* bsad) {
+// Integer ME for one CU over the square window of half-width R around
+// (wx, wy): exhaustive over dy = wy-R..wy+R (outer), dx = wx-R..wx+R (inner);
+// J = SAD * 65536 + s * (se(4dx) + se(4dy)); first strict minimum.  The full
+// search is the window centred at (0, 0).
+void cu_motion_search(const Pic& cur, const Pic& ref, int x0, int y0, int n, int wx, int wy,
+                      int R, int64_t s, int* bmx, int* bmy, int64_t* bsad) {
   int64_t best = INT64_MAX;
-  for (int dy = -R; dy <= R; ++dy)
-    for (int dx = -R; dx <= R; ++dx) {
+  for (int dy = wy - R; dy <= wy + R; ++dy)
+    for (int dx = wx - R; dx <= wx + R; ++dx) {
       int64_t sad = 0;
       for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i)
@@ -210,9 +222,47 @@ void cu_motion_search(const Pic& cur, const Pic& ref, int x0, int y0, int n, int
     }
 }
 
+// Reference MVs for a seeded search: the per-8x8 MV map of a search of the
+// same content at another resolution (ref_w x ref_h), and the refinement
+// half-width r.
+struct Seed {
+  const int16_t* ref_mv;  // [ceil(ref_h/8)][ceil(ref_w/8)][2]
+  int ref_w, ref_h;
+  int r;
+};
+
+// m * num / den rounded to the nearest integer, halves away from zero.
+int scale_round(int m, int num, int den) {
+  int64_t a = std::abs((int64_t)m) * num;
+  int64_t q = (2 * a + den) / (2 * (int64_t)den);
+  return (int)(m < 0 ? -q : q);
+}
+
+// Search centre of the n x n CU at (x0, y0) of a cur_w x cur_h picture: the
+// reference unit co-located with the CU's centre sample (same mapping as the
+// depth bounds), its MV scaled by the dimension ratios, clamped so that the
+// window of half-width r stays inside [-R, R].
+void mv_centre(const Seed& sd, int cur_w, int cur_h, int R, int x0, int y0, int n, int* cx,
+               int* cy) {
+  int64_t px = x0 + n / 2, py = y0 + n / 2;
+  int64_t xr = std::min<int64_t>(px * sd.ref_w / cur_w, sd.ref_w - 1);
+  int64_t yr = std::min<int64_t>(py * sd.ref_h / cur_h, sd.ref_h - 1);
+  int ruw = (sd.ref_w + 7) / 8;
+  const int16_t* m = sd.ref_mv + 2 * ((yr / 8) * ruw + xr / 8);
+  int lim = R - sd.r;
+  *cx = std::clamp(scale_round(m[0], cur_w, sd.ref_w), -lim, lim);
+  *cy = std::clamp(scale_round(m[1], cur_h, sd.ref_h), -lim, lim);
+}
+
 void evaluate_leaf(const Pic& cur, const Pic& ref, int x0, int y0, int n, int R, int64_t s,
-                   Node* nd) {
-  cu_motion_search(cur, ref, x0, y0, n, R, s, &nd->mx, &nd->my, &nd->sad);
+                   const Seed* seed, Node* nd) {
+  if (seed) {
+    int cx, cy;
+    mv_centre(*seed, cur.w, cur.h, R, x0, y0, n, &cx, &cy);
+    cu_motion_search(cur, ref, x0, y0, n, cx, cy, seed->r, s, &nd->mx, &nd->my, &nd->sad);
+  } else {
+    cu_motion_search(cur, ref, x0, y0, n, 0, 0, R, s, &nd->mx, &nd->my, &nd->sad);
+  }
   std::vector<int> resid(n * n), pred(n * n);
   for (int j = 0; j < n; ++j)
     for (int i = 0; i < n; ++i)
@@ -247,6 +297,7 @@ struct CtuJob {
   int R;
   int64_t s;
   const uint8_t* bounds;  // [h8/8][w8/8][2] or null
+  const Seed* seed;       // null for the full search
   int cx, cy;             // CTU origin in pixels
   Node nodes[85];
 };
@@ -304,7 +355,7 @@ Result best_tree(CtuJob& job, int d, int lx, int ly, bool* choose_leaf) {
   }
   Result leaf{INT64_MAX, 0, 0};
   if (leaf_ok) {
-    if (!nd.evaluated) evaluate_leaf(*job.cur, *job.ref, x0, y0, n, job.R, job.s, &nd);
+    if (!nd.evaluated) evaluate_leaf(*job.cur, *job.ref, x0, y0, n, job.R, job.s, job.seed, &nd);
     int flag = d < 3 ? 1 : 0;
     leaf = Result{nd.leaf_j + job.s * flag, nd.leaf_d, nd.leaf_r + flag};
   }
@@ -382,8 +433,30 @@ int orc_cu_motion_search(const uint8_t* cur, const uint8_t* ref, int w, int h, i
   Pic c = make_pic(cur, w, h, stride), r = make_pic(ref, w, h, stride);
   int a, b;
   int64_t sd;
-  cu_motion_search(c, r, x0, y0, n, R, sqrt_lambda_q16(qp), &a, &b, &sd);
+  cu_motion_search(c, r, x0, y0, n, 0, 0, R, sqrt_lambda_q16(qp), &a, &b, &sd);
   *mx = a, *my = b, *sad = sd;
+  return 0;
+}
+
+// Seed arguments shared by the entry points below: ref_mv null means full
+// search; otherwise the reference MV map of a ref_w x ref_h picture and the
+// refinement half-width r (0 <= r <= R).
+static bool make_seed(const int16_t* ref_mv, int ref_w, int ref_h, int r, int R, Seed* sd) {
+  if (!ref_mv) return true;
+  if (ref_w <= 0 || ref_h <= 0 || r < 0 || r > R) return false;
+  *sd = Seed{ref_mv, ref_w, ref_h, r};
+  return true;
+}
+
+// Search centre of one CU for a seeded search (see mv_centre).
+int orc_mv_centre(const int16_t* ref_mv, int ref_w, int ref_h, int cur_w, int cur_h, int R,
+                  int r, int x0, int y0, int n, int32_t* cx, int32_t* cy) {
+  Seed sd{};
+  if (!ref_mv || cur_w <= 0 || cur_h <= 0 || !make_seed(ref_mv, ref_w, ref_h, r, R, &sd))
+    return -1;
+  int a, b;
+  mv_centre(sd, cur_w, cur_h, R, x0, y0, n, &a, &b);
+  *cx = a, *cy = b;
   return 0;
 }
 
@@ -391,11 +464,16 @@ int orc_cu_motion_search(const uint8_t* cur, const uint8_t* ref, int w, int h, i
 // per node: kind, mode, mx, my, sad, satd_inter, satd_planar, satd_dc, leaf_j,
 // leaf_d, leaf_r (11 int64).  Used to check the decision against enumeration.
 int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int qp,
-                  int R, int ctu_x, int ctu_y, int64_t* rec) {
-  if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || qp < 0 || qp > 51) return -1;
+                  int R, int ctu_x, int ctu_y, const int16_t* ref_mv, int ref_w, int ref_h,
+                  int refine_r, int64_t* rec) {
+  Seed sd{};
+  if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || qp < 0 || qp > 51 ||
+      !make_seed(ref_mv, ref_w, ref_h, refine_r, R, &sd))
+    return -1;
   Pic c = make_pic(cur, w, h, stride), r = make_pic(ref, w, h, stride);
   CtuJob* job = new CtuJob();
   job->cur = &c, job->ref = &r, job->R = R, job->s = sqrt_lambda_q16(qp), job->bounds = nullptr;
+  job->seed = ref_mv ? &sd : nullptr;
   job->cx = ctu_x * kCtu, job->cy = ctu_y * kCtu;
   for (int d = 0; d < 4; ++d)
     for (int ly = 0; ly < (1 << d); ++ly)
@@ -407,7 +485,7 @@ int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stri
         else if (x0 + n > c.w8 || y0 + n > c.h8) nd.kind = 1;
         else {
           nd.kind = 2;
-          evaluate_leaf(c, r, x0, y0, n, R, job->s, &nd);
+          evaluate_leaf(c, r, x0, y0, n, R, job->s, job->seed, &nd);
         }
         int64_t* o = rec + 11 * node_index(d, lx, ly);
         o[0] = nd.kind, o[1] = nd.mode, o[2] = nd.mx, o[3] = nd.my, o[4] = nd.sad;
@@ -423,13 +501,18 @@ int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stri
 //   depth, mode: [h8/8][w8/8] u8; mv: [h8/8][w8/8][2] i16;
 //   ctu_cost/dist/bits: [ceil(h/64)][ceil(w/64)] i64.
 // bounds: null for full search, else [h8/8][w8/8][2] {lo, hi}.
+// ref_mv: null for full search, else a seeded search (see make_seed).
 int orc_ctu_search(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int qp,
-                   int R, const uint8_t* bounds, uint8_t* depth, uint8_t* mode, int16_t* mv,
+                   int R, const uint8_t* bounds, const int16_t* ref_mv, int ref_w, int ref_h,
+                   int refine_r, uint8_t* depth, uint8_t* mode, int16_t* mv,
                    int64_t* ctu_cost, int64_t* ctu_dist, int64_t* ctu_bits,
                    const int32_t* ctu_list, int n_list, int n_threads) {
+  Seed sd{};
   if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || R > 128 || qp < 0 || qp > 51 ||
-      !depth || !mode || !mv || !ctu_cost || !ctu_dist || !ctu_bits)
+      !depth || !mode || !mv || !ctu_cost || !ctu_dist || !ctu_bits ||
+      !make_seed(ref_mv, ref_w, ref_h, refine_r, R, &sd))
     return -1;
+  const Seed* seed = ref_mv ? &sd : nullptr;
   Pic c = make_pic(cur, w, h, stride), r = make_pic(ref, w, h, stride);
   int ctw = (c.w8 + kCtu - 1) / kCtu, cth = (c.h8 + kCtu - 1) / kCtu;
   std::vector<int> list;
@@ -451,6 +534,7 @@ int orc_ctu_search(const uint8_t* cur, const uint8_t* ref, int w, int h, int str
       int t = list[k];
       *job = CtuJob{};
       job->cur = &c, job->ref = &r, job->R = R, job->s = s, job->bounds = bounds;
+      job->seed = seed;
       job->cx = (t % ctw) * kCtu, job->cy = (t / ctw) * kCtu;
       bool leaf;
       Result root = best_tree(*job, 0, 0, 0, &leaf);
