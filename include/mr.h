@@ -102,18 +102,53 @@ typedef struct {
 int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
                   const uint8_t* bounds, mr_search_out* out, void* hip_stream);
 
-/* One frame pair of a batch (same meaning as the mr_ctu_search arguments). */
+/* Reference motion vectors for a seeded search (motion-vector reuse with
+ * refinement: the x265 refine-mv option of the analysis-refinement appendix,
+ * and the reuse of a reference representation's motion vectors at scaled
+ * resolutions in the related-work section).
+ *   ref_mv: device [ceil(ref_h/8)][ceil(ref_w/8)][2] i16, the mv output of a
+ *     search of the same content at ref_w x ref_h (1..8192 each);
+ *   refine_range: r, 0 <= r <= search_range.
+ * Every CU (n x n at (x0, y0) of a W x H picture) takes the MV (mx, my) of
+ * the reference unit co-located with its centre sample:
+ *   xr = min(((x0 + n/2) * ref_w) / W, ref_w - 1), yr likewise with heights;
+ * scales it to cx = mx * W / ref_w, cy = my * H / ref_h rounded to nearest
+ * with halves away from zero, clamps both to [-(R - r), R - r], and searches
+ * dx in [cx - r, cx + r], dy in [cy - r, cy + r] with the full search's ME
+ * cost and tie order (first minimum in raster order).  MV bits keep the
+ * (0, 0) predictor.  r = R is the full search.  The thesis leaves the
+ * refinement table empty; this is the library's definition. */
+typedef struct {
+  const int16_t* ref_mv;
+  int32_t ref_w, ref_h;
+  int32_t refine_range;
+} mr_mv_seed;
+
+/* mr_ctu_search with a seed: NULL seed = mr_ctu_search.  The seed's map is
+ * read on the device during the call (stream-ordered).  Scratch includes an
+ * edge-padded copy of the reference, (H8 + 2R) x (W8 + 2P) bytes with
+ * P = R + 24 rounded up to a multiple of 4.
+ * Errors: MR_EINVAL (as mr_ctu_search, plus a null ref_mv, seed sizes or
+ * r outside [0, R]), MR_ENOMEM, MR_EHIP. */
+int mr_ctu_search_seeded(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
+                         const uint8_t* bounds, const mr_mv_seed* seed, mr_search_out* out,
+                         void* hip_stream);
+
+/* One frame pair of a batch (same meaning as the mr_ctu_search_seeded
+ * arguments; seed points to host memory and NULL means full search). */
 typedef struct {
   mr_frame cur, ref;
   mr_search_params params;
   const uint8_t* bounds; /* device [U][V][2] or NULL */
   mr_search_out out;
+  const mr_mv_seed* seed; /* host pointer or NULL */
 } mr_search_job;
 
 /* Batched coding-tree search: the CTUs of all jobs (frames of any sizes,
  * ranges and QPs) go through one persistent work-queue search launch fed by a
  * flattened item list ordered longest-first, between one prep and one leaf
- * launch over the flattened CTUs.  Results are identical to calling
+ * launch over the flattened CTUs; seeded jobs go through one refinement
+ * launch over their CTUs instead of the full search.  Results are identical to calling
  * mr_ctu_search per job.  Host-blocking while it uploads the job list, then
  * asynchronous on hip_stream.  Errors: MR_EINVAL (n_jobs < 1 or any job
  * invalid; nothing is launched), MR_ENOMEM, MR_EHIP. */
@@ -124,9 +159,10 @@ int mr_ctu_search_batch(const mr_search_job* jobs, int32_t n_jobs, void* hip_str
  * mr_batch_launch replays.  Caller-owned frames, bounds and outputs must stay
  * valid while launches that use them are in flight.
  *   mr_batch_create : plan + allocate + capture (host-blocking).
- *   mr_batch_set_jobs: swap in new frame / bounds / output pointers for jobs
- *     of the same count, sizes, QPs, ranges and bounds presence (else
- *     MR_EINVAL); waits for this batch's previous launch to finish.
+ *   mr_batch_set_jobs: swap in new frame / bounds / seed / output pointers
+ *     for jobs of the same count, sizes, QPs, ranges, bounds presence and
+ *     seed presence (else MR_EINVAL); waits for this batch's previous launch
+ *     to finish.
  *   mr_batch_launch : replay on hip_stream (with stage profiling enabled, the
  *     three kernels are launched directly between timing events instead).
  *   mr_batch_destroy: waits for the last launch, frees everything (NULL ok).
@@ -155,8 +191,9 @@ int mr_batch_destroy(mr_batch* b);
  * run, batches up to max_batch_jobs of them into one persistent search launch,
  * keeps up to two batches in flight, and releases dependents as references
  * complete (continuous batching).  Done reference jobs stay resident for later
- * dependents until their memory is needed.  Results equal mr_ctu_search on
- * the same frames (with the same bounds). */
+ * dependents until their memory is needed.  With reuse_mv, a dependent's
+ * search is also seeded with its reference job's MV map.  Results equal
+ * mr_ctu_search_seeded on the same frames (with the same bounds and seed). */
 typedef struct {
   int32_t width, height, qp, search_range;
   int32_t ref_rung; /* index of the rung whose depths bound this one, -1 = none */
@@ -170,6 +207,11 @@ typedef struct {
   int32_t max_inflight;        /* 1..65536 admitted, unfinished jobs */
   int32_t max_queue;           /* 1..1<<20 submitted, unfinished jobs (else MR_EAGAIN) */
   int32_t max_batch_jobs;      /* 1..4096 jobs per device launch */
+  int32_t reuse_mv;            /* 0: dependents run the (bounded) full search;
+                                  1: dependents are also seeded (mr_mv_seed) with
+                                  their reference job's MVs */
+  int32_t refine_range;        /* r of seeded dependents, 0..128 (capped at each
+                                  rung's search_range); ignored when reuse_mv = 0 */
 } mr_ladder_config;
 
 typedef struct {

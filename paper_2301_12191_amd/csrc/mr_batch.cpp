@@ -11,9 +11,10 @@ using namespace mr;
 struct mr_batch {
   int device = 0;
   Plan plan;
-  uint8_t* mem = nullptr;      // device: jobs | items | counter | scratch
+  uint8_t* mem = nullptr;      // device: jobs | items | rlist | counter | scratch
   JobDesc* jobs_d = nullptr;
   uint2* items_d = nullptr;
+  int* rlist_d = nullptr;
   uint32_t* counter_d = nullptr;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -31,45 +32,51 @@ struct Unpacked {
   std::vector<const mr_search_params*> p;
   std::vector<const uint8_t*> bounds;
   std::vector<const mr_search_out*> out;
+  std::vector<const mr_mv_seed*> seed;
 };
 
 int unpack(const mr_search_job* jobs, int n, Unpacked* u) {
   if (!jobs || n < 1) return MR_EINVAL;
   u->cur.resize(n), u->ref.resize(n), u->p.resize(n), u->bounds.resize(n), u->out.resize(n);
+  u->seed.resize(n);
   for (int j = 0; j < n; ++j) {
     u->cur[j] = &jobs[j].cur;
     u->ref[j] = &jobs[j].ref;
     u->p[j] = &jobs[j].params;
     u->bounds[j] = jobs[j].bounds;
     u->out[j] = &jobs[j].out;
+    u->seed[j] = jobs[j].seed;
   }
   return MR_OK;
 }
 
-// Device layout of a batch: job array, items, counter, then per-job scratch.
+// Device layout of a batch: job array, items, seeded-job list, counter, then
+// per-job scratch.
 struct Layout {
-  size_t jobs, items, counter, scratch, total;
+  size_t jobs, items, rlist, counter, scratch, total;
 };
 
 Layout layout_of(const Plan& P) {
   Layout L;
   L.jobs = 0;
   L.items = up256(sizeof(JobDesc) * P.n_jobs);
-  L.counter = L.items + up256(sizeof(uint2) * P.items.size());
+  L.rlist = L.items + up256(sizeof(uint2) * P.items.size());
+  L.counter = L.rlist + up256(sizeof(int) * P.rlist.size());
   L.scratch = L.counter + 256;
   L.total = L.scratch + P.scratch_bytes;
   return L;
 }
 
-hipError_t launch_all(const Plan& P, JobDesc* jobs_d, const uint2* items_d, uint32_t* counter,
-                      hipStream_t st, StageEvents* ev) {
-  hipError_t e = launch_prep(jobs_d, P.n_jobs, P.n_ctus, counter, st);
-  if (ev) profile_mark(ev, 1, st);
-  if (e == hipSuccess)
-    e = launch_search(jobs_d, items_d, P.n_items, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
-  if (ev) profile_mark(ev, 2, st);
-  if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, st);
-  if (ev) profile_mark(ev, 3, st);
+// Upload the job array, items and seeded-job list of a bound plan.
+hipError_t upload(const Plan& P, uint8_t* mem, const Layout& L, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(mem + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs,
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !P.items.empty())
+    e = hipMemcpyAsync(mem + L.items, P.items.data(), sizeof(uint2) * P.items.size(),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !P.rlist.empty())
+    e = hipMemcpyAsync(mem + L.rlist, P.rlist.data(), sizeof(int) * P.rlist.size(),
+                       hipMemcpyHostToDevice, st);
   return e;
 }
 
@@ -82,24 +89,21 @@ int mr_ctu_search_batch(const mr_search_job* jobs, int32_t n_jobs, void* hip_str
   int rc = unpack(jobs, n_jobs, &u);
   if (rc != MR_OK) return rc;
   Plan P;
-  rc = make_plan(u.cur.data(), u.ref.data(), u.p.data(), u.bounds.data(), u.out.data(), n_jobs,
-                 true, &P);
+  rc = make_plan(u.cur.data(), u.ref.data(), u.p.data(), u.bounds.data(), u.out.data(),
+                 u.seed.data(), n_jobs, true, &P);
   if (rc != MR_OK) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   const Layout L = layout_of(P);
   uint8_t* mem = nullptr;
   if (hipMallocAsync((void**)&mem, L.total, st) != hipSuccess) return MR_ENOMEM;
   bind_scratch(P, mem + L.scratch);
-  hipError_t e = hipMemcpyAsync(mem + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs,
-                                hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(mem + L.items, P.items.data(), sizeof(uint2) * P.items.size(),
-                       hipMemcpyHostToDevice, st);
+  hipError_t e = upload(P, mem, L, st);
   StageEvents ev{};
   const bool prof = e == hipSuccess && profile_on() && profile_begin(&ev, st) == MR_OK;
   if (e == hipSuccess)
-    e = launch_all(P, (JobDesc*)(mem + L.jobs), (const uint2*)(mem + L.items),
-                   (uint32_t*)(mem + L.counter), st, prof ? &ev : nullptr);
+    e = launch_plan(P, (JobDesc*)(mem + L.jobs), (const uint2*)(mem + L.items),
+                    (const int*)(mem + L.rlist), (uint32_t*)(mem + L.counter), st,
+                    prof ? &ev : nullptr);
   if (prof) profile_push(ev);
   const hipError_t ef = hipFreeAsync(mem, st);
   return (e == hipSuccess && ef == hipSuccess) ? MR_OK : MR_EHIP;
@@ -126,8 +130,8 @@ int mr_batch_create(const mr_search_job* jobs, int32_t n_jobs, mr_batch** out) {
   if (rc != MR_OK) return rc;
   mr_batch* b = new mr_batch();
   (void)hipGetDevice(&b->device);
-  rc = make_plan(u.cur.data(), u.ref.data(), u.p.data(), u.bounds.data(), u.out.data(), n_jobs,
-                 true, &b->plan);
+  rc = make_plan(u.cur.data(), u.ref.data(), u.p.data(), u.bounds.data(), u.out.data(),
+                 u.seed.data(), n_jobs, true, &b->plan);
   if (rc != MR_OK) {
     delete b;
     return rc;
@@ -139,23 +143,22 @@ int mr_batch_create(const mr_search_job* jobs, int32_t n_jobs, mr_batch** out) {
   }
   b->jobs_d = (JobDesc*)(b->mem + L.jobs);
   b->items_d = (uint2*)(b->mem + L.items);
+  b->rlist_d = (int*)(b->mem + L.rlist);
   b->counter_d = (uint32_t*)(b->mem + L.counter);
   bind_scratch(b->plan, b->mem + L.scratch);
-  if (hipMemcpy(b->jobs_d, b->plan.jobs.data(), sizeof(JobDesc) * n_jobs,
-                hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->items_d, b->plan.items.data(), sizeof(uint2) * b->plan.items.size(),
-                hipMemcpyHostToDevice) != hipSuccess ||
+  if (upload(b->plan, b->mem, L, nullptr) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess ||
       hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     mr_batch_destroy(b);
     return MR_EHIP;
   }
-  // Capture prep -> search -> leaf.  The work-queue head is reset by the prep
-  // kernel itself, so the graph holds kernel nodes only.
+  // Capture prep -> [pad] -> [search] -> [refine] -> leaf.  The work-queue head
+  // is reset by the prep kernel itself, so the graph holds kernel nodes only.
   hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const hipError_t el = launch_all(b->plan, b->jobs_d, b->items_d, b->counter_d, b->cap_stream,
-                                     nullptr);
+    const hipError_t el = launch_plan(b->plan, b->jobs_d, b->items_d, b->rlist_d, b->counter_d,
+                                      b->cap_stream, nullptr);
     e = hipStreamEndCapture(b->cap_stream, &b->graph);
     if (el != hipSuccess) e = el;
   }
@@ -173,10 +176,12 @@ int mr_batch_set_jobs(mr_batch* b, const mr_search_job* jobs, int32_t n_jobs) {
   for (int j = 0; j < n_jobs; ++j) {
     const JobDesc& jd = b->plan.jobs[j];
     const mr_search_job& q = jobs[j];
-    const int rc = validate_job(&q.cur, &q.ref, &q.params, &q.out);
+    int rc = validate_job(&q.cur, &q.ref, &q.params, &q.out);
+    if (rc == MR_OK) rc = validate_seed(q.seed, &q.params);
     if (rc != MR_OK) return rc;
     if (q.cur.width != jd.w || q.cur.height != jd.h || q.params.search_range != jd.R ||
-        sqrt_lambda_q16(q.params.qp) != jd.s || (q.bounds != nullptr) != (jd.bounds != nullptr))
+        sqrt_lambda_q16(q.params.qp) != jd.s || (q.bounds != nullptr) != (jd.bounds != nullptr) ||
+        (q.seed != nullptr) != (jd.seed_mv != nullptr))
       return MR_EINVAL;
   }
   if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return MR_EHIP;
@@ -193,6 +198,7 @@ int mr_batch_set_jobs(mr_batch* b, const mr_search_job* jobs, int32_t n_jobs) {
     jd.ctu_cost = q.out.ctu_cost;
     jd.ctu_dist = q.out.ctu_dist;
     jd.ctu_bits = q.out.ctu_bits;
+    set_job_seed(jd, q.seed);
   }
   if (hipMemcpy(b->jobs_d, b->plan.jobs.data(), sizeof(JobDesc) * n_jobs,
                 hipMemcpyHostToDevice) != hipSuccess)
@@ -207,7 +213,7 @@ int mr_batch_launch(mr_batch* b, void* hip_stream) {
   if (profile_on()) {
     StageEvents ev{};
     if (profile_begin(&ev, st) != MR_OK) return MR_EHIP;
-    e = launch_all(b->plan, b->jobs_d, b->items_d, b->counter_d, st, &ev);
+    e = launch_plan(b->plan, b->jobs_d, b->items_d, b->rlist_d, b->counter_d, st, &ev);
     profile_push(ev);
   } else {
     e = hipGraphLaunch(b->exec, st);

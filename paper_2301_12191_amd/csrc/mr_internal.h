@@ -13,6 +13,11 @@ constexpr uint32_t kCinv = 1050000u;  // cost field of candidates outside the wi
 constexpr uint64_t kKeyNone = ~0ull;
 constexpr int kMaxStrip = 4;        // CTUs (wavefronts) per search workgroup
 constexpr int kCurRingBytes = 512;  // per wavefront: two 16x16 regions of the current CTU
+constexpr int kRefineChunk = 16;    // seeded search: horizontal candidates per register pass
+
+// Column margin of the padded reference of a seeded job with range R: the
+// refinement loads reach 3 bytes left of -R and 20 bytes right of w8 - 8 + R.
+__host__ __device__ inline int refine_pad_x(int R) { return (R + 24 + 3) & ~3; }
 
 // Search work item of a batch: x = job, y = row << 16 | first CTU column << 4 | band.
 __host__ __device__ inline uint32_t pack_item_y(int row, int col0, int band) {
@@ -56,6 +61,14 @@ struct JobDesc {
   const uint8_t* bounds;   // [U][V][2] or null
   uint8_t* elig;           // [ctus][85] 1 = node may be a leaf (inside and allowed)
   uint32_t* eligbits;      // [ctus][4] the same as a bit mask (bit n of word n / 32)
+  // Seeded search (reference MV reuse with a refinement window); seed_mv null
+  // means full search.
+  const int16_t* seed_mv;  // [ceil(seed_h/8)][ceil(seed_w/8)][2] reference MVs
+  int32_t seed_w, seed_h;  // dimensions of the picture the MVs belong to
+  int32_t seed_r;          // refinement half-width r
+  int32_t rctu_start;      // first CTU of this job among the seeded jobs' CTUs
+  int32_t pad_x, pad_pitch;  // padded reference: columns [-pad_x, w8 + pad_x), row pitch
+  uint8_t* refpad;         // [h8 + 2R][pad_pitch] reference, coordinates clamped
   uint8_t* depth;          // outputs
   uint8_t* mode;
   int16_t* mv;

@@ -1,5 +1,6 @@
 // Ladder server (mr_ladder_*): the GPU executor of the serving scheduler and
 // its request-loop thread.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -39,7 +40,8 @@ struct BatchState {
 
 class GpuExecutor : public Executor {
  public:
-  GpuExecutor(const SchedConfig& cfg, int dlo, int dhi) : cfg_(cfg), dlo_(dlo), dhi_(dhi) {}
+  GpuExecutor(const SchedConfig& cfg, int dlo, int dhi, int refine_r)
+      : cfg_(cfg), dlo_(dlo), dhi_(dhi), refine_r_(refine_r) {}
 
   int init() {
     if (hipGetDevice(&device_) != hipSuccess) return MR_EHIP;
@@ -89,11 +91,20 @@ class GpuExecutor : public Executor {
     return o;
   }
 
+  // Refinement half-width of a rung's jobs, -1 for the full search.
+  int refine_of(const RungCfg& r) const {
+    return (refine_r_ >= 0 && r.ref_rung >= 0) ? std::min(refine_r_, r.search_range) : -1;
+  }
+
   size_t footprint(const SchedJob& j) override {
     const RungCfg& r = cfg_.rungs[j.rung];
     size_t off[7];
-    const size_t T = (((r.height + 7) / 8 * 8 + 63) / 64) * (((r.width + 7) / 8 * 8 + 63) / 64);
-    return out_bytes(r, r.ref_rung >= 0, off) + T * (4096 + 85 * 9) + 4096;
+    const size_t w8 = (r.width + 7) / 8 * 8, h8 = (r.height + 7) / 8 * 8;
+    const size_t T = ((h8 + 63) / 64) * ((w8 + 63) / 64);
+    size_t pad = 0;  // padded reference of a seeded search
+    if (refine_of(r) >= 0)
+      pad = (h8 + 2 * r.search_range) * (w8 + 2 * (size_t)refine_pad_x(r.search_range)) + 256;
+    return out_bytes(r, r.ref_rung >= 0, off) + T * (4096 + 85 * 9) + pad + 4096;
   }
 
   int launch(const std::vector<SchedJob*>& jobs, void** handle) override {
@@ -103,6 +114,8 @@ class GpuExecutor : public Executor {
     std::vector<mr_search_params> prm(n);
     std::vector<const uint8_t*> bnd(n, nullptr);
     std::vector<mr_search_out> outs(n);
+    std::vector<mr_mv_seed> seeds(n);
+    std::vector<const mr_mv_seed*> ps(n, nullptr);
     for (int i = 0; i < n; ++i) {
       SchedJob& j = *jobs[i];
       const RungCfg& r = cfg_.rungs[j.rung];
@@ -138,6 +151,11 @@ class GpuExecutor : public Executor {
                                 o->bounds, st) != hipSuccess)
           return MR_EHIP;
         bnd[i] = o->bounds;
+        const int rr_refine = refine_of(r);
+        if (rr_refine >= 0) {
+          seeds[i] = mr_mv_seed{ro->out.mv, rr.width, rr.height, rr_refine};
+          ps[i] = &seeds[i];
+        }
       }
       outs[i] = o->out;
     }
@@ -146,23 +164,27 @@ class GpuExecutor : public Executor {
     std::vector<const mr_search_out*> po(n);
     for (int i = 0; i < n; ++i) pc[i] = &cur[i], pr[i] = &ref[i], pp[i] = &prm[i], po[i] = &outs[i];
     Plan P;
-    int rc = make_plan(pc.data(), pr.data(), pp.data(), bnd.data(), po.data(), n, true, &P);
+    int rc = make_plan(pc.data(), pr.data(), pp.data(), bnd.data(), po.data(), ps.data(), n, true,
+                       &P);
     if (rc != MR_OK) return rc;
+    // Device: jobs | items | seeded-job list | counter | scratch.
     const size_t off_items = up256(sizeof(JobDesc) * n);
-    const size_t off_ctr = off_items + up256(sizeof(uint2) * P.items.size());
+    const size_t off_rlist = off_items + up256(sizeof(uint2) * P.items.size());
+    const size_t off_ctr = off_rlist + up256(sizeof(int) * P.rlist.size());
     const size_t off_scr = off_ctr + 256;
     uint8_t* mem = nullptr;
     if (hipMallocAsync((void**)&mem, off_scr + P.scratch_bytes, st) != hipSuccess) return MR_ENOMEM;
     bind_scratch(P, mem + off_scr);
     hipError_t e = hipMemcpyAsync(mem, P.jobs.data(), sizeof(JobDesc) * n, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !P.items.empty())
       e = hipMemcpyAsync(mem + off_items, P.items.data(), sizeof(uint2) * P.items.size(),
                          hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_prep((JobDesc*)mem, n, P.n_ctus, (uint32_t*)(mem + off_ctr), st);
+    if (e == hipSuccess && !P.rlist.empty())
+      e = hipMemcpyAsync(mem + off_rlist, P.rlist.data(), sizeof(int) * P.rlist.size(),
+                         hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-      e = launch_search((JobDesc*)mem, (const uint2*)(mem + off_items), P.n_items, P.D, P.strip,
-                        P.n_wg, P.lds_bytes, (uint32_t*)(mem + off_ctr), st);
-    if (e == hipSuccess) e = launch_leaf((JobDesc*)mem, n, P.n_ctus, st);
+      e = launch_plan(P, (JobDesc*)mem, (const uint2*)(mem + off_items),
+                      (const int*)(mem + off_rlist), (uint32_t*)(mem + off_ctr), st, nullptr);
     const hipError_t ef = hipFreeAsync(mem, st);
     BatchState* b = new BatchState();
     b->stream = st;
@@ -209,6 +231,7 @@ class GpuExecutor : public Executor {
  private:
   SchedConfig cfg_;
   int dlo_, dhi_;
+  int refine_r_;  // -1: dependents are not seeded
   int device_ = 0;
   hipStream_t streams_[2] = {nullptr, nullptr};
   unsigned next_ = 0;
@@ -261,7 +284,9 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
   if (!cfg || cfg->n_rungs < 1 || cfg->n_rungs > 8 || cfg->delta_lo < 0 || cfg->delta_lo > 3 ||
       cfg->delta_hi < 0 || cfg->delta_hi > 3 || cfg->hbm_budget_bytes == 0 ||
       cfg->max_inflight < 1 || cfg->max_inflight > 65536 || cfg->max_queue < 1 ||
-      cfg->max_queue > (1 << 20) || cfg->max_batch_jobs < 1 || cfg->max_batch_jobs > 4096)
+      cfg->max_queue > (1 << 20) || cfg->max_batch_jobs < 1 || cfg->max_batch_jobs > 4096 ||
+      cfg->reuse_mv < 0 || cfg->reuse_mv > 1 ||
+      (cfg->reuse_mv && (cfg->refine_range < 0 || cfg->refine_range > 128)))
     return MR_EINVAL;
   SchedConfig sc;
   for (int r = 0; r < cfg->n_rungs; ++r) {
@@ -284,7 +309,8 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
   sc.max_batch_jobs = cfg->max_batch_jobs;
   mr_ladder* l = new mr_ladder();
   l->cfg = sc;
-  l->ex.reset(new GpuExecutor(sc, cfg->delta_lo, cfg->delta_hi));
+  l->ex.reset(new GpuExecutor(sc, cfg->delta_lo, cfg->delta_hi,
+                              cfg->reuse_mv ? cfg->refine_range : -1));
   if (l->ex->init() != MR_OK) {
     delete l;
     return MR_EHIP;

@@ -213,6 +213,21 @@ int validate_job(const mr_frame* cur, const mr_frame* ref, const mr_search_param
   return MR_OK;
 }
 
+int validate_seed(const mr_mv_seed* seed, const mr_search_params* p) {
+  if (!seed) return MR_OK;
+  if (!seed->ref_mv || seed->ref_w < 1 || seed->ref_h < 1 || seed->ref_w > 8192 ||
+      seed->ref_h > 8192 || seed->refine_range < 0 || seed->refine_range > p->search_range)
+    return MR_EINVAL;
+  return MR_OK;
+}
+
+void set_job_seed(JobDesc& jb, const mr_mv_seed* seed) {
+  jb.seed_mv = seed ? seed->ref_mv : nullptr;
+  jb.seed_w = seed ? seed->ref_w : 0;
+  jb.seed_h = seed ? seed->ref_h : 0;
+  jb.seed_r = seed ? seed->refine_range : 0;
+}
+
 int device_cu_count() {
   static int cached[64] = {0};
   int dev = 0;
@@ -243,17 +258,21 @@ size_t device_lds_max() {
 
 int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
               const mr_search_params* const* p, const uint8_t* const* bounds,
-              const mr_search_out* const* out, int n_jobs, bool materialize_items, Plan* P) {
+              const mr_search_out* const* out, const mr_mv_seed* const* seeds, int n_jobs,
+              bool materialize_items, Plan* P) {
   if (n_jobs < 1 || n_jobs > (1 << 20)) return MR_EINVAL;
+  auto seed_of = [&](int j) { return seeds ? seeds[j] : nullptr; };
   for (int j = 0; j < n_jobs; ++j) {
-    const int rc = validate_job(cur[j], ref[j], p[j], out[j]);
+    int rc = validate_job(cur[j], ref[j], p[j], out[j]);
+    if (rc == MR_OK) rc = validate_seed(seed_of(j), p[j]);
     if (rc != MR_OK) return rc;
   }
-  // Batch-wide D and strip from the job with the most search work.
+  // Batch-wide D and strip from the full-search job with the most search work.
   int heavy = 0;
   double heavy_work = -1;
   int max_ctus_w = 1;
   for (int j = 0; j < n_jobs; ++j) {
+    if (seed_of(j)) continue;
     const double r = 2.0 * p[j]->search_range + 1;
     const double work = r * r * (double)cur[j]->width * cur[j]->height;
     if (work > heavy_work) heavy_work = work, heavy = j;
@@ -267,6 +286,9 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
   P->jobs.assign(n_jobs, JobDesc{});
   P->job_off.assign(n_jobs, 0);
   P->items.clear();
+  P->rlist.clear();
+  P->n_rjobs = P->n_rctus = 0;
+  P->max_pad_dwords = 0;
   P->n_ctus = 0;
   P->scratch_bytes = 0;
   P->lds_bytes = 0;
@@ -290,27 +312,10 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     jb.h8 = (jb.h + 7) / 8 * 8;
     jb.ctus_w = (jb.w8 + kCtu - 1) / kCtu;
     jb.ctus_h = (jb.h8 + kCtu - 1) / kCtu;
-    int nb = choose_bands(R, P->D, P->strip, jb.ctus_w, jb.ctus_h, kLdsBudget, min_items);
-    TileConfig tj;
-    if (get_tile_override(R, &tj) && tj.D == P->D && tj.nbands) nb = tj.nbands;
-    const SearchLayout L = make_layout(R, P->D, nb);
-    KeyTables kt;
-    const int rc = get_key_tables(p[j]->qp, L, &kt);
-    if (rc != MR_OK) return rc;
+    const int n_ctus = jb.ctus_w * jb.ctus_h;
     jb.R = R;
-    jb.D = P->D;
-    jb.Q = L.Q;
-    jb.nbands = L.nbands;
-    jb.strip = P->strip;
-    jb.win_dwords = L.Q + 16 * P->strip;
     jb.ctu_start = P->n_ctus;
-    for (int b = 0; b <= kMaxBands; ++b) {
-      jb.band_g0[b] = L.band_g0[b];
-      jb.band_step0[b] = L.band_step0[b];
-    }
     jb.s = sqrt_lambda_q16(p[j]->qp);
-    jb.qtab = kt.qtab;
-    jb.dtab = kt.dtab;
     jb.bounds = bounds[j];
     jb.depth = out[j]->depth;
     jb.mode = out[j]->mode;
@@ -318,11 +323,42 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     jb.ctu_cost = out[j]->ctu_cost;
     jb.ctu_dist = out[j]->ctu_dist;
     jb.ctu_bits = out[j]->ctu_bits;
-    const int n_ctus = jb.ctus_w * jb.ctus_h;
     P->job_off[j] = P->scratch_bytes;
     P->scratch_bytes += up256((size_t)n_ctus * 4096) + up256((size_t)n_ctus * kNodes * 8) +
                         up256((size_t)n_ctus * kNodes) + up256((size_t)n_ctus * 16);
     P->n_ctus += n_ctus;
+    if (seed_of(j)) {
+      // Seeded: refinement around reference MVs instead of the full search.
+      set_job_seed(jb, seed_of(j));
+      jb.rctu_start = P->n_rctus;
+      jb.pad_x = refine_pad_x(R);
+      jb.pad_pitch = jb.w8 + 2 * jb.pad_x;
+      const int64_t pad_bytes = (int64_t)(jb.h8 + 2 * R) * jb.pad_pitch;
+      P->scratch_bytes += up256((size_t)pad_bytes);
+      P->max_pad_dwords = std::max(P->max_pad_dwords, pad_bytes / 4);
+      P->rlist.push_back(j);
+      P->n_rjobs += 1;
+      P->n_rctus += n_ctus;
+      continue;
+    }
+    int nb = choose_bands(R, P->D, P->strip, jb.ctus_w, jb.ctus_h, kLdsBudget, min_items);
+    TileConfig tj;
+    if (get_tile_override(R, &tj) && tj.D == P->D && tj.nbands) nb = tj.nbands;
+    const SearchLayout L = make_layout(R, P->D, nb);
+    KeyTables kt;
+    const int rc = get_key_tables(p[j]->qp, L, &kt);
+    if (rc != MR_OK) return rc;
+    jb.D = P->D;
+    jb.Q = L.Q;
+    jb.nbands = L.nbands;
+    jb.strip = P->strip;
+    jb.win_dwords = L.Q + 16 * P->strip;
+    for (int b = 0; b <= kMaxBands; ++b) {
+      jb.band_g0[b] = L.band_g0[b];
+      jb.band_step0[b] = L.band_step0[b];
+    }
+    jb.qtab = kt.qtab;
+    jb.dtab = kt.dtab;
     P->lds_bytes = std::max(P->lds_bytes, window_bytes(L, P->strip));
     const int spr = (jb.ctus_w + P->strip - 1) / P->strip;
     total_items += (int64_t)spr * jb.ctus_h * L.nbands;
@@ -347,8 +383,12 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     P->items.resize(work.size());
     for (size_t i = 0; i < work.size(); ++i) P->items[i] = make_uint2(work[i].job, work[i].y);
   }
-  const int occ = std::max(1, search_occupancy(P->D, P->strip, P->lds_bytes));
-  P->n_wg = (int)std::min<int64_t>(P->n_items, (int64_t)occ * device_cu_count());
+  if (P->n_items > 0) {
+    const int occ = std::max(1, search_occupancy(P->D, P->strip, P->lds_bytes));
+    P->n_wg = (int)std::min<int64_t>(P->n_items, (int64_t)occ * device_cu_count());
+  } else {
+    P->n_wg = 0;
+  }
   return MR_OK;
 }
 
@@ -364,7 +404,24 @@ void bind_scratch(Plan& P, uint8_t* base) {
     jb.elig = sp;
     sp += up256((size_t)n_ctus * kNodes);
     jb.eligbits = (uint32_t*)sp;
+    sp += up256((size_t)n_ctus * 16);
+    jb.refpad = jb.seed_mv ? sp : nullptr;
   }
+}
+
+hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, const int* rlist_d,
+                       uint32_t* counter, hipStream_t st, StageEvents* ev) {
+  hipError_t e = launch_prep(jobs_d, P.n_jobs, P.n_ctus, counter, st);
+  if (ev) profile_mark(ev, 1, st);
+  if (e == hipSuccess && P.n_rjobs > 0)
+    e = launch_pad(jobs_d, rlist_d, P.n_rjobs, P.max_pad_dwords, st);
+  if (e == hipSuccess && P.n_items > 0)
+    e = launch_search(jobs_d, items_d, P.n_items, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
+  if (e == hipSuccess && P.n_rjobs > 0) e = launch_refine(jobs_d, rlist_d, P.n_rjobs, P.n_rctus, st);
+  if (ev) profile_mark(ev, 2, st);
+  if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, st);
+  if (ev) profile_mark(ev, 3, st);
+  return e;
 }
 
 // -------------------------------------------------------------------- profiling
@@ -417,12 +474,13 @@ const char* mr_status_str(int status) {
   }
 }
 
-int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
-                  const uint8_t* bounds, mr_search_out* out, void* hip_stream) {
+int mr_ctu_search_seeded(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
+                         const uint8_t* bounds, const mr_mv_seed* seed, mr_search_out* out,
+                         void* hip_stream) {
   hipStream_t st = (hipStream_t)hip_stream;
   Plan P;
   const mr_search_out* o = out;
-  int rc = make_plan(&cur, &ref, &p, &bounds, &o, 1, false, &P);
+  int rc = make_plan(&cur, &ref, &p, &bounds, &o, &seed, 1, false, &P);
   if (rc != MR_OK) return rc;
   // Scratch: job descriptor, queue counter, per-job buffers.
   const size_t head = up256(sizeof(JobDesc)) + 256;
@@ -434,19 +492,16 @@ int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_para
   StageEvents ev{};
   const bool prof = profile_on() && profile_begin(&ev, st) == MR_OK;
   hipError_t e = launch_store_job(P.jobs[0], jobs_d, st);
-  if (e == hipSuccess) e = launch_prep(jobs_d, 1, P.n_ctus, counter, st);
-  if (prof) profile_mark(&ev, 1, st);
-  if (e == hipSuccess)
-    e = launch_search(jobs_d, nullptr, P.n_items, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
-  if (prof) profile_mark(&ev, 2, st);
-  if (e == hipSuccess) e = launch_leaf(jobs_d, 1, P.n_ctus, st);
-  if (prof) {
-    profile_mark(&ev, 3, st);
-    profile_push(ev);
-  }
+  if (e == hipSuccess) e = launch_plan(P, jobs_d, nullptr, nullptr, counter, st, prof ? &ev : nullptr);
+  if (prof) profile_push(ev);
   const hipError_t ef = hipFreeAsync(scratch, st);
   if (e != hipSuccess || ef != hipSuccess) return MR_EHIP;
   return MR_OK;
+}
+
+int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
+                  const uint8_t* bounds, mr_search_out* out, void* hip_stream) {
+  return mr_ctu_search_seeded(cur, ref, p, bounds, nullptr, out, hip_stream);
 }
 
 int64_t mr_sqrt_lambda_q16(int32_t qp) { return qp < 0 || qp > 51 ? -1 : sqrt_lambda_q16(qp); }

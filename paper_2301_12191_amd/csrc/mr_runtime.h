@@ -41,6 +41,7 @@ int get_key_tables(int qp, const SearchLayout& L, KeyTables* out);
 
 int validate_job(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
                  const mr_search_out* out);
+int validate_seed(const mr_mv_seed* seed, const mr_search_params* p);
 
 // A planned batch: job descriptors (scratch pointers relative to a base until
 // bound), the search items in longest-first order, and launch geometry.
@@ -51,14 +52,27 @@ struct Plan {
   std::vector<JobDesc> jobs;
   std::vector<uint2> items;           // empty when implicit (single job)
   std::vector<size_t> job_off;        // per-job scratch offset
-  size_t scratch_bytes = 0;           // per-job scratch total (curpack, keys, elig)
+  size_t scratch_bytes = 0;           // per-job scratch total (curpack, keys, elig, refpad)
+  // Seeded jobs: their indices in rctu_start order, CTU total, largest padded
+  // reference in dwords.
+  std::vector<int> rlist;
+  int n_rjobs = 0, n_rctus = 0;
+  int64_t max_pad_dwords = 0;
 };
 
-// Build a plan.  tiles: batch-wide D / strip (0 = choose); materialize_items:
-// false only for a single job (the kernel derives items from the job).
+// Build a plan.  seeds: null, or per job a seed (null entry = full search);
+// materialize_items: false only for a single job (the kernel derives items
+// from the job).
 int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
               const mr_search_params* const* p, const uint8_t* const* bounds,
-              const mr_search_out* const* out, int n_jobs, bool materialize_items, Plan* P);
+              const mr_search_out* const* out, const mr_mv_seed* const* seeds, int n_jobs,
+              bool materialize_items, Plan* P);
+// Copy a seed's fields into a job descriptor (seed null: full search).
+void set_job_seed(JobDesc& jb, const mr_mv_seed* seed);
+// prep -> [pad] -> [search] -> [refine] -> leaf for a bound plan; rlist_d is
+// the device copy of P.rlist (null for a single job).
+hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, const int* rlist_d,
+                       uint32_t* counter, hipStream_t st, struct StageEvents* ev);
 // Point each job's scratch fields into `base` (device memory of P.scratch_bytes).
 void bind_scratch(Plan& P, uint8_t* base);
 
@@ -72,6 +86,10 @@ hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* co
 hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, int D, int strip,
                          int n_wg, size_t lds_bytes, uint32_t* counter, hipStream_t st);
 hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st);
+hipError_t launch_pad(const JobDesc* jobs, const int* rlist, int n_rjobs, int64_t max_dwords,
+                      hipStream_t st);
+hipError_t launch_refine(const JobDesc* jobs, const int* rlist, int n_rjobs, int n_rctus,
+                         hipStream_t st);
 hipError_t launch_depth_bounds(const uint8_t* ref_depth, int ref_w, int ref_h, int dep_w,
                                int dep_h, int dlo, int dhi, uint8_t* out, hipStream_t st);
 int search_occupancy(int D, int strip, size_t lds_bytes);

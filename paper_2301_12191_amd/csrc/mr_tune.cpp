@@ -22,7 +22,7 @@ int time_search(const mr_search_job* jobs, int n, int reps, double* ms_out) {
     cur[j] = &jobs[j].cur, ref[j] = &jobs[j].ref, p[j] = &jobs[j].params,
     b[j] = jobs[j].bounds, o[j] = &jobs[j].out;
   Plan P;
-  int rc = make_plan(cur.data(), ref.data(), p.data(), b.data(), o.data(), n, true, &P);
+  int rc = make_plan(cur.data(), ref.data(), p.data(), b.data(), o.data(), nullptr, n, true, &P);
   if (rc != MR_OK) return rc;
   const size_t off_items = up256(sizeof(JobDesc) * n);
   const size_t off_ctr = off_items + up256(sizeof(uint2) * P.items.size());

@@ -41,9 +41,15 @@ class mr_search_out(ctypes.Structure):
                 ("ctu_bits", ctypes.c_void_p)]
 
 
+class mr_mv_seed(ctypes.Structure):
+    _fields_ = [("ref_mv", ctypes.c_void_p), ("ref_w", ctypes.c_int32), ("ref_h", ctypes.c_int32),
+                ("refine_range", ctypes.c_int32)]
+
+
 class mr_search_job(ctypes.Structure):
     _fields_ = [("cur", mr_frame), ("ref", mr_frame), ("params", mr_search_params),
-                ("bounds", ctypes.c_void_p), ("out", mr_search_out)]
+                ("bounds", ctypes.c_void_p), ("out", mr_search_out),
+                ("seed", ctypes.POINTER(mr_mv_seed))]
 
 
 class mr_tune_result(ctypes.Structure):
@@ -71,6 +77,11 @@ def lib():
         L.mr_ctu_search.argtypes = [ctypes.POINTER(mr_frame), ctypes.POINTER(mr_frame),
                                     ctypes.POINTER(mr_search_params), vp,
                                     ctypes.POINTER(mr_search_out), vp]
+        L.mr_ctu_search_seeded.restype = ctypes.c_int
+        L.mr_ctu_search_seeded.argtypes = [ctypes.POINTER(mr_frame), ctypes.POINTER(mr_frame),
+                                           ctypes.POINTER(mr_search_params), vp,
+                                           ctypes.POINTER(mr_mv_seed),
+                                           ctypes.POINTER(mr_search_out), vp]
         L.mr_depth_bounds.restype = ctypes.c_int
         L.mr_depth_bounds.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
         L.mr_ctu_search_batch.restype = ctypes.c_int
@@ -145,9 +156,25 @@ def _frame(t: torch.Tensor, name):
     return mr_frame(_dev_ptr(t, torch.uint8, name), t.shape[1], t.shape[0], t.stride(0))
 
 
+def _seed_struct(seed):
+    """seed: dict {ref_mv: (ceil(ref_h/8), ceil(ref_w/8), 2) int16 device tensor, ref_w, ref_h,
+    r}, or None."""
+    if seed is None:
+        return None
+    rm = seed["ref_mv"]
+    if rm.dim() != 3 or rm.shape[2] != 2:
+        raise ValueError("ref_mv must be (ceil(ref_h/8), ceil(ref_w/8), 2) int16")
+    if tuple(rm.shape[:2]) != unit_shape(seed["ref_w"], seed["ref_h"]):
+        raise ValueError("ref_mv shape does not match ref_w x ref_h")
+    return mr_mv_seed(_dev_ptr(rm, torch.int16, "ref_mv"), seed["ref_w"], seed["ref_h"],
+                      seed["r"])
+
+
 def mr_ctu_search(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: int,
-                  bounds: torch.Tensor | None = None, out: dict | None = None, stream=None):
-    """Coding-tree search of one frame pair (see mr_ctu_search in include/mr.h)."""
+                  bounds: torch.Tensor | None = None, out: dict | None = None, stream=None,
+                  seed: dict | None = None):
+    """Coding-tree search of one frame pair (see mr_ctu_search and mr_ctu_search_seeded in
+    include/mr.h); seeded when ``seed`` is given."""
     H, W = cur.shape
     if out is None:
         out = alloc_outputs(W, H, cur.device)
@@ -160,10 +187,18 @@ def mr_ctu_search(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: i
                       _dev_ptr(out["dist"], torch.int64, "dist"),
                       _dev_ptr(out["bits"], torch.int64, "bits"))
     bp = None if bounds is None else _dev_ptr(bounds, torch.uint8, "bounds")
-    rc = lib().mr_ctu_search(ctypes.byref(fc), ctypes.byref(fr), ctypes.byref(prm), bp,
-                             ctypes.byref(o), _stream_handle(stream))
+    if seed is None:
+        rc = lib().mr_ctu_search(ctypes.byref(fc), ctypes.byref(fr), ctypes.byref(prm), bp,
+                                 ctypes.byref(o), _stream_handle(stream))
+        where = "mr_ctu_search"
+    else:
+        sd = _seed_struct(seed)
+        rc = lib().mr_ctu_search_seeded(ctypes.byref(fc), ctypes.byref(fr), ctypes.byref(prm),
+                                        bp, ctypes.byref(sd), ctypes.byref(o),
+                                        _stream_handle(stream))
+        where = "mr_ctu_search_seeded"
     if rc != MR_OK:
-        raise MRError(rc, "mr_ctu_search")
+        raise MRError(rc, where)
     return out
 
 
@@ -177,17 +212,24 @@ def _out_struct(out):
 
 
 def _job_array(jobs):
-    """jobs: list of dicts {cur, ref, qp, search_range, bounds (optional), out (optional)}."""
+    """jobs: list of dicts {cur, ref, qp, search_range, bounds (optional), out (optional),
+    seed (optional, as for mr_ctu_search)}."""
     arr = (mr_search_job * len(jobs))()
+    arr._seeds = []  # keep the seed structs alive with the array
     for i, j in enumerate(jobs):
         cur = j["cur"]
         if j.get("out") is None:
             j["out"] = alloc_outputs(cur.shape[1], cur.shape[0], cur.device)
         b = j.get("bounds")
+        sd = _seed_struct(j.get("seed"))
+        sp = None
+        if sd is not None:
+            arr._seeds.append(sd)
+            sp = ctypes.pointer(sd)
         arr[i] = mr_search_job(_frame(cur, "cur"), _frame(j["ref"], "ref"),
                                mr_search_params(j["qp"], j["search_range"]),
                                None if b is None else _dev_ptr(b, torch.uint8, "bounds"),
-                               _out_struct(j["out"]))
+                               _out_struct(j["out"]), sp)
     return arr
 
 
@@ -303,7 +345,8 @@ class mr_ladder_config(ctypes.Structure):
     _fields_ = [("n_rungs", ctypes.c_int32), ("rungs", mr_rung * 8), ("delta_lo", ctypes.c_int32),
                 ("delta_hi", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_int32), ("max_queue", ctypes.c_int32),
-                ("max_batch_jobs", ctypes.c_int32)]
+                ("max_batch_jobs", ctypes.c_int32), ("reuse_mv", ctypes.c_int32),
+                ("refine_range", ctypes.c_int32)]
 
 
 class mr_job(ctypes.Structure):
@@ -364,7 +407,7 @@ class Ladder:
     """mr_ladder_* handle: continuous-batching server of ladder frame-pair jobs."""
 
     def __init__(self, rungs, delta_lo=0, delta_hi=1, budget_bytes=8 << 30, max_inflight=256,
-                 max_queue=8192, max_batch_jobs=64):
+                 max_queue=8192, max_batch_jobs=64, refine_range=None):
         L = _ladder_lib()
         cfg = mr_ladder_config()
         cfg.n_rungs = len(rungs)
@@ -374,6 +417,10 @@ class Ladder:
         cfg.delta_lo, cfg.delta_hi = delta_lo, delta_hi
         cfg.hbm_budget_bytes = budget_bytes
         cfg.max_inflight, cfg.max_queue, cfg.max_batch_jobs = max_inflight, max_queue, max_batch_jobs
+        # refine_range None: dependents run the bounded full search; an int r seeds them with
+        # their reference job's MVs (refinement half-width r).
+        cfg.reuse_mv = 0 if refine_range is None else 1
+        cfg.refine_range = 0 if refine_range is None else refine_range
         self.rungs = rungs
         self._h = ctypes.c_void_p()
         self._frames = {}

@@ -37,21 +37,26 @@ def _frames(n_streams, n_frames):
     return fr
 
 
-def _alone(mr, fr, s, f, r, ref_depth_cache):
-    """The job run by itself through mr_ctu_search (+ mr_depth_bounds for dependents)."""
+def _alone(mr, fr, s, f, r, ref_cache, refine=None):
+    """The job run by itself through mr_ctu_search (+ mr_depth_bounds for dependents, and a
+    seed of the reference job's MVs when refine is set)."""
     import torch
     cfg = RUNGS[r]
-    bounds = None
+    bounds = seed = None
     if cfg["ref_rung"] >= 0:
         rr = cfg["ref_rung"]
-        if (s, f) not in ref_depth_cache:
-            rc = RUNGS[rr]
-            ref_depth_cache[(s, f)] = mr.mr_ctu_search(fr[(s, f, rr)], fr[(s, f - 1, rr)], rc["qp"],
-                                                       rc["search_range"])["depth"]
-        bounds = mr.mr_depth_bounds(ref_depth_cache[(s, f)], RUNGS[rr]["width"],
-                                    RUNGS[rr]["height"], cfg["width"], cfg["height"], 0, 1)
+        rcfg = RUNGS[rr]
+        if (s, f) not in ref_cache:
+            ref_cache[(s, f)] = mr.mr_ctu_search(fr[(s, f, rr)], fr[(s, f - 1, rr)], rcfg["qp"],
+                                                 rcfg["search_range"])
+        ref_out = ref_cache[(s, f)]
+        bounds = mr.mr_depth_bounds(ref_out["depth"], rcfg["width"], rcfg["height"],
+                                    cfg["width"], cfg["height"], 0, 1)
+        if refine is not None:
+            seed = dict(ref_mv=ref_out["mv"], ref_w=rcfg["width"], ref_h=rcfg["height"],
+                        r=min(refine, cfg["search_range"]))
     out = mr.mr_ctu_search(fr[(s, f, r)], fr[(s, f - 1, r)], cfg["qp"], cfg["search_range"],
-                           bounds=bounds)
+                           bounds=bounds, seed=seed)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}
 
@@ -148,3 +153,17 @@ def test_ladder_errors(mr):
         lad.close()
     with pytest.raises(mr.MRError):
         mr.Ladder([dict(width=64, height=64, qp=30, search_range=8, ref_rung=0)])  # self-reference
+
+
+def test_mv_reuse_dependents_equal_seeded_alone(mr):
+    """With reuse_mv, every dependent equals mr_ctu_search_seeded with its reference job's MVs
+    and depth bounds; references are unchanged."""
+    fr = _frames(2, 3)
+    jobs = [(s, f, r) for s in range(2) for f in (1, 2) for r in (2, 1, 0)]
+    got, st = _run_mix(mr, fr, jobs, refine_range=4)
+    assert st["completed"] == len(jobs) + st["implied"] and st["failed"] == 0
+    cache = {}
+    for key in jobs:
+        exp = _alone(mr, fr, *key, cache, refine=4)
+        for k in FIELDS:
+            assert np.array_equal(got[key][k], exp[k]), (key, k)

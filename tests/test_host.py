@@ -111,7 +111,7 @@ def test_batch_rejects_invalid_jobs_before_launch(libmr):
     arr = (mr.mr_search_job * 2)()
     for i in range(2):
         arr[i] = mr.mr_search_job(_fake_frame(mr), _fake_frame(mr), mr.mr_search_params(30, 16),
-                                  None, _fake_out(mr))
+                                  None, _fake_out(mr), None)
     assert libmr.mr_ctu_search_batch(arr, 0, None) == mr.MR_EINVAL
     arr[1].params.qp = 99
     assert libmr.mr_ctu_search_batch(arr, 2, None) == mr.MR_EINVAL
@@ -122,6 +122,54 @@ def test_batch_rejects_invalid_jobs_before_launch(libmr):
     assert libmr.mr_batch_launch(None, None) == mr.MR_EINVAL
     assert libmr.mr_batch_set_jobs(None, arr, 2) == mr.MR_EINVAL
     assert libmr.mr_batch_destroy(None) == mr.MR_OK
+
+
+@pytest.mark.parametrize("case", ["null_map", "zero_w", "huge_h", "r_neg", "r_above_range"])
+def test_seeded_search_rejects_invalid_seeds_before_launch(libmr, case):
+    from paper_2301_12191_amd import mr
+    cur, ref = _fake_frame(mr), _fake_frame(mr)
+    prm = mr.mr_search_params(30, 16)
+    out = _fake_out(mr)
+    sd = mr.mr_mv_seed(ctypes.c_void_p(0x3000), 32, 32, 4)
+    if case == "null_map":
+        sd.ref_mv = None
+    elif case == "zero_w":
+        sd.ref_w = 0
+    elif case == "huge_h":
+        sd.ref_h = 8193
+    elif case == "r_neg":
+        sd.refine_range = -1
+    elif case == "r_above_range":
+        sd.refine_range = 17
+    rc = libmr.mr_ctu_search_seeded(ctypes.byref(cur), ctypes.byref(ref), ctypes.byref(prm), None,
+                                    ctypes.byref(sd), ctypes.byref(out), None)
+    assert rc == mr.MR_EINVAL
+    # The same seed inside a batch job is rejected before anything is launched.
+    arr = (mr.mr_search_job * 2)()
+    for i in range(2):
+        arr[i] = mr.mr_search_job(_fake_frame(mr), _fake_frame(mr), mr.mr_search_params(30, 16),
+                                  None, _fake_out(mr), None)
+    arr[1].seed = ctypes.pointer(sd)
+    assert libmr.mr_ctu_search_batch(arr, 2, None) == mr.MR_EINVAL
+    h = ctypes.c_void_p()
+    assert libmr.mr_batch_create(arr, 2, ctypes.byref(h)) == mr.MR_EINVAL
+
+
+@pytest.mark.parametrize("reuse,r", [(2, 0), (-1, 0), (1, -1), (1, 129)])
+def test_ladder_rejects_invalid_mv_reuse_config(libmr, reuse, r):
+    from paper_2301_12191_amd import mr
+    L = mr._ladder_lib()
+    cfg = mr.mr_ladder_config()
+    cfg.n_rungs = 2
+    cfg.rungs[0] = mr.mr_rung(64, 64, 30, 8, -1)
+    cfg.rungs[1] = mr.mr_rung(128, 128, 30, 16, 0)
+    cfg.delta_lo, cfg.delta_hi = 0, 1
+    cfg.hbm_budget_bytes = 1 << 30
+    cfg.max_inflight, cfg.max_queue, cfg.max_batch_jobs = 8, 8, 8
+    cfg.reuse_mv, cfg.refine_range = reuse, r
+    h = ctypes.c_void_p()
+    assert L.mr_ladder_open(ctypes.byref(cfg), ctypes.byref(h)) == mr.MR_EINVAL
+    assert not h.value
 
 
 def test_tile_override_validation(libmr):
