@@ -13,7 +13,9 @@ Beside it the JSON line carries:
   pruned       : multi-resolution pruning on a 3840x2160 source: 960x540
                  reference (QP 32, R 32) bounds 1920x1080 (QP 27, R 64) and
                  3840x2160 (QP 22, R 128), refine depths n..n+1; speedup of
-                 pruned over full search and the exact RD-cost increase;
+                 pruned over full search and the exact RD-cost increase; the
+                 same with the reference MVs reused as search centres
+                 (refinement r = 4), and the refinement stage's absdiff rate;
   cpu_baseline : the CPU oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-pruned]
@@ -29,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 # Packed-byte SAD peak: 256 CUs x 64 lanes x 2.4 GHz x 4 absolute differences per v_sad_u8.
 PEAK_ABSDIFF = 256 * 64 * 2.4e9 * 4
+# Refinement half-width of the seeded (MV reuse) variant.
+REFINE_R = 4
 
 
 def log(msg):
@@ -154,37 +158,72 @@ def main():
         bounds = {w: mr.mr_depth_bounds(ref_out["depth"], 960, 540, w, h, 0, 1)
                   for (w, h, _, _) in deps}
         torch.cuda.synchronize()
-        res = {"full_ms": 0.0, "pruned_ms": 0.0, "J_full": 0, "J_pruned": 0, "per_rung": {}}
+        seed540 = dict(ref_mv=ref_out["mv"], ref_w=960, ref_h=540, r=REFINE_R)
+        variants = (("full", False, False), ("pruned", True, False), ("reuse", True, True))
+        res = {f"{v}_ms": 0.0 for v, _, _ in variants}
+        res.update({f"J_{v}": 0 for v, _, _ in variants})
+        res["per_rung"] = {}
         reps = 3
         for (w, h, qp, rr) in deps:
             ref_t, cur_t = rungs[w]
-            of, op = mr.alloc_outputs(w, h, dev), mr.alloc_outputs(w, h, dev)
-            times = {}
-            for name, b, o in (("full", None, of), ("pruned", bounds[w], op)):
-                mr.mr_ctu_search(cur_t, ref_t, qp, rr, bounds=b, out=o)  # warm
+            times, J = {}, {}
+            for name, use_b, use_s in variants:
+                o = mr.alloc_outputs(w, h, dev)
+                kw = dict(bounds=bounds[w] if use_b else None, seed=seed540 if use_s else None,
+                          out=o)
+                mr.mr_ctu_search(cur_t, ref_t, qp, rr, **kw)  # warm
                 torch.cuda.synchronize()
                 ta = time.perf_counter()
                 for _ in range(reps):
-                    mr.mr_ctu_search(cur_t, ref_t, qp, rr, bounds=b, out=o)
+                    mr.mr_ctu_search(cur_t, ref_t, qp, rr, **kw)
                 torch.cuda.synchronize()
                 times[name] = (time.perf_counter() - ta) * 1e3 / reps
-            jf, jp = int(of["cost"].sum().item()), int(op["cost"].sum().item())
-            res["full_ms"] += times["full"]
-            res["pruned_ms"] += times["pruned"]
-            res["J_full"] += jf
-            res["J_pruned"] += jp
+                J[name] = int(o["cost"].sum().item())
+                res[f"{name}_ms"] += times[name]
+                res[f"J_{name}"] += J[name]
             res["per_rung"][f"{w}x{h}"] = {
-                "full_ms": round(times["full"], 3), "pruned_ms": round(times["pruned"], 3),
+                **{f"{v}_ms": round(times[v], 3) for v, _, _ in variants},
                 "speedup": round(times["full"] / times["pruned"], 4),
-                "rd_cost_increase_pct": round(100.0 * (jp - jf) / jf, 6)}
+                "reuse_speedup": round(times["full"] / times["reuse"], 4),
+                "rd_cost_increase_pct": round(100.0 * (J["pruned"] - J["full"]) / J["full"], 6),
+                "reuse_rd_cost_increase_pct":
+                    round(100.0 * (J["reuse"] - J["full"]) / J["full"], 6)}
+        pct = lambda a: round(100.0 * (res[f"J_{a}"] - res["J_full"]) / res["J_full"], 6)
         pruned = {
             "workload": "3840x2160 source; 960x540 QP32 R32 reference bounds 1920x1080 QP27 R64 "
-                        "and 3840x2160 QP22 R128 (depths n..n+1)",
+                        "and 3840x2160 QP22 R128 (depths n..n+1); reuse adds the reference MVs "
+                        f"as search centres (refinement r = {REFINE_R})",
             "speedup": round(res["full_ms"] / res["pruned_ms"], 4),
-            "rd_cost_increase_pct": round(100.0 * (res["J_pruned"] - res["J_full"]) / res["J_full"], 6),
+            "rd_cost_increase_pct": pct("pruned"),
+            "reuse_speedup": round(res["full_ms"] / res["reuse_ms"], 4),
+            "reuse_rd_cost_increase_pct": pct("reuse"),
             "full_ms": round(res["full_ms"], 3), "pruned_ms": round(res["pruned_ms"], 3),
-            "per_rung": res["per_rung"]}
+            "reuse_ms": round(res["reuse_ms"], 3), "per_rung": res["per_rung"]}
         log(f"pruned: {pruned}")
+
+        # Refinement kernel throughput: 3840x2160 seeded (no bounds), every inside CU searched.
+        ref_t, cur_t = rungs[3840]
+        o = mr.alloc_outputs(3840, 2160, dev)
+        seed = dict(ref_mv=ref_out["mv"], ref_w=960, ref_h=540, r=REFINE_R)
+        mr.mr_ctu_search(cur_t, ref_t, 22, 128, seed=seed, out=o)
+        torch.cuda.synchronize()
+        mr.mr_profile_read(reset=True)
+        mr.mr_profile_enable(True)
+        for _ in range(5):
+            mr.mr_ctu_search(cur_t, ref_t, 22, 128, seed=seed, out=o)
+        torch.cuda.synchronize()
+        stages = mr.mr_profile_read(reset=True)
+        mr.mr_profile_enable(False)
+        w8, h8 = 3840, 2160
+        absdiff = sum((w8 // n) * (h8 // n) * n * n for n in (64, 32, 16, 8)) * (2 * REFINE_R + 1) ** 2
+        st_ms = stages["search"][0] / stages["search"][1]
+        pruned["refine"] = {
+            "workload": f"3840x2160 QP22 R128 seeded from 960x540 MVs, r = {REFINE_R}, no bounds",
+            "stage_ms": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
+            "absdiff_per_launch": absdiff,
+            "achieved_T_absdiff_s": round(absdiff / (st_ms * 1e-3) / 1e12, 3),
+            "frac_of_peak_pad_plus_refine": round(absdiff / (st_ms * 1e-3) / PEAK_ABSDIFF, 4)}
+        log(f"refine: {pruned['refine']}")
 
     # ------------------------------------------------------- six-rung ladder, one launch
     ladder = None

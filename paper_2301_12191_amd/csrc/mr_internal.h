@@ -13,7 +13,6 @@ constexpr uint32_t kCinv = 1050000u;  // cost field of candidates outside the wi
 constexpr uint64_t kKeyNone = ~0ull;
 constexpr int kMaxStrip = 4;        // CTUs (wavefronts) per search workgroup
 constexpr int kCurRingBytes = 512;  // per wavefront: two 16x16 regions of the current CTU
-constexpr int kRefineChunk = 16;    // seeded search: horizontal candidates per register pass
 
 // Column margin of the padded reference of a seeded job with range R: the
 // refinement loads reach 3 bytes left of -R and 20 bytes right of w8 - 8 + R.

@@ -15,27 +15,11 @@
 //            quad-tree decision with optional depth bounds, outputs.
 // All arithmetic is integer and matches the CPU definition bit for bit.
 #include <hip/hip_runtime.h>
-
-#include <algorithm>
 #include <stdint.h>
 
-#include "mr_internal.h"
+#include "mr_device.h"
 
 namespace mr {
-
-typedef const __attribute__((address_space(4))) uint32_t* sptr32;  // scalar (uniform) loads
-typedef const __attribute__((address_space(4))) JobDesc* cjob;     // job descriptor, scalar loads
-
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-// Z-order (Morton) position -> (x, y) for 6-bit indices.
-__device__ __forceinline__ int zx(int z) { return (z & 1) | ((z >> 1) & 2) | ((z >> 2) & 4); }
-__device__ __forceinline__ int zy(int z) { return ((z >> 1) & 1) | ((z >> 2) & 2) | ((z >> 3) & 4); }
-
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWMASK, 0xF, false);
-}
 
 // Minimum over the 64 lanes of a wavefront (all lanes active); wave-uniform result.
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
@@ -331,10 +315,6 @@ __device__ __forceinline__ uint32_t satd4x4(int d[16]) {
   return s >> 1;
 }
 
-__device__ __forceinline__ int se_bits_dev(int v) {
-  const uint32_t k = v > 0 ? 2u * (uint32_t)v - 1u : 2u * (uint32_t)(-v);
-  return 2 * (31 - __builtin_clz(k + 1u)) + 1;
-}
 
 // Offsets of each node's reference arrays in LDS: left column 2N+1, top row 2N.
 __device__ __forceinline__ int ref_offset(int node) {
@@ -592,127 +572,6 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
 }
 
 
-// ------------------------------------------------------------------ seeded search
-// Motion-vector reuse with refinement: each CU searches the (2r+1)^2 integer
-// displacements around the scaled MV of the reference unit co-located with its
-// centre (clamped to [-(R - r), R - r]), with the full search's cost and tie
-// order.  The reference is first copied with a margin and clamped coordinates
-// (pad_kernel) so that every window load is a plain dword load.
-
-// m * num / den rounded to nearest, halves away from zero.
-__device__ __forceinline__ int scale_round_dev(int m, int num, int den) {
-  const int64_t a = (int64_t)(m < 0 ? -m : m) * num;
-  const int q = (int)((2 * a + den) / (2 * (int64_t)den));
-  return m < 0 ? -q : q;
-}
-
-// Sum of v over aligned groups of 4^(3-d) lanes (d = 3: none; 2: quads; 1: rows
-// of 16; 0: the wavefront), every lane of a group receiving the group's sum.
-__device__ __forceinline__ uint32_t group_sum(uint32_t v, int d) {
-  if (d == 3) return v;
-  v += dpp_mov<0xB1, 0xF>(v, v);   // quad_perm [1,0,3,2]
-  v += dpp_mov<0x4E, 0xF>(v, v);   // quad_perm [2,3,0,1]
-  if (d == 2) return v;
-  v += dpp_mov<0x141, 0xF>(v, v);  // row_half_mirror
-  v += dpp_mov<0x140, 0xF>(v, v);  // row_mirror
-  if (d == 1) return v;
-  return (uint32_t)(__builtin_amdgcn_readlane((int)v, 0) + __builtin_amdgcn_readlane((int)v, 16) +
-                    __builtin_amdgcn_readlane((int)v, 32) + __builtin_amdgcn_readlane((int)v, 48));
-}
-
-// One workgroup (256 threads) per CTU of a seeded job; wavefront d searches the
-// CUs of depth d; lane b holds the 8x8 block at Z-order position b and the
-// lanes of one CU reduce their block SADs per candidate.
-__device__ void refine_ctu(cjob jb, int ctu) {
-  const int d = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int b = threadIdx.x & 63;
-  const int bx = zx(b), by = zy(b);
-  const int ctu_x = (ctu % jb->ctus_w) * kCtu, ctu_y = (ctu / jb->ctus_w) * kCtu;
-  const int n = kCtu >> d, sh3 = 3 - d;
-  const int lx = bx >> sh3, ly = by >> sh3;
-  const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
-  const bool e = jb->elig[(size_t)ctu * kNodes + node] != 0;
-  if (__ballot(e) == 0) return;  // no CU of this depth may be a leaf
-
-  const int R = jb->R, r = jb->seed_r, lim = R - r, span = 2 * R + 1;
-  const int W = jb->w, H = jb->h;
-  // Search centre of this lane's CU.
-  int cxm, cym;
-  {
-    const int64_t px = ctu_x + lx * n + n / 2, py = ctu_y + ly * n + n / 2;
-    const int sw = jb->seed_w, shh = jb->seed_h;
-    const int64_t xr = min(px * sw / W, (int64_t)sw - 1);
-    const int64_t yr = min(py * shh / H, (int64_t)shh - 1);
-    const int16_t* m = jb->seed_mv + 2 * ((yr >> 3) * ((sw + 7) >> 3) + (xr >> 3));
-    cxm = clampi(scale_round_dev(m[0], W, sw), -lim, lim);
-    cym = clampi(scale_round_dev(m[1], H, shh), -lim, lim);
-  }
-  // This lane's block (blocks outside the coded picture belong to CUs that are
-  // not searched; their loads are kept inside the padded reference).
-  const int X0 = min(ctu_x + 8 * bx, jb->w8 - 8), Y0 = min(ctu_y + 8 * by, jb->h8 - 8);
-  uint32_t c[16];
-  {
-    const uint4* cp = (const uint4*)(jb->curpack + (size_t)ctu * 1024 + b * 16);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint4 v = cp[i];
-      c[4 * i] = v.x, c[4 * i + 1] = v.y, c[4 * i + 2] = v.z, c[4 * i + 3] = v.w;
-    }
-  }
-  const int pitch = jb->pad_pitch;
-  const int64_t s = jb->s;
-  const int ncand = 2 * r + 1;
-  const int nchunks = (ncand + kRefineChunk - 1) / kRefineChunk;
-  uint64_t best = kKeyNone;
-  for (int iy = 0; iy < ncand; ++iy) {
-    const int dy = cym - r + iy;
-    const int bits_y = se_bits_dev(4 * dy);
-    const uint8_t* rowp = jb->refpad + (size_t)(Y0 + dy + R) * pitch;
-    for (int ch = 0; ch < nchunks; ++ch) {
-      const int rem = ncand - ch * kRefineChunk;  // valid candidates of this chunk (uniform)
-      const int dx0 = cxm - r + ch * kRefineChunk;
-      const int xs = X0 + dx0 + jb->pad_x;
-      const int shb = xs & 3;
-      const uint32_t* src = (const uint32_t*)(rowp + (xs & ~3));
-      uint32_t acc[kRefineChunk];
-#pragma unroll
-      for (int k = 0; k < kRefineChunk; ++k) acc[k] = 0;
-#pragma unroll
-      for (int row = 0; row < 8; ++row) {
-        const uint32_t* rp = src + row * (pitch >> 2);
-        uint32_t raw[7], al[6];
-#pragma unroll
-        for (int j = 0; j < 7; ++j) raw[j] = rp[j];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) al[j] = __builtin_amdgcn_alignbyte(raw[j + 1], raw[j], shb);
-#pragma unroll
-        for (int q = 0; q < kRefineChunk / 4; ++q) {
-          if (4 * q < rem) {
-#pragma unroll
-            for (int o = 0; o < 4; ++o) {
-              const uint32_t lo = o ? __builtin_amdgcn_alignbyte(al[q + 1], al[q], o) : al[q];
-              const uint32_t hi = o ? __builtin_amdgcn_alignbyte(al[q + 2], al[q + 1], o) : al[q + 1];
-              acc[4 * q + o] = __builtin_amdgcn_sad_u8(c[2 * row], lo, acc[4 * q + o]);
-              acc[4 * q + o] = __builtin_amdgcn_sad_u8(c[2 * row + 1], hi, acc[4 * q + o]);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kRefineChunk; ++k) {
-        if (k < rem) {
-          const uint32_t sad = group_sum(acc[k], d);
-          const int dx = dx0 + k;
-          const uint64_t J = ((uint64_t)sad << 16) + (uint64_t)(s * (bits_y + se_bits_dev(4 * dx)));
-          const uint64_t key = (J << 17) | (uint64_t)((dy + R) * span + dx + R);
-          best = key < best ? key : best;
-        }
-      }
-    }
-  }
-  if (e && (b & ((1 << (2 * sh3)) - 1)) == 0) jb->keys[(size_t)ctu * kNodes + node] = best;
-}
-
 // ------------------------------------------------------------------------- depth bounds
 __global__ __launch_bounds__(256) void depth_bounds_kernel(const uint8_t* __restrict__ ref_depth,
                                                            int ref_w, int ref_h, int dep_w,
@@ -821,58 +680,6 @@ __global__ __launch_bounds__(256) void search_kernel_d8(const JobDesc* jobs_, co
   search_persistent<8>(jobs_, items_, n_items, counter, win, win_dwords_max);
 }
 
-// Seeded job owning CTU `flat` among the seeded jobs' CTUs (rlist lists the
-// seeded jobs in rctu_start order; null: job 0 alone).
-__device__ int find_rjob(cjob jobs, const int* rlist, int n_rjobs, int flat) {
-  if (!rlist) return 0;
-  int lo = 0, hi = n_rjobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[rlist[mid]].rctu_start <= flat) lo = mid;
-    else hi = mid - 1;
-  }
-  return rlist[lo];
-}
-
-// Padded reference of every seeded job: grid-stride over the seeded jobs in y
-// and over each job's [h8 + 2R][pad_pitch] bytes, in dwords, in x.
-__global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const int* rlist,
-                                                  int n_rjobs) {
-  for (int k = blockIdx.y; k < n_rjobs; k += gridDim.y) {
-    const cjob jb = (cjob)jobs_ + (rlist ? rlist[k] : 0);
-    const int R = jb->R, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
-    const int dw = jb->pad_pitch >> 2;
-    const int64_t total = (int64_t)(jb->h8 + 2 * R) * dw;
-    const uint8_t* ref = jb->ref;
-    const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0);
-    uint32_t* dst = (uint32_t*)jb->refpad;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-      const int row = (int)(i / dw), c = (int)(i - (int64_t)row * dw);
-      const uint8_t* rp = ref + (size_t)clampi(row - R, 0, h - 1) * stride;
-      const int x = 4 * c - P;
-      uint32_t v;
-      if (dword_ok && x >= 0 && x + 3 < w) {
-        v = *(const uint32_t*)(rp + x);
-      } else {
-        v = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[clampi(x + b, 0, w - 1)] << (8 * b);
-      }
-      dst[i] = v;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void refine_kernel(const JobDesc* jobs_, const int* rlist,
-                                                     int n_rjobs, int n_rctus) {
-  const cjob jobs = (cjob)jobs_;
-  const int flat = blockIdx.x;
-  if (flat >= n_rctus) return;
-  const int j = __builtin_amdgcn_readfirstlane(find_rjob(jobs, rlist, n_rjobs, flat));
-  refine_ctu(jobs + j, flat - jobs[j].rctu_start);
-}
-
 __global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus) {
   __shared__ LeafShared sh;
   const cjob jobs = (cjob)jobs_;
@@ -932,22 +739,6 @@ hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, i
 
 hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st) {
   hipLaunchKernelGGL(leaf_kernel, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus);
-  return hipGetLastError();
-}
-
-hipError_t launch_pad(const JobDesc* jobs, const int* rlist, int n_rjobs, int64_t max_dwords,
-                      hipStream_t st) {
-  const int64_t blocks = std::min<int64_t>((max_dwords + 255) / 256, 2048);
-  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1),
-                                      (unsigned)std::min(n_rjobs, 65535)),
-                     dim3(256), 0, st, jobs, rlist, n_rjobs);
-  return hipGetLastError();
-}
-
-hipError_t launch_refine(const JobDesc* jobs, const int* rlist, int n_rjobs, int n_rctus,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(refine_kernel, dim3(n_rctus), dim3(256), 0, st, jobs, rlist, n_rjobs,
-                     n_rctus);
   return hipGetLastError();
 }
 

@@ -1,0 +1,318 @@
+// HIP kernels of libmr for gfx950 (CDNA4): the seeded search (reference motion
+// vectors reused as search centres with a refinement window).
+//
+// Each CU searches the (2r+1)^2 integer displacements around the scaled MV of
+// the reference unit co-located with its centre (clamped to [-(R - r), R - r])
+// with the full search's cost and tie order.  Per batch: pad_kernel copies each
+// seeded job's reference with a margin and clamped coordinates, so that every
+// window load is a plain dword load; refine_kernel then runs one wavefront per
+// (CTU, CU depth, pass of 8 candidate columns, band of window rows) and merges
+// the results in the same arg-min keys the full search writes.  The prep and
+// leaf kernels are the full search's.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "mr_device.h"
+
+namespace mr {
+
+// m * num / den rounded to nearest, halves away from zero (|m| < 2^15,
+// 1 <= num, den <= 8192: every intermediate fits 32 bits).
+__device__ __forceinline__ int scale_round_dev(int m, int num, int den) {
+  const uint32_t a = (uint32_t)(m < 0 ? -m : m) * (uint32_t)num;
+  const int q = (int)((2u * a + (uint32_t)den) / (2u * (uint32_t)den));
+  return m < 0 ? -q : q;
+}
+
+// v plus the value of another lane (DPP permutation CTRL) in one v_add_u32.
+template <int CTRL>
+__device__ __forceinline__ uint32_t add_dpp(uint32_t v) {
+  return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// Sums of acc[k] over aligned groups of 4^(3-d) lanes (d = 3: none; 2: quads;
+// 1: rows of 16; 0: the wavefront), every lane of a group receiving its sum.
+// d is uniform; independent DPP adds are interleaved across k.
+template <int NP>
+__device__ __forceinline__ void group_sums(uint32_t (&acc)[NP], int d) {
+  if (d < 3) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0xB1>(acc[k]);  // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x4E>(acc[k]);  // quad_perm [2,3,0,1]
+  }
+  if (d < 2) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x141>(acc[k]);  // row_half_mirror
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x140>(acc[k]);  // row_mirror
+  }
+  if (d == 0) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+      acc[k] = (uint32_t)(__builtin_amdgcn_readlane((int)acc[k], 0) +
+                          __builtin_amdgcn_readlane((int)acc[k], 16) +
+                          __builtin_amdgcn_readlane((int)acc[k], 32) +
+                          __builtin_amdgcn_readlane((int)acc[k], 48));
+  }
+}
+
+// Signed Exp-Golomb length of v without a branch on the sign.
+__device__ __forceinline__ uint32_t se_len(int v) {
+  const uint32_t k = 2u * (uint32_t)(v < 0 ? -v : v) - (v > 0 ? 1u : 0u);
+  return 2u * (31u - (uint32_t)__builtin_clz(k + 1u)) + 1u;
+}
+
+// The four byte shifts of a reference row segment of NQ + 2 dwords:
+// out[o][j] = bytes 4j + o .. 4j + o + 3, j = 0..NQ.
+template <int NQ>
+__device__ __forceinline__ void shifts(const uint32_t (&raw)[NQ + 2], uint32_t (&out)[4][NQ + 1]) {
+#pragma unroll
+  for (int j = 0; j <= NQ; ++j) {
+    out[0][j] = raw[j];
+#pragma unroll
+    for (int o = 1; o < 4; ++o) out[o][j] = __builtin_amdgcn_alignbyte(raw[j + 1], raw[j], o);
+  }
+}
+
+// One wavefront: the CUs of depth d (uniform) of one CTU, one pass of NP = 4 NQ
+// candidate columns, one band of window rows.  Lane b holds the 8x8 block at
+// Z-order position b; the lanes of one CU sum their block SADs per candidate.
+//
+// Keys.  The arg-min key J * 2^17 + idx of candidate (dx, dy) is split as
+//   T(dx) + SAD * 2^33 + U(dy),  T = s * se(4dx) * 2^17 + dx + R,
+//   U = s * se(4dy) * 2^17 + (dy + R) * (2R + 1),
+// so a window row is reduced with T alone and U is added once per row
+// (s * se < 2^28 and every key < 2^54).
+// Columns.  Pass p covers byte positions p NP .. p NP + NP - 1 counted from the
+// dword-aligned reference column at or left of the window's first column;
+// position k reads dwords k / 4 and k / 4 + 1 shifted by k % 4.  Positions
+// outside this lane's window get T = 2^62, above every valid key.
+// Rows.  The 8 reference rows of the current dy are a ring of pre-shifted rows
+// S[slot][o][j] (bytes 4j + o .. 4j + o + 3); step u of a group of 8 uses slot
+// (u + row) & 7 for window row `row`, and the row loaded during step u (8 rows
+// below) replaces slot u, which step u + 1 no longer needs: the ring turns by
+// renaming, one new row per step, loaded one step ahead.
+template <int NQ>
+__device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nband) {
+  constexpr int NP = 4 * NQ, NDW = NQ + 2;
+  const int n = kCtu >> d, sh3 = 3 - d;
+  const int b = threadIdx.x & 63;
+  const int bx = zx(b), by = zy(b);
+  const int ctu_x = (ctu % jb->ctus_w) * kCtu, ctu_y = (ctu / jb->ctus_w) * kCtu;
+  const int lx = bx >> sh3, ly = by >> sh3;
+  const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
+  const bool e = jb->elig[(size_t)ctu * kNodes + node] != 0;
+  if (__ballot(e) == 0) return;  // no CU of this depth may be a leaf
+
+  const int R = jb->R, r = jb->seed_r, lim = R - r, span = 2 * R + 1;
+  const int ncand = 2 * r + 1;
+  const int npos = ncand + 3;  // positions any lane may need (uniform)
+  if (pass * NP >= npos) return;
+  const int bh = (ncand + nband - 1) / nband;
+  const int iy0 = band * bh, iy1 = min(ncand, iy0 + bh);
+  if (iy0 >= iy1) return;
+  const int W = jb->w, H = jb->h;
+  // Search centre of this lane's CU (all products < 2^27).
+  int cxm, cym;
+  {
+    const uint32_t px = ctu_x + lx * n + n / 2, py = ctu_y + ly * n + n / 2;
+    const uint32_t sw = jb->seed_w, shh = jb->seed_h;
+    const uint32_t xr = min(px * sw / (uint32_t)W, sw - 1);
+    const uint32_t yr = min(py * shh / (uint32_t)H, shh - 1);
+    const int16_t* m = jb->seed_mv + 2 * ((yr >> 3) * ((sw + 7) >> 3) + (xr >> 3));
+    cxm = clampi(scale_round_dev(m[0], W, sw), -lim, lim);
+    cym = clampi(scale_round_dev(m[1], H, shh), -lim, lim);
+  }
+  // This lane's block (blocks outside the coded picture belong to CUs that are
+  // not searched; their loads are kept inside the padded reference).
+  const int X0 = min(ctu_x + 8 * bx, jb->w8 - 8), Y0 = min(ctu_y + 8 * by, jb->h8 - 8);
+  uint32_t c[16];
+  {
+    const uint4* cp = (const uint4*)(jb->curpack + (size_t)ctu * 1024 + b * 16);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint4 v = cp[i];
+      c[4 * i] = v.x, c[4 * i + 1] = v.y, c[4 * i + 2] = v.z, c[4 * i + 3] = v.w;
+    }
+  }
+  const int pitch = jb->pad_pitch;
+  const uint32_t s = (uint32_t)jb->s;
+  // First window column in the padded reference, its dword-aligned start and
+  // the window's first position in that dword (0..3, per lane).
+  const int xw = X0 + cxm - r + jb->pad_x;
+  const int shb = xw & 3;
+  const int xa = xw - shb;
+  const int rem = npos - pass * NP;  // positions of this pass any lane may need (uniform)
+  uint64_t T[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int p = pass * NP + k - shb;  // window column of position k (valid: 0..2r)
+    const int dx = cxm - r + p;
+    T[k] = (p >= 0 && p < ncand) ? ((uint64_t)(s * se_len(4 * dx)) << 17) + (uint64_t)(dx + R)
+                                 : (1ull << 62);
+  }
+  const uint32_t* src = (const uint32_t*)(jb->refpad + (size_t)(Y0 + cym - r + iy0 + R) * pitch +
+                                          xa + pass * NP);
+  const int dwp = pitch >> 2;
+  uint32_t S[8][4][NQ + 1];
+#pragma unroll
+  for (int row = 0; row < 8; ++row) {
+    uint32_t raw[NDW];
+#pragma unroll
+    for (int j = 0; j < NDW; ++j) raw[j] = src[row * dwp + j];
+    shifts<NQ>(raw, S[row]);
+  }
+  const int nrow = iy1 - iy0;
+  uint64_t best = kKeyNone;
+  for (int g = 0; g < nrow; g += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = g + u;
+      if (t >= nrow) break;
+      // Keep each step's loads and shifts in its own step: hoisting them
+      // across steps multiplies the live registers.
+      __builtin_amdgcn_sched_barrier(0);
+      const int dy = cym - r + iy0 + t;
+      uint32_t nxt[NDW];
+      const bool more = t + 1 < nrow;
+      if (more) {
+#pragma unroll
+        for (int j = 0; j < NDW; ++j) nxt[j] = src[(t + 8) * dwp + j];
+      }
+      uint32_t acc[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) acc[k] = 0;
+#pragma unroll
+      for (int row = 0; row < 8; ++row) {
+        const int sl = (u + row) & 7;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (4 * q < rem) {
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+              acc[4 * q + o] = __builtin_amdgcn_sad_u8(c[2 * row], S[sl][o][q], acc[4 * q + o]);
+              acc[4 * q + o] =
+                  __builtin_amdgcn_sad_u8(c[2 * row + 1], S[sl][o][q + 1], acc[4 * q + o]);
+            }
+          }
+        }
+      }
+      group_sums<NP>(acc, d);
+      uint64_t rb = kKeyNone;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (4 * q < rem) {
+#pragma unroll
+          for (int o = 0; o < 4; ++o) {
+            const int k = 4 * q + o;
+            const uint64_t key = T[k] + ((uint64_t)acc[k] << 33);
+            rb = key < rb ? key : rb;
+          }
+        }
+      }
+      const uint64_t U = ((uint64_t)(s * se_len(4 * dy)) << 17) + (uint64_t)((dy + R) * span);
+      rb += U;
+      best = rb < best ? rb : best;
+      if (more) shifts<NQ>(nxt, S[u]);
+    }
+  }
+  // Passes and bands of one CU meet in its key (reset to all ones by prep).
+  if (e && (b & ((1 << (2 * sh3)) - 1)) == 0)
+    atomicMin((unsigned long long*)&jb->keys[(size_t)ctu * kNodes + node],
+              (unsigned long long)best);
+}
+
+// Seeded job owning CTU `flat` among the seeded jobs' CTUs (rlist lists the
+// seeded jobs in rctu_start order; null: job 0 alone).
+__device__ int find_rjob(cjob jobs, const int* rlist, int n_rjobs, int flat) {
+  if (!rlist) return 0;
+  int lo = 0, hi = n_rjobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[rlist[mid]].rctu_start <= flat) lo = mid;
+    else hi = mid - 1;
+  }
+  return rlist[lo];
+}
+
+// Padded reference of every seeded job: grid-stride over the seeded jobs in y
+// and over each job's [h8 + 2R][pad_pitch] bytes, in dwords, in x.
+__global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const int* rlist,
+                                                  int n_rjobs) {
+  for (int k = blockIdx.y; k < n_rjobs; k += gridDim.y) {
+    const cjob jb = (cjob)jobs_ + (rlist ? rlist[k] : 0);
+    const int R = jb->R, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
+    const int dw = jb->pad_pitch >> 2;
+    const int64_t total = (int64_t)(jb->h8 + 2 * R) * dw;
+    const uint8_t* ref = jb->ref;
+    const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0);
+    uint32_t* dst = (uint32_t*)jb->refpad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const int row = (int)(i / dw), c = (int)(i - (int64_t)row * dw);
+      const uint8_t* rp = ref + (size_t)clampi(row - R, 0, h - 1) * stride;
+      const int x = 4 * c - P;
+      uint32_t v;
+      if (dword_ok && x >= 0 && x + 3 < w) {
+        v = *(const uint32_t*)(rp + x);
+      } else {
+        v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[clampi(x + b, 0, w - 1)] << (8 * b);
+      }
+      dst[i] = v;
+    }
+  }
+}
+
+// The CUs of depth D of every seeded CTU: one single-wavefront workgroup per
+// CTU.  Each depth is its own kernel, so that its registers are allocated for
+// it alone.  NQ: quads of candidate positions per pass over the window rows
+// (1: r = 0; 2: any r, in passes of 8 positions).
+// One single-wavefront workgroup per (CTU, CU depth) in x (depths of a CTU
+// adjacent), pass of NP candidate columns in y, band of window rows in z.
+// NQ: quads of candidate columns per pass (1 when r = 0 for every job, else 2).
+template <int NQ>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void refine_kernel(
+    const JobDesc* jobs_, const int* rlist, int n_rjobs, int n_rctus) {
+  const cjob jobs = (cjob)jobs_;
+  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+  // eighth of the (CTU, depth) list so that its L2 holds one band of the
+  // frames.  (A bijection on [0, gridDim.x) whatever the dispatch order.)
+  const int gx = gridDim.x, x = blockIdx.x;
+  const int q = gx >> 3, rm = gx & 7, xcd = x & 7, k = x >> 3;
+  const int lin = xcd * q + min(xcd, rm) + k;
+  const int flat = lin >> 2, d = lin & 3;
+  if (flat >= n_rctus) return;
+  const int j = __builtin_amdgcn_readfirstlane(find_rjob(jobs, rlist, n_rjobs, flat));
+  refine_wave<NQ>(jobs + j, flat - jobs[j].rctu_start, d, blockIdx.y, blockIdx.z, gridDim.z);
+}
+
+hipError_t launch_pad(const JobDesc* jobs, const int* rlist, int n_rjobs, int64_t max_dwords,
+                      hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((max_dwords + 255) / 256, 2048);
+  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1),
+                                      (unsigned)std::min(n_rjobs, 65535)),
+                     dim3(256), 0, st, jobs, rlist, n_rjobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(const JobDesc* jobs, const int* rlist, int n_rjobs, int n_rctus,
+                         int max_r, hipStream_t st) {
+  if ((int64_t)n_rctus * 4 > INT32_MAX) return hipErrorInvalidValue;
+  // Grid: (CTU, depth) x passes of 4 NQ columns x bands of about 10 window rows.
+  const int ncand = 2 * max_r + 1, npos = ncand + 3;
+  const int nq = npos <= 4 ? 1 : 2;
+  const int npass = (npos + 4 * nq - 1) / (4 * nq);
+  const int nband = std::min(8, (ncand + 9) / 10);
+  const dim3 grid(4 * n_rctus, npass, nband), block(64);
+  if (nq == 1)
+    hipLaunchKernelGGL(refine_kernel<1>, grid, block, 0, st, jobs, rlist, n_rjobs, n_rctus);
+  else
+    hipLaunchKernelGGL(refine_kernel<2>, grid, block, 0, st, jobs, rlist, n_rjobs, n_rctus);
+  return hipGetLastError();
+}
+
+}  // namespace mr

@@ -287,7 +287,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
   P->job_off.assign(n_jobs, 0);
   P->items.clear();
   P->rlist.clear();
-  P->n_rjobs = P->n_rctus = 0;
+  P->n_rjobs = P->n_rctus = P->max_r = 0;
   P->max_pad_dwords = 0;
   P->n_ctus = 0;
   P->scratch_bytes = 0;
@@ -339,6 +339,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
       P->rlist.push_back(j);
       P->n_rjobs += 1;
       P->n_rctus += n_ctus;
+      P->max_r = std::max(P->max_r, jb.seed_r);
       continue;
     }
     int nb = choose_bands(R, P->D, P->strip, jb.ctus_w, jb.ctus_h, kLdsBudget, min_items);
@@ -417,7 +418,8 @@ hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, con
     e = launch_pad(jobs_d, rlist_d, P.n_rjobs, P.max_pad_dwords, st);
   if (e == hipSuccess && P.n_items > 0)
     e = launch_search(jobs_d, items_d, P.n_items, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
-  if (e == hipSuccess && P.n_rjobs > 0) e = launch_refine(jobs_d, rlist_d, P.n_rjobs, P.n_rctus, st);
+  if (e == hipSuccess && P.n_rjobs > 0)
+    e = launch_refine(jobs_d, rlist_d, P.n_rjobs, P.n_rctus, P.max_r, st);
   if (ev) profile_mark(ev, 2, st);
   if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, st);
   if (ev) profile_mark(ev, 3, st);

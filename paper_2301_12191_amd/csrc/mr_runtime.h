@@ -56,7 +56,7 @@ struct Plan {
   // Seeded jobs: their indices in rctu_start order, CTU total, largest padded
   // reference in dwords.
   std::vector<int> rlist;
-  int n_rjobs = 0, n_rctus = 0;
+  int n_rjobs = 0, n_rctus = 0, max_r = 0;
   int64_t max_pad_dwords = 0;
 };
 
@@ -89,7 +89,7 @@ hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t 
 hipError_t launch_pad(const JobDesc* jobs, const int* rlist, int n_rjobs, int64_t max_dwords,
                       hipStream_t st);
 hipError_t launch_refine(const JobDesc* jobs, const int* rlist, int n_rjobs, int n_rctus,
-                         hipStream_t st);
+                         int max_r, hipStream_t st);
 hipError_t launch_depth_bounds(const uint8_t* ref_depth, int ref_w, int ref_h, int dep_w,
                                int dep_h, int dlo, int dhi, uint8_t* out, hipStream_t st);
 int search_occupancy(int D, int strip, size_t lds_bytes);
