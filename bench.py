@@ -16,9 +16,13 @@ Beside it the JSON line carries:
                  pruned over full search and the exact RD-cost increase; the
                  same with the reference MVs reused as search centres
                  (refinement r = 4), and the refinement stage's absdiff rate;
+  multi_qp     : one 1920x1080 pair at QPs 22/26/30/34/38 with the median QP as
+                 master (same-resolution sharing): speedup of master + bounded,
+                 seeded dependents over five full searches, RD-cost increase per QP;
   cpu_baseline : the CPU oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-pruned]
+                      [--no-multi-qp] [--no-ladder] [--no-serving]
 """
 import argparse
 import json
@@ -33,6 +37,8 @@ sys.path.insert(0, ROOT)
 PEAK_ABSDIFF = 256 * 64 * 2.4e9 * 4
 # Refinement half-width of the seeded (MV reuse) variant.
 REFINE_R = 4
+# ... and of the same-resolution multi-QP dependents (exact co-located MVs).
+MULTI_QP_R = 2
 
 
 def log(msg):
@@ -46,6 +52,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
+    ap.add_argument("--no-multi-qp", action="store_true")
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -225,6 +232,52 @@ def main():
             "frac_of_peak_pad_plus_refine": round(absdiff / (st_ms * 1e-3) / PEAK_ABSDIFF, 4)}
         log(f"refine: {pruned['refine']}")
 
+    # ------------------------------------------- one resolution, five QPs, median master
+    multi_qp = None
+    if not args.no_multi_qp:
+        log("multi-QP: 1920x1080 at QPs 22..38, QP 30 master")
+        src = synth.Scene(synth.SEED_BASE + 5, 1920, 1080, 24, 48, 4)
+        r_t = torch.from_numpy(src.render(0)).to(dev)
+        c_t = torch.from_numpy(src.render(1)).to(dev)
+        qps, master_qp, R = [22, 26, 30, 34, 38], 30, 64
+        deps = [q for q in qps if q != master_qp]
+        outs_full = {q: mr.alloc_outputs(1920, 1080, dev) for q in qps}
+        outs_re = {q: mr.alloc_outputs(1920, 1080, dev) for q in qps}
+
+        def run_full():
+            mr.mr_ctu_search_batch([dict(cur=c_t, ref=r_t, qp=q, search_range=R, out=outs_full[q])
+                                    for q in qps])
+
+        def run_reuse():
+            m = mr.mr_ctu_search(c_t, r_t, master_qp, R, out=outs_re[master_qp])
+            b = mr.mr_depth_bounds(m["depth"], 1920, 1080, 1920, 1080, 1, 1)
+            seed = dict(ref_mv=m["mv"], ref_w=1920, ref_h=1080, r=MULTI_QP_R)
+            mr.mr_ctu_search_batch([dict(cur=c_t, ref=r_t, qp=q, search_range=R, bounds=b,
+                                         seed=seed, out=outs_re[q]) for q in deps])
+
+        times = {}
+        for name, fn in (("full", run_full), ("reuse", run_reuse)):
+            fn()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - ta) * 1e3 / 3
+        per_qp = {}
+        for q in qps:
+            jf = int(outs_full[q]["cost"].sum().item())
+            jr = int(outs_re[q]["cost"].sum().item())
+            per_qp[str(q)] = round(100.0 * (jr - jf) / jf, 6)
+        multi_qp = {
+            "workload": "1920x1080 pair, R 64, QPs 22/26/30/34/38; full: one batch of 5 full "
+                        "searches; reuse: QP 30 full search, then QPs 22/26/34/38 in one batch "
+                        f"bounded by its depths (d-1..d+1) and seeded by its MVs (r = {MULTI_QP_R})",
+            "full_ms": round(times["full"], 3), "reuse_ms": round(times["reuse"], 3),
+            "speedup": round(times["full"] / times["reuse"], 4),
+            "rd_cost_increase_pct_per_qp": per_qp}
+        log(f"multi-QP: {multi_qp}")
+
     # ------------------------------------------------------- six-rung ladder, one launch
     ladder = None
     if not args.no_ladder:
@@ -346,7 +399,7 @@ def main():
         "config": {"workload": "1920x1080 luma, 8 frame pairs, full search R64 QP27",
                    "ctus_per_step": ctus_per_step, "frames": NP + 1, "search_range": R,
                    "qp": QP},
-        "roofline": roofline, "cpu_baseline": cpu, "pruned": pruned, "ladder": ladder,
+        "roofline": roofline, "cpu_baseline": cpu, "pruned": pruned, "multi_qp": multi_qp, "ladder": ladder,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

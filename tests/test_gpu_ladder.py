@@ -167,3 +167,51 @@ def test_mv_reuse_dependents_equal_seeded_alone(mr):
         exp = _alone(mr, fr, *key, cache, refine=4)
         for k in FIELDS:
             assert np.array_equal(got[key][k], exp[k]), (key, k)
+
+
+def test_multi_qp_ladder_with_median_master(mr):
+    """One resolution at QPs 22, 26, 30, 34, 38 with the QP-30 rung as the master of the
+    others (bounds d-1..d+1 at ratio 1 and MV reuse r = 2): every job equals the seeded
+    search run alone with the master job's depths and MVs."""
+    import torch
+    qps = [22, 26, 30, 34, 38]
+    rungs = [dict(width=320, height=180, qp=q, search_range=16, ref_rung=-1 if q == 30 else 2)
+             for q in qps]
+    fr = {}
+    for s in range(2):
+        src = synth.Scene(synth.SEED_BASE + 40 + 1000 * s, 1920, 1080, 12, 30, 4)
+        for f in range(3):
+            img = torch.from_numpy(synth.box_downscale(src.render(f), 6, 320, 180)).cuda()
+            for r in range(5):
+                fr[(s, f, r)] = img
+    jobs = [(s, f, r) for s in range(2) for f in (1, 2) for r in (0, 4, 2, 1, 3)]
+    lad = mr.Ladder(rungs, delta_lo=1, delta_hi=1, refine_range=2)
+    got = {}
+    try:
+        for (s, f, r), t in fr.items():
+            lad.put_frame(s, f, r, t)
+        ids = {lad.submit(*j): j for j in jobs}
+        deadline = 2000
+        while len(got) < len(ids) and deadline > 0:
+            for c in lad.poll(64, 100000):
+                assert c.status == 0
+                if c.job_id in ids:
+                    torch.cuda.synchronize()
+                    got[ids[c.job_id]] = {k: v.cpu().numpy() for k, v in lad.outputs(c).items()}
+                lad.release(c.job_id)
+            deadline -= 1
+        st = lad.stats()
+    finally:
+        lad.close()
+    assert len(got) == len(jobs) and st["failed"] == 0
+    for (s, f, r) in jobs:
+        master = mr.mr_ctu_search(fr[(s, f, 2)], fr[(s, f - 1, 2)], 30, 16)
+        if r == 2:
+            exp = master
+        else:
+            b = mr.mr_depth_bounds(master["depth"], 320, 180, 320, 180, 1, 1)
+            exp = mr.mr_ctu_search(fr[(s, f, r)], fr[(s, f - 1, r)], qps[r], 16, bounds=b,
+                                   seed=dict(ref_mv=master["mv"], ref_w=320, ref_h=180, r=2))
+        torch.cuda.synchronize()
+        for k in FIELDS:
+            assert np.array_equal(got[(s, f, r)][k], exp[k].cpu().numpy()), ((s, f, r), k)

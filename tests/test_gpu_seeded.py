@@ -3,8 +3,9 @@
 libmr's mr_ctu_search_seeded (HIP, through the C ABI) against the oracle's seeded
 search, element by element: depth, mode, MV per 8x8 unit and J / D / R per CTU.
 Seed maps are seeded random fields (any MV map is a valid input) or the oracle's
-own search of a downscaled picture.  Window widths 2r+1 cover one, two and three
-register passes of 16 candidates; r = R must equal the full search.
+own search of a downscaled picture.  Window widths 2r+1 cover one to five passes
+of 8 candidate columns; r = R must equal the full search.  The multi-QP chain
+(one resolution, a median-QP master) runs the same path at ratio 1.
 """
 import ctypes
 
@@ -99,9 +100,9 @@ def _rand_map(seed, w, h, amp):
     (200, 136, 32, 16, 2, 100, 68),    # dyadic
     (203, 141, 37, 9, 3, 135, 94),     # ratio 3/2, sizes not multiples of 8
     (130, 70, 45, 24, 7, 260, 140),    # seed from a larger picture
-    (96, 200, 12, 32, 8, 48, 100),     # window of 17 candidates: two passes
-    (416, 240, 32, 16, 15, 208, 120),  # 31 candidates: two passes
-    (416, 240, 32, 20, 16, 208, 120),  # 33 candidates: three passes
+    (96, 200, 12, 32, 8, 48, 100),     # window of 17 candidates: three passes
+    (416, 240, 32, 16, 15, 208, 120),  # 31 candidates: four passes
+    (416, 240, 32, 20, 16, 208, 120),  # 33 candidates: five passes (two bands)
     (256, 128, 30, 40, 17, 128, 64),   # 35 candidates, centres clamped to +-23
 ])
 def test_seeded_matches_oracle(mr, W, H, qp, R, r, rw, rh):
@@ -253,3 +254,24 @@ def test_mixed_batch_and_graph_replays(mr):
             bt.set_jobs(bad)
     finally:
         bt.close()
+
+
+def test_multi_qp_chain_same_resolution(mr):
+    """416x240 at QP 30 (master, full search) bounds (ratio 1, depths d-1..d+1) and seeds
+    (r = 2) the same pair at QPs 22, 26, 34 and 38; GPU chain against the oracle's chain."""
+    import torch
+    W, H, R = 416, 240, 16
+    ref, cur = _pair(81, W, H, 6, 12, 2)
+    g_m = _gpu(mr, cur, ref, 30, R)
+    o_m = _oracle(cur, ref, 30, R)
+    _compare(g_m, o_m, W, H, label="QP 30 master")
+    gb = mr.mr_depth_bounds(_dev(g_m["depth"]), W, H, W, H, 1, 1)
+    torch.cuda.synchronize()
+    ob = oracle.depth_bounds(o_m["depth"], W, H, W, H, 1, 1)
+    assert np.array_equal(gb.cpu().numpy(), ob)
+    gmv = _dev(g_m["mv"])
+    for qp in (22, 26, 34, 38):
+        got = _host(mr.mr_ctu_search(_dev(cur), _dev(ref), qp, R, bounds=gb,
+                                     seed=dict(ref_mv=gmv, ref_w=W, ref_h=H, r=2)))
+        exp = _oracle(cur, ref, qp, R, bounds=ob, seed=(o_m["mv"], W, H, 2))
+        _compare(got, exp, W, H, label=f"QP {qp} dependent")

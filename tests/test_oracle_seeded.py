@@ -236,3 +236,48 @@ def test_global_shift_found_from_scaled_seed(sx, sy):
             if cx0 + sx >= 0 and cy0 + sy >= 0 and cx0 + n + sx <= W and cy0 + n + sy <= H:
                 assert tuple(out_hit["mv"][uy, ux]) == (sx, sy)
             assert np.all(np.abs(out_miss["mv"][uy, ux]) <= 1)
+
+
+# ------------------------------------------------- same resolution, several QPs
+@pytest.mark.parametrize("r", [0, 1, 3, 6])
+def test_same_qp_reuse_with_forced_depths_reproduces_the_master(r):
+    """Ratio 1, same QP: the master's depths forced by (0, 0) bounds and its MVs as centres.
+    Every CU of the forced partition is the master's CU, its centre is the master's MV (the
+    full-search optimum over [-R, R]^2), and the clamped window still contains that MV, so the
+    restricted arg-min is the same MV and every output equals the master's, for any r."""
+    W, H, R, qp = 200, 136, 6, 30
+    sc = synth.Scene(71, W, H, 5, 6, 2)
+    ref, cur = sc.render(0), sc.render(1)
+    master = oracle.ctu_search(cur, ref, qp, R)
+    b = oracle.depth_bounds(master["depth"], W, H, W, H, 0, 0)
+    dep = oracle.ctu_search(cur, ref, qp, R, bounds=b, seed=oracle.Seed(master["mv"], W, H, r))
+    for k in master:
+        assert np.array_equal(dep[k], master[k]), k
+
+
+def test_multi_qp_dependents_stay_within_their_bounds_and_windows():
+    """QPs 22, 26, 34, 38 reusing the QP-30 master (bounds (1, 1) at ratio 1, seed r = 2): every
+    unit's depth lies within one of the master's, every MV within 2 of the master MV at the
+    unit's CU centre, and J = D * 65536 + s * R per CTU.  (A CTU's J may fall below the full
+    search's: motion is chosen by SAD cost, the leaf by SATD.)"""
+    W, H, R, r = 136, 72, 8, 2
+    sc = synth.Scene(72, W, H, 5, 7, 2)
+    ref, cur = sc.render(0), sc.render(1)
+    master = oracle.ctu_search(cur, ref, 30, R)
+    b = oracle.depth_bounds(master["depth"], W, H, W, H, 1, 1)
+    seed = oracle.Seed(master["mv"], W, H, r)
+    for qp in (22, 26, 34, 38):
+        dep = oracle.ctu_search(cur, ref, qp, R, bounds=b, seed=seed)
+        full = oracle.ctu_search(cur, ref, qp, R)
+        assert np.all(np.abs(dep["depth"].astype(int) - master["depth"].astype(int)) <= 1)
+        for uy in range(H // 8):
+            for ux in range(W // 8):
+                n = 64 >> int(dep["depth"][uy, ux])
+                x0, y0 = 8 * ux - (8 * ux) % n, 8 * uy - (8 * uy) % n
+                cx, cy = oracle.mv_centre(seed, W, H, R, x0, y0, n)
+                assert abs(int(dep["mv"][uy, ux, 0]) - cx) <= r
+                assert abs(int(dep["mv"][uy, ux, 1]) - cy) <= r
+        s_q = oracle.sqrt_lambda_q16(qp)
+        assert np.array_equal(dep["cost"], dep["dist"] * 65536 + s_q * dep["bits"])
+        assert not np.array_equal(dep["depth"], full["depth"]) or \
+            not np.array_equal(dep["mv"], full["mv"]) or np.array_equal(dep["cost"], full["cost"])
