@@ -19,10 +19,13 @@ Beside it the JSON line carries:
   multi_qp     : one 1920x1080 pair at QPs 22/26/30/34/38 with the median QP as
                  master (same-resolution sharing): speedup of master + bounded,
                  seeded dependents over five full searches, RD-cost increase per QP;
+  dag          : the multi-encoding scheme (3 resolutions x 5 QPs, median-QP masters
+                 chained 540p -> 1080p -> 2160p) through the ladder server, frame by
+                 frame and pipelined across frames, against 15 full searches;
   cpu_baseline : the CPU oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-pruned]
-                      [--no-multi-qp] [--no-ladder] [--no-serving]
+                      [--no-multi-qp] [--no-dag] [--no-ladder] [--no-serving]
 """
 import argparse
 import json
@@ -45,6 +48,110 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def dag_spec(sizes, qps=(30, 22, 26, 34, 38)):
+    """Rungs of the multi-encoding scheme: per resolution, the median QP (first) is the master
+    of the other QPs (ratio 1: depths d-1..d+1, r = 2); masters chain across resolutions
+    (ratio 2: depths d..d+1, r = 4)."""
+    rungs = []
+    for li, (w, h, R) in enumerate(sizes):
+        for k, qp in enumerate(qps):
+            if k == 0:
+                rungs.append(dict(width=w, height=h, qp=qp, search_range=R,
+                                  ref_rung=-1 if li == 0 else 5 * (li - 1),
+                                  delta_lo=0, delta_hi=1, refine_range=REFINE_R))
+            else:
+                rungs.append(dict(width=w, height=h, qp=qp, search_range=R, ref_rung=5 * li,
+                                  delta_lo=1, delta_hi=1, refine_range=MULTI_QP_R))
+    return rungs
+
+
+def run_dag(mr, synth, torch, dev, n_frames=4):
+    """The 15-representation DAG served frame by frame and pipelined (all frames submitted at
+    once: tiers of frame t overlap masters of frame t + 1), against 15 full searches."""
+    sizes = [(960, 540, 32), (1920, 1080, 64), (3840, 2160, 128)]
+    rungs = dag_spec(sizes)
+    src = synth.Scene(synth.SEED_BASE + 6, 3840, 2160, 24, 96, 8)
+    frames = {}
+    for f in range(n_frames + 1):
+        img = src.render(f)
+        for (w, h, _), k in zip(sizes, (4, 2, 1)):
+            frames[(f, w)] = torch.from_numpy(synth.box_downscale(img, k, w, h)).to(dev)
+    n_ctus = sum(mr.ctu_shape(r["width"], r["height"])[0] * mr.ctu_shape(r["width"], r["height"])[1]
+                 for r in rungs)
+    # Baseline: the 15 representations of frame 1 as full searches, one batch.
+    full_jobs = [dict(cur=frames[(1, r["width"])], ref=frames[(0, r["width"])], qp=r["qp"],
+                      search_range=r["search_range"]) for r in rungs]
+    mr.mr_ctu_search_batch(full_jobs)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    outs = mr.mr_ctu_search_batch(full_jobs)
+    torch.cuda.synchronize()
+    full_ms = (time.perf_counter() - ta) * 1e3
+    j_full = [int(o["cost"].sum().item()) for o in outs]
+
+    def serve(pipelined):
+        lad = mr.Ladder(rungs, max_batch_jobs=64)
+        j_dag, lat, held = {}, [], []
+        try:
+            for f in range(n_frames + 1):
+                for i, r in enumerate(rungs):
+                    lad.put_frame(0, f, i, frames[(f, r["width"])])
+            t0 = time.perf_counter()
+            order = [(f, i) for f in range(1, n_frames + 1) for i in range(len(rungs))]
+            groups = [order] if pipelined else [[x for x in order if x[0] == f]
+                                                for f in range(1, n_frames + 1)]
+            for grp in groups:
+                ids = {lad.submit(0, f, i): (f, i) for f, i in grp}
+                done, idle = 0, 0
+                while done < len(ids):
+                    got = lad.poll(64, 200000)
+                    idle = 0 if got else idle + 1
+                    if idle > 150:  # 30 s without a completion
+                        raise RuntimeError("dag: ladder made no progress")
+                    for c in got:
+                        if c.status != 0:
+                            raise RuntimeError(f"dag: job failed with status {c.status}")
+                        if c.job_id in ids:
+                            done += 1
+                            f, i = ids[c.job_id]
+                            lat.append((c.t_done_ns - c.t_arrive_ns) * 1e-6)
+                            if f == 1:  # read after the timed region (no device sync here)
+                                held.append((i, c))
+                                continue
+                        lad.release(c.job_id)
+            t1 = time.perf_counter()
+            for i, c in held:
+                j_dag[i] = int(lad.outputs(c)["cost"].sum().item())
+                lad.release(c.job_id)
+        finally:
+            lad.close()
+        return (t1 - t0) * 1e3 / n_frames, j_dag, sorted(lat)
+
+    serve(True)  # warm-up (plans, key tables, allocator)
+    seq_ms, _, _ = serve(False)
+    pipe_ms, j_dag, lat = serve(True)
+    rd = {}
+    for li, (w, h, _) in enumerate(sizes):
+        jf = sum(j_full[5 * li:5 * li + 5])
+        jd = sum(j_dag[i] for i in range(5 * li, 5 * li + 5))
+        rd[f"{w}x{h}"] = round(100.0 * (jd - jf) / jf, 6)
+    pct = lambda p: lat[min(len(lat) - 1, max(0, int(p * len(lat) + 0.999999) - 1))]
+    return {
+        "workload": f"{n_frames} frames of 960x540 (R32) / 1920x1080 (R64) / 3840x2160 (R128) x "
+                    "QPs 30/22/26/34/38 = 15 representations per frame; per resolution the QP-30 "
+                    "job masters the others (depths d-1..d+1, r = 2); QP-30 masters chain "
+                    "540p -> 1080p -> 2160p (depths d..d+1, r = 4); ladder server, one stream",
+        "ctus_per_frame": n_ctus,
+        "full_search_frame_ms": round(full_ms, 3),
+        "dag_frame_by_frame_ms": round(seq_ms, 3),
+        "dag_pipelined_frame_ms": round(pipe_ms, 3),
+        "speedup_pipelined_vs_full": round(full_ms / pipe_ms, 3),
+        "pipelining_gain": round(seq_ms / pipe_ms, 3),
+        "pipelined_ctus_per_s": round(n_ctus / (pipe_ms * 1e-3), 1),
+        "job_latency_p50_ms": round(pct(0.5), 3), "job_latency_p99_ms": round(pct(0.99), 3),
+        "rd_cost_increase_pct_frame1": rd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +160,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
     ap.add_argument("--no-multi-qp", action="store_true")
+    ap.add_argument("--no-dag", action="store_true")
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -278,6 +386,12 @@ def main():
             "rd_cost_increase_pct_per_qp": per_qp}
         log(f"multi-QP: {multi_qp}")
 
+    # ------------------------------ multi-encoding DAG (3 resolutions x 5 QPs), served
+    dag = None
+    if not args.no_dag:
+        dag = run_dag(mr, synth, torch, dev)
+        log(f"dag: {dag}")
+
     # ------------------------------------------------------- six-rung ladder, one launch
     ladder = None
     if not args.no_ladder:
@@ -399,7 +513,7 @@ def main():
         "config": {"workload": "1920x1080 luma, 8 frame pairs, full search R64 QP27",
                    "ctus_per_step": ctus_per_step, "frames": NP + 1, "search_range": R,
                    "qp": QP},
-        "roofline": roofline, "cpu_baseline": cpu, "pruned": pruned, "multi_qp": multi_qp, "ladder": ladder,
+        "roofline": roofline, "cpu_baseline": cpu, "pruned": pruned, "multi_qp": multi_qp, "dag": dag, "ladder": ladder,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

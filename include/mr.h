@@ -192,16 +192,29 @@ int mr_batch_destroy(mr_batch* b);
  * keeps up to two batches in flight, and releases dependents as references
  * complete (continuous batching).  Done reference jobs stay resident for later
  * dependents until their memory is needed.  With reuse_mv, a dependent's
- * search is also seeded with its reference job's MV map.  Results equal
- * mr_ctu_search_seeded on the same frames (with the same bounds and seed). */
+ * search is also seeded with its reference job's MV map.  Each rung may carry
+ * its own policy (own_policy), so that one configuration holds both
+ * cross-resolution and same-resolution (multi-QP) edges, e.g. the
+ * multi-encoding scheme whose per-resolution median-QP masters chain
+ * 540p -> 1080p -> 2160p (proposed multi-encoding section).  Jobs of
+ * different frames overlap freely (a dependent of frame t runs beside its
+ * master's frame t + 1: frame-delay overlap of tiers, future-work section).
+ * Results equal mr_ctu_search_seeded on the same frames (with the same bounds
+ * and seed). */
 typedef struct {
   int32_t width, height, qp, search_range;
-  int32_t ref_rung; /* index of the rung whose depths bound this one, -1 = none */
+  int32_t ref_rung;   /* index of the rung whose job bounds (and seeds) this one, -1 = none */
+  int32_t own_policy; /* 0: the config's delta_lo/delta_hi/reuse_mv/refine_range apply;
+                         1: this rung's four fields below (same ranges) */
+  int32_t delta_lo, delta_hi;
+  int32_t reuse_mv, refine_range;
 } mr_rung;
 
+#define MR_MAX_RUNGS 16
+
 typedef struct {
-  int32_t n_rungs;       /* 1..8 */
-  mr_rung rungs[8];
+  int32_t n_rungs;       /* 1..MR_MAX_RUNGS */
+  mr_rung rungs[MR_MAX_RUNGS];
   int32_t delta_lo, delta_hi;  /* bound policy of dependents (0..3 each) */
   uint64_t hbm_budget_bytes;   /* admission budget, > 0 */
   int32_t max_inflight;        /* 1..65536 admitted, unfinished jobs */

@@ -40,8 +40,7 @@ struct BatchState {
 
 class GpuExecutor : public Executor {
  public:
-  GpuExecutor(const SchedConfig& cfg, int dlo, int dhi, int refine_r)
-      : cfg_(cfg), dlo_(dlo), dhi_(dhi), refine_r_(refine_r) {}
+  explicit GpuExecutor(const SchedConfig& cfg) : cfg_(cfg) {}
 
   int init() {
     if (hipGetDevice(&device_) != hipSuccess) return MR_EHIP;
@@ -92,8 +91,8 @@ class GpuExecutor : public Executor {
   }
 
   // Refinement half-width of a rung's jobs, -1 for the full search.
-  int refine_of(const RungCfg& r) const {
-    return (refine_r_ >= 0 && r.ref_rung >= 0) ? std::min(refine_r_, r.search_range) : -1;
+  static int refine_of(const RungCfg& r) {
+    return (r.refine >= 0 && r.ref_rung >= 0) ? std::min(r.refine, r.search_range) : -1;
   }
 
   size_t footprint(const SchedJob& j) override {
@@ -147,8 +146,8 @@ class GpuExecutor : public Executor {
         const RungCfg& rr = cfg_.rungs[r.ref_rung];
         const JobOut* ro = (const JobOut*)ref_state_(j.ref_job);
         if (!ro) return MR_EDEPEND;
-        if (launch_depth_bounds(ro->out.depth, rr.width, rr.height, r.width, r.height, dlo_, dhi_,
-                                o->bounds, st) != hipSuccess)
+        if (launch_depth_bounds(ro->out.depth, rr.width, rr.height, r.width, r.height, r.dlo,
+                                r.dhi, o->bounds, st) != hipSuccess)
           return MR_EHIP;
         bnd[i] = o->bounds;
         const int rr_refine = refine_of(r);
@@ -230,8 +229,6 @@ class GpuExecutor : public Executor {
 
  private:
   SchedConfig cfg_;
-  int dlo_, dhi_;
-  int refine_r_;  // -1: dependents are not seeded
   int device_ = 0;
   hipStream_t streams_[2] = {nullptr, nullptr};
   unsigned next_ = 0;
@@ -281,21 +278,31 @@ extern "C" {
 int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
   if (!out) return MR_EINVAL;
   *out = nullptr;
-  if (!cfg || cfg->n_rungs < 1 || cfg->n_rungs > 8 || cfg->delta_lo < 0 || cfg->delta_lo > 3 ||
-      cfg->delta_hi < 0 || cfg->delta_hi > 3 || cfg->hbm_budget_bytes == 0 ||
+  auto policy_ok = [](int dlo, int dhi, int reuse, int refine) {
+    return dlo >= 0 && dlo <= 3 && dhi >= 0 && dhi <= 3 && reuse >= 0 && reuse <= 1 &&
+           (!reuse || (refine >= 0 && refine <= 128));
+  };
+  if (!cfg || cfg->n_rungs < 1 || cfg->n_rungs > MR_MAX_RUNGS ||
+      !policy_ok(cfg->delta_lo, cfg->delta_hi, cfg->reuse_mv, cfg->refine_range) ||
+      cfg->hbm_budget_bytes == 0 ||
       cfg->max_inflight < 1 || cfg->max_inflight > 65536 || cfg->max_queue < 1 ||
-      cfg->max_queue > (1 << 20) || cfg->max_batch_jobs < 1 || cfg->max_batch_jobs > 4096 ||
-      cfg->reuse_mv < 0 || cfg->reuse_mv > 1 ||
-      (cfg->reuse_mv && (cfg->refine_range < 0 || cfg->refine_range > 128)))
+      cfg->max_queue > (1 << 20) || cfg->max_batch_jobs < 1 || cfg->max_batch_jobs > 4096)
     return MR_EINVAL;
   SchedConfig sc;
   for (int r = 0; r < cfg->n_rungs; ++r) {
     const mr_rung& g = cfg->rungs[r];
     if (g.width < 1 || g.height < 1 || g.width > 8192 || g.height > 8192 || g.qp < 0 ||
         g.qp > 51 || g.search_range < 0 || g.search_range > 128 || g.ref_rung < -1 ||
-        g.ref_rung >= cfg->n_rungs || g.ref_rung == r)
+        g.ref_rung >= cfg->n_rungs || g.ref_rung == r || g.own_policy < 0 || g.own_policy > 1 ||
+        (g.own_policy && !policy_ok(g.delta_lo, g.delta_hi, g.reuse_mv, g.refine_range)))
       return MR_EINVAL;
-    sc.rungs.push_back(RungCfg{g.width, g.height, g.qp, g.search_range, g.ref_rung});
+    RungCfg rc{g.width, g.height, g.qp, g.search_range, g.ref_rung};
+    const bool own = g.own_policy != 0;
+    rc.dlo = own ? g.delta_lo : cfg->delta_lo;
+    rc.dhi = own ? g.delta_hi : cfg->delta_hi;
+    const int reuse = own ? g.reuse_mv : cfg->reuse_mv;
+    rc.refine = reuse ? (own ? g.refine_range : cfg->refine_range) : -1;
+    sc.rungs.push_back(rc);
   }
   // Reference chains must end (no cycles).
   for (int r = 0; r < cfg->n_rungs; ++r) {
@@ -309,8 +316,7 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
   sc.max_batch_jobs = cfg->max_batch_jobs;
   mr_ladder* l = new mr_ladder();
   l->cfg = sc;
-  l->ex.reset(new GpuExecutor(sc, cfg->delta_lo, cfg->delta_hi,
-                              cfg->reuse_mv ? cfg->refine_range : -1));
+  l->ex.reset(new GpuExecutor(sc));
   if (l->ex->init() != MR_OK) {
     delete l;
     return MR_EHIP;

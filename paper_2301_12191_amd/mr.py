@@ -336,13 +336,20 @@ def mr_autotune(jobs, reps: int = 3) -> dict:
 
 
 # ------------------------------------------------------------------ ladder server
+MR_MAX_RUNGS = 16
+
+
 class mr_rung(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("qp", ctypes.c_int32),
-                ("search_range", ctypes.c_int32), ("ref_rung", ctypes.c_int32)]
+                ("search_range", ctypes.c_int32), ("ref_rung", ctypes.c_int32),
+                ("own_policy", ctypes.c_int32), ("delta_lo", ctypes.c_int32),
+                ("delta_hi", ctypes.c_int32), ("reuse_mv", ctypes.c_int32),
+                ("refine_range", ctypes.c_int32)]
 
 
 class mr_ladder_config(ctypes.Structure):
-    _fields_ = [("n_rungs", ctypes.c_int32), ("rungs", mr_rung * 8), ("delta_lo", ctypes.c_int32),
+    _fields_ = [("n_rungs", ctypes.c_int32), ("rungs", mr_rung * MR_MAX_RUNGS),
+                ("delta_lo", ctypes.c_int32),
                 ("delta_hi", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_int32), ("max_queue", ctypes.c_int32),
                 ("max_batch_jobs", ctypes.c_int32), ("reuse_mv", ctypes.c_int32),
@@ -410,10 +417,18 @@ class Ladder:
                  max_queue=8192, max_batch_jobs=64, refine_range=None):
         L = _ladder_lib()
         cfg = mr_ladder_config()
+        if not 1 <= len(rungs) <= MR_MAX_RUNGS:
+            raise ValueError(f"1..{MR_MAX_RUNGS} rungs")
         cfg.n_rungs = len(rungs)
         for i, r in enumerate(rungs):
+            # A rung dict with any of delta_lo / delta_hi / refine_range carries its own policy
+            # (refine_range None or absent: not seeded); otherwise the ladder-wide one applies.
+            own = any(k in r for k in ("delta_lo", "delta_hi", "refine_range"))
+            rr = r.get("refine_range")
             cfg.rungs[i] = mr_rung(r["width"], r["height"], r["qp"], r["search_range"],
-                                   r.get("ref_rung", -1))
+                                   r.get("ref_rung", -1), 1 if own else 0, r.get("delta_lo", 0),
+                                   r.get("delta_hi", 1), 0 if rr is None else 1,
+                                   0 if rr is None else rr)
         cfg.delta_lo, cfg.delta_hi = delta_lo, delta_hi
         cfg.hbm_budget_bytes = budget_bytes
         cfg.max_inflight, cfg.max_queue, cfg.max_batch_jobs = max_inflight, max_queue, max_batch_jobs

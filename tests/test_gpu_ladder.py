@@ -215,3 +215,62 @@ def test_multi_qp_ladder_with_median_master(mr):
         torch.cuda.synchronize()
         for k in FIELDS:
             assert np.array_equal(got[(s, f, r)][k], exp[k].cpu().numpy()), ((s, f, r), k)
+
+
+def test_multi_encoding_dag_through_the_ladder(mr):
+    """15 rungs (3 resolutions x 5 QPs, per-rung policies): the server's results for two frames
+    of two streams equal the DAG computed job by job."""
+    import torch
+    from dag_spec import dag_rungs
+    sizes = [(160, 96, 8), (320, 192, 16), (640, 384, 24)]
+    spec = dag_rungs(sizes)
+    rungs = [dict(width=w, height=h, qp=q, search_range=R, ref_rung=ref, delta_lo=dlo,
+                  delta_hi=dhi, refine_range=r) for (w, h, q, R, ref, dlo, dhi, r) in spec]
+    fr = {}
+    for s in range(2):
+        src = synth.Scene(synth.SEED_BASE + 50 + 1000 * s, 640, 384, 8, 16, 2)
+        for f in range(3):
+            img = src.render(f)
+            for i, (w, h, *_rest) in enumerate(spec):
+                k = 640 // w
+                fr[(s, f, i)] = torch.from_numpy(synth.box_downscale(img, k, w, h)).cuda()
+    # Submit the leaves first: the server implies their masters.
+    jobs = [(s, f, i) for f in (1, 2) for s in range(2) for i in reversed(range(15))]
+    lad = mr.Ladder(rungs, max_batch_jobs=16)
+    got = {}
+    try:
+        for key, t in fr.items():
+            lad.put_frame(*key, t)
+        ids = {}
+        for j in jobs:
+            ids[lad.submit(*j)] = j
+        deadline = 4000
+        while len(got) < len(ids) and deadline > 0:
+            for c in lad.poll(64, 100000):
+                assert c.status == 0
+                if c.job_id in ids:
+                    torch.cuda.synchronize()
+                    got[ids[c.job_id]] = {k: v.cpu().numpy() for k, v in lad.outputs(c).items()}
+                lad.release(c.job_id)
+            deadline -= 1
+        st = lad.stats()
+    finally:
+        lad.close()
+    assert len(got) == len(jobs) and st["failed"] == 0
+    for s in range(2):
+        for f in (1, 2):
+            alone = []
+            for i, (w, h, q, R, ref, dlo, dhi, r) in enumerate(spec):
+                cur, prev = fr[(s, f, i)], fr[(s, f - 1, i)]
+                if ref < 0:
+                    o = mr.mr_ctu_search(cur, prev, q, R)
+                else:
+                    rw, rh = spec[ref][:2]
+                    b = mr.mr_depth_bounds(alone[ref]["depth"], rw, rh, w, h, dlo, dhi)
+                    o = mr.mr_ctu_search(cur, prev, q, R, bounds=b,
+                                         seed=dict(ref_mv=alone[ref]["mv"], ref_w=rw, ref_h=rh,
+                                                   r=r))
+                alone.append(o)
+                torch.cuda.synchronize()
+                for k in FIELDS:
+                    assert np.array_equal(got[(s, f, i)][k], o[k].cpu().numpy()), ((s, f, i), k)

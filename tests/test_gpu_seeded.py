@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import synth
+from dag_spec import dag_rungs
 
 pytestmark = pytest.mark.gpu
 
@@ -275,3 +276,30 @@ def test_multi_qp_chain_same_resolution(mr):
                                      seed=dict(ref_mv=gmv, ref_w=W, ref_h=H, r=2)))
         exp = _oracle(cur, ref, qp, R, bounds=ob, seed=(o_m["mv"], W, H, 2))
         _compare(got, exp, W, H, label=f"QP {qp} dependent")
+
+
+def test_multi_encoding_dag_against_oracle(mr):
+    import torch
+    sizes = [(160, 96, 8), (320, 192, 16), (640, 384, 24)]
+    src = synth.Scene(synth.SEED_BASE + 9, 640, 384, 8, 16, 2)
+    s0, s1 = src.render(0), src.render(1)
+    frames = {}
+    for (w, h, _), k in zip(sizes, (4, 2, 1)):
+        frames[w] = (synth.box_downscale(s0, k, w, h), synth.box_downscale(s1, k, w, h))
+    got, exp = [], []
+    for (w, h, qp, R, ref, dlo, dhi, r) in dag_rungs(sizes):
+        f0, f1 = frames[w]
+        if ref < 0:
+            g = _gpu(mr, f1, f0, qp, R)
+            o = _oracle(f1, f0, qp, R)
+        else:
+            rw, rh = dag_rungs(sizes)[ref][:2]
+            gb = mr.mr_depth_bounds(_dev(got[ref]["depth"]), rw, rh, w, h, dlo, dhi)
+            g = _host(mr.mr_ctu_search(_dev(f1), _dev(f0), qp, R, bounds=gb,
+                                       seed=dict(ref_mv=_dev(got[ref]["mv"]), ref_w=rw,
+                                                 ref_h=rh, r=r)))
+            ob = oracle.depth_bounds(exp[ref]["depth"], rw, rh, w, h, dlo, dhi)
+            o = _oracle(f1, f0, qp, R, bounds=ob, seed=(exp[ref]["mv"], rw, rh, r))
+        _compare(g, o, w, h, label=f"{w}x{h} QP {qp}")
+        got.append(g)
+        exp.append(o)

@@ -172,6 +172,34 @@ def test_ladder_rejects_invalid_mv_reuse_config(libmr, reuse, r):
     assert not h.value
 
 
+@pytest.mark.parametrize("case", ["too_many_rungs", "own_policy_2", "rung_delta", "rung_refine",
+                                  "cycle"])
+def test_ladder_rejects_invalid_rung_policies(libmr, case):
+    from paper_2301_12191_amd import mr
+    L = mr._ladder_lib()
+    cfg = mr.mr_ladder_config()
+    cfg.n_rungs = 3
+    cfg.rungs[0] = mr.mr_rung(64, 64, 30, 8, -1)
+    cfg.rungs[1] = mr.mr_rung(128, 128, 30, 16, 0, 1, 0, 1, 1, 4)
+    cfg.rungs[2] = mr.mr_rung(128, 128, 34, 16, 1, 1, 1, 1, 1, 2)
+    cfg.delta_lo, cfg.delta_hi = 0, 1
+    cfg.hbm_budget_bytes = 1 << 30
+    cfg.max_inflight, cfg.max_queue, cfg.max_batch_jobs = 8, 8, 8
+    if case == "too_many_rungs":
+        cfg.n_rungs = mr.MR_MAX_RUNGS + 1
+    elif case == "own_policy_2":
+        cfg.rungs[1].own_policy = 2
+    elif case == "rung_delta":
+        cfg.rungs[2].delta_hi = 4
+    elif case == "rung_refine":
+        cfg.rungs[1].refine_range = 129
+    elif case == "cycle":
+        cfg.rungs[1].ref_rung = 2
+    h = ctypes.c_void_p()
+    assert L.mr_ladder_open(ctypes.byref(cfg), ctypes.byref(h)) == mr.MR_EINVAL
+    assert not h.value
+
+
 def test_tile_override_validation(libmr):
     from paper_2301_12191_amd import mr
     assert libmr.mr_set_tiles(200, 4, 1) == mr.MR_EINVAL
