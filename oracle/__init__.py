@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 NODE_FIELDS = ("kind", "mode", "mx", "my", "sad", "satd_inter", "satd_planar", "satd_dc",
-               "leaf_j", "leaf_d", "leaf_r")
+               "leaf_j", "leaf_d", "leaf_r", "qmx", "qmy")
 
 
 def build(force: bool = True) -> str:
@@ -56,11 +56,15 @@ def lib():
         L.orc_intra_predict.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, vp]
         L.orc_cu_motion_search.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, vp,
                                            vp, vp]
-        L.orc_ctu_nodes.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, i32, i32,
-                                    i32, vp]
-        L.orc_ctu_search.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, i32, i32, i32, vp,
-                                     vp, vp, vp, vp, vp, vp, i32, i32]
-        L.orc_mv_centre.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, vp, vp]
+        L.orc_ctu_nodes.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, vp, i32,
+                                    i32, i32, i32, vp]
+        L.orc_ctu_search.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, i32,
+                                     i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32]
+        L.orc_mv_centre.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, i32, vp,
+                                    vp]
+        L.orc_interp_qpel.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.orc_subpel_refine.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32,
+                                        vp, vp, vp]
         L.orc_depth_bounds.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp]
         _lib = L
     return _lib
@@ -105,47 +109,51 @@ def cu_motion_search(cur, ref, x0, y0, n, R, qp):
 
 class Seed:
     """Reference MVs for a seeded search: the [ceil(ref_h/8), ceil(ref_w/8), 2] int16 MV map of
-    a ref_w x ref_h search of the same content, and the refinement half-width r."""
+    a ref_w x ref_h search of the same content (quarter-pel units when qpel), and the
+    refinement half-width r."""
 
-    def __init__(self, ref_mv, ref_w: int, ref_h: int, r: int):
+    def __init__(self, ref_mv, ref_w: int, ref_h: int, r: int, qpel: bool = False):
         self.ref_mv = np.ascontiguousarray(ref_mv, dtype=np.int16)
         assert self.ref_mv.shape == ((ref_h + 7) // 8, (ref_w + 7) // 8, 2)
         self.ref_w, self.ref_h, self.r = int(ref_w), int(ref_h), int(r)
+        self.qpel = 1 if qpel else 0
 
     def args(self):
-        return (_p(self.ref_mv), self.ref_w, self.ref_h, self.r)
+        return (_p(self.ref_mv), self.ref_w, self.ref_h, self.r, self.qpel)
 
 
-_NO_SEED = (None, 0, 0, 0)
+_NO_SEED = (None, 0, 0, 0, 0)
 
 
 def mv_centre(seed: Seed, cur_w, cur_h, R, x0, y0, n):
     """Search centre (cx, cy) of the n x n CU at (x0, y0) for a seeded search."""
     cx, cy = ctypes.c_int32(), ctypes.c_int32()
-    rc = lib().orc_mv_centre(*seed.args()[:3], cur_w, cur_h, R, seed.r, x0, y0, n,
+    rc = lib().orc_mv_centre(*seed.args()[:3], cur_w, cur_h, R, seed.r, seed.qpel, x0, y0, n,
                              ctypes.byref(cx), ctypes.byref(cy))
     if rc != 0:
         raise ValueError("orc_mv_centre: invalid arguments")
     return cx.value, cy.value
 
 
-def ctu_nodes(cur, ref, qp, R, ctu_x, ctu_y, seed: Seed | None = None) -> np.ndarray:
-    """(85, 11) int64 per-node leaf evaluation of one CTU (fields: NODE_FIELDS)."""
+def ctu_nodes(cur, ref, qp, R, ctu_x, ctu_y, seed: Seed | None = None,
+              subpel: bool = False) -> np.ndarray:
+    """(85, 13) int64 per-node leaf evaluation of one CTU (fields: NODE_FIELDS)."""
     c = np.ascontiguousarray(cur, dtype=np.uint8)
     r = np.ascontiguousarray(ref, dtype=np.uint8)
     rec = np.zeros((85, len(NODE_FIELDS)), dtype=np.int64)
     sa = seed.args() if seed is not None else _NO_SEED
-    rc = lib().orc_ctu_nodes(_p(c), _p(r), c.shape[1], c.shape[0], c.shape[1], qp, R, ctu_x,
-                             ctu_y, *sa, _p(rec))
+    rc = lib().orc_ctu_nodes(_p(c), _p(r), c.shape[1], c.shape[0], c.shape[1], qp, R,
+                             1 if subpel else 0, ctu_x, ctu_y, *sa, _p(rec))
     if rc != 0:
         raise ValueError("orc_ctu_nodes: invalid arguments")
     return rec
 
 
 def ctu_search(cur, ref, qp, R, bounds=None, ctu_list=None, n_threads=0,
-               seed: Seed | None = None):
+               seed: Seed | None = None, subpel: bool = False):
     """Coding-tree search of a frame pair (all CTUs or a listed subset); seeded when ``seed``
-    is given.
+    is given; with ``subpel`` the inter MVs are refined to quarter-pel (and output in
+    quarter-pel units).
 
     Returns a dict of numpy arrays: depth, mode ([H8/8, W8/8] u8), mv ([H8/8, W8/8, 2] i16),
     cost, dist, bits ([ceil(H/64), ceil(W/64)] i64).  Units of CTUs outside the list keep 0.
@@ -167,7 +175,8 @@ def ctu_search(cur, ref, qp, R, bounds=None, ctu_list=None, n_threads=0,
     if ctu_list is not None:
         lst = np.ascontiguousarray(np.asarray(ctu_list, dtype=np.int32))
     sa = seed.args() if seed is not None else _NO_SEED
-    rc = lib().orc_ctu_search(_p(c), _p(r), W, H, W, qp, R, _p(b), *sa, _p(out["depth"]),
+    rc = lib().orc_ctu_search(_p(c), _p(r), W, H, W, qp, R, 1 if subpel else 0, _p(b), *sa,
+                              _p(out["depth"]),
                               _p(out["mode"]), _p(out["mv"]), _p(out["cost"]), _p(out["dist"]),
                               _p(out["bits"]), _p(lst), 0 if lst is None else len(lst),
                               n_threads)
@@ -184,3 +193,25 @@ def depth_bounds(ref_depth, ref_w, ref_h, dep_w, dep_h, delta_lo, delta_hi):
     if rc != 0:
         raise ValueError("orc_depth_bounds: invalid arguments")
     return out
+
+
+def interp_qpel(ref, qx: int, qy: int) -> int:
+    """Interpolated 8-bit prediction sample at quarter-pel position (qx, qy) of ``ref``."""
+    r = np.ascontiguousarray(ref, dtype=np.uint8)
+    v = lib().orc_interp_qpel(_p(r), r.shape[1], r.shape[0], r.shape[1], qx, qy)
+    if v < 0:
+        raise ValueError("orc_interp_qpel: invalid arguments")
+    return int(v)
+
+
+def subpel_refine(cur, ref, x0, y0, n, mx, my, qp):
+    """Quarter-pel refinement of the integer MV (mx, my) of one CU: (qx, qy, satd)."""
+    c = np.ascontiguousarray(cur, dtype=np.uint8)
+    r = np.ascontiguousarray(ref, dtype=np.uint8)
+    assert c.shape == r.shape
+    qx, qy, sd = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    rc = lib().orc_subpel_refine(_p(c), _p(r), c.shape[1], c.shape[0], c.shape[1], x0, y0, n,
+                                 mx, my, qp, ctypes.byref(qx), ctypes.byref(qy), ctypes.byref(sd))
+    if rc != 0:
+        raise ValueError("orc_subpel_refine: invalid arguments")
+    return qx.value, qy.value, sd.value

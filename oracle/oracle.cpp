@@ -45,6 +45,14 @@
  *     [-(R - r), R - r] and searches the (2r+1)^2 displacements around it
  *     with the same cost and tie order as the full search.  r = R is the
  *     full search.
+ *   - Sub-pel refinement (SATD for quarter-pel motion estimation, cost-function
+ *     subsection; interpolation filters among the thesis's optimised
+ *     functions).  READING: H.265 8-bit luma fractional interpolation with the
+ *     default uni-prediction rounding; after the integer ME, a half-pel stage
+ *     and a quarter-pel stage, each over the current best and its 8
+ *     neighbours, J = SATD * 65536 + s * (se(qx) + se(qy)) in quarter-pel
+ *     units, ties to the centre then raster order; MVs are then output in
+ *     quarter-pel units.
  *
  * No blocking, fusion or reordering: SAD is summed directly per CU and per
  * candidate; the DP is a plain recursion.
@@ -195,7 +203,8 @@ void intra_predict(const Pic& c, int x0, int y0, int n, int mode, int* pred) {
 
 struct Node {
   int kind;  // 0 absent (outside the coded picture), 1 crosses its edge, 2 inside
-  int mx, my;
+  int mx, my;          // integer ME result
+  int qmx, qmy;        // final MV in quarter-pel units (4 mx, 4 my without sub-pel refinement)
   int64_t sad;
   int64_t satd_inter, satd_planar, satd_dc;
   int mode;            // 0 inter, 1 planar, 2 DC
@@ -229,6 +238,7 @@ struct Seed {
   const int16_t* ref_mv;  // [ceil(ref_h/8)][ceil(ref_w/8)][2]
   int ref_w, ref_h;
   int r;
+  int qpel;  // 1: the map holds quarter-pel MVs (a search with sub-pel refinement)
 };
 
 // m * num / den rounded to the nearest integer, halves away from zero.
@@ -250,12 +260,91 @@ void mv_centre(const Seed& sd, int cur_w, int cur_h, int R, int x0, int y0, int 
   int ruw = (sd.ref_w + 7) / 8;
   const int16_t* m = sd.ref_mv + 2 * ((yr / 8) * ruw + xr / 8);
   int lim = R - sd.r;
-  *cx = std::clamp(scale_round(m[0], cur_w, sd.ref_w), -lim, lim);
-  *cy = std::clamp(scale_round(m[1], cur_h, sd.ref_h), -lim, lim);
+  const int unit = sd.qpel ? 4 : 1;  // map units per pixel
+  *cx = std::clamp(scale_round(m[0], cur_w, sd.ref_w * unit), -lim, lim);
+  *cy = std::clamp(scale_round(m[1], cur_h, sd.ref_h * unit), -lim, lim);
+}
+
+// ------------------------------------------------------------- sub-pel motion
+// H.265 luma fractional-sample interpolation for 8-bit samples, then the
+// default (unweighted) uni-prediction rounding back to 8 bits.  Filter taps per
+// quarter-pel phase (the standard's luma interpolation filter table).
+const int kLumaTaps[4][8] = {{0, 0, 0, 64, 0, 0, 0, 0},
+                             {-1, 4, -10, 58, 17, -5, 1, 0},
+                             {-1, 4, -11, 40, 40, -11, 4, -1},
+                             {0, 1, -5, 17, 58, -10, 4, -1}};
+
+// Floor division of a quarter-pel coordinate into (integer, phase).
+inline void qsplit(int q, int* i, int* f) {
+  *f = q & 3;
+  *i = (q - *f) / 4;
+}
+
+// Prediction sample at quarter-pel position (qx, qy) of the reference.
+// Integer positions: the sample scaled by 64; one fractional axis: the 8-tap
+// sum (no shift for 8-bit); both: horizontal sums, then the vertical 8-tap sum
+// of those shifted right by 6 (arithmetic).  Last: (v + 32) >> 6, clipped.
+int interp_qpel(const Pic& ref, int qx, int qy) {
+  int xi, fx, yi, fy;
+  qsplit(qx, &xi, &fx);
+  qsplit(qy, &yi, &fy);
+  int64_t v;
+  if (fx == 0 && fy == 0) {
+    v = (int64_t)refs(ref, xi, yi) << 6;
+  } else if (fy == 0) {
+    v = 0;
+    for (int i = 0; i < 8; ++i) v += kLumaTaps[fx][i] * refs(ref, xi + i - 3, yi);
+  } else if (fx == 0) {
+    v = 0;
+    for (int i = 0; i < 8; ++i) v += kLumaTaps[fy][i] * refs(ref, xi, yi + i - 3);
+  } else {
+    int64_t acc = 0;
+    for (int j = 0; j < 8; ++j) {
+      int64_t h = 0;
+      for (int i = 0; i < 8; ++i) h += kLumaTaps[fx][i] * refs(ref, xi + i - 3, yi + j - 3);
+      acc += kLumaTaps[fy][j] * h;
+    }
+    v = acc >> 6;  // arithmetic shift: floor
+  }
+  int64_t p = (v + 32) >> 6;
+  return (int)std::min<int64_t>(255, std::max<int64_t>(0, p));
+}
+
+// SATD of the n x n CU at (x0, y0) against the prediction at quarter-pel MV (qmx, qmy).
+int64_t satd_at_qpel(const Pic& cur, const Pic& ref, int x0, int y0, int n, int qmx, int qmy) {
+  std::vector<int> resid(n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i)
+      resid[j * n + i] =
+          coded(cur, x0 + i, y0 + j) - interp_qpel(ref, 4 * (x0 + i) + qmx, 4 * (y0 + j) + qmy);
+  return satd_block(resid.data(), n, n);
+}
+
+// Sub-pel refinement of an integer MV: a half-pel stage (step 2) and a
+// quarter-pel stage (step 1), each over the current best and its 8
+// neighbours at the step; J = SATD * 65536 + s * (se(qx) + se(qy)) with the
+// MV in quarter-pel units; the centre keeps ties, then raster order (dy outer).
+void subpel_refine(const Pic& cur, const Pic& ref, int x0, int y0, int n, int mx, int my,
+                   int64_t s, int* bqx, int* bqy, int64_t* bsatd) {
+  int qx = 4 * mx, qy = 4 * my;
+  int64_t sd = satd_at_qpel(cur, ref, x0, y0, n, qx, qy);
+  int64_t best = sd * 65536 + s * (se_bits(qx) + se_bits(qy));
+  for (int step = 2; step >= 1; --step) {
+    const int cqx = qx, cqy = qy;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (dx == 0 && dy == 0) continue;
+        const int tx = cqx + step * dx, ty = cqy + step * dy;
+        const int64_t t = satd_at_qpel(cur, ref, x0, y0, n, tx, ty);
+        const int64_t j = t * 65536 + s * (se_bits(tx) + se_bits(ty));
+        if (j < best) best = j, qx = tx, qy = ty, sd = t;
+      }
+  }
+  *bqx = qx, *bqy = qy, *bsatd = sd;
 }
 
 void evaluate_leaf(const Pic& cur, const Pic& ref, int x0, int y0, int n, int R, int64_t s,
-                   const Seed* seed, Node* nd) {
+                   const Seed* seed, bool subpel, Node* nd) {
   if (seed) {
     int cx, cy;
     mv_centre(*seed, cur.w, cur.h, R, x0, y0, n, &cx, &cy);
@@ -264,18 +353,25 @@ void evaluate_leaf(const Pic& cur, const Pic& ref, int x0, int y0, int n, int R,
     cu_motion_search(cur, ref, x0, y0, n, 0, 0, R, s, &nd->mx, &nd->my, &nd->sad);
   }
   std::vector<int> resid(n * n), pred(n * n);
-  for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i)
-      resid[j * n + i] = coded(cur, x0 + i, y0 + j) - refs(ref, x0 + i + nd->mx, y0 + j + nd->my);
-  nd->satd_inter = satd_block(resid.data(), n, n);
+  if (subpel) {
+    subpel_refine(cur, ref, x0, y0, n, nd->mx, nd->my, s, &nd->qmx, &nd->qmy, &nd->satd_inter);
+  } else {
+    nd->qmx = 4 * nd->mx, nd->qmy = 4 * nd->my;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i)
+        resid[j * n + i] =
+            coded(cur, x0 + i, y0 + j) - refs(ref, x0 + i + nd->mx, y0 + j + nd->my);
+    nd->satd_inter = satd_block(resid.data(), n, n);
+  }
   for (int mode = 1; mode <= 2; ++mode) {
     intra_predict(cur, x0, y0, n, mode, pred.data());
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) resid[j * n + i] = coded(cur, x0 + i, y0 + j) - pred[j * n + i];
     (mode == 1 ? nd->satd_planar : nd->satd_dc) = satd_block(resid.data(), n, n);
   }
-  // Mode bits: 1 (prediction mode) + MV bits for inter; planar 3, DC 4.
-  int64_t r_inter = 1 + mv_bits(nd->mx, nd->my), r_pl = 3, r_dc = 4;
+  // Mode bits: 1 (prediction mode) + MV bits (quarter-pel components) for
+  // inter; planar 3, DC 4.
+  int64_t r_inter = 1 + se_bits(nd->qmx) + se_bits(nd->qmy), r_pl = 3, r_dc = 4;
   int64_t j_inter = nd->satd_inter * 65536 + s * r_inter;
   int64_t j_pl = nd->satd_planar * 65536 + s * r_pl;
   int64_t j_dc = nd->satd_dc * 65536 + s * r_dc;
@@ -298,6 +394,7 @@ struct CtuJob {
   int64_t s;
   const uint8_t* bounds;  // [h8/8][w8/8][2] or null
   const Seed* seed;       // null for the full search
+  bool subpel;            // half- and quarter-pel refinement of the inter MV
   int cx, cy;             // CTU origin in pixels
   Node nodes[85];
 };
@@ -355,7 +452,8 @@ Result best_tree(CtuJob& job, int d, int lx, int ly, bool* choose_leaf) {
   }
   Result leaf{INT64_MAX, 0, 0};
   if (leaf_ok) {
-    if (!nd.evaluated) evaluate_leaf(*job.cur, *job.ref, x0, y0, n, job.R, job.s, job.seed, &nd);
+    if (!nd.evaluated)
+      evaluate_leaf(*job.cur, *job.ref, x0, y0, n, job.R, job.s, job.seed, job.subpel, &nd);
     int flag = d < 3 ? 1 : 0;
     leaf = Result{nd.leaf_j + job.s * flag, nd.leaf_d, nd.leaf_r + flag};
   }
@@ -392,8 +490,9 @@ void write_tree(CtuJob& job, int d, int lx, int ly, uint8_t* depth_out, uint8_t*
       int64_t u = (int64_t)(y / 8) * uw + x / 8;
       depth_out[u] = (uint8_t)d;
       mode_out[u] = (uint8_t)nd.mode;
-      mv_out[2 * u] = (int16_t)nd.mx;
-      mv_out[2 * u + 1] = (int16_t)nd.my;
+      // Integer-pel units, or quarter-pel units with sub-pel refinement.
+      mv_out[2 * u] = (int16_t)(job.subpel ? nd.qmx : nd.mx);
+      mv_out[2 * u + 1] = (int16_t)(job.subpel ? nd.qmy : nd.my);
     }
 }
 
@@ -441,18 +540,39 @@ int orc_cu_motion_search(const uint8_t* cur, const uint8_t* ref, int w, int h, i
 // Seed arguments shared by the entry points below: ref_mv null means full
 // search; otherwise the reference MV map of a ref_w x ref_h picture and the
 // refinement half-width r (0 <= r <= R).
-static bool make_seed(const int16_t* ref_mv, int ref_w, int ref_h, int r, int R, Seed* sd) {
+static bool make_seed(const int16_t* ref_mv, int ref_w, int ref_h, int r, int R, int qpel,
+                      Seed* sd) {
   if (!ref_mv) return true;
-  if (ref_w <= 0 || ref_h <= 0 || r < 0 || r > R) return false;
-  *sd = Seed{ref_mv, ref_w, ref_h, r};
+  if (ref_w <= 0 || ref_h <= 0 || r < 0 || r > R || qpel < 0 || qpel > 1) return false;
+  *sd = Seed{ref_mv, ref_w, ref_h, r, qpel};
   return true;
+}
+
+// Interpolated prediction sample at quarter-pel position (qx, qy).
+int orc_interp_qpel(const uint8_t* ref, int w, int h, int stride, int qx, int qy) {
+  if (!valid_pic(ref, w, h, stride)) return -1;
+  return interp_qpel(make_pic(ref, w, h, stride), qx, qy);
+}
+
+// Sub-pel refinement of the integer MV (mx, my) of one CU: quarter-pel MV and its SATD.
+int orc_subpel_refine(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int x0,
+                      int y0, int n, int mx, int my, int qp, int32_t* qx, int32_t* qy,
+                      int64_t* satd) {
+  if (!valid_pic(cur, w, h, stride) || !ref || qp < 0 || qp > 51 || n < 4) return -1;
+  Pic c = make_pic(cur, w, h, stride), r = make_pic(ref, w, h, stride);
+  int a, b;
+  int64_t sd;
+  subpel_refine(c, r, x0, y0, n, mx, my, sqrt_lambda_q16(qp), &a, &b, &sd);
+  *qx = a, *qy = b, *satd = sd;
+  return 0;
 }
 
 // Search centre of one CU for a seeded search (see mv_centre).
 int orc_mv_centre(const int16_t* ref_mv, int ref_w, int ref_h, int cur_w, int cur_h, int R,
-                  int r, int x0, int y0, int n, int32_t* cx, int32_t* cy) {
+                  int r, int qpel, int x0, int y0, int n, int32_t* cx, int32_t* cy) {
   Seed sd{};
-  if (!ref_mv || cur_w <= 0 || cur_h <= 0 || !make_seed(ref_mv, ref_w, ref_h, r, R, &sd))
+  if (!ref_mv || cur_w <= 0 || cur_h <= 0 ||
+      !make_seed(ref_mv, ref_w, ref_h, r, R, qpel, &sd))
     return -1;
   int a, b;
   mv_centre(sd, cur_w, cur_h, R, x0, y0, n, &a, &b);
@@ -462,18 +582,20 @@ int orc_mv_centre(const int16_t* ref_mv, int ref_w, int ref_h, int cur_w, int cu
 
 // Per-node leaf evaluation of one CTU (all 85 nodes, no bounds); record layout
 // per node: kind, mode, mx, my, sad, satd_inter, satd_planar, satd_dc, leaf_j,
-// leaf_d, leaf_r (11 int64).  Used to check the decision against enumeration.
+// leaf_d, leaf_r, qmx, qmy (13 int64; mx, my integer ME, qmx, qmy the final MV
+// in quarter-pel units).  Used to check the decision against enumeration.
 int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int qp,
-                  int R, int ctu_x, int ctu_y, const int16_t* ref_mv, int ref_w, int ref_h,
-                  int refine_r, int64_t* rec) {
+                  int R, int subpel, int ctu_x, int ctu_y, const int16_t* ref_mv, int ref_w,
+                  int ref_h, int refine_r, int seed_qpel, int64_t* rec) {
   Seed sd{};
-  if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || qp < 0 || qp > 51 ||
-      !make_seed(ref_mv, ref_w, ref_h, refine_r, R, &sd))
+  if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || qp < 0 || qp > 51 || subpel < 0 ||
+      subpel > 1 || !make_seed(ref_mv, ref_w, ref_h, refine_r, R, seed_qpel, &sd))
     return -1;
   Pic c = make_pic(cur, w, h, stride), r = make_pic(ref, w, h, stride);
   CtuJob* job = new CtuJob();
   job->cur = &c, job->ref = &r, job->R = R, job->s = sqrt_lambda_q16(qp), job->bounds = nullptr;
   job->seed = ref_mv ? &sd : nullptr;
+  job->subpel = subpel != 0;
   job->cx = ctu_x * kCtu, job->cy = ctu_y * kCtu;
   for (int d = 0; d < 4; ++d)
     for (int ly = 0; ly < (1 << d); ++ly)
@@ -485,10 +607,11 @@ int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stri
         else if (x0 + n > c.w8 || y0 + n > c.h8) nd.kind = 1;
         else {
           nd.kind = 2;
-          evaluate_leaf(c, r, x0, y0, n, R, job->s, job->seed, &nd);
+          evaluate_leaf(c, r, x0, y0, n, R, job->s, job->seed, job->subpel, &nd);
         }
-        int64_t* o = rec + 11 * node_index(d, lx, ly);
+        int64_t* o = rec + 13 * node_index(d, lx, ly);
         o[0] = nd.kind, o[1] = nd.mode, o[2] = nd.mx, o[3] = nd.my, o[4] = nd.sad;
+        o[11] = nd.qmx, o[12] = nd.qmy;
         o[5] = nd.satd_inter, o[6] = nd.satd_planar, o[7] = nd.satd_dc, o[8] = nd.leaf_j;
         o[9] = nd.leaf_d, o[10] = nd.leaf_r;
       }
@@ -503,14 +626,14 @@ int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stri
 // bounds: null for full search, else [h8/8][w8/8][2] {lo, hi}.
 // ref_mv: null for full search, else a seeded search (see make_seed).
 int orc_ctu_search(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int qp,
-                   int R, const uint8_t* bounds, const int16_t* ref_mv, int ref_w, int ref_h,
-                   int refine_r, uint8_t* depth, uint8_t* mode, int16_t* mv,
-                   int64_t* ctu_cost, int64_t* ctu_dist, int64_t* ctu_bits,
+                   int R, int subpel, const uint8_t* bounds, const int16_t* ref_mv, int ref_w,
+                   int ref_h, int refine_r, int seed_qpel, uint8_t* depth, uint8_t* mode,
+                   int16_t* mv, int64_t* ctu_cost, int64_t* ctu_dist, int64_t* ctu_bits,
                    const int32_t* ctu_list, int n_list, int n_threads) {
   Seed sd{};
   if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || R > 128 || qp < 0 || qp > 51 ||
-      !depth || !mode || !mv || !ctu_cost || !ctu_dist || !ctu_bits ||
-      !make_seed(ref_mv, ref_w, ref_h, refine_r, R, &sd))
+      subpel < 0 || subpel > 1 || !depth || !mode || !mv || !ctu_cost || !ctu_dist ||
+      !ctu_bits || !make_seed(ref_mv, ref_w, ref_h, refine_r, R, seed_qpel, &sd))
     return -1;
   const Seed* seed = ref_mv ? &sd : nullptr;
   Pic c = make_pic(cur, w, h, stride), r = make_pic(ref, w, h, stride);
@@ -535,6 +658,7 @@ int orc_ctu_search(const uint8_t* cur, const uint8_t* ref, int w, int h, int str
       *job = CtuJob{};
       job->cur = &c, job->ref = &r, job->R = R, job->s = s, job->bounds = bounds;
       job->seed = seed;
+      job->subpel = subpel != 0;
       job->cx = (t % ctw) * kCtu, job->cy = (t / ctw) * kCtu;
       bool leaf;
       Result root = best_tree(*job, 0, 0, 0, &leaf);
