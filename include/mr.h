@@ -69,10 +69,20 @@ typedef struct {
   int32_t width, height, stride;
 } mr_frame;
 
-/* qp: 0..51.  search_range R: 0..128 (integer-pel, candidates [-R, R]^2). */
+/* qp: 0..51.  search_range R: 0..128 (integer-pel, candidates [-R, R]^2).
+ * subpel: 0 = integer motion only; 1 = each CU's integer MV is refined to
+ * quarter-pel (SATD for quarter-pel ME, cost-function subsection): H.265 8-bit
+ * luma fractional interpolation (8-tap / 7-tap filters, 14-bit intermediate,
+ * default uni-prediction rounding, reference coordinates clamped), a half-pel
+ * stage then a quarter-pel stage, each over the current best and its 8
+ * neighbours at the stage's step, J = SATD * 65536 + s * (se(qx) + se(qy))
+ * with (qx, qy) in quarter-pel units, the centre keeping ties, then raster
+ * order (dy outer).  The leaf's inter candidate is then that MV and SATD, and
+ * out.mv holds quarter-pel units. */
 typedef struct {
   int32_t qp;
   int32_t search_range;
+  int32_t subpel;
 } mr_search_params;
 
 /* Outputs (device, caller-allocated).  With U = ceil(H/8) rows and
@@ -98,7 +108,7 @@ typedef struct {
  * a node at depth d covering units S may stop (be a leaf) iff
  * d >= min_S lo or it may not split, and may split iff d < 3 and
  * d < max_S hi.  Scratch memory is allocated stream-ordered on hip_stream.
- * Errors: MR_EINVAL (null pointers, sizes, qp, R), MR_ENOMEM, MR_EHIP. */
+ * Errors: MR_EINVAL (null pointers, sizes, qp, R, subpel), MR_ENOMEM, MR_EHIP. */
 int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
                   const uint8_t* bounds, mr_search_out* out, void* hip_stream);
 
@@ -122,14 +132,18 @@ typedef struct {
   const int16_t* ref_mv;
   int32_t ref_w, ref_h;
   int32_t refine_range;
+  int32_t quarter_pel; /* 1: ref_mv is in quarter-pel units (written by a search
+                          with subpel = 1); the scaled centre divides by 4 more,
+                          cx = mx * W / (4 ref_w) rounded as above */
 } mr_mv_seed;
 
 /* mr_ctu_search with a seed: NULL seed = mr_ctu_search.  The seed's map is
- * read on the device during the call (stream-ordered).  Scratch includes an
- * edge-padded copy of the reference, (H8 + 2R) x (W8 + 2P) bytes with
- * P = R + 24 rounded up to a multiple of 4.
- * Errors: MR_EINVAL (as mr_ctu_search, plus a null ref_mv, seed sizes or
- * r outside [0, R]), MR_ENOMEM, MR_EHIP. */
+ * read on the device during the call (stream-ordered).  Scratch of a seeded or
+ * sub-pel search includes an edge-padded copy of the reference,
+ * (H8 + 2R + 16) x (W8 + 2P) bytes with P = R + 24 rounded up to a multiple
+ * of 4.
+ * Errors: MR_EINVAL (as mr_ctu_search, plus a null ref_mv, seed sizes,
+ * r outside [0, R] or quarter_pel not 0 / 1), MR_ENOMEM, MR_EHIP. */
 int mr_ctu_search_seeded(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
                          const uint8_t* bounds, const mr_mv_seed* seed, mr_search_out* out,
                          void* hip_stream);
@@ -204,6 +218,7 @@ int mr_batch_destroy(mr_batch* b);
 typedef struct {
   int32_t width, height, qp, search_range;
   int32_t ref_rung;   /* index of the rung whose job bounds (and seeds) this one, -1 = none */
+  int32_t subpel;     /* quarter-pel refinement of this rung's MVs (mr_search_params) */
   int32_t own_policy; /* 0: the config's delta_lo/delta_hi/reuse_mv/refine_range apply;
                          1: this rung's four fields below (same ranges) */
   int32_t delta_lo, delta_hi;

@@ -2,6 +2,7 @@
 // flattened (job, strip, band) items of many frame pairs, and a reusable batch
 // object that replays prep -> search -> leaf as a captured HIP graph.
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "mr_runtime.h"
@@ -11,10 +12,10 @@ using namespace mr;
 struct mr_batch {
   int device = 0;
   Plan plan;
-  uint8_t* mem = nullptr;      // device: jobs | items | rlist | counter | scratch
+  uint8_t* mem = nullptr;      // device: jobs | items | job lists | counter | scratch
   JobDesc* jobs_d = nullptr;
   uint2* items_d = nullptr;
-  int* rlist_d = nullptr;
+  PlanLists lists{nullptr, nullptr, nullptr};
   uint32_t* counter_d = nullptr;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -50,37 +51,47 @@ int unpack(const mr_search_job* jobs, int n, Unpacked* u) {
   return MR_OK;
 }
 
-// Device layout of a batch: job array, items, seeded-job list, counter, then
-// per-job scratch.
-struct Layout {
-  size_t jobs, items, rlist, counter, scratch, total;
-};
+}  // namespace
 
-Layout layout_of(const Plan& P) {
-  Layout L;
+namespace mr {
+
+// Device layout of a planned batch: job array, items, the seeded / sub-pel /
+// padded job lists, queue counter, then per-job scratch.
+BatchLayout batch_layout(const Plan& P) {
+  BatchLayout L;
   L.jobs = 0;
   L.items = up256(sizeof(JobDesc) * P.n_jobs);
   L.rlist = L.items + up256(sizeof(uint2) * P.items.size());
-  L.counter = L.rlist + up256(sizeof(int) * P.rlist.size());
+  L.slist = L.rlist + up256(sizeof(int) * P.rlist.size());
+  L.plist = L.slist + up256(sizeof(int) * P.slist.size());
+  L.counter = L.plist + up256(sizeof(int) * P.plist.size());
   L.scratch = L.counter + 256;
   L.total = L.scratch + P.scratch_bytes;
   return L;
 }
 
-// Upload the job array, items and seeded-job list of a bound plan.
-hipError_t upload(const Plan& P, uint8_t* mem, const Layout& L, hipStream_t st) {
+PlanLists batch_lists(uint8_t* mem, const BatchLayout& L) {
+  return PlanLists{(const int*)(mem + L.rlist), (const int*)(mem + L.slist),
+                   (const int*)(mem + L.plist)};
+}
+
+// Upload the job array, items and job lists of a bound plan.
+hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st) {
   hipError_t e = hipMemcpyAsync(mem + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs,
                                 hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !P.items.empty())
     e = hipMemcpyAsync(mem + L.items, P.items.data(), sizeof(uint2) * P.items.size(),
                        hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !P.rlist.empty())
-    e = hipMemcpyAsync(mem + L.rlist, P.rlist.data(), sizeof(int) * P.rlist.size(),
-                       hipMemcpyHostToDevice, st);
+  const std::pair<const std::vector<int>*, size_t> lists[3] = {
+      {&P.rlist, L.rlist}, {&P.slist, L.slist}, {&P.plist, L.plist}};
+  for (const auto& pl : lists)
+    if (e == hipSuccess && !pl.first->empty())
+      e = hipMemcpyAsync(mem + pl.second, pl.first->data(), sizeof(int) * pl.first->size(),
+                         hipMemcpyHostToDevice, st);
   return e;
 }
 
-}  // namespace
+}  // namespace mr
 
 extern "C" {
 
@@ -93,16 +104,16 @@ int mr_ctu_search_batch(const mr_search_job* jobs, int32_t n_jobs, void* hip_str
                  u.seed.data(), n_jobs, true, &P);
   if (rc != MR_OK) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
-  const Layout L = layout_of(P);
+  const BatchLayout L = batch_layout(P);
   uint8_t* mem = nullptr;
   if (hipMallocAsync((void**)&mem, L.total, st) != hipSuccess) return MR_ENOMEM;
   bind_scratch(P, mem + L.scratch);
-  hipError_t e = upload(P, mem, L, st);
+  hipError_t e = batch_upload(P, mem, L, st);
   StageEvents ev{};
   const bool prof = e == hipSuccess && profile_on() && profile_begin(&ev, st) == MR_OK;
   if (e == hipSuccess)
     e = launch_plan(P, (JobDesc*)(mem + L.jobs), (const uint2*)(mem + L.items),
-                    (const int*)(mem + L.rlist), (uint32_t*)(mem + L.counter), st,
+                    batch_lists(mem, L), (uint32_t*)(mem + L.counter), st,
                     prof ? &ev : nullptr);
   if (prof) profile_push(ev);
   const hipError_t ef = hipFreeAsync(mem, st);
@@ -136,17 +147,17 @@ int mr_batch_create(const mr_search_job* jobs, int32_t n_jobs, mr_batch** out) {
     delete b;
     return rc;
   }
-  const Layout L = layout_of(b->plan);
+  const BatchLayout L = batch_layout(b->plan);
   if (hipMalloc((void**)&b->mem, L.total) != hipSuccess) {
     mr_batch_destroy(b);
     return MR_ENOMEM;
   }
   b->jobs_d = (JobDesc*)(b->mem + L.jobs);
   b->items_d = (uint2*)(b->mem + L.items);
-  b->rlist_d = (int*)(b->mem + L.rlist);
+  b->lists = batch_lists(b->mem, L);
   b->counter_d = (uint32_t*)(b->mem + L.counter);
   bind_scratch(b->plan, b->mem + L.scratch);
-  if (upload(b->plan, b->mem, L, nullptr) != hipSuccess ||
+  if (batch_upload(b->plan, b->mem, L, nullptr) != hipSuccess ||
       hipStreamSynchronize(nullptr) != hipSuccess ||
       hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -157,7 +168,7 @@ int mr_batch_create(const mr_search_job* jobs, int32_t n_jobs, mr_batch** out) {
   // is reset by the prep kernel itself, so the graph holds kernel nodes only.
   hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const hipError_t el = launch_plan(b->plan, b->jobs_d, b->items_d, b->rlist_d, b->counter_d,
+    const hipError_t el = launch_plan(b->plan, b->jobs_d, b->items_d, b->lists, b->counter_d,
                                       b->cap_stream, nullptr);
     e = hipStreamEndCapture(b->cap_stream, &b->graph);
     if (el != hipSuccess) e = el;
@@ -181,7 +192,7 @@ int mr_batch_set_jobs(mr_batch* b, const mr_search_job* jobs, int32_t n_jobs) {
     if (rc != MR_OK) return rc;
     if (q.cur.width != jd.w || q.cur.height != jd.h || q.params.search_range != jd.R ||
         sqrt_lambda_q16(q.params.qp) != jd.s || (q.bounds != nullptr) != (jd.bounds != nullptr) ||
-        (q.seed != nullptr) != (jd.seed_mv != nullptr))
+        (q.seed != nullptr) != (jd.seed_mv != nullptr) || q.params.subpel != jd.subpel)
       return MR_EINVAL;
   }
   if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return MR_EHIP;
@@ -213,7 +224,7 @@ int mr_batch_launch(mr_batch* b, void* hip_stream) {
   if (profile_on()) {
     StageEvents ev{};
     if (profile_begin(&ev, st) != MR_OK) return MR_EHIP;
-    e = launch_plan(b->plan, b->jobs_d, b->items_d, b->rlist_d, b->counter_d, st, &ev);
+    e = launch_plan(b->plan, b->jobs_d, b->items_d, b->lists, b->counter_d, st, &ev);
     profile_push(ev);
   } else {
     e = hipGraphLaunch(b->exec, st);

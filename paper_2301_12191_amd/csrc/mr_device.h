@@ -27,4 +27,29 @@ __device__ __forceinline__ int se_bits_dev(int v) {
   return 2 * (31 - __builtin_clz(k + 1u)) + 1;
 }
 
+// v plus the value of another lane (DPP permutation CTRL) in one v_add_u32.
+template <int CTRL>
+__device__ __forceinline__ uint32_t add_dpp(uint32_t v) {
+  return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// SATD of a 4x4 residual: sum |H d H^T| / 2 via butterflies.
+__device__ __forceinline__ uint32_t satd4x4(int d[16]) {
+  int t[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {  // rows
+    const int a0 = d[4 * i] + d[4 * i + 1], a1 = d[4 * i] - d[4 * i + 1];
+    const int a2 = d[4 * i + 2] + d[4 * i + 3], a3 = d[4 * i + 2] - d[4 * i + 3];
+    t[4 * i] = a0 + a2, t[4 * i + 1] = a1 + a3, t[4 * i + 2] = a0 - a2, t[4 * i + 3] = a1 - a3;
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {  // columns
+    const int a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
+    const int a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
+    s += abs(a0 + a2) + abs(a1 + a3) + abs(a0 - a2) + abs(a1 - a3);
+  }
+  return s >> 1;
+}
+
 }  // namespace mr

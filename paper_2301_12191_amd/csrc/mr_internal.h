@@ -17,6 +17,8 @@ constexpr int kCurRingBytes = 512;  // per wavefront: two 16x16 regions of the c
 // Column margin of the padded reference of a seeded job with range R: the
 // refinement loads reach 3 bytes left of -R and 20 bytes right of w8 - 8 + R.
 __host__ __device__ inline int refine_pad_x(int R) { return (R + 24 + 3) & ~3; }
+// Row margin: the refinement reaches R rows, the sub-pel patches R + 4.
+__host__ __device__ inline int refine_pad_y(int R) { return R + 8; }
 
 // Search work item of a batch: x = job, y = row << 16 | first CTU column << 4 | band.
 __host__ __device__ inline uint32_t pack_item_y(int row, int col0, int band) {
@@ -65,9 +67,16 @@ struct JobDesc {
   const int16_t* seed_mv;  // [ceil(seed_h/8)][ceil(seed_w/8)][2] reference MVs
   int32_t seed_w, seed_h;  // dimensions of the picture the MVs belong to
   int32_t seed_r;          // refinement half-width r
+  int32_t seed_qpel;       // 1: seed_mv in quarter-pel units
   int32_t rctu_start;      // first CTU of this job among the seeded jobs' CTUs
-  int32_t pad_x, pad_pitch;  // padded reference: columns [-pad_x, w8 + pad_x), row pitch
-  uint8_t* refpad;         // [h8 + 2R][pad_pitch] reference, coordinates clamped
+  // Sub-pel refinement: per node {quarter-pel MV (qx | qy << 16), SATD}.
+  int32_t subpel;
+  int32_t sctu_start;      // first CTU of this job among the sub-pel jobs' CTUs
+  uint32_t* subres;        // [ctus][85][2]
+  // Padded reference (seeded or sub-pel jobs): rows [-pad_y, h8 + pad_y),
+  // columns [-pad_x, w8 + pad_x), coordinates clamped to the picture.
+  int32_t pad_x, pad_y, pad_pitch;
+  uint8_t* refpad;         // [h8 + 2 pad_y][pad_pitch]
   uint8_t* depth;          // outputs
   uint8_t* mode;
   int16_t* mv;

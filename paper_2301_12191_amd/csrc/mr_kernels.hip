@@ -296,26 +296,6 @@ __device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win, uin
 }
 
 // ---------------------------------------------------------------------------------- leaf
-// SATD of a 4x4 residual: sum |H d H^T| / 2 via butterflies.
-__device__ __forceinline__ uint32_t satd4x4(int d[16]) {
-  int t[16];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {  // rows
-    const int a0 = d[4 * i] + d[4 * i + 1], a1 = d[4 * i] - d[4 * i + 1];
-    const int a2 = d[4 * i + 2] + d[4 * i + 3], a3 = d[4 * i + 2] - d[4 * i + 3];
-    t[4 * i] = a0 + a2, t[4 * i + 1] = a1 + a3, t[4 * i + 2] = a0 - a2, t[4 * i + 3] = a1 - a3;
-  }
-  uint32_t s = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {  // columns
-    const int a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
-    const int a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
-    s += abs(a0 + a2) + abs(a1 + a3) + abs(a0 - a2) + abs(a1 - a3);
-  }
-  return s >> 1;
-}
-
-
 // Offsets of each node's reference arrays in LDS: left column 2N+1, top row 2N.
 __device__ __forceinline__ int ref_offset(int node) {
   if (node == 0) return 0;
@@ -328,7 +308,8 @@ constexpr int kRefTotal = 257 + 4 * 129 + 16 * 65 + 64 * 33;  // 3925
 struct LeafShared {
   uint8_t cur[64 * 64];
   int16_t refs[kRefTotal];
-  int16_t mvx[kNodes], mvy[kNodes];
+  int16_t mvx[kNodes], mvy[kNodes];  // integer-pel, or quarter-pel with sub-pel refinement
+  uint32_t satq[kNodes];             // sub-pel: SATD at the refined MV
   int32_t dc[kNodes];
   uint32_t satd[kNodes][3];
   uint32_t part0[4][3];          // per-wave partial sums for the 64x64 node
@@ -366,12 +347,17 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     const uint8_t e = jb->elig[(size_t)ctu * kNodes + node];
     sh.elig[node] = e;
     int mx = 0, my = 0;
-    if (e) {
+    uint32_t sq = 0;
+    if (e && jb->subpel) {
+      const uint32_t* o = jb->subres + ((size_t)ctu * kNodes + node) * 2;
+      mx = (int16_t)(o[0] & 0xFFFFu), my = (int16_t)(o[0] >> 16), sq = o[1];
+    } else if (e) {
       const uint64_t key = jb->keys[(size_t)ctu * kNodes + node];
       const int idx = (int)(key & 0x1FFFF);
       my = idx / span - jb->R;
       mx = idx - (my + jb->R) * span - jb->R;
     }
+    sh.satq[node] = sq;
     sh.mvx[node] = (int16_t)mx, sh.mvy[node] = (int16_t)my;
     // bounds admissibility (same rule the prep kernel applied)
     bool split_ok = d < 3, leaf_ok = true;
@@ -454,15 +440,17 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
       uint32_t v0 = 0, v1 = 0, v2 = 0;
       if (sh.elig[node]) {
-        const int mx = sh.mvx[node], my = sh.mvy[node];
         int r[16];
+        if (!jb->subpel) {  // with sub-pel refinement the inter SATD comes from subres
+          const int mx = sh.mvx[node], my = sh.mvy[node];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int x = clampi(cx + tx * 4 + (i & 3) + mx, 0, jb->w - 1);
-          const int y = clampi(cy + ty * 4 + (i >> 2) + my, 0, jb->h - 1);
-          r[i] = c[i] - (int)jb->ref[(size_t)y * jb->stride + x];
+          for (int i = 0; i < 16; ++i) {
+            const int x = clampi(cx + tx * 4 + (i & 3) + mx, 0, jb->w - 1);
+            const int y = clampi(cy + ty * 4 + (i >> 2) + my, 0, jb->h - 1);
+            r[i] = c[i] - (int)jb->ref[(size_t)y * jb->stride + x];
+          }
+          v0 = satd4x4(r);
         }
-        v0 = satd4x4(r);
         const int16_t* L = sh.refs + ref_offset(node);
         const int16_t* T = L + 2 * n + 1;
         const int px0 = tx * 4 - lx * n, py0 = ty * 4 - ly * n;  // position inside the CU
@@ -502,8 +490,11 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   __syncthreads();
   if (tid < kNodes && sh.elig[tid]) {
     const int node = tid;
-    const int64_t r_inter = 1 + se_bits_dev(4 * sh.mvx[node]) + se_bits_dev(4 * sh.mvy[node]);
-    int64_t j = (int64_t)sh.satd[node][0] * 65536 + s * r_inter, dd = sh.satd[node][0], rr = r_inter;
+    // Inter: MV bits of the quarter-pel components (4 x integer MVs without sub-pel).
+    const int q = jb->subpel ? 1 : 4;
+    const int64_t r_inter = 1 + se_bits_dev(q * sh.mvx[node]) + se_bits_dev(q * sh.mvy[node]);
+    const uint32_t si = jb->subpel ? sh.satq[node] : sh.satd[node][0];
+    int64_t j = (int64_t)si * 65536 + s * r_inter, dd = si, rr = r_inter;
     uint8_t m = 0;
     const int64_t jp = (int64_t)sh.satd[node][1] * 65536 + s * 3;
     if (jp < j) j = jp, dd = sh.satd[node][1], rr = 3, m = 1;

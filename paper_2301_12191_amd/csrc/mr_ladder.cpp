@@ -100,9 +100,11 @@ class GpuExecutor : public Executor {
     size_t off[7];
     const size_t w8 = (r.width + 7) / 8 * 8, h8 = (r.height + 7) / 8 * 8;
     const size_t T = ((h8 + 63) / 64) * ((w8 + 63) / 64);
-    size_t pad = 0;  // padded reference of a seeded search
-    if (refine_of(r) >= 0)
-      pad = (h8 + 2 * r.search_range) * (w8 + 2 * (size_t)refine_pad_x(r.search_range)) + 256;
+    size_t pad = 0;  // padded reference of a seeded or sub-pel search, sub-pel results
+    if (refine_of(r) >= 0 || r.subpel)
+      pad = (h8 + 2 * (size_t)refine_pad_y(r.search_range)) *
+                (w8 + 2 * (size_t)refine_pad_x(r.search_range)) + 256;
+    if (r.subpel) pad += T * kNodes * 8 + 256;
     return out_bytes(r, r.ref_rung >= 0, off) + T * (4096 + 85 * 9) + pad + 4096;
   }
 
@@ -126,7 +128,7 @@ class GpuExecutor : public Executor {
       }
       cur[i] = mr_frame{fc.luma, r.width, r.height, fc.stride};
       ref[i] = mr_frame{fr.luma, r.width, r.height, fr.stride};
-      prm[i] = mr_search_params{r.qp, r.search_range};
+      prm[i] = mr_search_params{r.qp, r.search_range, r.subpel};
       JobOut* o = new JobOut();
       size_t off[7];
       const size_t bytes = out_bytes(r, j.ref_job != 0, off);
@@ -152,7 +154,7 @@ class GpuExecutor : public Executor {
         bnd[i] = o->bounds;
         const int rr_refine = refine_of(r);
         if (rr_refine >= 0) {
-          seeds[i] = mr_mv_seed{ro->out.mv, rr.width, rr.height, rr_refine};
+          seeds[i] = mr_mv_seed{ro->out.mv, rr.width, rr.height, rr_refine, rr.subpel};
           ps[i] = &seeds[i];
         }
       }
@@ -166,24 +168,14 @@ class GpuExecutor : public Executor {
     int rc = make_plan(pc.data(), pr.data(), pp.data(), bnd.data(), po.data(), ps.data(), n, true,
                        &P);
     if (rc != MR_OK) return rc;
-    // Device: jobs | items | seeded-job list | counter | scratch.
-    const size_t off_items = up256(sizeof(JobDesc) * n);
-    const size_t off_rlist = off_items + up256(sizeof(uint2) * P.items.size());
-    const size_t off_ctr = off_rlist + up256(sizeof(int) * P.rlist.size());
-    const size_t off_scr = off_ctr + 256;
+    const BatchLayout L = batch_layout(P);
     uint8_t* mem = nullptr;
-    if (hipMallocAsync((void**)&mem, off_scr + P.scratch_bytes, st) != hipSuccess) return MR_ENOMEM;
-    bind_scratch(P, mem + off_scr);
-    hipError_t e = hipMemcpyAsync(mem, P.jobs.data(), sizeof(JobDesc) * n, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !P.items.empty())
-      e = hipMemcpyAsync(mem + off_items, P.items.data(), sizeof(uint2) * P.items.size(),
-                         hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !P.rlist.empty())
-      e = hipMemcpyAsync(mem + off_rlist, P.rlist.data(), sizeof(int) * P.rlist.size(),
-                         hipMemcpyHostToDevice, st);
+    if (hipMallocAsync((void**)&mem, L.total, st) != hipSuccess) return MR_ENOMEM;
+    bind_scratch(P, mem + L.scratch);
+    hipError_t e = batch_upload(P, mem, L, st);
     if (e == hipSuccess)
-      e = launch_plan(P, (JobDesc*)mem, (const uint2*)(mem + off_items),
-                      (const int*)(mem + off_rlist), (uint32_t*)(mem + off_ctr), st, nullptr);
+      e = launch_plan(P, (JobDesc*)(mem + L.jobs), (const uint2*)(mem + L.items),
+                      batch_lists(mem, L), (uint32_t*)(mem + L.counter), st, nullptr);
     const hipError_t ef = hipFreeAsync(mem, st);
     BatchState* b = new BatchState();
     b->stream = st;
@@ -296,7 +288,9 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
         g.ref_rung >= cfg->n_rungs || g.ref_rung == r || g.own_policy < 0 || g.own_policy > 1 ||
         (g.own_policy && !policy_ok(g.delta_lo, g.delta_hi, g.reuse_mv, g.refine_range)))
       return MR_EINVAL;
+    if (g.subpel < 0 || g.subpel > 1) return MR_EINVAL;
     RungCfg rc{g.width, g.height, g.qp, g.search_range, g.ref_rung};
+    rc.subpel = g.subpel;
     const bool own = g.own_policy != 0;
     rc.dlo = own ? g.delta_lo : cfg->delta_lo;
     rc.dhi = own ? g.delta_hi : cfg->delta_hi;

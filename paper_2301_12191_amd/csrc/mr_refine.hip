@@ -18,17 +18,11 @@
 namespace mr {
 
 // m * num / den rounded to nearest, halves away from zero (|m| < 2^15,
-// 1 <= num, den <= 8192: every intermediate fits 32 bits).
+// 1 <= num <= 8192, 1 <= den <= 32768: every intermediate fits 32 bits).
 __device__ __forceinline__ int scale_round_dev(int m, int num, int den) {
   const uint32_t a = (uint32_t)(m < 0 ? -m : m) * (uint32_t)num;
   const int q = (int)((2u * a + (uint32_t)den) / (2u * (uint32_t)den));
   return m < 0 ? -q : q;
-}
-
-// v plus the value of another lane (DPP permutation CTRL) in one v_add_u32.
-template <int CTRL>
-__device__ __forceinline__ uint32_t add_dpp(uint32_t v) {
-  return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
 // Sums of acc[k] over aligned groups of 4^(3-d) lanes (d = 3: none; 2: quads;
@@ -122,8 +116,9 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
     const uint32_t xr = min(px * sw / (uint32_t)W, sw - 1);
     const uint32_t yr = min(py * shh / (uint32_t)H, shh - 1);
     const int16_t* m = jb->seed_mv + 2 * ((yr >> 3) * ((sw + 7) >> 3) + (xr >> 3));
-    cxm = clampi(scale_round_dev(m[0], W, sw), -lim, lim);
-    cym = clampi(scale_round_dev(m[1], H, shh), -lim, lim);
+    const int qs = 2 * jb->seed_qpel;  // quarter-pel maps: 4 map units per pixel
+    cxm = clampi(scale_round_dev(m[0], W, sw << qs), -lim, lim);
+    cym = clampi(scale_round_dev(m[1], H, shh << qs), -lim, lim);
   }
   // This lane's block (blocks outside the coded picture belong to CUs that are
   // not searched; their loads are kept inside the padded reference).
@@ -153,7 +148,8 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
     T[k] = (p >= 0 && p < ncand) ? ((uint64_t)(s * se_len(4 * dx)) << 17) + (uint64_t)(dx + R)
                                  : (1ull << 62);
   }
-  const uint32_t* src = (const uint32_t*)(jb->refpad + (size_t)(Y0 + cym - r + iy0 + R) * pitch +
+  const uint32_t* src = (const uint32_t*)(jb->refpad +
+                                          (size_t)(Y0 + cym - r + iy0 + jb->pad_y) * pitch +
                                           xa + pass * NP);
   const int dwp = pitch >> 2;
   uint32_t S[8][4][NQ + 1];
@@ -237,22 +233,23 @@ __device__ int find_rjob(cjob jobs, const int* rlist, int n_rjobs, int flat) {
   return rlist[lo];
 }
 
-// Padded reference of every seeded job: grid-stride over the seeded jobs in y
-// and over each job's [h8 + 2R][pad_pitch] bytes, in dwords, in x.
-__global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const int* rlist,
-                                                  int n_rjobs) {
-  for (int k = blockIdx.y; k < n_rjobs; k += gridDim.y) {
-    const cjob jb = (cjob)jobs_ + (rlist ? rlist[k] : 0);
-    const int R = jb->R, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
+// Padded reference of every job that has one (seeded or sub-pel): grid-stride
+// over those jobs in y and over each job's [h8 + 2 pad_y][pad_pitch] bytes, in
+// dwords, in x.
+__global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const int* plist,
+                                                  int n_pjobs) {
+  for (int k = blockIdx.y; k < n_pjobs; k += gridDim.y) {
+    const cjob jb = (cjob)jobs_ + (plist ? plist[k] : 0);
+    const int PY = jb->pad_y, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
     const int dw = jb->pad_pitch >> 2;
-    const int64_t total = (int64_t)(jb->h8 + 2 * R) * dw;
+    const int64_t total = (int64_t)(jb->h8 + 2 * PY) * dw;
     const uint8_t* ref = jb->ref;
     const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0);
     uint32_t* dst = (uint32_t*)jb->refpad;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
       const int row = (int)(i / dw), c = (int)(i - (int64_t)row * dw);
-      const uint8_t* rp = ref + (size_t)clampi(row - R, 0, h - 1) * stride;
+      const uint8_t* rp = ref + (size_t)clampi(row - PY, 0, h - 1) * stride;
       const int x = 4 * c - P;
       uint32_t v;
       if (dword_ok && x >= 0 && x + 3 < w) {
@@ -290,12 +287,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
   refine_wave<NQ>(jobs + j, flat - jobs[j].rctu_start, d, blockIdx.y, blockIdx.z, gridDim.z);
 }
 
-hipError_t launch_pad(const JobDesc* jobs, const int* rlist, int n_rjobs, int64_t max_dwords,
+hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int64_t max_dwords,
                       hipStream_t st) {
   const int64_t blocks = std::min<int64_t>((max_dwords + 255) / 256, 2048);
   hipLaunchKernelGGL(pad_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1),
-                                      (unsigned)std::min(n_rjobs, 65535)),
-                     dim3(256), 0, st, jobs, rlist, n_rjobs);
+                                      (unsigned)std::min(n_pjobs, 65535)),
+                     dim3(256), 0, st, jobs, plist, n_pjobs);
   return hipGetLastError();
 }
 

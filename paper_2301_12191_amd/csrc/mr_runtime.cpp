@@ -206,7 +206,9 @@ int validate_job(const mr_frame* cur, const mr_frame* ref, const mr_search_param
   if (!frame_ok(cur) || !frame_ok(ref) || !p || !out) return MR_EINVAL;
   if (cur->width != ref->width || cur->height != ref->height || cur->stride != ref->stride)
     return MR_EINVAL;
-  if (p->qp < 0 || p->qp > 51 || p->search_range < 0 || p->search_range > 128) return MR_EINVAL;
+  if (p->qp < 0 || p->qp > 51 || p->search_range < 0 || p->search_range > 128 || p->subpel < 0 ||
+      p->subpel > 1)
+    return MR_EINVAL;
   if (!out->depth || !out->mode || !out->mv || !out->ctu_cost || !out->ctu_dist ||
       !out->ctu_bits)
     return MR_EINVAL;
@@ -216,7 +218,8 @@ int validate_job(const mr_frame* cur, const mr_frame* ref, const mr_search_param
 int validate_seed(const mr_mv_seed* seed, const mr_search_params* p) {
   if (!seed) return MR_OK;
   if (!seed->ref_mv || seed->ref_w < 1 || seed->ref_h < 1 || seed->ref_w > 8192 ||
-      seed->ref_h > 8192 || seed->refine_range < 0 || seed->refine_range > p->search_range)
+      seed->ref_h > 8192 || seed->refine_range < 0 || seed->refine_range > p->search_range ||
+      seed->quarter_pel < 0 || seed->quarter_pel > 1)
     return MR_EINVAL;
   return MR_OK;
 }
@@ -226,6 +229,7 @@ void set_job_seed(JobDesc& jb, const mr_mv_seed* seed) {
   jb.seed_w = seed ? seed->ref_w : 0;
   jb.seed_h = seed ? seed->ref_h : 0;
   jb.seed_r = seed ? seed->refine_range : 0;
+  jb.seed_qpel = seed ? seed->quarter_pel : 0;
 }
 
 int device_cu_count() {
@@ -287,7 +291,10 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
   P->job_off.assign(n_jobs, 0);
   P->items.clear();
   P->rlist.clear();
+  P->slist.clear();
+  P->plist.clear();
   P->n_rjobs = P->n_rctus = P->max_r = 0;
+  P->n_sjobs = P->n_sctus = 0;
   P->max_pad_dwords = 0;
   P->n_ctus = 0;
   P->scratch_bytes = 0;
@@ -327,15 +334,27 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     P->scratch_bytes += up256((size_t)n_ctus * 4096) + up256((size_t)n_ctus * kNodes * 8) +
                         up256((size_t)n_ctus * kNodes) + up256((size_t)n_ctus * 16);
     P->n_ctus += n_ctus;
+    jb.subpel = p[j]->subpel;
+    if (jb.subpel) {
+      jb.sctu_start = P->n_sctus;
+      P->scratch_bytes += up256((size_t)n_ctus * kNodes * 8);  // subres
+      P->slist.push_back(j);
+      P->n_sjobs += 1;
+      P->n_sctus += n_ctus;
+    }
+    if (seed_of(j) || jb.subpel) {
+      jb.pad_x = refine_pad_x(R);
+      jb.pad_y = refine_pad_y(R);
+      jb.pad_pitch = jb.w8 + 2 * jb.pad_x;
+      const int64_t pad_bytes = (int64_t)(jb.h8 + 2 * jb.pad_y) * jb.pad_pitch;
+      P->scratch_bytes += up256((size_t)pad_bytes);
+      P->max_pad_dwords = std::max(P->max_pad_dwords, pad_bytes / 4);
+      P->plist.push_back(j);
+    }
     if (seed_of(j)) {
       // Seeded: refinement around reference MVs instead of the full search.
       set_job_seed(jb, seed_of(j));
       jb.rctu_start = P->n_rctus;
-      jb.pad_x = refine_pad_x(R);
-      jb.pad_pitch = jb.w8 + 2 * jb.pad_x;
-      const int64_t pad_bytes = (int64_t)(jb.h8 + 2 * R) * jb.pad_pitch;
-      P->scratch_bytes += up256((size_t)pad_bytes);
-      P->max_pad_dwords = std::max(P->max_pad_dwords, pad_bytes / 4);
       P->rlist.push_back(j);
       P->n_rjobs += 1;
       P->n_rctus += n_ctus;
@@ -406,20 +425,27 @@ void bind_scratch(Plan& P, uint8_t* base) {
     sp += up256((size_t)n_ctus * kNodes);
     jb.eligbits = (uint32_t*)sp;
     sp += up256((size_t)n_ctus * 16);
-    jb.refpad = jb.seed_mv ? sp : nullptr;
+    jb.subres = nullptr;
+    if (jb.subpel) {
+      jb.subres = (uint32_t*)sp;
+      sp += up256((size_t)n_ctus * kNodes * 8);
+    }
+    jb.refpad = (jb.seed_mv || jb.subpel) ? sp : nullptr;
   }
 }
 
-hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, const int* rlist_d,
+hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, const PlanLists& L,
                        uint32_t* counter, hipStream_t st, StageEvents* ev) {
   hipError_t e = launch_prep(jobs_d, P.n_jobs, P.n_ctus, counter, st);
   if (ev) profile_mark(ev, 1, st);
-  if (e == hipSuccess && P.n_rjobs > 0)
-    e = launch_pad(jobs_d, rlist_d, P.n_rjobs, P.max_pad_dwords, st);
+  if (e == hipSuccess && !P.plist.empty())
+    e = launch_pad(jobs_d, L.plist, (int)P.plist.size(), P.max_pad_dwords, st);
   if (e == hipSuccess && P.n_items > 0)
     e = launch_search(jobs_d, items_d, P.n_items, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
   if (e == hipSuccess && P.n_rjobs > 0)
-    e = launch_refine(jobs_d, rlist_d, P.n_rjobs, P.n_rctus, P.max_r, st);
+    e = launch_refine(jobs_d, L.rlist, P.n_rjobs, P.n_rctus, P.max_r, st);
+  if (e == hipSuccess && P.n_sjobs > 0)
+    e = launch_subpel(jobs_d, L.slist, P.n_sjobs, P.n_sctus, st);
   if (ev) profile_mark(ev, 2, st);
   if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, st);
   if (ev) profile_mark(ev, 3, st);
@@ -494,7 +520,9 @@ int mr_ctu_search_seeded(const mr_frame* cur, const mr_frame* ref, const mr_sear
   StageEvents ev{};
   const bool prof = profile_on() && profile_begin(&ev, st) == MR_OK;
   hipError_t e = launch_store_job(P.jobs[0], jobs_d, st);
-  if (e == hipSuccess) e = launch_plan(P, jobs_d, nullptr, nullptr, counter, st, prof ? &ev : nullptr);
+  if (e == hipSuccess)
+    e = launch_plan(P, jobs_d, nullptr, PlanLists{nullptr, nullptr, nullptr}, counter, st,
+                    prof ? &ev : nullptr);
   if (prof) profile_push(ev);
   const hipError_t ef = hipFreeAsync(scratch, st);
   if (e != hipSuccess || ef != hipSuccess) return MR_EHIP;

@@ -53,10 +53,12 @@ struct Plan {
   std::vector<uint2> items;           // empty when implicit (single job)
   std::vector<size_t> job_off;        // per-job scratch offset
   size_t scratch_bytes = 0;           // per-job scratch total (curpack, keys, elig, refpad)
-  // Seeded jobs: their indices in rctu_start order, CTU total, largest padded
+  // Seeded jobs (refinement) in rctu_start order, sub-pel jobs in sctu_start
+  // order, jobs with a padded reference (seeded or sub-pel); largest padded
   // reference in dwords.
-  std::vector<int> rlist;
+  std::vector<int> rlist, slist, plist;
   int n_rjobs = 0, n_rctus = 0, max_r = 0;
+  int n_sjobs = 0, n_sctus = 0;
   int64_t max_pad_dwords = 0;
 };
 
@@ -69,9 +71,22 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
               bool materialize_items, Plan* P);
 // Copy a seed's fields into a job descriptor (seed null: full search).
 void set_job_seed(JobDesc& jb, const mr_mv_seed* seed);
-// prep -> [pad] -> [search] -> [refine] -> leaf for a bound plan; rlist_d is
-// the device copy of P.rlist (null for a single job).
-hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, const int* rlist_d,
+// Device copies of a plan's job lists (all null for a single job).
+struct PlanLists {
+  const int* rlist;
+  const int* slist;
+  const int* plist;
+};
+// Device layout of a planned batch (job array, items, job lists, counter,
+// scratch), its upload, and the device job lists inside it.
+struct BatchLayout {
+  size_t jobs, items, rlist, slist, plist, counter, scratch, total;
+};
+BatchLayout batch_layout(const Plan& P);
+hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st);
+PlanLists batch_lists(uint8_t* mem, const BatchLayout& L);
+// prep -> [pad] -> [search] -> [refine] -> [subpel] -> leaf for a bound plan.
+hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, const PlanLists& L,
                        uint32_t* counter, hipStream_t st, struct StageEvents* ev);
 // Point each job's scratch fields into `base` (device memory of P.scratch_bytes).
 void bind_scratch(Plan& P, uint8_t* base);
@@ -86,8 +101,10 @@ hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* co
 hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, int D, int strip,
                          int n_wg, size_t lds_bytes, uint32_t* counter, hipStream_t st);
 hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st);
-hipError_t launch_pad(const JobDesc* jobs, const int* rlist, int n_rjobs, int64_t max_dwords,
+hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int64_t max_dwords,
                       hipStream_t st);
+hipError_t launch_subpel(const JobDesc* jobs, const int* slist, int n_sjobs, int n_sctus,
+                         hipStream_t st);
 hipError_t launch_refine(const JobDesc* jobs, const int* rlist, int n_rjobs, int n_rctus,
                          int max_r, hipStream_t st);
 hipError_t launch_depth_bounds(const uint8_t* ref_depth, int ref_w, int ref_h, int dep_w,

@@ -20,6 +20,7 @@ struct RungCfg {
   int width, height, qp, search_range, ref_rung;  // ref_rung -1: a root (no dependency)
   int dlo = 0, dhi = 1;  // depth-bound policy of this rung as a dependent
   int refine = -1;       // refinement half-width of its seed, -1: not seeded
+  int subpel = 0;        // quarter-pel refinement of its MVs
 };
 
 struct SchedConfig {

@@ -32,7 +32,8 @@ class mr_frame(ctypes.Structure):
 
 
 class mr_search_params(ctypes.Structure):
-    _fields_ = [("qp", ctypes.c_int32), ("search_range", ctypes.c_int32)]
+    _fields_ = [("qp", ctypes.c_int32), ("search_range", ctypes.c_int32),
+                ("subpel", ctypes.c_int32)]
 
 
 class mr_search_out(ctypes.Structure):
@@ -43,7 +44,7 @@ class mr_search_out(ctypes.Structure):
 
 class mr_mv_seed(ctypes.Structure):
     _fields_ = [("ref_mv", ctypes.c_void_p), ("ref_w", ctypes.c_int32), ("ref_h", ctypes.c_int32),
-                ("refine_range", ctypes.c_int32)]
+                ("refine_range", ctypes.c_int32), ("quarter_pel", ctypes.c_int32)]
 
 
 class mr_search_job(ctypes.Structure):
@@ -158,7 +159,7 @@ def _frame(t: torch.Tensor, name):
 
 def _seed_struct(seed):
     """seed: dict {ref_mv: (ceil(ref_h/8), ceil(ref_w/8), 2) int16 device tensor, ref_w, ref_h,
-    r}, or None."""
+    r, qpel (optional: the map is in quarter-pel units)}, or None."""
     if seed is None:
         return None
     rm = seed["ref_mv"]
@@ -167,19 +168,20 @@ def _seed_struct(seed):
     if tuple(rm.shape[:2]) != unit_shape(seed["ref_w"], seed["ref_h"]):
         raise ValueError("ref_mv shape does not match ref_w x ref_h")
     return mr_mv_seed(_dev_ptr(rm, torch.int16, "ref_mv"), seed["ref_w"], seed["ref_h"],
-                      seed["r"])
+                      seed["r"], 1 if seed.get("qpel") else 0)
 
 
 def mr_ctu_search(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: int,
                   bounds: torch.Tensor | None = None, out: dict | None = None, stream=None,
-                  seed: dict | None = None):
+                  seed: dict | None = None, subpel: bool = False):
     """Coding-tree search of one frame pair (see mr_ctu_search and mr_ctu_search_seeded in
-    include/mr.h); seeded when ``seed`` is given."""
+    include/mr.h); seeded when ``seed`` is given; with ``subpel`` the MVs are refined to
+    quarter-pel and returned in quarter-pel units."""
     H, W = cur.shape
     if out is None:
         out = alloc_outputs(W, H, cur.device)
     fc, fr = _frame(cur, "cur"), _frame(ref, "ref")
-    prm = mr_search_params(qp, search_range)
+    prm = mr_search_params(qp, search_range, 1 if subpel else 0)
     o = mr_search_out(_dev_ptr(out["depth"], torch.uint8, "depth"),
                       _dev_ptr(out["mode"], torch.uint8, "mode"),
                       _dev_ptr(out["mv"], torch.int16, "mv"),
@@ -227,7 +229,8 @@ def _job_array(jobs):
             arr._seeds.append(sd)
             sp = ctypes.pointer(sd)
         arr[i] = mr_search_job(_frame(cur, "cur"), _frame(j["ref"], "ref"),
-                               mr_search_params(j["qp"], j["search_range"]),
+                               mr_search_params(j["qp"], j["search_range"],
+                                                1 if j.get("subpel") else 0),
                                None if b is None else _dev_ptr(b, torch.uint8, "bounds"),
                                _out_struct(j["out"]), sp)
     return arr
@@ -342,7 +345,7 @@ MR_MAX_RUNGS = 16
 class mr_rung(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("qp", ctypes.c_int32),
                 ("search_range", ctypes.c_int32), ("ref_rung", ctypes.c_int32),
-                ("own_policy", ctypes.c_int32), ("delta_lo", ctypes.c_int32),
+                ("subpel", ctypes.c_int32), ("own_policy", ctypes.c_int32), ("delta_lo", ctypes.c_int32),
                 ("delta_hi", ctypes.c_int32), ("reuse_mv", ctypes.c_int32),
                 ("refine_range", ctypes.c_int32)]
 
@@ -426,7 +429,8 @@ class Ladder:
             own = any(k in r for k in ("delta_lo", "delta_hi", "refine_range"))
             rr = r.get("refine_range")
             cfg.rungs[i] = mr_rung(r["width"], r["height"], r["qp"], r["search_range"],
-                                   r.get("ref_rung", -1), 1 if own else 0, r.get("delta_lo", 0),
+                                   r.get("ref_rung", -1), 1 if r.get("subpel") else 0,
+                                   1 if own else 0, r.get("delta_lo", 0),
                                    r.get("delta_hi", 1), 0 if rr is None else 1,
                                    0 if rr is None else rr)
         cfg.delta_lo, cfg.delta_hi = delta_lo, delta_hi

@@ -1,0 +1,242 @@
+"""GPU parity of the quarter-pel refinement (subpel = 1) against the oracle.
+
+Depth, mode, quarter-pel MV per 8x8 unit and J / D / R per CTU must match the
+oracle bit for bit: full search, bounded, seeded (integer and quarter-pel seed
+maps), batched and graph-replayed, and through the ladder server.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("depth", "mode", "mv", "cost", "dist", "bits")
+
+
+@pytest.fixture(scope="module")
+def mr():
+    import torch
+    from paper_2301_12191_amd import mr as m
+    assert torch.cuda.is_available()
+    m.lib()
+    oracle.build(force=False)
+    synth.build(force=False)
+    return m
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(out):
+    import torch
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _compare(got, exp, W, H, ctus=None, label=""):
+    if ctus is None:
+        for k in FIELDS:
+            if not np.array_equal(got[k], exp[k]):
+                bad = np.argwhere(got[k] != exp[k])
+                raise AssertionError(f"{label}: {k} differs at {bad[:5].tolist()} "
+                                     f"(got {got[k][tuple(bad[0])]}, exp {exp[k][tuple(bad[0])]})")
+        return
+    uh, uw = (H + 7) // 8, (W + 7) // 8
+    tw = (uw * 8 + 63) // 64
+    m = np.zeros((uh, uw), bool)
+    for t in ctus:
+        m[(t // tw) * 8:(t // tw) * 8 + 8, (t % tw) * 8:(t % tw) * 8 + 8] = True
+    for k in ("depth", "mode", "mv"):
+        assert np.array_equal(got[k][m], exp[k][m]), f"{label}: {k} differs on sampled CTUs"
+    for k in ("cost", "dist", "bits"):
+        assert np.array_equal(got[k].ravel()[ctus], exp[k].ravel()[ctus]), f"{label}: {k}"
+
+
+def _pair(seed, W, H, n_rects, mv_max, pan=0):
+    sc = synth.Scene(seed, W, H, n_rects, mv_max, pan)
+    return sc.render(0), sc.render(1)
+
+
+def _gpu(mr, cur, ref, qp, R, bounds=None, seed=None):
+    b = None if bounds is None else _dev(bounds)
+    sd = None
+    if seed is not None:
+        rm, rw, rh, r, q = seed
+        sd = dict(ref_mv=_dev(rm), ref_w=rw, ref_h=rh, r=r, qpel=q)
+    return _host(mr.mr_ctu_search(_dev(cur), _dev(ref), qp, R, bounds=b, seed=sd, subpel=True))
+
+
+def _oracle(cur, ref, qp, R, bounds=None, seed=None, ctu_list=None):
+    sd = None if seed is None else oracle.Seed(seed[0], seed[1], seed[2], seed[3], qpel=seed[4])
+    return oracle.ctu_search(cur, ref, qp, R, bounds=bounds, seed=sd, ctu_list=ctu_list,
+                             subpel=True)
+
+
+@pytest.mark.parametrize("W,H,qp,R", [
+    (8, 8, 30, 2), (64, 64, 32, 4), (72, 40, 27, 5), (203, 141, 37, 9), (130, 70, 45, 12),
+    (200, 136, 22, 16), (96, 200, 12, 8),
+])
+def test_subpel_matches_oracle(mr, W, H, qp, R):
+    ref, cur = _pair(W * 3 + H + qp, W, H, 5, min(R, 12) + 1, 2)
+    _compare(_gpu(mr, cur, ref, qp, R), _oracle(cur, ref, qp, R), W, H, label=f"{W}x{H} R{R}")
+
+
+def test_subpel_416x240_full(mr):
+    ref, cur = _pair(91, 416, 240, 6, 12, 2)
+    _compare(_gpu(mr, cur, ref, 32, 16), _oracle(cur, ref, 32, 16), 416, 240, label="416x240")
+
+
+def test_subpel_identical_and_half_pel_content(mr):
+    f = synth.Scene(93, 128, 64, 4, 6, 0).render(0)
+    got = _gpu(mr, f, f, 30, 6)
+    _compare(got, _oracle(f, f, 30, 6), 128, 64, label="identical")
+    assert np.all(got["mv"] == 0)
+    # cur = the reference interpolated at (1.5, -0.5) px: CUs with clean motion land on (6, -2).
+    ref = synth.Scene(94, 128, 64, 3, 4, 0).render(0)
+    cur = np.zeros_like(ref)
+    for y in range(64):
+        for x in range(128):
+            cur[y, x] = oracle.interp_qpel(ref, 4 * x + 6, 4 * y - 2)
+    got = _gpu(mr, cur, ref, 27, 4)
+    _compare(got, _oracle(cur, ref, 27, 4), 128, 64, label="half-pel shift")
+    assert np.mean((got["mv"][..., 0] == 6) & (got["mv"][..., 1] == -2)) > 0.8
+
+
+def test_subpel_with_bounds_and_seeds(mr):
+    W, H, R = 216, 152, 12
+    ref, cur = _pair(95, W, H, 6, 10, 2)
+    rng = np.random.default_rng(5)
+    lo = rng.integers(0, 4, size=((H + 7) // 8, (W + 7) // 8)).astype(np.uint8)
+    hi = np.minimum(3, lo + rng.integers(0, 3, size=lo.shape)).astype(np.uint8)
+    b = np.stack([lo, hi], axis=-1)
+    _compare(_gpu(mr, cur, ref, 32, R, bounds=b), _oracle(cur, ref, 32, R, bounds=b), W, H,
+             label="bounds")
+    rm = rng.integers(-6, 7, size=((H // 2 + 7) // 8, (W // 2 + 7) // 8, 2)).astype(np.int16)
+    seed = (rm, W // 2, H // 2, 2, False)
+    _compare(_gpu(mr, cur, ref, 32, R, bounds=b, seed=seed),
+             _oracle(cur, ref, 32, R, bounds=b, seed=seed), W, H, label="seeded + bounds")
+    # A quarter-pel seed map (as written by a sub-pel search of the half-size picture).
+    rq = rng.integers(-24, 25, size=rm.shape).astype(np.int16)
+    seed = (rq, W // 2, H // 2, 3, True)
+    _compare(_gpu(mr, cur, ref, 32, R, seed=seed), _oracle(cur, ref, 32, R, seed=seed), W, H,
+             label="quarter-pel seed")
+
+
+def test_subpel_chain_quarter_pel_seeds(mr):
+    """208x120 sub-pel search; its quarter-pel MVs seed the 416x240 sub-pel search."""
+    import torch
+    src = synth.Scene(synth.SEED_BASE + 11, 416, 240, 6, 12, 2)
+    s0, s1 = src.render(0), src.render(1)
+    r0, r1 = synth.box_downscale(s0, 2, 208, 120), synth.box_downscale(s1, 2, 208, 120)
+    g_ref = _gpu(mr, r1, r0, 35, 8)
+    o_ref = _oracle(r1, r0, 35, 8)
+    _compare(g_ref, o_ref, 208, 120, label="reference rung")
+    gb = mr.mr_depth_bounds(_dev(g_ref["depth"]), 208, 120, 416, 240, 0, 1)
+    torch.cuda.synchronize()
+    ob = oracle.depth_bounds(o_ref["depth"], 208, 120, 416, 240, 0, 1)
+    got = _host(mr.mr_ctu_search(_dev(s1), _dev(s0), 32, 16, bounds=gb, subpel=True,
+                                 seed=dict(ref_mv=_dev(g_ref["mv"]), ref_w=208, ref_h=120, r=4,
+                                           qpel=True)))
+    exp = _oracle(s1, s0, 32, 16, bounds=ob, seed=(o_ref["mv"], 208, 120, 4, True))
+    _compare(got, exp, 416, 240, label="dependent rung")
+
+
+def test_subpel_1080p_sampled(mr):
+    sc = synth.Scene(synth.SEED_BASE + 1, 1920, 1080, 24, 48, 4)
+    ref, cur = sc.render(0), sc.render(1)
+    got = _gpu(mr, cur, ref, 27, 64)
+    ctus = [0, 29, 255, 509]
+    _compare(got, _oracle(cur, ref, 27, 64, ctu_list=ctus), 1920, 1080, ctus=ctus,
+             label="1080p R64 sub-pel")
+
+
+def test_subpel_batch_and_graph(mr):
+    """Sub-pel and integer jobs, full and seeded, in one batch and a replayed graph."""
+    specs = []
+    ra, ca = _pair(97, 200, 136, 5, 10, 2)
+    specs.append(dict(cur=ca, ref=ra, qp=32, R=16, subpel=True, seed=None))
+    rb, cb = _pair(98, 416, 240, 6, 12, 2)
+    rm = np.random.default_rng(2).integers(-16, 17, size=(15, 26, 2)).astype(np.int16)
+    specs.append(dict(cur=cb, ref=rb, qp=30, R=16, subpel=True, seed=(rm, 208, 120, 3, False)))
+    rc_, cc = _pair(99, 72, 40, 3, 5, 1)
+    specs.append(dict(cur=cc, ref=rc_, qp=27, R=5, subpel=False, seed=None))
+    exp = []
+    for sp in specs:
+        sd = None if sp["seed"] is None else oracle.Seed(*sp["seed"][:4], qpel=sp["seed"][4])
+        exp.append(oracle.ctu_search(sp["cur"], sp["ref"], sp["qp"], sp["R"], seed=sd,
+                                     subpel=sp["subpel"]))
+
+    def jobs():
+        out = []
+        for sp in specs:
+            j = dict(cur=_dev(sp["cur"]), ref=_dev(sp["ref"]), qp=sp["qp"], search_range=sp["R"],
+                     subpel=sp["subpel"])
+            if sp["seed"] is not None:
+                rm_, rw, rh, r, q = sp["seed"]
+                j["seed"] = dict(ref_mv=_dev(rm_), ref_w=rw, ref_h=rh, r=r, qpel=q)
+            out.append(j)
+        return out
+
+    outs = mr.mr_ctu_search_batch(jobs())
+    for i, (o, e) in enumerate(zip(outs, exp)):
+        H, W = specs[i]["cur"].shape
+        _compare(_host(o), e, W, H, label=f"batch job {i}")
+    bt = mr.Batch(jobs())
+    try:
+        for rep in range(3):
+            for i, (o, e) in enumerate(zip(bt.launch(), exp)):
+                H, W = specs[i]["cur"].shape
+                _compare(_host(o), e, W, H, label=f"replay {rep} job {i}")
+    finally:
+        bt.close()
+
+
+def test_subpel_ladder_reference_rung(mr):
+    """A sub-pel reference rung seeds its dependents with quarter-pel MVs; every job equals the
+    same search run alone."""
+    import torch
+    rungs = [dict(width=160, height=96, qp=32, search_range=8, ref_rung=-1, subpel=True),
+             dict(width=320, height=192, qp=30, search_range=16, ref_rung=0, subpel=True,
+                  delta_lo=0, delta_hi=1, refine_range=4),
+             dict(width=320, height=192, qp=34, search_range=16, ref_rung=1, subpel=False,
+                  delta_lo=1, delta_hi=1, refine_range=2)]
+    fr = {}
+    for f in range(3):
+        img = synth.Scene(synth.SEED_BASE + 60, 320, 192, 6, 10, 2).render(f)
+        fr[(0, f, 0)] = torch.from_numpy(synth.box_downscale(img, 2, 160, 96)).cuda()
+        fr[(0, f, 1)] = torch.from_numpy(img).cuda()
+        fr[(0, f, 2)] = fr[(0, f, 1)]
+    lad = mr.Ladder(rungs)
+    got = {}
+    try:
+        for key, t in fr.items():
+            lad.put_frame(*key, t)
+        ids = {lad.submit(0, f, r): (f, r) for f in (1, 2) for r in (2, 1, 0)}
+        deadline = 2000
+        while len(got) < len(ids) and deadline > 0:
+            for c in lad.poll(64, 100000):
+                assert c.status == 0
+                if c.job_id in ids:
+                    torch.cuda.synchronize()
+                    got[ids[c.job_id]] = {k: v.cpu().numpy() for k, v in lad.outputs(c).items()}
+                lad.release(c.job_id)
+            deadline -= 1
+    finally:
+        lad.close()
+    assert len(got) == 6
+    for f in (1, 2):
+        o0 = mr.mr_ctu_search(fr[(0, f, 0)], fr[(0, f - 1, 0)], 32, 8, subpel=True)
+        b1 = mr.mr_depth_bounds(o0["depth"], 160, 96, 320, 192, 0, 1)
+        o1 = mr.mr_ctu_search(fr[(0, f, 1)], fr[(0, f - 1, 1)], 30, 16, bounds=b1, subpel=True,
+                              seed=dict(ref_mv=o0["mv"], ref_w=160, ref_h=96, r=4, qpel=True))
+        b2 = mr.mr_depth_bounds(o1["depth"], 320, 192, 320, 192, 1, 1)
+        o2 = mr.mr_ctu_search(fr[(0, f, 2)], fr[(0, f - 1, 2)], 34, 16, bounds=b2,
+                              seed=dict(ref_mv=o1["mv"], ref_w=320, ref_h=192, r=2, qpel=True))
+        torch.cuda.synchronize()
+        for r, o in enumerate((o0, o1, o2)):
+            for k in FIELDS:
+                assert np.array_equal(got[(f, r)][k], o[k].cpu().numpy()), ((f, r), k)

@@ -50,7 +50,7 @@ def _fake_out(mr):
 
 @pytest.mark.parametrize("case", ["qp_low", "qp_high", "range_neg", "range_big", "null_cur",
                                   "size_mismatch", "stride_small", "zero_width", "huge",
-                                  "null_out_field"])
+                                  "null_out_field", "subpel_2", "subpel_neg"])
 def test_search_rejects_invalid_arguments_before_launch(libmr, case):
     from paper_2301_12191_amd import mr
     cur, ref = _fake_frame(mr), _fake_frame(mr)
@@ -76,6 +76,10 @@ def test_search_rejects_invalid_arguments_before_launch(libmr, case):
         cur, ref = _fake_frame(mr, 8193, 64), _fake_frame(mr, 8193, 64)
     elif case == "null_out_field":
         out.mv = None
+    elif case == "subpel_2":
+        prm.subpel = 2
+    elif case == "subpel_neg":
+        prm.subpel = -1
     rc = libmr.mr_ctu_search(ctypes.byref(cur), ctypes.byref(ref), ctypes.byref(prm), None,
                              ctypes.byref(out), None)
     assert rc == mr.MR_EINVAL
@@ -124,7 +128,8 @@ def test_batch_rejects_invalid_jobs_before_launch(libmr):
     assert libmr.mr_batch_destroy(None) == mr.MR_OK
 
 
-@pytest.mark.parametrize("case", ["null_map", "zero_w", "huge_h", "r_neg", "r_above_range"])
+@pytest.mark.parametrize("case", ["null_map", "zero_w", "huge_h", "r_neg", "r_above_range",
+                                  "qpel_2"])
 def test_seeded_search_rejects_invalid_seeds_before_launch(libmr, case):
     from paper_2301_12191_amd import mr
     cur, ref = _fake_frame(mr), _fake_frame(mr)
@@ -141,6 +146,8 @@ def test_seeded_search_rejects_invalid_seeds_before_launch(libmr, case):
         sd.refine_range = -1
     elif case == "r_above_range":
         sd.refine_range = 17
+    elif case == "qpel_2":
+        sd.quarter_pel = 2
     rc = libmr.mr_ctu_search_seeded(ctypes.byref(cur), ctypes.byref(ref), ctypes.byref(prm), None,
                                     ctypes.byref(sd), ctypes.byref(out), None)
     assert rc == mr.MR_EINVAL
@@ -173,15 +180,17 @@ def test_ladder_rejects_invalid_mv_reuse_config(libmr, reuse, r):
 
 
 @pytest.mark.parametrize("case", ["too_many_rungs", "own_policy_2", "rung_delta", "rung_refine",
-                                  "cycle"])
+                                  "cycle", "rung_subpel"])
 def test_ladder_rejects_invalid_rung_policies(libmr, case):
     from paper_2301_12191_amd import mr
     L = mr._ladder_lib()
     cfg = mr.mr_ladder_config()
     cfg.n_rungs = 3
     cfg.rungs[0] = mr.mr_rung(64, 64, 30, 8, -1)
-    cfg.rungs[1] = mr.mr_rung(128, 128, 30, 16, 0, 1, 0, 1, 1, 4)
-    cfg.rungs[2] = mr.mr_rung(128, 128, 34, 16, 1, 1, 1, 1, 1, 2)
+    cfg.rungs[1] = mr.mr_rung(128, 128, 30, 16, 0, own_policy=1, delta_lo=0, delta_hi=1,
+                              reuse_mv=1, refine_range=4)
+    cfg.rungs[2] = mr.mr_rung(128, 128, 34, 16, 1, own_policy=1, delta_lo=1, delta_hi=1,
+                              reuse_mv=1, refine_range=2)
     cfg.delta_lo, cfg.delta_hi = 0, 1
     cfg.hbm_budget_bytes = 1 << 30
     cfg.max_inflight, cfg.max_queue, cfg.max_batch_jobs = 8, 8, 8
@@ -195,6 +204,8 @@ def test_ladder_rejects_invalid_rung_policies(libmr, case):
         cfg.rungs[1].refine_range = 129
     elif case == "cycle":
         cfg.rungs[1].ref_rung = 2
+    elif case == "rung_subpel":
+        cfg.rungs[2].subpel = 2
     h = ctypes.c_void_p()
     assert L.mr_ladder_open(ctypes.byref(cfg), ctypes.byref(h)) == mr.MR_EINVAL
     assert not h.value
