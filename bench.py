@@ -16,6 +16,8 @@ Beside it the JSON line carries:
                  pruned over full search and the exact RD-cost increase; the
                  same with the reference MVs reused as search centres
                  (refinement r = 4), and the refinement stage's absdiff rate;
+  subpel       : the headline workload with quarter-pel refinement (SATD, H.265
+                 interpolation): time, the refinement's share, RD-cost change;
   multi_qp     : one 1920x1080 pair at QPs 22/26/30/34/38 with the median QP as
                  master (same-resolution sharing): speedup of master + bounded,
                  seeded dependents over five full searches, RD-cost increase per QP;
@@ -25,7 +27,8 @@ Beside it the JSON line carries:
   cpu_baseline : the CPU oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-pruned]
-                      [--no-multi-qp] [--no-dag] [--no-ladder] [--no-serving]
+                      [--no-subpel] [--no-multi-qp] [--no-dag] [--no-ladder]
+                      [--no-serving]
 """
 import argparse
 import json
@@ -160,6 +163,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
     ap.add_argument("--no-multi-qp", action="store_true")
+    ap.add_argument("--no-subpel", action="store_true")
     ap.add_argument("--no-dag", action="store_true")
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -256,6 +260,38 @@ def main():
         "tiles": {"d": tune["d"], "nbands": tune["nbands"], "strip": tune["strip"],
                   "autotune_shapes": tune["tried"]},
     }
+
+    # ----------------------------------------- quarter-pel refinement, same workload
+    subpel = None
+    if not args.no_subpel:
+        jobs_sp = [dict(cur=frames[k + 1], ref=frames[k], qp=QP, search_range=R, subpel=True)
+                   for k in range(NP)]
+        bsp = mr.Batch(jobs_sp)
+        for _ in range(max(1, args.warmup)):
+            bsp.launch(stream)
+        torch.cuda.synchronize()
+        mr.mr_profile_read(reset=True)
+        mr.mr_profile_enable(True)
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            bsp.launch(stream)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        mr.mr_profile_enable(False)
+        pst = mr.mr_profile_read(reset=True)
+        j_int = sum(int(j["out"]["cost"].sum().item()) for j in jobs)
+        j_sp = sum(int(j["out"]["cost"].sum().item()) for j in jobs_sp)
+        sp_ms = (tb - ta) * 1e3 / args.steps
+        stage = {k: round(v[0] / max(1, v[1]), 4) for k, v in pst.items()}
+        subpel = {
+            "workload": "the headline 8 pairs (1920x1080, R 64, QP 27) with half- and quarter-pel "
+                        "SATD refinement of every CU's MV (H.265 luma interpolation)",
+            "ms_per_step": round(sp_ms, 4), "ctus_per_s": round(ctus_per_step / (sp_ms * 1e-3), 1),
+            "stage_avg_ms": stage,
+            "refinement_ms": round(stage["search"] - roofline["stage_avg_ms"]["search"], 4),
+            "rd_cost_change_pct": round(100.0 * (j_sp - j_int) / j_int, 6)}
+        bsp.close()
+        log(f"subpel: {subpel}")
 
     # ------------------------------------------------------------- pruned vs full search
     pruned = None
@@ -513,7 +549,7 @@ def main():
         "config": {"workload": "1920x1080 luma, 8 frame pairs, full search R64 QP27",
                    "ctus_per_step": ctus_per_step, "frames": NP + 1, "search_range": R,
                    "qp": QP},
-        "roofline": roofline, "cpu_baseline": cpu, "pruned": pruned, "multi_qp": multi_qp, "dag": dag, "ladder": ladder,
+        "roofline": roofline, "cpu_baseline": cpu, "subpel": subpel, "pruned": pruned, "multi_qp": multi_qp, "dag": dag, "ladder": ladder,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

@@ -114,7 +114,8 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
       }
     }
     int cqx = 4 * mx, cqy = 4 * my;
-    uint32_t csatd = 0;
+    uint32_t csatd = 0, csatd_tile = 0;
+#pragma unroll 1
     for (int step = 2; step >= 1; --step) {
       uint32_t sat[9];
 #pragma unroll
@@ -144,6 +145,12 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
         }
 #pragma unroll
         for (int iy = 0; iy < 3; ++iy) {
+          // The quarter-pel stage's centre is the half-pel stage's best, whose
+          // SATD is already known.
+          if (step == 1 && ix == 1 && iy == 1) {
+            sat[4] = csatd_tile;
+            continue;
+          }
           const int qy = cqy + step * (iy - 1);
           const int fy = qy & 3, g = ((qy - fy) >> 2) - my;  // g in {-1, 0}
           uint32_t tv[4];
@@ -169,6 +176,8 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
           sat[iy * 3 + ix] = satd4x4(resid);
         }
       }
+      const uint32_t tile_sat[9] = {sat[0], sat[1], sat[2], sat[3], sat[4], sat[5], sat[6],
+                                    sat[7], sat[8]};
       // Sum each candidate's SATD over the CU's tiles.
       if (d == 0) {
 #pragma unroll
@@ -202,6 +211,10 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
       cqx += step * (bk % 3 - 1);
       cqy += step * (bk / 3 - 1);
       csatd = sat[bk];
+      // This tile's share of the best candidate's SATD (the next stage's centre).
+      csatd_tile = tile_sat[0];
+#pragma unroll
+      for (int k = 1; k < 9; ++k) csatd_tile = bk == k ? tile_sat[k] : csatd_tile;
     }
     const int gsz = 1 << (2 * (4 - d));  // tiles per CU
     if (e && (t & (gsz - 1)) == 0) {
