@@ -310,7 +310,7 @@ struct LeafShared {
   int16_t refs[kRefTotal];
   int16_t mvx[kNodes], mvy[kNodes];  // integer-pel, or quarter-pel with sub-pel refinement
   uint32_t satq[kNodes];             // sub-pel: SATD at the refined MV
-  int32_t dc[kNodes];
+  int32_t dc[kNodes];                // DC: sum of the n top and n left neighbours
   uint32_t satd[kNodes][3];
   uint32_t part0[4][3];          // per-wave partial sums for the 64x64 node
   int64_t jt[kNodes], dt[kNodes], rt[kNodes];
@@ -375,53 +375,43 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     }
     sh.split_ok[node] = split_ok, sh.leaf_ok[node] = leaf_ok;
   }
-  // Raw neighbour samples, -1 where unavailable (outside the coded picture).
+  if (tid < kNodes) sh.dc[tid] = 0;  // DC sums, accumulated below
+  __syncthreads();
+  // Neighbour samples after H.265 reference substitution, one entry per
+  // thread.  In the substitution's scan order (left column bottom to top,
+  // corner, top row left to right; scan index k = 2n - off for the left column
+  // and k = off for the top row) the available samples -- those inside the
+  // coded picture -- form one interval [a, b]: an unavailable sample takes the
+  // nearest available one scanned before it, or the first available one when
+  // none is, i.e. the sample at clamp(k, a, b); with none available, 128.
   for (int i = tid; i < kRefTotal; i += blockDim.x) {
     int node, off;
     if (i < 257) node = 0, off = i;
     else if (i < 257 + 4 * 129) node = 1 + (i - 257) / 129, off = (i - 257) % 129;
     else if (i < 257 + 4 * 129 + 16 * 65) node = 5 + (i - 773) / 65, off = (i - 773) % 65;
     else node = 21 + (i - 1813) / 33, off = (i - 1813) % 33;
+    if (!sh.elig[node]) continue;
     const int d = node == 0 ? 0 : node < 5 ? 1 : node < 21 ? 2 : 3;
     const int local = node - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
     const int n = kCtu >> d, x0 = cx + (local % (1 << d)) * n, y0 = cy + (local / (1 << d)) * n;
-    int x, y;
-    if (off <= 2 * n) x = x0 - 1, y = y0 - 1 + off;        // left column p[-1][off-1]
-    else x = x0 + (off - 2 * n - 1), y = y0 - 1;            // top row p[off-2n-1][-1]
-    int v = -1;
-    if (x >= 0 && y >= 0 && x < W8 && y < H8)
+    const bool hasL = x0 >= 1, hasT = y0 >= 1;
+    int v = 128;
+    if (hasL || hasT) {
+      // Left column entries p[-1][i - 1], i = 0..2n (i = 0 the corner), are
+      // available for i in [hasT ? 0 : 1, min(2n, H8 - y0)]; top-row entries
+      // p[i][-1] for i in [0, min(2n - 1, W8 - 1 - x0)].
+      const int iLlo = hasT ? 0 : 1, iLhi = min(2 * n, H8 - y0);
+      const int a = hasL ? 2 * n - iLhi : 2 * n + 1;
+      const int b = hasT ? 2 * n + 1 + min(2 * n - 1, W8 - 1 - x0) : 2 * n - iLlo;
+      const int k = clampi(off <= 2 * n ? 2 * n - off : off, a, b);
+      int x, y;
+      if (k <= 2 * n) x = x0 - 1, y = y0 - 1 + (2 * n - k);  // left column / corner
+      else x = x0 + (k - 2 * n - 1), y = y0 - 1;             // top row
       v = jb->cur[(size_t)min(y, jb->h - 1) * jb->stride + min(x, jb->w - 1)];
-    sh.refs[i] = (int16_t)v;
-  }
-  __syncthreads();
-  // Substitution per node (sequential scan), then the DC value.
-  if (tid < kNodes && sh.elig[tid]) {
-    const int node = tid;
-    const int d = node == 0 ? 0 : node < 5 ? 1 : node < 21 ? 2 : 3;
-    const int n = kCtu >> d;
-    int16_t* L = sh.refs + ref_offset(node);  // L[0..2n] = p[-1][-1..2n-1]
-    int16_t* T = L + 2 * n + 1;               // T[0..2n-1] = p[0..2n-1][-1]
-    bool any = false;
-    for (int i = 0; i <= 2 * n; ++i) any |= L[i] >= 0;
-    for (int i = 0; i < 2 * n; ++i) any |= T[i] >= 0;
-    if (!any) {
-      for (int i = 0; i <= 2 * n; ++i) L[i] = 128;
-      for (int i = 0; i < 2 * n; ++i) T[i] = 128;
-    } else {
-      if (L[2 * n] < 0) {
-        int v = -1;
-        for (int i = 2 * n - 1; i >= 0 && v < 0; --i) v = L[i];
-        for (int i = 0; i < 2 * n && v < 0; ++i) v = T[i];
-        L[2 * n] = (int16_t)v;
-      }
-      for (int i = 2 * n - 1; i >= 0; --i)
-        if (L[i] < 0) L[i] = L[i + 1];
-      for (int i = 0; i < 2 * n; ++i)
-        if (T[i] < 0) T[i] = i == 0 ? L[0] : T[i - 1];
     }
-    int s = n;
-    for (int i = 0; i < n; ++i) s += T[i] + L[i + 1];
-    sh.dc[node] = s >> (31 - __builtin_clz((unsigned)n) + 1);
+    sh.refs[i] = (int16_t)v;
+    // DC: p[0..n-1][-1] (off 2n+1 .. 3n) and p[-1][0..n-1] (off 1 .. n).
+    if ((off >= 1 && off <= n) || (off > 2 * n && off <= 3 * n)) atomicAdd(&sh.dc[node], v);
   }
   __syncthreads();
 
@@ -462,7 +452,7 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
           r[i] = c[i] - p;
         }
         v1 = satd4x4(r);
-        const int dcv = sh.dc[node];
+        const int dcv = (sh.dc[node] + n) >> (lg + 1);
 #pragma unroll
         for (int i = 0; i < 16; ++i) r[i] = c[i] - dcv;
         v2 = satd4x4(r);
