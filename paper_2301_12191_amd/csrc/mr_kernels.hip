@@ -121,16 +121,18 @@ __device__ __forceinline__ void merge_keys(uint32_t vk, const uint64_t* __restri
   }
 }
 
-// One wavefront: all steps of one (CTU, band); `win` points at this CTU's
-// column 0 of the staged window (dx = -R); `ring` is this wavefront's
-// 512-byte LDS ring for the current CTU (two 16x16 regions of 64 dwords).
+// One wavefront: steps [st_lo, st_hi) of one (CTU, band); `win` points at
+// this CTU's column 0 of the staged window (dx = -R); `ring` is this
+// wavefront's 512-byte LDS ring for the current CTU (two 16x16 regions of 64
+// dwords).
 template <int D>
-__device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win, uint32_t* ring) {
+__device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, const uint32_t* win,
+                            uint32_t* ring) {
   const int lane = threadIdx.x & 63;
   const int Q = jb->Q, Wd = jb->win_dwords;
   const int g0 = jb->band_g0[band], g1 = jb->band_g0[band + 1];
   const int ntasks = (g1 - g0) * Q;
-  const int step0 = jb->band_step0[band], nsteps = jb->band_step0[band + 1] - step0;
+  const int step0 = jb->band_step0[band];
   // Leaf-eligible nodes as an 85-bit mask in SGPRs (bit n of word n >> 5).
   const sptr32 eb = (sptr32)(jb->eligbits + (size_t)ctu * 4);
   const uint32_t em0 = eb[0], em1 = eb[1], em2 = eb[2];
@@ -140,7 +142,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, const uint32_t* win, uin
   const uint64_t* __restrict__ dtab = jb->dtab;
   uint64_t best8 = kKeyNone, bestB = kKeyNone;
 
-  for (int st = 0; st < nsteps; ++st) {
+  for (int st = st_lo; st < st_hi; ++st) {
     const int gstep = step0 + st;
     int task = st * kWaveSteps + lane;
     if (task >= ntasks) task = ntasks - 1;  // idle lane: its table entries are invalid
@@ -605,9 +607,14 @@ __global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_j
 }
 
 // Persistent search: each workgroup pops items until the queue is empty.  An
-// item is a strip of up to `strip` horizontally adjacent CTUs (one wavefront
-// each) and one dy band; the strip's reference window band is staged once in
-// LDS and shared by its wavefronts.  items == null: one job, items implicit.
+// item is a strip of up to `strip` horizontally adjacent CTUs and one dy band;
+// the strip's reference window band is staged once in LDS and shared by the
+// workgroup's `strip` wavefronts.  The item's (CTU, step) pairs are dealt to
+// the wavefronts in equal contiguous shares: one CTU per wavefront for a full
+// strip; a partial strip at the right picture edge splits each CTU's steps
+// over several wavefronts instead of leaving some idle (partial results merge
+// through the same atomic minima as bands do).  items == null: one job, items
+// implicit.
 template <int D>
 __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const uint2* items_,
                                                   int n_items, uint32_t* counter, uint32_t* win,
@@ -637,10 +644,17 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
     const int rows = (g1 - g0) * D + 63;
     stage_window(jb, col0 * kCtu - jb->R, row * kCtu - jb->R + g0 * D, rows, win);
     __syncthreads();
-    const int col = col0 + wave;
     // This wavefront's current-CTU ring follows the largest window of the launch.
     uint32_t* ring = win + win_dwords_max + wave * (kCurRingBytes / 4);
-    if (col < jb->ctus_w) search_wave<D>(jb, row * jb->ctus_w + col, band, win + 16 * wave, ring);
+    const int nw = jb->strip, sw = min(nw, jb->ctus_w - col0);
+    const int nst = jb->band_step0[band + 1] - jb->band_step0[band];
+    int lo = wave * sw * nst / nw;
+    const int hi = (wave + 1) * sw * nst / nw;
+    while (lo < hi) {
+      const int c = lo / nst, s0 = lo - c * nst, s1 = min(nst, s0 + (hi - lo));
+      search_wave<D>(jb, row * jb->ctus_w + col0 + c, band, s0, s1, win + 16 * c, ring);
+      lo += s1 - s0;
+    }
     __syncthreads();  // the window is restaged for the next item
   }
 }

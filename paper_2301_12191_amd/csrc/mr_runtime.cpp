@@ -386,10 +386,14 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
       for (int b = 0; b < L.nbands; ++b) {
         const int steps = L.band_step0[b + 1] - L.band_step0[b];
         const int rows = (L.band_g0[b + 1] - L.band_g0[b]) * P->D + 63;
-        const int64_t cost = (int64_t)steps * 4096 + rows;  // compute + staging
         for (int row = 0; row < jb.ctus_h; ++row)
-          for (int sidx = 0; sidx < spr; ++sidx)
+          for (int sidx = 0; sidx < spr; ++sidx) {
+            // A partial strip spreads its CTUs' steps over all the strip's wavefronts.
+            const int sw = std::min(P->strip, jb.ctus_w - sidx * P->strip);
+            const int64_t span = ((int64_t)sw * steps + P->strip - 1) / P->strip;
+            const int64_t cost = span * 4096 + rows;  // compute + staging
             work.push_back(Work{cost, (uint32_t)j, pack_item_y(row, sidx * P->strip, b)});
+          }
       }
     }
   }
