@@ -22,14 +22,26 @@
 namespace mr {
 
 // Minimum over the 64 lanes of a wavefront (all lanes active); wave-uniform result.
+// The within-row steps read a valid source lane everywhere, so their "old"
+// operand is never used; passing ~0 (the identity of min) lets each step fuse
+// into one v_min_u32_dpp.
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-  v = min(v, dpp_mov<0xB1, 0xF>(v, v));          // quad_perm [1,0,3,2]
-  v = min(v, dpp_mov<0x4E, 0xF>(v, v));          // quad_perm [2,3,0,1]
-  v = min(v, dpp_mov<0x141, 0xF>(v, v));         // row_half_mirror
-  v = min(v, dpp_mov<0x140, 0xF>(v, v));         // row_mirror
+  v = min(v, dpp_mov<0xB1, 0xF>(0xFFFFFFFFu, v));   // quad_perm [1,0,3,2]
+  v = min(v, dpp_mov<0x4E, 0xF>(0xFFFFFFFFu, v));   // quad_perm [2,3,0,1]
+  v = min(v, dpp_mov<0x141, 0xF>(0xFFFFFFFFu, v));  // row_half_mirror
+  v = min(v, dpp_mov<0x140, 0xF>(0xFFFFFFFFu, v));  // row_mirror
   v = min(v, dpp_mov<0x142, 0xA>(0xFFFFFFFFu, v));  // row_bcast:15
   v = min(v, dpp_mov<0x143, 0xC>(0xFFFFFFFFu, v));  // row_bcast:31
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// v_writelane_b32: clang has no builtin for it, so bind the LLVM intrinsic.
+__device__ int amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// v with lane `l` (wave-uniform) replaced by the wave-uniform value u: one
+// v_writelane instead of a compare, a move and a select.
+__device__ __forceinline__ uint32_t set_lane(uint32_t v, uint32_t u, int l) {
+  return (uint32_t)amdgcn_writelane((int)u, l, (int)v);
 }
 
 // ---------------------------------------------------------------------------------- prep
@@ -220,7 +232,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
             for (int k = 0; k < 4; ++k) m = min(m, acc[j][k] * 2048u + kq[j][k]);
           const uint32_t mk = wave_min(m);
-          vk8 = lane == bz ? mk : vk8;
+          vk8 = set_lane(vk8, mk, bz);
         }
 #pragma unroll
         for (int j = 0; j < D; ++j)
@@ -241,7 +253,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
             for (int k = 0; k < 4; ++k) m = min(m, s16[j][k] * 2048u + kq[j][k]);
           const uint32_t mk = wave_min(m);
-          vkB = lane == reg ? mk : vkB;
+          vkB = set_lane(vkB, mk, reg);
         }
         if ((reg & 3) == 0) {
 #pragma unroll
@@ -263,7 +275,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
             for (int k = 0; k < 4; ++k) m = min(m, s32[j][k] * 2048u + kq[j][k]);
           const uint32_t mk = wave_min(m);
-          vkB = lane == 16 + qz ? mk : vkB;
+          vkB = set_lane(vkB, mk, 16 + qz);
         }
 #pragma unroll
         for (int j = 0; j < D; ++j)
@@ -278,7 +290,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
         for (int k = 0; k < 4; ++k) m = min(m, s64[j][k] * 2048u + kq[j][k]);
       const uint32_t mk = wave_min(m);
-      vkB = lane == 20 ? mk : vkB;
+      vkB = set_lane(vkB, mk, 20);
     }
     const uint64_t* dt = dtab + (size_t)gstep * 2048;
     merge_keys(vk8, dt, best8);
