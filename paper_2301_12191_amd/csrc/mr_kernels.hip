@@ -35,6 +35,29 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Minima over the wavefront of four per-lane values at once: on return lane l
+// holds the minimum over all 64 lanes of v[l & 3].  Two exchange steps leave
+// each lane of a quad with the quad minimum of its own value (lane bit 0, then
+// bit 1, selects which pair/value a lane keeps); rotations by 4 and 8 within a
+// row and exchanges with lanes l ^ 16 and l ^ 32 keep the low two bits, so
+// they complete the reduction per value.
+__device__ __forceinline__ uint32_t wave_min4(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3) {
+  const int lane = threadIdx.x & 63;
+  const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0;
+  uint32_t k0 = b0 ? v1 : v0, s0 = b0 ? v0 : v1;
+  uint32_t k1 = b0 ? v3 : v2, s1 = b0 ? v2 : v3;
+  k0 = min(k0, dpp_mov<0xB1, 0xF>(0xFFFFFFFFu, s0));  // lane ^ 1 (quad_perm [1,0,3,2])
+  k1 = min(k1, dpp_mov<0xB1, 0xF>(0xFFFFFFFFu, s1));
+  uint32_t k = b1 ? k1 : k0;
+  const uint32_t sk = b1 ? k0 : k1;
+  k = min(k, dpp_mov<0x4E, 0xF>(0xFFFFFFFFu, sk));   // lane ^ 2 (quad_perm [2,3,0,1])
+  k = min(k, dpp_mov<0x124, 0xF>(0xFFFFFFFFu, k));   // row_ror:4
+  k = min(k, dpp_mov<0x128, 0xF>(0xFFFFFFFFu, k));   // row_ror:8
+  k = min(k, (uint32_t)__builtin_amdgcn_ds_swizzle((int)k, 0x401F));  // lane ^ 16
+  k = min(k, (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)k));  // lane ^ 32
+  return k;
+}
+
 // v_writelane_b32: clang has no builtin for it, so bind the LLVM intrinsic.
 __device__ int amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
@@ -182,6 +205,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 
     for (int reg = 0; reg < 16; ++reg) {
       const uint32_t* rcur = ring + (reg & 1) * 64;
+      uint32_t m8[4];  // per-lane minimum key of each 8x8 block of the region
 #pragma unroll
       for (int sub = 0; sub < 4; ++sub) {
         const int bz = reg * 4 + sub;
@@ -201,10 +225,17 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
           for (int k = 0; k < 4; ++k) acc[j][k] = 0;
         const uint32_t* rb = lbase + by * 8 * Wd + 2 * bx;
+        // Window rows are loaded one row ahead of their use, so each row's LDS
+        // latency overlaps the previous row's SADs.
+        uint32_t n0 = rb[0], n1 = rb[1], n2 = rb[2];
 #pragma unroll
         for (int w = 0; w < D + 7; ++w) {
-          const uint32_t* rp = rb + w * Wd;
-          const uint32_t d0 = rp[0], d1 = rp[1], d2 = rp[2];
+          const uint32_t d0 = n0, d1 = n1, d2 = n2;
+          if (w + 1 < D + 7) {
+            const uint32_t* np = rb + (w + 1) * Wd;
+            n0 = np[0], n1 = np[1], n2 = np[2];
+          }
+          __builtin_amdgcn_sched_barrier(0);
           uint32_t a0[4], a1[4];
           a0[0] = d0, a1[0] = d1;
 #pragma unroll
@@ -225,19 +256,25 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
         }
         const int n8 = 21 + by * 8 + bx;  // 21..84
         const uint32_t ew = n8 < 32 ? em0 : (n8 < 64 ? em1 : em2);
+        m8[sub] = 0xFFFFFFFFu;  // not leaf-eligible: no key
         if ((ew >> (n8 & 31)) & 1u) {
           uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
           for (int j = 0; j < D; ++j)
 #pragma unroll
             for (int k = 0; k < 4; ++k) m = min(m, acc[j][k] * 2048u + kq[j][k]);
-          const uint32_t mk = wave_min(m);
-          vk8 = set_lane(vk8, mk, bz);
+          m8[sub] = m;
         }
 #pragma unroll
         for (int j = 0; j < D; ++j)
 #pragma unroll
           for (int k = 0; k < 4; ++k) s16[j][k] = sub == 0 ? acc[j][k] : s16[j][k] + acc[j][k];
+      }
+      // The region's four 8x8 CUs are blocks 4 reg .. 4 reg + 3, i.e. lanes
+      // whose low two bits name the block: one joint wavefront reduction.
+      {
+        const uint32_t r = wave_min4(m8[0], m8[1], m8[2], m8[3]);
+        vk8 = (lane >> 2) == reg ? r : vk8;
       }
       // Next-but-one region into the slot this region used.
       if (reg < 15) {
