@@ -207,6 +207,29 @@ def test_2160p_r128_sampled(mr):
              label="2160p R128")
 
 
+@pytest.mark.parametrize("W,R,strip,nb", [
+    (320, 16, 4, 1), (320, 24, 4, 3),   # 5 CTUs per row: strips of 4 + 1
+    (448, 32, 4, 2),                    # 7: 4 + 3
+    (384, 24, 4, 5),                    # 6: 4 + 2
+    (320, 32, 3, 2),                    # 5: 3 + 2
+    (256, 16, 3, 1),                    # 4: 3 + 1
+    (192, 24, 2, 4),                    # 3: 2 + 1
+    (200, 32, 1, 3),                    # 4 strips of 1
+    (130, 24, 4, 1),                    # 3 CTUs, one partial strip narrower than the workgroup
+])
+def test_partial_strips_bit_exact(mr, W, R, strip, nb):
+    """Search workgroups forced to strips of `strip` CTUs on widths that leave a partial strip
+    at the right edge, whose (CTU, step) pairs are dealt over all the workgroup's wavefronts."""
+    H, qp = 136, 30
+    ref, cur = _pair(0x5700 + 7 * W + strip, W, H, 5, 12, 2)
+    mr.mr_set_tiles3(R, 4, nb, strip)
+    try:
+        got = _gpu(mr, cur, ref, qp, R)
+    finally:
+        mr.mr_set_tiles(R, 0, 1)
+    _compare(got, oracle.ctu_search(cur, ref, qp, R), W, H, label=f"W{W} R{R} strip{strip} nb{nb}")
+
+
 def test_padded_stride_and_unaligned_pointer(mr):
     """Frames inside larger buffers: stride > width and a base address not 4-byte aligned
     (the window staging falls back to byte loads); results equal the packed frames'."""
