@@ -63,7 +63,9 @@ typedef enum {
 } mr_status;
 
 /* One 8-bit luma picture: device pointer, width x height samples, row stride
- * in bytes (stride >= width).  1 <= width, height <= 8192. */
+ * in bytes (stride >= width).  1 <= width, height <= 8192, and
+ * stride * (height - 1) + width < 2^31 (samples are addressed with 32-bit
+ * offsets); other frames are rejected with MR_EINVAL. */
 typedef struct {
   const uint8_t* luma;
   int32_t width, height, stride;

@@ -52,4 +52,53 @@ __device__ __forceinline__ uint32_t satd4x4(int d[16]) {
   return s >> 1;
 }
 
+// Two 4x4 residuals at once in packed 16-bit lanes (v_pk_* ops).  Row then
+// column butterflies; the last column stage is folded into
+// |x + y| + |x - y| = 2 max(|x|, |y|), so each half returns sum |H d H^T| / 2
+// directly.  Residuals within +-255 keep every intermediate within +-2040 and
+// each half's result within 16320.
+typedef short sh2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ sh2 pk_abs(sh2 x) { return __builtin_elementwise_max(x, (sh2)(0) - x); }
+
+__device__ __forceinline__ uint32_t satd4x4_pair(const sh2 d[16]) {
+  sh2 t[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {  // rows
+    const sh2 a0 = d[4 * i] + d[4 * i + 1], a1 = d[4 * i] - d[4 * i + 1];
+    const sh2 a2 = d[4 * i + 2] + d[4 * i + 3], a3 = d[4 * i + 2] - d[4 * i + 3];
+    t[4 * i] = a0 + a2, t[4 * i + 1] = a1 + a3, t[4 * i + 2] = a0 - a2, t[4 * i + 3] = a1 - a3;
+  }
+  sh2 s = (sh2)(0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {  // columns
+    const sh2 a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
+    const sh2 a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
+    s += __builtin_elementwise_max(pk_abs(a0), pk_abs(a2)) +
+         __builtin_elementwise_max(pk_abs(a1), pk_abs(a3));
+  }
+  return __builtin_bit_cast(uint32_t, s);  // low half: d.x residual, high half: d.y
+}
+
+// sum |H c H^T| over all 16 coefficients of a 4x4 block and its (0,0)
+// coefficient S (the sum of the block), with the same folded last stage.
+__device__ __forceinline__ int hadamard_abs_sum(const int c[16], int& S) {
+  int t[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int a0 = c[4 * i] + c[4 * i + 1], a1 = c[4 * i] - c[4 * i + 1];
+    const int a2 = c[4 * i + 2] + c[4 * i + 3], a3 = c[4 * i + 2] - c[4 * i + 3];
+    t[4 * i] = a0 + a2, t[4 * i + 1] = a1 + a3, t[4 * i + 2] = a0 - a2, t[4 * i + 3] = a1 - a3;
+  }
+  int m = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
+    const int a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
+    m += max(abs(a0), abs(a2)) + max(abs(a1), abs(a3));
+    if (j == 0) S = a0 + a2;
+  }
+  return 2 * m;
+}
+
 }  // namespace mr

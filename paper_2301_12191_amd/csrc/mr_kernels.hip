@@ -362,6 +362,8 @@ struct LeafShared {
   int16_t mvx[kNodes], mvy[kNodes];  // integer-pel, or quarter-pel with sub-pel refinement
   uint32_t satq[kNodes];             // sub-pel: SATD at the refined MV
   int32_t dc[kNodes];                // DC: sum of the n top and n left neighbours
+  int16_t nx0[kNodes], ny0[kNodes];  // node origin in the picture
+  int16_t na[kNodes], nb[kNodes];    // available neighbours: scan interval [a, b] (a > b: none)
   uint32_t satd[kNodes][3];
   uint32_t part0[4][3];          // per-wave partial sums for the 64x64 node
   int64_t jt[kNodes], dt[kNodes], rt[kNodes];
@@ -425,44 +427,60 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       leaf_ok = d >= min_lo || !split_ok;
     }
     sh.split_ok[node] = split_ok, sh.leaf_ok[node] = leaf_ok;
-  }
-  if (tid < kNodes) sh.dc[tid] = 0;  // DC sums, accumulated below
-  __syncthreads();
-  // Neighbour samples after H.265 reference substitution, one entry per
-  // thread.  In the substitution's scan order (left column bottom to top,
-  // corner, top row left to right; scan index k = 2n - off for the left column
-  // and k = off for the top row) the available samples -- those inside the
-  // coded picture -- form one interval [a, b]: an unavailable sample takes the
-  // nearest available one scanned before it, or the first available one when
-  // none is, i.e. the sample at clamp(k, a, b); with none available, 128.
-  for (int i = tid; i < kRefTotal; i += blockDim.x) {
-    int node, off;
-    if (i < 257) node = 0, off = i;
-    else if (i < 257 + 4 * 129) node = 1 + (i - 257) / 129, off = (i - 257) % 129;
-    else if (i < 257 + 4 * 129 + 16 * 65) node = 5 + (i - 773) / 65, off = (i - 773) % 65;
-    else node = 21 + (i - 1813) / 33, off = (i - 1813) % 33;
-    if (!sh.elig[node]) continue;
-    const int d = node == 0 ? 0 : node < 5 ? 1 : node < 21 ? 2 : 3;
-    const int local = node - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
-    const int n = kCtu >> d, x0 = cx + (local % (1 << d)) * n, y0 = cy + (local / (1 << d)) * n;
+    // Neighbour samples after H.265 reference substitution.  In the
+    // substitution's scan order (left column bottom to top, corner, top row
+    // left to right; scan index k = 2n - off for the left column and k = off
+    // for the top row) the available samples -- those inside the coded
+    // picture -- form one interval [a, b]: an unavailable sample takes the
+    // nearest available one scanned before it, or the first available one when
+    // none is, i.e. the sample at clamp(k, a, b); with none available, 128.
+    // Left-column entries p[-1][i - 1], i = 0..2n (i = 0 the corner), are
+    // available for i in [hasT ? 0 : 1, min(2n, H8 - y0)]; top-row entries
+    // p[i][-1] for i in [0, min(2n - 1, W8 - 1 - x0)].
     const bool hasL = x0 >= 1, hasT = y0 >= 1;
-    int v = 128;
+    int a = 1, b = 0;
     if (hasL || hasT) {
-      // Left column entries p[-1][i - 1], i = 0..2n (i = 0 the corner), are
-      // available for i in [hasT ? 0 : 1, min(2n, H8 - y0)]; top-row entries
-      // p[i][-1] for i in [0, min(2n - 1, W8 - 1 - x0)].
       const int iLlo = hasT ? 0 : 1, iLhi = min(2 * n, H8 - y0);
-      const int a = hasL ? 2 * n - iLhi : 2 * n + 1;
-      const int b = hasT ? 2 * n + 1 + min(2 * n - 1, W8 - 1 - x0) : 2 * n - iLlo;
-      const int k = clampi(off <= 2 * n ? 2 * n - off : off, a, b);
-      int x, y;
-      if (k <= 2 * n) x = x0 - 1, y = y0 - 1 + (2 * n - k);  // left column / corner
-      else x = x0 + (k - 2 * n - 1), y = y0 - 1;             // top row
-      v = jb->cur[(size_t)min(y, jb->h - 1) * jb->stride + min(x, jb->w - 1)];
+      a = hasL ? 2 * n - iLhi : 2 * n + 1;
+      b = hasT ? 2 * n + 1 + min(2 * n - 1, W8 - 1 - x0) : 2 * n - iLlo;
     }
-    sh.refs[i] = (int16_t)v;
-    // DC: p[0..n-1][-1] (off 2n+1 .. 3n) and p[-1][0..n-1] (off 1 .. n).
-    if ((off >= 1 && off <= n) || (off > 2 * n && off <= 3 * n)) atomicAdd(&sh.dc[node], v);
+    sh.nx0[node] = (int16_t)x0, sh.ny0[node] = (int16_t)y0;
+    sh.na[node] = (int16_t)a, sh.nb[node] = (int16_t)b;
+    sh.dc[node] = 0;  // DC sums, accumulated below
+  }
+  __syncthreads();
+  // Neighbour arrays, one depth level at a time: the 256 threads split evenly
+  // over the level's nodes (256, 64, 16 or 4 per node), so a thread's node and
+  // its entries follow from its index; samples inside the CTU come from LDS.
+  const int stride = jb->stride;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int n = kCtu >> d, len = 4 * n + 1, tpn = 256 >> (2 * d);
+    const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + (tid >> (8 - 2 * d));
+    const int j = tid & (tpn - 1);
+    if (sh.elig[node]) {
+      const int x0 = sh.nx0[node], y0 = sh.ny0[node], a = sh.na[node], b = sh.nb[node];
+      int16_t* R = sh.refs + ref_offset(node);
+      int dcs = 0;
+      for (int off = j; off < len; off += tpn) {
+        int v = 128;
+        if (a <= b) {
+          const int k = clampi(off <= 2 * n ? 2 * n - off : off, a, b);
+          int x, y;
+          if (k <= 2 * n) x = x0 - 1, y = y0 - 1 + (2 * n - k);  // left column / corner
+          else x = x0 + (k - 2 * n - 1), y = y0 - 1;             // top row
+          const int lx = x - cx, ly = y - cy;
+          if ((unsigned)lx < 64u && (unsigned)ly < 64u) v = sh.cur[ly * 64 + lx];
+          else v = jb->cur[min(y, jb->h - 1) * stride + min(x, jb->w - 1)];
+        }
+        R[off] = (int16_t)v;
+        // DC: p[0..n-1][-1] (off 2n+1 .. 3n) and p[-1][0..n-1] (off 1 .. n).
+        if ((off >= 1 && off <= n) || (off > 2 * n && off <= 3 * n)) dcs += v;
+      }
+      const int g = tpn < 64 ? tpn : 64;  // the node's threads within this wavefront
+      dcs = (int)shfl_sum((uint32_t)dcs, g);
+      if ((tid & (g - 1)) == 0) atomicAdd(&sh.dc[node], dcs);
+    }
   }
   __syncthreads();
 
@@ -474,6 +492,12 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     int c[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) c[i] = sh.cur[(ty * 4 + (i >> 2)) * 64 + tx * 4 + (i & 3)];
+    // The transform is linear and a constant block only moves its (0,0)
+    // coefficient (by 16 times the constant), so the DC SATD of this tile at
+    // any node follows from the tile's own coefficients: with A = sum |coef|
+    // and S = the (0,0) coefficient (>= 0), SATD = (A - S + |S - 16 dc|) / 2.
+    int S;
+    const int A = hadamard_abs_sum(c, S);
 #pragma unroll
     for (int d = 3; d >= 0; --d) {
       const int n = kCtu >> d, lg = 6 - d;
@@ -481,32 +505,38 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
       uint32_t v0 = 0, v1 = 0, v2 = 0;
       if (sh.elig[node]) {
-        int r[16];
-        if (!jb->subpel) {  // with sub-pel refinement the inter SATD comes from subres
+        // Inter residual (zero with sub-pel refinement: that SATD comes from
+        // subres) in the low halves, planar residual in the high halves.
+        int ri[16];
+        if (!jb->subpel) {
           const int mx = sh.mvx[node], my = sh.mvy[node];
+          int xo[4], yo[4];
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int x = clampi(cx + tx * 4 + (i & 3) + mx, 0, jb->w - 1);
-            const int y = clampi(cy + ty * 4 + (i >> 2) + my, 0, jb->h - 1);
-            r[i] = c[i] - (int)jb->ref[(size_t)y * jb->stride + x];
+          for (int q = 0; q < 4; ++q) {
+            xo[q] = clampi(cx + tx * 4 + q + mx, 0, jb->w - 1);
+            yo[q] = clampi(cy + ty * 4 + q + my, 0, jb->h - 1) * stride;
           }
-          v0 = satd4x4(r);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) ri[i] = c[i] - (int)jb->ref[yo[i >> 2] + xo[i & 3]];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) ri[i] = 0;
         }
         const int16_t* L = sh.refs + ref_offset(node);
         const int16_t* T = L + 2 * n + 1;
         const int px0 = tx * 4 - lx * n, py0 = ty * 4 - ly * n;  // position inside the CU
+        sh2 pr[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int px = px0 + (i & 3), py = py0 + (i >> 2);
           const int p = ((n - 1 - px) * L[py + 1] + (px + 1) * T[n] + (n - 1 - py) * T[px] +
                          (py + 1) * L[n + 1] + n) >> (lg + 1);
-          r[i] = c[i] - p;
+          pr[i] = (sh2){(short)ri[i], (short)(c[i] - p)};
         }
-        v1 = satd4x4(r);
+        const uint32_t pk = satd4x4_pair(pr);
+        v0 = pk & 0xFFFFu, v1 = pk >> 16;
         const int dcv = (sh.dc[node] + n) >> (lg + 1);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) r[i] = c[i] - dcv;
-        v2 = satd4x4(r);
+        v2 = (uint32_t)(A - S + abs(S - 16 * dcv)) >> 1;
       }
       // Tiles of a node are consecutive threads: 4^(3-d+1) of them.
       const int width = 4 << (2 * (3 - d));  // 4, 16, 64, 256

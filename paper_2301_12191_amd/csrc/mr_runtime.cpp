@@ -197,8 +197,10 @@ int get_key_tables(int qp, const SearchLayout& L, KeyTables* out) {
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static bool frame_ok(const mr_frame* f) {
+  // The kernels address samples with 32-bit offsets.
   return f && f->luma && f->width >= 1 && f->height >= 1 && f->width <= 8192 &&
-         f->height <= 8192 && f->stride >= f->width;
+         f->height <= 8192 && f->stride >= f->width &&
+         (int64_t)f->stride * (f->height - 1) + f->width <= (int64_t)INT32_MAX;
 }
 
 int validate_job(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
