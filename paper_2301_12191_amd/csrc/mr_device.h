@@ -33,8 +33,9 @@ __device__ __forceinline__ uint32_t add_dpp(uint32_t v) {
   return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
-// SATD of a 4x4 residual: sum |H d H^T| / 2 via butterflies.
-__device__ __forceinline__ uint32_t satd4x4(int d[16]) {
+// SATD of a 4x4 residual: sum |H d H^T| / 2 via butterflies.  The last
+// column stage is folded into |x + y| + |x - y| = 2 max(|x|, |y|).
+__device__ __forceinline__ uint32_t satd4x4(const int d[16]) {
   int t[16];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {  // rows
@@ -47,9 +48,9 @@ __device__ __forceinline__ uint32_t satd4x4(int d[16]) {
   for (int j = 0; j < 4; ++j) {  // columns
     const int a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
     const int a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
-    s += abs(a0 + a2) + abs(a1 + a3) + abs(a0 - a2) + abs(a1 - a3);
+    s += max(abs(a0), abs(a2)) + max(abs(a1), abs(a3));
   }
-  return s >> 1;
+  return s;
 }
 
 // Two 4x4 residuals at once in packed 16-bit lanes (v_pk_* ops).  Row then

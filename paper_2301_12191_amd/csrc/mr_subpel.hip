@@ -126,7 +126,7 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
         // Horizontal pass: h[r][k] for patch rows r = 0..11, tile columns k,
         // taps at patch bytes k + f + 1 .. k + f + 8; packed as 16-bit pairs of
         // consecutive rows Q[r][k] = (h[r][k], h[r + 1][k]).
-        uint32_t Q[11][4];
+        uint32_t Q[12][4];  // Q[11] = (h[11], 0) pads the vertical window
         int hprev[4];
 #pragma unroll
         for (int r = 0; r < 12; ++r) {
@@ -144,36 +144,57 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
           }
         }
 #pragma unroll
-        for (int iy = 0; iy < 3; ++iy) {
-          // The quarter-pel stage's centre is the half-pel stage's best, whose
-          // SATD is already known.
-          if (step == 1 && ix == 1 && iy == 1) {
-            sat[4] = csatd_tile;
-            continue;
-          }
+        for (int k = 0; k < 4; ++k) Q[11][k] = (uint32_t)hprev[k] & 0xFFFFu;
+        // Vertical pass of candidate row iy (qy = cqy + step (iy - 1)): the
+        // residual of each tile sample.
+        auto residual = [&](int iy, int resid[16]) {
           const int qy = cqy + step * (iy - 1);
           const int fy = qy & 3, g = ((qy - fy) >> 2) - my;  // g in {-1, 0}
-          uint32_t tv[4];
+          // Filter tap j applies to patch row i + g + 1 + j.  Over the window
+          // of rows i .. i + 9 (pairs Q[i + 2p], p = 0..4) that is window tap
+          // j + g + 1: the taps move by one row for g = 0 instead of the rows.
+          uint32_t tw[5], prev = 0;
 #pragma unroll
-          for (int p = 0; p < 4; ++p) tv[p] = taps16(fy, p);
-          int resid[16];
+          for (int p = 0; p < 5; ++p) {
+            const uint32_t cur = p < 4 ? taps16(fy, p) : 0u;
+            tw[p] = g == 0 ? __builtin_amdgcn_alignbyte(cur, prev, 2) : cur;
+            prev = cur;
+          }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-              // rows i + g + 1 + j, j = 0..7, as pairs starting at i + g + 1 + 2p
-              int v = 0;
+              // (v >> 6) + 32 >> 6 == (v + 2048) >> 12 (arithmetic shifts)
+              int v = 2048;
 #pragma unroll
-              for (int p = 0; p < 4; ++p) {
-                const uint32_t q = g == 0 ? Q[i + 2 * p + 1][k] : Q[i + 2 * p][k];
-                v = dot2(q, tv[p], v);
-              }
-              v >>= 6;  // arithmetic
-              const int pred = clampi((v + 32) >> 6, 0, 255);
+              for (int p = 0; p < 5; ++p) v = dot2(Q[i + 2 * p][k], tw[p], v);
+              const int pred = clampi(v >> 12, 0, 255);
               resid[4 * i + k] = c[4 * i + k] - pred;
             }
           }
-          sat[iy * 3 + ix] = satd4x4(resid);
+        };
+        // The quarter-pel stage's centre is the half-pel stage's best, whose
+        // SATD is already known.  The first two candidates of the column share
+        // one packed 16-bit transform.
+        const bool centre_known = step == 1 && ix == 1;
+        {
+          int ra[16], rb[16];
+          residual(0, ra);
+          residual(centre_known ? 2 : 1, rb);
+          sh2 pr[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) pr[i] = (sh2){(short)ra[i], (short)rb[i]};
+          const uint32_t pk = satd4x4_pair(pr);
+          sat[ix] = pk & 0xFFFFu;
+          if (centre_known) sat[6 + ix] = pk >> 16;
+          else sat[3 + ix] = pk >> 16;
+        }
+        if (centre_known) {
+          sat[4] = csatd_tile;
+        } else {
+          int rc[16];
+          residual(2, rc);
+          sat[6 + ix] = satd4x4(rc);
         }
       }
       const uint32_t tile_sat[9] = {sat[0], sat[1], sat[2], sat[3], sat[4], sat[5], sat[6],
