@@ -325,10 +325,16 @@ def main():
                 mr.mr_ctu_search(cur_t, ref_t, qp, rr, **kw)  # warm
                 torch.cuda.synchronize()
                 ta = time.perf_counter()
-                for _ in range(reps):
+                mr.mr_ctu_search(cur_t, ref_t, qp, rr, **kw)
+                torch.cuda.synchronize()
+                # enough calls for ~10 ms, so that short (seeded) calls are not timer noise
+                t1 = time.perf_counter() - ta
+                n = max(reps, min(100, int(0.010 / max(t1, 1e-6)) + 1))
+                ta = time.perf_counter()
+                for _ in range(n):
                     mr.mr_ctu_search(cur_t, ref_t, qp, rr, **kw)
                 torch.cuda.synchronize()
-                times[name] = (time.perf_counter() - ta) * 1e3 / reps
+                times[name] = (time.perf_counter() - ta) * 1e3 / n
                 J[name] = int(o["cost"].sum().item())
                 res[f"{name}_ms"] += times[name]
                 res[f"J_{name}"] += J[name]
