@@ -178,7 +178,8 @@ int mr_ctu_search_batch(const mr_search_job* jobs, int32_t n_jobs, void* hip_str
  *   mr_batch_set_jobs: swap in new frame / bounds / seed / output pointers
  *     for jobs of the same count, sizes, QPs, ranges, bounds presence and
  *     seed presence (else MR_EINVAL); waits for this batch's previous launch
- *     to finish.
+ *     to finish.  Seeds may change their refinement half-width; a new
+ *     largest half-width re-records the graph (host-blocking).
  *   mr_batch_launch : replay on hip_stream (with stage profiling enabled, the
  *     three kernels are launched directly between timing events instead).
  *   mr_batch_destroy: waits for the last launch, frees everything (NULL ok).

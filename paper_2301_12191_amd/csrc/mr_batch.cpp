@@ -1,6 +1,7 @@
 // Batched coding-tree search: one persistent work-queue search launch over the
 // flattened (job, strip, band) items of many frame pairs, and a reusable batch
 // object that replays prep -> search -> leaf as a captured HIP graph.
+#include <algorithm>
 #include <cstring>
 #include <utility>
 #include <vector>
@@ -120,6 +121,23 @@ int mr_ctu_search_batch(const mr_search_job* jobs, int32_t n_jobs, void* hip_str
   return (e == hipSuccess && ef == hipSuccess) ? MR_OK : MR_EHIP;
 }
 
+// Capture prep -> [pad] -> [search] -> [refine] -> [sub-pel] -> leaf of the
+// batch's plan (replacing an earlier graph).  The work-queue head is reset by
+// the prep kernel itself, so the graph holds kernel nodes only.
+static hipError_t capture(mr_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec), b->exec = nullptr;
+  if (b->graph) (void)hipGraphDestroy(b->graph), b->graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t el = launch_plan(b->plan, b->jobs_d, b->items_d, b->lists, b->counter_d,
+                                      b->cap_stream, nullptr);
+    e = hipStreamEndCapture(b->cap_stream, &b->graph);
+    if (el != hipSuccess) e = el;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  return e;
+}
+
 int mr_batch_destroy(mr_batch* b) {
   if (!b) return MR_OK;
   int rc = MR_OK;
@@ -164,17 +182,7 @@ int mr_batch_create(const mr_search_job* jobs, int32_t n_jobs, mr_batch** out) {
     mr_batch_destroy(b);
     return MR_EHIP;
   }
-  // Capture prep -> [pad] -> [search] -> [refine] -> leaf.  The work-queue head
-  // is reset by the prep kernel itself, so the graph holds kernel nodes only.
-  hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    const hipError_t el = launch_plan(b->plan, b->jobs_d, b->items_d, b->lists, b->counter_d,
-                                      b->cap_stream, nullptr);
-    e = hipStreamEndCapture(b->cap_stream, &b->graph);
-    if (el != hipSuccess) e = el;
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
+  if (capture(b) != hipSuccess) {
     mr_batch_destroy(b);
     return MR_EHIP;
   }
@@ -214,6 +222,15 @@ int mr_batch_set_jobs(mr_batch* b, const mr_search_job* jobs, int32_t n_jobs) {
   if (hipMemcpy(b->jobs_d, b->plan.jobs.data(), sizeof(JobDesc) * n_jobs,
                 hipMemcpyHostToDevice) != hipSuccess)
     return MR_EHIP;
+  // The refinement grid follows the largest refinement half-width: a new one
+  // needs a new graph.
+  int max_r = 0;
+  for (int j = 0; j < n_jobs; ++j)
+    if (jobs[j].seed) max_r = std::max(max_r, jobs[j].seed->refine_range);
+  if (max_r != b->plan.max_r) {
+    b->plan.max_r = max_r;
+    if (capture(b) != hipSuccess) return MR_EHIP;
+  }
   return MR_OK;
 }
 

@@ -6,9 +6,9 @@
 // with the full search's cost and tie order.  Per batch: pad_kernel copies each
 // seeded job's reference with a margin and clamped coordinates, so that every
 // window load is a plain dword load; refine_kernel then runs one wavefront per
-// (CTU, CU depth, pass of 8 candidate columns, band of window rows) and merges
-// the results in the same arg-min keys the full search writes.  The prep and
-// leaf kernels are the full search's.
+// (CTU, CU depth, pass of 4 NQ + 1 candidate columns, band of window rows) and
+// merges the results in the same arg-min keys the full search writes.  The
+// prep and leaf kernels are the full search's.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,39 +58,49 @@ __device__ __forceinline__ uint32_t se_len(int v) {
   return 2u * (31u - (uint32_t)__builtin_clz(k + 1u)) + 1u;
 }
 
-// The four byte shifts of a reference row segment of NQ + 2 dwords:
-// out[o][j] = bytes 4j + o .. 4j + o + 3, j = 0..NQ.
+// A reference row segment of NQ + 3 dwords, re-aligned on this lane's first
+// window column (byte sh of raw[0], per lane), as the four byte shifts of its
+// first NQ + 1 dwords plus one more plain dword:
+// out[o][j] = window bytes 4j + o .. 4j + o + 3 (j = 0..NQ), x = bytes
+// 4 NQ + 4 .. 4 NQ + 7.
 template <int NQ>
-__device__ __forceinline__ void shifts(const uint32_t (&raw)[NQ + 2], uint32_t (&out)[4][NQ + 1]) {
+__device__ __forceinline__ void shifts(const uint32_t (&raw)[NQ + 3], int sh,
+                                       uint32_t (&out)[4][NQ + 1], uint32_t& x) {
+  uint32_t e[NQ + 2];
+#pragma unroll
+  for (int m = 0; m < NQ + 2; ++m) e[m] = __builtin_amdgcn_alignbyte(raw[m + 1], raw[m], sh);
 #pragma unroll
   for (int j = 0; j <= NQ; ++j) {
-    out[0][j] = raw[j];
+    out[0][j] = e[j];
 #pragma unroll
-    for (int o = 1; o < 4; ++o) out[o][j] = __builtin_amdgcn_alignbyte(raw[j + 1], raw[j], o);
+    for (int o = 1; o < 4; ++o) out[o][j] = __builtin_amdgcn_alignbyte(e[j + 1], e[j], o);
   }
+  x = e[NQ + 1];
 }
 
-// One wavefront: the CUs of depth d (uniform) of one CTU, one pass of NP = 4 NQ
-// candidate columns, one band of window rows.  Lane b holds the 8x8 block at
-// Z-order position b; the lanes of one CU sum their block SADs per candidate.
+// One wavefront: the CUs of depth d (uniform) of one CTU, one pass of
+// NP = 4 NQ + 1 candidate columns, one band of window rows.  Lane b holds the
+// 8x8 block at Z-order position b; the lanes of one CU sum their block SADs per
+// candidate.
 //
 // Keys.  The arg-min key J * 2^17 + idx of candidate (dx, dy) is split as
 //   T(dx) + SAD * 2^33 + U(dy),  T = s * se(4dx) * 2^17 + dx + R,
 //   U = s * se(4dy) * 2^17 + (dy + R) * (2R + 1),
 // so a window row is reduced with T alone and U is added once per row
 // (s * se < 2^28 and every key < 2^54).
-// Columns.  Pass p covers byte positions p NP .. p NP + NP - 1 counted from the
-// dword-aligned reference column at or left of the window's first column;
-// position k reads dwords k / 4 and k / 4 + 1 shifted by k % 4.  Positions
-// outside this lane's window get T = 2^62, above every valid key.
+// Columns.  Pass p covers window columns p NP .. p NP + NP - 1.  Every new
+// reference row is re-aligned on this lane's first column of the pass (a
+// per-lane byte shift), so position k = 4q + o reads the pre-shifted dwords
+// S[o][q] and S[o][q + 1], and position 4 NQ reads S[0][NQ] and X.  Columns
+// past the window (last pass only, uniform) are skipped or get T = 2^62.
 // Rows.  The 8 reference rows of the current dy are a ring of pre-shifted rows
-// S[slot][o][j] (bytes 4j + o .. 4j + o + 3); step u of a group of 8 uses slot
-// (u + row) & 7 for window row `row`, and the row loaded during step u (8 rows
-// below) replaces slot u, which step u + 1 no longer needs: the ring turns by
-// renaming, one new row per step, loaded one step ahead.
+// S[slot][o][j]; step u of a group of 8 uses slot (u + row) & 7 for window row
+// `row`, and the row loaded during step u (8 rows below) replaces slot u, which
+// step u + 1 no longer needs: the ring turns by renaming, one new row per step,
+// loaded one step ahead.
 template <int NQ>
 __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nband) {
-  constexpr int NP = 4 * NQ, NDW = NQ + 2;
+  constexpr int NP = 4 * NQ + 1, NDW = NQ + 3;
   const int n = kCtu >> d, sh3 = 3 - d;
   const int b = threadIdx.x & 63;
   const int bx = zx(b), by = zy(b);
@@ -102,8 +112,8 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
 
   const int R = jb->R, r = jb->seed_r, lim = R - r, span = 2 * R + 1;
   const int ncand = 2 * r + 1;
-  const int npos = ncand + 3;  // positions any lane may need (uniform)
-  if (pass * NP >= npos) return;
+  const int rem = ncand - pass * NP;  // window columns left for this pass (uniform)
+  if (rem <= 0) return;
   const int bh = (ncand + nband - 1) / nband;
   const int iy0 = band * bh, iy1 = min(ncand, iy0 + bh);
   if (iy0 >= iy1) return;
@@ -134,31 +144,28 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   }
   const int pitch = jb->pad_pitch;
   const uint32_t s = (uint32_t)jb->s;
-  // First window column in the padded reference, its dword-aligned start and
-  // the window's first position in that dword (0..3, per lane).
-  const int xw = X0 + cxm - r + jb->pad_x;
-  const int shb = xw & 3;
-  const int xa = xw - shb;
-  const int rem = npos - pass * NP;  // positions of this pass any lane may need (uniform)
+  // This pass's first window column in the padded reference, the dword-aligned
+  // column at or left of it and its byte in that dword (0..3, per lane).
+  const int xs = X0 + cxm - r + jb->pad_x + pass * NP;
+  const int shb = xs & 3;
   uint64_t T[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    const int p = pass * NP + k - shb;  // window column of position k (valid: 0..2r)
+    const int p = pass * NP + k;  // window column of position k (valid: 0..2r)
     const int dx = cxm - r + p;
-    T[k] = (p >= 0 && p < ncand) ? ((uint64_t)(s * se_len(4 * dx)) << 17) + (uint64_t)(dx + R)
-                                 : (1ull << 62);
+    T[k] = p < ncand ? ((uint64_t)(s * se_len(4 * dx)) << 17) + (uint64_t)(dx + R) : (1ull << 62);
   }
   const uint32_t* src = (const uint32_t*)(jb->refpad +
                                           (size_t)(Y0 + cym - r + iy0 + jb->pad_y) * pitch +
-                                          xa + pass * NP);
+                                          (xs - shb));
   const int dwp = pitch >> 2;
-  uint32_t S[8][4][NQ + 1];
+  uint32_t S[8][4][NQ + 1], X[8];
 #pragma unroll
   for (int row = 0; row < 8; ++row) {
     uint32_t raw[NDW];
 #pragma unroll
     for (int j = 0; j < NDW; ++j) raw[j] = src[row * dwp + j];
-    shifts<NQ>(raw, S[row]);
+    shifts<NQ>(raw, shb, S[row], X[row]);
   }
   const int nrow = iy1 - iy0;
   uint64_t best = kKeyNone;
@@ -194,24 +201,24 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
             }
           }
         }
+        if (4 * NQ < rem) {
+          acc[4 * NQ] = __builtin_amdgcn_sad_u8(c[2 * row], S[sl][0][NQ], acc[4 * NQ]);
+          acc[4 * NQ] = __builtin_amdgcn_sad_u8(c[2 * row + 1], X[sl], acc[4 * NQ]);
+        }
       }
       group_sums<NP>(acc, d);
       uint64_t rb = kKeyNone;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        if (4 * q < rem) {
-#pragma unroll
-          for (int o = 0; o < 4; ++o) {
-            const int k = 4 * q + o;
-            const uint64_t key = T[k] + ((uint64_t)acc[k] << 33);
-            rb = key < rb ? key : rb;
-          }
+      for (int k = 0; k < NP; ++k) {
+        if (k < rem) {
+          const uint64_t key = T[k] + ((uint64_t)acc[k] << 33);
+          rb = key < rb ? key : rb;
         }
       }
       const uint64_t U = ((uint64_t)(s * se_len(4 * dy)) << 17) + (uint64_t)((dy + R) * span);
       rb += U;
       best = rb < best ? rb : best;
-      if (more) shifts<NQ>(nxt, S[u]);
+      if (more) shifts<NQ>(nxt, shb, S[u], X[u]);
     }
   }
   // Passes and bands of one CU meet in its key (reset to all ones by prep).
@@ -264,16 +271,12 @@ __global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const in
   }
 }
 
-// The CUs of depth D of every seeded CTU: one single-wavefront workgroup per
-// CTU.  Each depth is its own kernel, so that its registers are allocated for
-// it alone.  NQ: quads of candidate positions per pass over the window rows
-// (1: r = 0; 2: any r, in passes of 8 positions).
 // One single-wavefront workgroup per (CTU, CU depth) in x (depths of a CTU
-// adjacent), pass of NP candidate columns in y, band of window rows in z.
-// NQ: quads of candidate columns per pass (1 when r = 0 for every job, else 2).
+// adjacent), pass of 4 NQ + 1 candidate columns in y, band of window rows in z.
+// NQ = 1 (5 columns) when every job has r <= 2, else 2 (9 columns).
 template <int NQ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void refine_kernel(
-    const JobDesc* jobs_, const int* rlist, int n_rjobs, int n_rctus) {
+__device__ __forceinline__ void refine_body(const JobDesc* jobs_, const int* rlist, int n_rjobs,
+                                            int n_rctus) {
   const cjob jobs = (cjob)jobs_;
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
   // eighth of the (CTU, depth) list so that its L2 holds one band of the
@@ -285,6 +288,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
   if (flat >= n_rctus) return;
   const int j = __builtin_amdgcn_readfirstlane(find_rjob(jobs, rlist, n_rjobs, flat));
   refine_wave<NQ>(jobs + j, flat - jobs[j].rctu_start, d, blockIdx.y, blockIdx.z, gridDim.z);
+}
+
+// 5 columns per pass: three wavefronts per SIMD (register budget 168).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void refine_kernel_q1(
+    const JobDesc* jobs_, const int* rlist, int n_rjobs, int n_rctus) {
+  refine_body<1>(jobs_, rlist, n_rjobs, n_rctus);
+}
+
+// 9 columns per pass: the ring of 8 pre-shifted rows takes 104 registers, so
+// two wavefronts per SIMD keep it (and everything else) out of scratch.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void refine_kernel_q2(
+    const JobDesc* jobs_, const int* rlist, int n_rjobs, int n_rctus) {
+  refine_body<2>(jobs_, rlist, n_rjobs, n_rctus);
 }
 
 hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int64_t max_dwords,
@@ -299,16 +315,16 @@ hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int64_
 hipError_t launch_refine(const JobDesc* jobs, const int* rlist, int n_rjobs, int n_rctus,
                          int max_r, hipStream_t st) {
   if ((int64_t)n_rctus * 4 > INT32_MAX) return hipErrorInvalidValue;
-  // Grid: (CTU, depth) x passes of 4 NQ columns x bands of about 10 window rows.
-  const int ncand = 2 * max_r + 1, npos = ncand + 3;
-  const int nq = npos <= 4 ? 1 : 2;
-  const int npass = (npos + 4 * nq - 1) / (4 * nq);
+  // Grid: (CTU, depth) x passes of 4 NQ + 1 columns x bands of about 10 window rows.
+  const int ncand = 2 * max_r + 1;
+  const int nq = ncand <= 5 ? 1 : 2;
+  const int npass = (ncand + 4 * nq) / (4 * nq + 1);
   const int nband = std::min(8, (ncand + 9) / 10);
   const dim3 grid(4 * n_rctus, npass, nband), block(64);
   if (nq == 1)
-    hipLaunchKernelGGL(refine_kernel<1>, grid, block, 0, st, jobs, rlist, n_rjobs, n_rctus);
+    hipLaunchKernelGGL(refine_kernel_q1, grid, block, 0, st, jobs, rlist, n_rjobs, n_rctus);
   else
-    hipLaunchKernelGGL(refine_kernel<2>, grid, block, 0, st, jobs, rlist, n_rjobs, n_rctus);
+    hipLaunchKernelGGL(refine_kernel_q2, grid, block, 0, st, jobs, rlist, n_rjobs, n_rctus);
   return hipGetLastError();
 }
 

@@ -257,6 +257,24 @@ def test_mixed_batch_and_graph_replays(mr):
         bt.close()
 
 
+def test_batch_set_jobs_changes_refinement_width(mr):
+    """A recorded batch re-targeted to seeds with a larger, then smaller, refinement
+    half-width (r 1 -> 6 -> 1: one, two and one passes of candidate columns) keeps parity
+    with the oracle on every replay."""
+    ref, cur = _pair(65, 320, 200, 5, 10, 2)
+    rm = _rand_map(5, 160, 100, 12)
+    R = 16
+    bt = mr.Batch([_job(cur, ref, 30, R, seed=(rm, 160, 100, 1))])
+    try:
+        for r in (1, 6, 1):
+            bt.set_jobs([_job(cur, ref, 30, R, seed=(rm, 160, 100, r))])
+            exp = _oracle(cur, ref, 30, R, seed=(rm, 160, 100, r))
+            for rep in range(2):
+                _compare(_host(bt.launch()[0]), exp, 320, 200, label=f"r {r} replay {rep}")
+    finally:
+        bt.close()
+
+
 def test_multi_qp_chain_same_resolution(mr):
     """416x240 at QP 30 (master, full search) bounds (ratio 1, depths d-1..d+1) and seeds
     (r = 2) the same pair at QPs 22, 26, 34 and 38; GPU chain against the oracle's chain."""
