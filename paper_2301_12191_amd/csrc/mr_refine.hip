@@ -99,7 +99,8 @@ __device__ __forceinline__ void shifts(const uint32_t (&raw)[NQ + 3], int sh,
 // step u + 1 no longer needs: the ring turns by renaming, one new row per step,
 // loaded one step ahead.
 template <int NQ>
-__device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nband) {
+__device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nband,
+                            uint64_t (*Ts)[64]) {
   constexpr int NP = 4 * NQ + 1, NDW = NQ + 3;
   const int n = kCtu >> d, sh3 = 3 - d;
   const int b = threadIdx.x & 63;
@@ -148,12 +149,14 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   // column at or left of it and its byte in that dword (0..3, per lane).
   const int xs = X0 + cxm - r + jb->pad_x + pass * NP;
   const int shb = xs & 3;
-  uint64_t T[NP];
+  // Column key terms, one LDS slot per (position, lane): kept out of the
+  // register file, which the ring of pre-shifted rows fills.
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const int p = pass * NP + k;  // window column of position k (valid: 0..2r)
     const int dx = cxm - r + p;
-    T[k] = p < ncand ? ((uint64_t)(s * se_len(4 * dx)) << 17) + (uint64_t)(dx + R) : (1ull << 62);
+    Ts[k][b] = p < ncand ? ((uint64_t)(s * se_len(4 * dx)) << 17) + (uint64_t)(dx + R)
+                         : (1ull << 62);
   }
   const uint32_t* src = (const uint32_t*)(jb->refpad +
                                           (size_t)(Y0 + cym - r + iy0 + jb->pad_y) * pitch +
@@ -211,7 +214,7 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
         if (k < rem) {
-          const uint64_t key = T[k] + ((uint64_t)acc[k] << 33);
+          const uint64_t key = Ts[k][b] + ((uint64_t)acc[k] << 33);
           rb = key < rb ? key : rb;
         }
       }
@@ -277,6 +280,7 @@ __global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const in
 template <int NQ>
 __device__ __forceinline__ void refine_body(const JobDesc* jobs_, const int* rlist, int n_rjobs,
                                             int n_rctus) {
+  __shared__ uint64_t Ts[4 * NQ + 1][64];
   const cjob jobs = (cjob)jobs_;
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
   // eighth of the (CTU, depth) list so that its L2 holds one band of the
@@ -287,18 +291,18 @@ __device__ __forceinline__ void refine_body(const JobDesc* jobs_, const int* rli
   const int flat = lin >> 2, d = lin & 3;
   if (flat >= n_rctus) return;
   const int j = __builtin_amdgcn_readfirstlane(find_rjob(jobs, rlist, n_rjobs, flat));
-  refine_wave<NQ>(jobs + j, flat - jobs[j].rctu_start, d, blockIdx.y, blockIdx.z, gridDim.z);
+  refine_wave<NQ>(jobs + j, flat - jobs[j].rctu_start, d, blockIdx.y, blockIdx.z, gridDim.z, Ts);
 }
 
-// 5 columns per pass: three wavefronts per SIMD (register budget 168).
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void refine_kernel_q1(
+// 5 columns per pass: four wavefronts per SIMD (register budget 128).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel_q1(
     const JobDesc* jobs_, const int* rlist, int n_rjobs, int n_rctus) {
   refine_body<1>(jobs_, rlist, n_rjobs, n_rctus);
 }
 
-// 9 columns per pass: the ring of 8 pre-shifted rows takes 104 registers, so
-// two wavefronts per SIMD keep it (and everything else) out of scratch.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void refine_kernel_q2(
+// 9 columns per pass: the ring of 8 pre-shifted rows takes 104 registers;
+// three wavefronts per SIMD (register budget 168).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void refine_kernel_q2(
     const JobDesc* jobs_, const int* rlist, int n_rjobs, int n_rctus) {
   refine_body<2>(jobs_, rlist, n_rjobs, n_rctus);
 }
