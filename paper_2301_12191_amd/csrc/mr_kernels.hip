@@ -375,8 +375,16 @@ struct LeafShared {
   uint8_t split_ok[kNodes], leaf_ok[kNodes];
 };
 
-__device__ __forceinline__ uint32_t shfl_sum(uint32_t v, int width) {
-  for (int o = 1; o < width; o <<= 1) v += __shfl_xor((int)v, o, 64);
+// Sum over aligned groups of `width` lanes (4, 16 or 64; a compile-time
+// constant after unrolling), every lane of a group receiving it: DPP adds
+// within quads and rows of 16, then for 64 the four row sums read out of lanes
+// 0, 16, 32 and 48.  Every lane of a group must be active.
+__device__ __forceinline__ uint32_t group_sum(uint32_t v, int width) {
+  if (width >= 4) v = add_dpp<0xB1>(v), v = add_dpp<0x4E>(v);      // quad_perm
+  if (width >= 16) v = add_dpp<0x141>(v), v = add_dpp<0x140>(v);   // row half-mirror, mirror
+  if (width >= 64)
+    v = (uint32_t)(__builtin_amdgcn_readlane((int)v, 0) + __builtin_amdgcn_readlane((int)v, 16) +
+                   __builtin_amdgcn_readlane((int)v, 32) + __builtin_amdgcn_readlane((int)v, 48));
   return v;
 }
 
@@ -386,10 +394,16 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   const int W8 = jb->w8, H8 = jb->h8;
   const int span = 2 * jb->R + 1;
 
-  // Current CTU (coded picture, edge-replicated).
-  for (int i = tid; i < 64 * 64; i += blockDim.x) {
-    const int y = min(cy + (i >> 6), jb->h - 1), x = min(cx + (i & 63), jb->w - 1);
-    sh.cur[i] = jb->cur[(size_t)y * jb->stride + x];
+  // Current CTU (coded picture, edge-replicated) from the copy the prep kernel
+  // packed: 8x8 blocks in Z-order, 16 dwords each (row r, half c at 2r + c).
+  // Thread t takes dwords 4t .. 4t + 3: rows 2 (t & 3) and 2 (t & 3) + 1 of
+  // block t >> 2.
+  {
+    const uint4 v = ((const uint4*)(jb->curpack + (size_t)ctu * 1024))[tid];
+    const int bz = tid >> 2, y = zy(bz) * 8 + 2 * (tid & 3), x = zx(bz) * 8;
+    uint32_t* d = (uint32_t*)sh.cur;
+    d[(y * 64 + x) >> 2] = v.x, d[(y * 64 + x + 4) >> 2] = v.y;
+    d[((y + 1) * 64 + x) >> 2] = v.z, d[((y + 1) * 64 + x + 4) >> 2] = v.w;
   }
   if (tid < kNodes) {
     const int node = tid;
@@ -471,14 +485,14 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
           else x = x0 + (k - 2 * n - 1), y = y0 - 1;             // top row
           const int lx = x - cx, ly = y - cy;
           if ((unsigned)lx < 64u && (unsigned)ly < 64u) v = sh.cur[ly * 64 + lx];
-          else v = jb->cur[min(y, jb->h - 1) * stride + min(x, jb->w - 1)];
+          else v = jb->cur[(uint32_t)(min(y, jb->h - 1) * stride + min(x, jb->w - 1))];
         }
         R[off] = (int16_t)v;
         // DC: p[0..n-1][-1] (off 2n+1 .. 3n) and p[-1][0..n-1] (off 1 .. n).
         if ((off >= 1 && off <= n) || (off > 2 * n && off <= 3 * n)) dcs += v;
       }
       const int g = tpn < 64 ? tpn : 64;  // the node's threads within this wavefront
-      dcs = (int)shfl_sum((uint32_t)dcs, g);
+      dcs = (int)group_sum((uint32_t)dcs, g);
       if ((tid & (g - 1)) == 0) atomicAdd(&sh.dc[node], dcs);
     }
   }
@@ -510,14 +524,15 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
         int ri[16];
         if (!jb->subpel) {
           const int mx = sh.mvx[node], my = sh.mvy[node];
-          int xo[4], yo[4];
+          const uint8_t* __restrict__ rp = jb->ref;
+          uint32_t xo[4], yo[4];  // sample offsets (the library keeps them below 2^31)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            xo[q] = clampi(cx + tx * 4 + q + mx, 0, jb->w - 1);
-            yo[q] = clampi(cy + ty * 4 + q + my, 0, jb->h - 1) * stride;
+            xo[q] = (uint32_t)clampi(cx + tx * 4 + q + mx, 0, jb->w - 1);
+            yo[q] = (uint32_t)(clampi(cy + ty * 4 + q + my, 0, jb->h - 1) * stride);
           }
 #pragma unroll
-          for (int i = 0; i < 16; ++i) ri[i] = c[i] - (int)jb->ref[yo[i >> 2] + xo[i & 3]];
+          for (int i = 0; i < 16; ++i) ri[i] = c[i] - (int)rp[yo[i >> 2] + xo[i & 3]];
         } else {
 #pragma unroll
           for (int i = 0; i < 16; ++i) ri[i] = 0;
@@ -525,13 +540,27 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
         const int16_t* L = sh.refs + ref_offset(node);
         const int16_t* T = L + 2 * n + 1;
         const int px0 = tx * 4 - lx * n, py0 = ty * 4 - ly * n;  // position inside the CU
+        // Planar: the horizontal part (n-1-px) L[py+1] + (px+1) T[n] is linear
+        // in px along a row and the vertical part (n-1-py) T[px] + (py+1) L[n+1]
+        // linear in py along a column, so each tile row / column is set up once.
+        const int Tn = T[n], Ln1 = L[n + 1];
+        int hr[4], dh[4], vc[4], dv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int Ly = L[py0 + j + 1];
+          hr[j] = (n - 1 - px0) * Ly + (px0 + 1) * Tn + n, dh[j] = Tn - Ly;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int Tx = T[px0 + i];
+          vc[i] = (n - 1 - py0) * Tx + (py0 + 1) * Ln1, dv[i] = Ln1 - Tx;
+        }
         sh2 pr[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int px = px0 + (i & 3), py = py0 + (i >> 2);
-          const int p = ((n - 1 - px) * L[py + 1] + (px + 1) * T[n] + (n - 1 - py) * T[px] +
-                         (py + 1) * L[n + 1] + n) >> (lg + 1);
-          pr[i] = (sh2){(short)ri[i], (short)(c[i] - p)};
+        for (int k = 0; k < 16; ++k) {
+          const int i = k & 3, j = k >> 2;
+          const int p = (hr[j] + i * dh[j] + vc[i] + j * dv[i]) >> (lg + 1);
+          pr[k] = (sh2){(short)ri[k], (short)(c[k] - p)};
         }
         const uint32_t pk = satd4x4_pair(pr);
         v0 = pk & 0xFFFFu, v1 = pk >> 16;
@@ -541,7 +570,7 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       // Tiles of a node are consecutive threads: 4^(3-d+1) of them.
       const int width = 4 << (2 * (3 - d));  // 4, 16, 64, 256
       const int w = width > 64 ? 64 : width;
-      v0 = shfl_sum(v0, w), v1 = shfl_sum(v1, w), v2 = shfl_sum(v2, w);
+      v0 = group_sum(v0, w), v1 = group_sum(v1, w), v2 = group_sum(v2, w);
       if (d > 0) {
         if ((lane & (w - 1)) == 0) sh.satd[node][0] = v0, sh.satd[node][1] = v1, sh.satd[node][2] = v2;
       } else if (lane == 0) {
