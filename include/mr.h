@@ -276,6 +276,13 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out);
  * Errors: MR_EINVAL (null, rung or ids out of range). Re-registering replaces. */
 int mr_ladder_put_frame(mr_ladder* l, int32_t stream_id, int32_t frame_idx, int32_t rung,
                         const uint8_t* luma, int32_t stride);
+/* Forget every registered frame of stream_id with frame_idx < before_frame
+ * (all rungs), so that a long-running server's frame table holds the frames
+ * still in use; the caller may then reuse or free that memory once the jobs
+ * that read those frames have completed.  A job submitted earlier whose frames
+ * are dropped before it starts completes with MR_EDEPEND.
+ * Errors: MR_EINVAL (null ladder, negative stream id). */
+int mr_ladder_drop_frames(mr_ladder* l, int32_t stream_id, int32_t before_frame);
 /* Errors: MR_EINVAL (ids, frames not resident), MR_EDEPEND, MR_EAGAIN (queue
  * full, or the job alone exceeds the budget), MR_ESTATE (closed). */
 int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id);
@@ -283,7 +290,9 @@ int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id);
  * (0 = do not wait).  MR_ETIMEOUT if none arrived. */
 int mr_ladder_poll(mr_ladder* l, mr_completion* out, int32_t max, int32_t timeout_us,
                    int32_t* n_out);
-/* Give a completed job's outputs back (MR_ESTATE if not completed yet). */
+/* Give a completed job's outputs back (MR_ESTATE if not completed yet).  Once
+ * a job is released, handed out by mr_ladder_poll and needed by no dependent,
+ * the server forgets it (its id then gives MR_EINVAL). */
 int mr_ladder_release(mr_ladder* l, uint64_t job_id);
 int mr_ladder_get_stats(mr_ladder* l, mr_ladder_stats* out);
 /* Waits for in-flight work, frees everything the ladder owns (NULL ok). */

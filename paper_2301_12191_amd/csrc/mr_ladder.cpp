@@ -70,6 +70,15 @@ class GpuExecutor : public Executor {
     frames_[std::make_tuple(stream, frame, rung)] = FrameRef{luma, stride};
   }
 
+  // Forget the frames of `stream` before `before_frame` (every rung).
+  void drop_frames(int stream, int before_frame) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = frames_.lower_bound(std::make_tuple(stream, 0, 0));
+    while (it != frames_.end() && std::get<0>(it->first) == stream &&
+           std::get<1>(it->first) < before_frame)
+      it = frames_.erase(it);
+  }
+
   bool frames_resident(int stream, int frame, int rung) override {
     std::lock_guard<std::mutex> lk(mu_);
     return frames_.count(std::make_tuple(stream, frame, rung)) &&
@@ -122,9 +131,13 @@ class GpuExecutor : public Executor {
       const RungCfg& r = cfg_.rungs[j.rung];
       FrameRef fc, fr;
       {
+        // The scheduler admits only jobs whose frames are resident; a frame
+        // dropped since then fails the batch instead of being read.
         std::lock_guard<std::mutex> lk(mu_);
-        fc = frames_[std::make_tuple(j.stream, j.frame, j.rung)];
-        fr = frames_[std::make_tuple(j.stream, j.frame - 1, j.rung)];
+        auto ic = frames_.find(std::make_tuple(j.stream, j.frame, j.rung));
+        auto ir = frames_.find(std::make_tuple(j.stream, j.frame - 1, j.rung));
+        if (ic == frames_.end() || ir == frames_.end()) return MR_EDEPEND;
+        fc = ic->second, fr = ir->second;
       }
       cur[i] = mr_frame{fc.luma, r.width, r.height, fc.stride};
       ref[i] = mr_frame{fr.luma, r.width, r.height, fr.stride};
@@ -335,6 +348,13 @@ int mr_ladder_put_frame(mr_ladder* l, int32_t stream_id, int32_t frame_idx, int3
   return MR_OK;
 }
 
+int mr_ladder_drop_frames(mr_ladder* l, int32_t stream_id, int32_t before_frame) {
+  if (!l || stream_id < 0) return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(l->mu);  // not between the scheduler's check and a launch
+  l->ex->drop_frames(stream_id, before_frame);
+  return MR_OK;
+}
+
 int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id) {
   if (!l || !job) return MR_EINVAL;
   std::lock_guard<std::mutex> lk(l->mu);
@@ -408,11 +428,7 @@ int mr_ladder_close(mr_ladder* l) {
   // Free every job's outputs still held.
   {
     std::lock_guard<std::mutex> lk(l->mu);
-    for (uint64_t id = 1;; ++id) {
-      const SchedJob* j = l->sched->job(id);
-      if (!j) break;
-      if (j->exec_state) l->ex->free_job(const_cast<SchedJob&>(*j));
-    }
+    l->sched->free_all();
   }
   l->ex->sync();
   delete l;

@@ -30,10 +30,7 @@ int Scheduler::submit(int stream, int frame, int rung, uint64_t* id) {
   if (id) *id = 0;
   if (stream < 0 || frame < 1 || rung < 0 || rung >= (int)cfg_.rungs.size()) return MR_EINVAL;
   if (!ex_->frames_resident(stream, frame, rung)) return MR_EINVAL;
-  int open = 0;
-  for (const auto& kv : jobs_)
-    if (kv.second->state != kDone && kv.second->state != kFailed) ++open;
-  if (open >= cfg_.max_queue) {
+  if (open_ >= cfg_.max_queue) {
     ++st_.rejected;
     return MR_EAGAIN;
   }
@@ -71,6 +68,7 @@ int Scheduler::submit(int stream, int frame, int rung, uint64_t* id) {
   latest_[std::make_tuple(stream, frame, rung)] = jid;
   jobs_[jid] = std::move(j);
   queue_.push_back(jid);
+  ++open_;
   ++st_.submitted;
   if (id) *id = jid;
   return MR_OK;
@@ -86,6 +84,35 @@ void Scheduler::maybe_free(SchedJob& j) {
   ex_->free_job(j);
   j.exec_state = nullptr;
   if (j.admitted) st_.bytes_in_use -= j.footprint, j.admitted = false;
+  retire_check_.push_back(j.id);
+}
+
+// Forget jobs that are finished, handed out, released and freed, and that no
+// dependent still needs.
+void Scheduler::retire_finished() {
+  while (!retire_check_.empty()) {
+    const uint64_t id = retire_check_.front();
+    retire_check_.pop_front();
+    auto it = jobs_.find(id);
+    if (it == jobs_.end()) continue;
+    const SchedJob& j = *it->second;
+    if ((j.state != kDone && j.state != kFailed) || !j.handed_out || !j.released ||
+        j.exec_state || j.pending_dependents > 0)
+      continue;
+    auto lt = latest_.find(std::make_tuple(j.stream, j.frame, j.rung));
+    if (lt != latest_.end() && lt->second == id) latest_.erase(lt);
+    jobs_.erase(it);
+  }
+}
+
+void Scheduler::free_all() {
+  for (auto& kv : jobs_) {
+    SchedJob& j = *kv.second;
+    if (!j.exec_state) continue;
+    ex_->free_job(j);
+    j.exec_state = nullptr;
+    if (j.admitted) st_.bytes_in_use -= j.footprint, j.admitted = false;
+  }
 }
 
 void Scheduler::complete(SchedJob& j, int status, int64_t t) {
@@ -94,6 +121,7 @@ void Scheduler::complete(SchedJob& j, int status, int64_t t) {
   j.state = status == MR_OK ? kDone : kFailed;
   j.depth_ready = status == MR_OK;
   --inflight_;
+  --open_;
   if (status == MR_OK) {
     ++st_.completed;
     st_.ctus_done += j.n_ctus;
@@ -108,12 +136,14 @@ void Scheduler::complete(SchedJob& j, int status, int64_t t) {
     if (it != jobs_.end()) {
       it->second->pending_dependents--;
       maybe_free(*it->second);
+      retire_check_.push_back(j.ref_job);
     }
   }
 }
 
 int Scheduler::step() {
   int done = 0;
+  retire_finished();
   const int64_t now = ex_->now_ns();
   // 1. Retire finished batches.
   for (size_t b = 0; b < running_.size();) {
@@ -153,6 +183,14 @@ int Scheduler::step() {
   for (uint64_t id : queue_) {
     SchedJob& j = *jobs_[id];
     if (j.state == kQueued) continue;  // waiting for its reference
+    if (!ex_->frames_resident(j.stream, j.frame, j.rung)) {
+      // Its frames were dropped after submission: it fails alone.
+      j.state = kRunning;  // transient; completed below
+      ++inflight_;
+      complete(j, MR_EDEPEND, now);
+      ++done;
+      continue;
+    }
     if ((int)batch.size() >= cfg_.max_batch_jobs || inflight_ >= cfg_.max_inflight) break;
     if (st_.bytes_in_use + j.footprint > cfg_.budget_bytes) {
       // Evict resident reference jobs nobody needs any more (oldest first).
@@ -163,6 +201,7 @@ int Scheduler::step() {
           ex_->free_job(r);
           r.exec_state = nullptr;
           if (r.admitted) st_.bytes_in_use -= r.footprint, r.admitted = false;
+          retire_check_.push_back(r.id);
         }
       }
       if (st_.bytes_in_use + j.footprint > cfg_.budget_bytes) break;
@@ -173,6 +212,9 @@ int Scheduler::step() {
     ++inflight_;
     batch.push_back(&j);
   }
+  queue_.erase(std::remove_if(queue_.begin(), queue_.end(),
+                              [&](uint64_t id) { return jobs_[id]->state == kFailed; }),
+               queue_.end());
   if (batch.empty()) return done;
   for (SchedJob* j : batch) j->state = kRunning;
   queue_.erase(std::remove_if(queue_.begin(), queue_.end(),
@@ -198,8 +240,12 @@ int Scheduler::step() {
 std::vector<uint64_t> Scheduler::take_completions(int max) {
   std::vector<uint64_t> out;
   while (!completions_.empty() && (int)out.size() < max) {
-    out.push_back(completions_.front());
+    const uint64_t id = completions_.front();
     completions_.pop_front();
+    auto it = jobs_.find(id);
+    if (it != jobs_.end()) it->second->handed_out = true;
+    retire_check_.push_back(id);  // retired at the next step(), after the caller read it
+    out.push_back(id);
   }
   return out;
 }
@@ -216,6 +262,7 @@ int Scheduler::release(uint64_t id) {
   if (j.state != kDone && j.state != kFailed) return MR_ESTATE;
   j.released = true;
   maybe_free(j);
+  retire_check_.push_back(id);
   return MR_OK;
 }
 

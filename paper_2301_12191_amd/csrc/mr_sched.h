@@ -39,6 +39,7 @@ struct SchedJob {
   int status = 0;
   bool implied = false;            // created by the server for a dependent
   bool released = false;           // caller released the outputs
+  bool handed_out = false;         // completion taken by take_completions
   uint64_t ref_job = 0;            // job whose depth map bounds this one (0 none)
   int pending_dependents = 0;      // dependents that still need this job's depth map
   bool depth_ready = false;        // reference depth map available (job done)
@@ -87,11 +88,17 @@ class Scheduler {
   int step();
   // Completed jobs not yet handed out (ids in completion order).
   std::vector<uint64_t> take_completions(int max);
+  // A job stays known (job(id) != null) until it is finished, handed out,
+  // released, its outputs are freed and no dependent needs it; step() then
+  // forgets it, so the tables hold live jobs only.
   const SchedJob* job(uint64_t id) const;
   int release(uint64_t id);
   bool idle() const;  // nothing queued or running
   SchedStats stats() const;
   int batches_in_flight() const { return (int)running_.size(); }
+  size_t jobs_known() const { return jobs_.size(); }
+  // Free the outputs of every job still holding them (server shutdown).
+  void free_all();
 
  private:
   struct Batch {
@@ -101,6 +108,7 @@ class Scheduler {
   SchedJob* find_ref(int stream, int frame, int ref_rung);
   void maybe_free(SchedJob& j);
   void complete(SchedJob& j, int status, int64_t t);
+  void retire_finished();
   SchedConfig cfg_;
   Executor* ex_;
   uint64_t next_id_ = 1;
@@ -110,8 +118,10 @@ class Scheduler {
   std::vector<Batch> running_;
   std::deque<uint64_t> completions_;
   std::vector<double> latencies_ms_;
+  std::deque<uint64_t> retire_check_;  // jobs whose retirement conditions may now hold
   SchedStats st_;
   int inflight_ = 0;
+  int open_ = 0;  // submitted, not yet completed
 };
 
 }  // namespace mr

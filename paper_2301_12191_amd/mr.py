@@ -388,14 +388,16 @@ def _ladder_lib():
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
         L.mr_ladder_open.argtypes = [ctypes.POINTER(mr_ladder_config), ctypes.POINTER(vp)]
         L.mr_ladder_put_frame.argtypes = [vp, i32, i32, i32, vp, i32]
+        L.mr_ladder_drop_frames.argtypes = [vp, i32, i32]
         L.mr_ladder_submit.argtypes = [vp, ctypes.POINTER(mr_job), ctypes.POINTER(ctypes.c_uint64)]
         L.mr_ladder_poll.argtypes = [vp, ctypes.POINTER(mr_completion), i32, i32,
                                      ctypes.POINTER(i32)]
         L.mr_ladder_release.argtypes = [vp, ctypes.c_uint64]
         L.mr_ladder_get_stats.argtypes = [vp, ctypes.POINTER(mr_ladder_stats)]
         L.mr_ladder_close.argtypes = [vp]
-        for f in ("mr_ladder_open", "mr_ladder_put_frame", "mr_ladder_submit", "mr_ladder_poll",
-                  "mr_ladder_release", "mr_ladder_get_stats", "mr_ladder_close"):
+        for f in ("mr_ladder_open", "mr_ladder_put_frame", "mr_ladder_drop_frames",
+                  "mr_ladder_submit", "mr_ladder_poll", "mr_ladder_release", "mr_ladder_get_stats",
+                  "mr_ladder_close"):
             getattr(L, f).restype = ctypes.c_int
         L._ladder_bound = True
     return L
@@ -453,6 +455,16 @@ class Ladder:
                                                _dev_ptr(luma, torch.uint8, "luma"), luma.stride(0))
         if rc != MR_OK:
             raise MRError(rc, "mr_ladder_put_frame")
+
+    def drop_frames(self, stream_id, before_frame):
+        """Forget the frames of a stream before `before_frame` and stop keeping their tensors
+        alive.  Jobs that read those frames must have completed (a job not yet started fails
+        with MR_EDEPEND instead)."""
+        rc = _ladder_lib().mr_ladder_drop_frames(self._h, stream_id, before_frame)
+        if rc != MR_OK:
+            raise MRError(rc, "mr_ladder_drop_frames")
+        for key in [k for k in self._frames if k[0] == stream_id and k[1] < before_frame]:
+            del self._frames[key]
 
     def submit(self, stream_id, frame_idx, rung) -> int:
         jid = ctypes.c_uint64()

@@ -2,6 +2,7 @@
 // dependencies and implied references, footprint admission, queue limits,
 // failure propagation, resident references and eviction, continuous batching,
 // latency statistics.  Exit code 0 = all checks passed.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -233,6 +234,57 @@ static void test_continuous_batching_and_latency() {
   CHECK(s.take_completions(100).empty());
 }
 
+static void test_finished_jobs_are_forgotten() {
+  // A long run: jobs are submitted, completed, handed out and released over and
+  // over; the scheduler's tables must hold only live jobs (no growth with time).
+  // Released reference jobs stay resident (for later dependents) until
+  // admission needs their memory: a budget of 10 jobs bounds them.
+  FakeExec ex;
+  ex.fp = {{0, 100}, {1, 100}, {2, 100}};
+  SchedConfig cfg = ladder_cfg(1000);
+  cfg.max_queue = 64;
+  Scheduler s(cfg, &ex);
+  size_t most = 0;
+  for (int f = 1; f <= 200; ++f) {
+    add_frames(ex, 0, f + 1, 3);
+    uint64_t a, b;
+    CHECK(s.submit(0, f, 1, &a) == MR_OK);  // implies the rung-0 reference
+    CHECK(s.submit(0, f, 2, &b) == MR_OK);
+    run_until_idle(s, ex);
+    for (uint64_t id : s.take_completions(100)) CHECK(s.release(id) == MR_OK);
+    s.step();
+    most = std::max(most, s.jobs_known());
+  }
+  // at most the resident references the budget holds, plus the frame in flight
+  CHECK(most <= 12);
+  CHECK(s.stats().bytes_in_use <= 1000);
+  CHECK(s.stats().completed == 600 && s.stats().implied == 200);
+  // a forgotten job's id is unknown
+  CHECK(s.job(1) == nullptr && s.release(1) == MR_EINVAL);
+  // the references still resident are freed by free_all
+  const int before = ex.freed;
+  s.free_all();
+  CHECK(ex.freed > before);
+}
+
+static void test_dropped_frames_fail_alone() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  add_frames(ex, 0, 3, 3);
+  add_frames(ex, 1, 3, 3);
+  Scheduler s(ladder_cfg(1 << 20), &ex);
+  uint64_t a, b;
+  CHECK(s.submit(0, 2, 0, &a) == MR_OK);
+  CHECK(s.submit(1, 2, 0, &b) == MR_OK);
+  // stream 0's frames go away before the jobs are admitted
+  for (int r = 0; r < 3; ++r) ex.frames.erase(std::make_tuple(0, 1, r));
+  run_until_idle(s, ex);
+  CHECK(s.job(a)->state == kFailed && s.job(a)->status == MR_EDEPEND);
+  CHECK(s.job(b)->state == kDone);
+  CHECK(ex.launched.size() == 1 && ex.launched[0].size() == 1 && ex.launched[0][0] == b);
+  CHECK(s.submit(0, 2, 0, &a) == MR_EINVAL);  // not resident any more
+}
+
 int main() {
   test_dependency_and_implied_reference();
   test_missing_reference_frames();
@@ -240,6 +292,8 @@ int main() {
   test_queue_limit();
   test_reference_failure_fails_dependents();
   test_continuous_batching_and_latency();
+  test_finished_jobs_are_forgotten();
+  test_dropped_frames_fail_alone();
   if (g_fail) {
     std::fprintf(stderr, "%d checks failed\n", g_fail);
     return 1;

@@ -155,6 +155,54 @@ def test_ladder_errors(mr):
         mr.Ladder([dict(width=64, height=64, qp=30, search_range=8, ref_rung=0)])  # self-reference
 
 
+def test_streaming_with_dropped_frames_and_forgotten_jobs(mr):
+    """A stream served frame after frame, dropping each frame once no job needs it: every job
+    still equals its result alone, a dropped frame can no longer be searched, and released
+    job ids are forgotten."""
+    import torch
+    fr = _frames(1, 5)
+    lad = mr.Ladder(RUNGS)
+    cache = {}
+    first_ids = []
+    try:
+        for r in range(3):
+            lad.put_frame(0, 0, r, fr[(0, 0, r)])
+        for f in range(1, 5):
+            for r in range(3):
+                lad.put_frame(0, f, r, fr[(0, f, r)])
+            ids = {lad.submit(0, f, r): r for r in (2, 1)}  # the reference is implied
+            seen = 0
+            for _ in range(2000):
+                for c in lad.poll(16, 100000):
+                    assert c.status == 0
+                    if c.job_id in ids:
+                        torch.cuda.synchronize()
+                        got = {k: v.cpu().numpy() for k, v in lad.outputs(c).items()}
+                        exp = _alone(mr, fr, 0, f, ids[c.job_id], cache)
+                        for k in FIELDS:
+                            assert np.array_equal(got[k], exp[k]), (f, ids[c.job_id], k)
+                        seen += 1
+                        if f == 1:  # not reference-rung jobs: freed on release
+                            first_ids.append(c.job_id)
+                    lad.release(c.job_id)
+                if seen == len(ids):
+                    break
+            assert seen == len(ids)
+            lad.drop_frames(0, f)  # frame f - 1 is no longer needed
+        with pytest.raises(mr.MRError) as e:
+            lad.submit(0, 2, 1)  # frame 1 was dropped
+        assert e.value.code in (mr.MR_EINVAL, mr.MR_EDEPEND)
+        import time
+        time.sleep(0.05)  # the server loop forgets released, handed-out jobs
+        assert len(first_ids) == 2
+        for jid in first_ids:
+            with pytest.raises(mr.MRError) as e:
+                lad.release(jid)
+            assert e.value.code == mr.MR_EINVAL
+    finally:
+        lad.close()
+
+
 def test_mv_reuse_dependents_equal_seeded_alone(mr):
     """With reuse_mv, every dependent equals mr_ctu_search_seeded with its reference job's MVs
     and depth bounds; references are unchanged."""
