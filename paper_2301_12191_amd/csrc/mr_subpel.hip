@@ -135,11 +135,13 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
             const int sbyte = k + f + 1;  // 0..4
             const uint32_t lo = sbyte == 4 ? P[r][1] : __builtin_amdgcn_alignbyte(P[r][1], P[r][0], sbyte);
             const uint32_t hi = sbyte == 4 ? P[r][2] : __builtin_amdgcn_alignbyte(P[r][2], P[r][1], sbyte);
-            // sum of taps * (sample - 128), plus 128 * 64 for the offset
+            // sum of taps * (sample - 128), plus 128 * 64 for the offset (the
+            // first dot product's initial accumulator)
             const int h = __builtin_amdgcn_sdot4((int)lo, (int)tlo,
-                                                 __builtin_amdgcn_sdot4((int)hi, (int)thi, 0, false),
-                                                 false) + 8192;
-            if (r > 0) Q[r - 1][k] = ((uint32_t)hprev[k] & 0xFFFFu) | ((uint32_t)h << 16);
+                                                 __builtin_amdgcn_sdot4((int)hi, (int)thi, 8192, false),
+                                                 false);
+            // (low halves of) hprev | h << 16 in one v_perm_b32
+            if (r > 0) Q[r - 1][k] = __builtin_amdgcn_perm((uint32_t)h, (uint32_t)hprev[k], 0x05040100u);
             hprev[k] = h;
           }
         }
