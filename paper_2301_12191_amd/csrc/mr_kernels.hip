@@ -72,21 +72,31 @@ __device__ __forceinline__ uint32_t set_lane(uint32_t v, uint32_t u, int l) {
 __device__ void prep_ctu(cjob jb, int ctu) {
   const int tid = threadIdx.x;
   const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
-  // 64 blocks x 16 dwords: thread -> (block, 4 dwords = 2 rows x 2 dwords)
+  // 64 blocks x 16 dwords (row r, half c of block bz at dword bz * 16 + 2r + c).
+  // Thread t reads dword t & 15 of CTU rows (t >> 4) + 16 i, i = 0..3, so a
+  // wavefront reads 4 whole CTU rows: plain dword loads when the frame is
+  // dword-aligned and the CTU lies inside it, else clamped byte loads.
   {
-    const int bz = tid >> 2, part = tid & 3;
-    const int bx = zx(bz), by = zy(bz);
-    uint32_t* dst = (uint32_t*)jb->curpack + (size_t)ctu * 1024 + bz * 16 + part * 4;
+    uint32_t* dst = (uint32_t*)jb->curpack + (size_t)ctu * 1024;
+    const int c16 = tid & 15, x0 = cx + 4 * c16;
+    const bool fast = ((jb->stride & 3) == 0) && ((((uintptr_t)jb->cur) & 3) == 0) &&
+                      cx + 64 <= jb->w && cy + 64 <= jb->h;  // uniform
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = part * 2 + (i >> 1), c = i & 1;
-      const int y = min(cy + by * 8 + r, jb->h - 1);
-      const uint8_t* row = jb->cur + (size_t)y * jb->stride;
-      const int x0 = cx + bx * 8 + c * 4;
-      uint32_t v = 0;
+      const int ry = (tid >> 4) + 16 * i;
+      uint32_t v;
+      if (fast) {
+        v = *(const uint32_t*)(jb->cur + (uint32_t)((cy + ry) * jb->stride + x0));
+      } else {
+        const uint8_t* row = jb->cur + (uint32_t)(min(cy + ry, jb->h - 1) * jb->stride);
+        v = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) v |= (uint32_t)row[min(x0 + b, jb->w - 1)] << (8 * b);
-      dst[i] = v;
+        for (int b = 0; b < 4; ++b) v |= (uint32_t)row[min(x0 + b, jb->w - 1)] << (8 * b);
+      }
+      const int bx = c16 >> 1, by = ry >> 3;
+      const int bz = (bx & 1) | ((by & 1) << 1) | ((bx & 2) << 1) | ((by & 2) << 2) |
+                     ((bx & 4) << 2) | ((by & 4) << 3);
+      dst[bz * 16 + (ry & 7) * 2 + (c16 & 1)] = v;
     }
   }
   if (tid < kNodes) {
