@@ -509,6 +509,8 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   __syncthreads();
 
   // SATD of every 4x4 tile under every eligible node: thread = tile in Z-order.
+  const bool ref_aligned = (((uintptr_t)jb->ref) & 3) == 0;
+  const uint32_t frame_bytes = (uint32_t)((jb->h - 1) * stride + jb->w);
   {
     const int t = tid;  // 0..255
     const int tx = (t & 1) | ((t >> 1) & 2) | ((t >> 2) & 4) | ((t >> 3) & 8);
@@ -535,14 +537,29 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
         if (!jb->subpel) {
           const int mx = sh.mvx[node], my = sh.mvy[node];
           const uint8_t* __restrict__ rp = jb->ref;
-          uint32_t xo[4], yo[4];  // sample offsets (the library keeps them below 2^31)
+          const int xf = cx + tx * 4 + mx;  // first reference column of the tile
+          uint32_t yo[4];  // sample offsets (the library keeps them below 2^31)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            xo[q] = (uint32_t)clampi(cx + tx * 4 + q + mx, 0, jb->w - 1);
+          for (int q = 0; q < 4; ++q)
             yo[q] = (uint32_t)(clampi(cy + ty * 4 + q + my, 0, jb->h - 1) * stride);
-          }
+          // Rows needing no horizontal clamping: the two dwords around the 4
+          // samples (inside the frame) and one v_alignbyte.
+          if (ref_aligned && xf >= 0 && xf + 3 < jb->w && yo[3] + (uint32_t)xf + 8u <= frame_bytes) {
 #pragma unroll
-          for (int i = 0; i < 16; ++i) ri[i] = c[i] - (int)rp[yo[i >> 2] + xo[i & 3]];
+            for (int q = 0; q < 4; ++q) {
+              const uint32_t o = yo[q] + (uint32_t)xf;
+              const uint32_t* a = (const uint32_t*)(rp + (o & ~3u));
+              const uint32_t v = __builtin_amdgcn_alignbyte(a[1], a[0], o & 3u);
+#pragma unroll
+              for (int k = 0; k < 4; ++k) ri[4 * q + k] = c[4 * q + k] - (int)((v >> (8 * k)) & 0xFFu);
+            }
+          } else {
+            uint32_t xo[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xo[q] = (uint32_t)clampi(xf + q, 0, jb->w - 1);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) ri[i] = c[i] - (int)rp[yo[i >> 2] + xo[i & 3]];
+          }
         } else {
 #pragma unroll
           for (int i = 0; i < 16; ++i) ri[i] = 0;
