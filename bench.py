@@ -492,41 +492,50 @@ def main():
                 img = sc.render(f)
                 for r, (w, h, n, qp) in enumerate(synth.LADDER):
                     content[(c, f, r)] = torch.from_numpy(synth.box_downscale(img, n, w, h)).to(dev)
-        lad = mr.Ladder(rungs, delta_lo=0, delta_hi=1, budget_bytes=16 << 30, max_inflight=512,
-                        max_queue=1 << 16, max_batch_jobs=64)
-        for st in range(n_streams):
-            for f in range(nfr):
-                for r in range(len(rungs)):
-                    lad.put_frame(st, f, r, content[(st % n_content, f, r)])
-        rng = random.Random(synth.SEED_BASE + 4)
-        t_next, t0s = 0.0, time.perf_counter()
-        submitted = done = 0
-        horizon = args.serve_seconds
-        while True:
-            now = time.perf_counter() - t0s
-            while t_next <= now and t_next < horizon:
-                lad.submit(rng.randrange(n_streams), rng.randrange(1, nfr), rng.randrange(len(rungs)))
-                submitted += 1
-                t_next += rng.expovariate(240.0)
-            for c in lad.poll(256, 200):
-                lad.release(c.job_id)
-                done += 1
-            st = lad.stats()
-            if t_next >= horizon and st["completed"] + st["failed"] >= st["submitted"]:
-                break
-            if now > horizon + 60:
-                break
-        st = lad.stats()
-        lad.close()
+        def serve(reuse):
+            """One Poisson arrival trace (same seed for both variants) through a ladder server;
+            reuse adds the reference MVs as search centres (refinement r = REFINE_R)."""
+            kw = dict(refine_range=REFINE_R) if reuse else {}
+            lad = mr.Ladder(rungs, delta_lo=0, delta_hi=1, budget_bytes=16 << 30,
+                            max_inflight=512, max_queue=1 << 16, max_batch_jobs=64, **kw)
+            try:
+                for st in range(n_streams):
+                    for f in range(nfr):
+                        for r in range(len(rungs)):
+                            lad.put_frame(st, f, r, content[(st % n_content, f, r)])
+                rng = random.Random(synth.SEED_BASE + 4)
+                t_next, t0s = 0.0, time.perf_counter()
+                horizon = args.serve_seconds
+                while True:
+                    now = time.perf_counter() - t0s
+                    while t_next <= now and t_next < horizon:
+                        lad.submit(rng.randrange(n_streams), rng.randrange(1, nfr),
+                                   rng.randrange(len(rungs)))
+                        t_next += rng.expovariate(240.0)
+                    for c in lad.poll(256, 200):
+                        lad.release(c.job_id)
+                    st = lad.stats()
+                    if t_next >= horizon and st["completed"] + st["failed"] >= st["submitted"]:
+                        break
+                    if now > horizon + 60:
+                        break
+                st = lad.stats()
+            finally:
+                lad.close()
+            return {"seconds": args.serve_seconds, "jobs_submitted": st["submitted"] - st["implied"],
+                    "implied_reference_jobs": st["implied"], "completed": st["completed"],
+                    "failed": st["failed"], "batches": st["batches"],
+                    "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                    "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                    "ctus_per_s": round(st["ctus_per_s"], 1)}
+
         serving = {"workload": "64 streams, 6-rung ladder frames resident, Poisson arrivals mean "
                                "240 jobs/s, rung uniform, 960x540 reference bounds the others "
                                "(depths n..n+1)",
-                   "seconds": horizon, "jobs_submitted": st["submitted"] - st["implied"],
-                   "implied_reference_jobs": st["implied"], "completed": st["completed"],
-                   "failed": st["failed"], "batches": st["batches"],
-                   "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-                   "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
-                   "ctus_per_s": round(st["ctus_per_s"], 1)}
+                   **serve(False)}
+        serving["reuse_mv"] = {"workload": "the same arrivals; dependents also search around the "
+                                           f"reference MVs (refinement r = {REFINE_R})",
+                               **serve(True)}
         log(f"serving: {serving}")
         del content
         torch.cuda.synchronize()
