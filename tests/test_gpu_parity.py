@@ -72,6 +72,9 @@ def _pair(seed, W, H, n_rects, mv_max, pan=0):
 @pytest.mark.parametrize("W,H,qp,R", [
     (64, 64, 32, 0), (64, 64, 32, 1), (64, 64, 22, 3), (8, 8, 30, 4), (72, 40, 27, 5),
     (200, 136, 32, 16), (203, 141, 37, 9), (130, 70, 45, 24), (96, 200, 12, 32),
+    # pictures smaller than one 8x8 unit (coded picture replicated from 1 or a few samples),
+    # and the QP extremes 0 and 51
+    (1, 1, 30, 2), (5, 3, 0, 3), (17, 9, 51, 8), (64, 64, 51, 7), (33, 71, 0, 16),
 ])
 def test_small_pairs_bit_exact(mr, W, H, qp, R):
     print(f"\ncase {W}x{H} qp {qp} R {R}", flush=True)

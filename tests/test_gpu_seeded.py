@@ -101,10 +101,15 @@ def _rand_map(seed, w, h, amp):
     (200, 136, 32, 16, 2, 100, 68),    # dyadic
     (203, 141, 37, 9, 3, 135, 94),     # ratio 3/2, sizes not multiples of 8
     (130, 70, 45, 24, 7, 260, 140),    # seed from a larger picture
-    (96, 200, 12, 32, 8, 48, 100),     # window of 17 candidates: three passes
-    (416, 240, 32, 16, 15, 208, 120),  # 31 candidates: four passes
-    (416, 240, 32, 20, 16, 208, 120),  # 33 candidates: five passes (two bands)
+    (96, 200, 12, 32, 8, 48, 100),     # window of 17 candidates: passes of 9 + 8
+    (416, 240, 32, 16, 15, 208, 120),  # 31 candidates: four passes, the last of 4
+    (416, 240, 32, 20, 16, 208, 120),  # 33 candidates: four passes (two bands)
     (256, 128, 30, 40, 17, 128, 64),   # 35 candidates, centres clamped to +-23
+    (200, 136, 30, 16, 3, 100, 68),    # 7 candidates: one pass of 9, two columns past the window
+    (200, 136, 30, 16, 4, 100, 68),    # 9 candidates: exactly one pass
+    (200, 136, 30, 16, 5, 100, 68),    # 11 candidates: passes of 9 + 2
+    (1, 1, 30, 4, 2, 1, 1),            # one sample
+    (5, 3, 0, 6, 3, 3, 2),             # smaller than one unit, QP 0
 ])
 def test_seeded_matches_oracle(mr, W, H, qp, R, r, rw, rh):
     ref, cur = _pair(W * 7 + H, W, H, 5, min(R, 12) + 1, 2)

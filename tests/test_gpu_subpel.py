@@ -79,6 +79,7 @@ def _oracle(cur, ref, qp, R, bounds=None, seed=None, ctu_list=None):
 @pytest.mark.parametrize("W,H,qp,R", [
     (8, 8, 30, 2), (64, 64, 32, 4), (72, 40, 27, 5), (203, 141, 37, 9), (130, 70, 45, 12),
     (200, 136, 22, 16), (96, 200, 12, 8),
+    (1, 1, 30, 2), (5, 3, 51, 3),  # pictures smaller than one unit; QP 51
 ])
 def test_subpel_matches_oracle(mr, W, H, qp, R):
     ref, cur = _pair(W * 3 + H + qp, W, H, 5, min(R, 12) + 1, 2)
