@@ -245,8 +245,10 @@ def main():
     try:
         import hashlib
         rec = json.load(open(os.path.join(ROOT, "profiles", "search_1080p_r64_traffic.json")))
-        src = open(os.path.join(ROOT, "paper_2301_12191_amd", "csrc", "mr_kernels.hip"), "rb").read()
-        if rec.get("kernels_source_sha256") == hashlib.sha256(src).hexdigest():
+        h = hashlib.sha256()
+        for f in rec["sources"]:  # every source the search kernel is compiled from
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if rec.get("sources_sha256") == h.hexdigest():
             traffic = rec["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
