@@ -96,6 +96,40 @@ def test_ladder_batch_equals_per_rung_launches(mr):
                 assert got[idx][k].ravel()[t] == exp[k].ravel()[t]
 
 
+def test_headline_batch_configuration_sampled(mr):
+    """The benchmark's launch: 8 consecutive 1920x1080 pairs (R 64, QP 27) in one recorded
+    batch, with the autotuner's shape installed, replayed twice; sampled CTUs of three pairs
+    (corners, edges, interior, the partial strip at the right edge) against the oracle."""
+    import torch
+    W, H, R, QP, NP = 1920, 1080, 64, 27, 8
+    scene = synth.Scene(synth.SEED_BASE + 1, W, H, 24, 48, 4)
+    host = [scene.render(t) for t in range(NP + 1)]
+    frames = [torch.from_numpy(f).cuda() for f in host]
+    jobs = [dict(cur=frames[k + 1], ref=frames[k], qp=QP, search_range=R) for k in range(NP)]
+    tune = mr.mr_autotune(jobs, reps=1)
+    try:
+        bt = mr.Batch(jobs)
+        try:
+            for _ in range(2):
+                outs = bt.launch()
+            got = [_np(o) for o in outs]
+        finally:
+            bt.close()
+    finally:
+        mr.mr_set_tiles(R, 0, 1)
+    print(f"\nheadline batch, tiles {tune}", flush=True)
+    ctus = [0, 29, 30, 58, 239, 255, 480, 509]  # 30 x 17 CTUs; strip 7 holds CTUs 28, 29
+    for k in (0, 3, 7):
+        exp = oracle.ctu_search(host[k + 1], host[k], QP, R, ctu_list=ctus)
+        tw = exp["cost"].shape[1]
+        for t in ctus:
+            cy, cx = (t // tw) * 8, (t % tw) * 8
+            for f in ("depth", "mode", "mv"):
+                assert np.array_equal(got[k][f][cy:cy + 8, cx:cx + 8], exp[f][cy:cy + 8, cx:cx + 8]), (k, t, f)
+            for f in ("cost", "dist", "bits"):
+                assert got[k][f].ravel()[t] == exp[f].ravel()[t], (k, t, f)
+
+
 def test_graph_replays_match_eager(mr):
     """Replay the captured graph several times with eager work and syncs in between."""
     import torch
