@@ -476,17 +476,21 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   // Neighbour arrays, one depth level at a time: the 256 threads split evenly
   // over the level's nodes (256, 64, 16 or 4 per node), so a thread's node and
   // its entries follow from its index; samples inside the CTU come from LDS.
+  // Planar and DC read p[-1][0..n] (entries 1 .. n + 1) and p[0..n][-1]
+  // (entries 2n + 1 .. 3n + 1) only, so just those 2n + 2 are computed: the
+  // closed form gives each one directly.
   const int stride = jb->stride;
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    const int n = kCtu >> d, len = 4 * n + 1, tpn = 256 >> (2 * d);
+    const int n = kCtu >> d, len = 2 * n + 2, tpn = 256 >> (2 * d);
     const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + (tid >> (8 - 2 * d));
     const int j = tid & (tpn - 1);
     if (sh.elig[node]) {
       const int x0 = sh.nx0[node], y0 = sh.ny0[node], a = sh.na[node], b = sh.nb[node];
       int16_t* R = sh.refs + ref_offset(node);
       int dcs = 0;
-      for (int off = j; off < len; off += tpn) {
+      for (int m = j; m < len; m += tpn) {
+        const int off = m <= n ? m + 1 : n + m;  // 1 .. n + 1, then 2n + 1 .. 3n + 1
         int v = 128;
         if (a <= b) {
           const int k = clampi(off <= 2 * n ? 2 * n - off : off, a, b);
