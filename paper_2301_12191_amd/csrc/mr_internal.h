@@ -31,12 +31,17 @@ __host__ __device__ inline int node_index(int d, int lx, int ly) {
 }
 
 // Per-job search layout.  The (2R+1)^2 window is covered by tasks of
-// 4 horizontal shifts (a quad) x D vertical shifts (a group); tasks are
-// grouped into wavefront steps of 64 and steps into dy bands.
+// 4 horizontal shifts (a quad) x D vertical shifts (a group), numbered group by
+// group (task t: group t / Q, quad t % Q); tasks are dealt to wavefront steps of
+// 64 in that order, and runs of whole steps form the dy bands.  When the task
+// count is one more than a multiple of 64 and the last task holds a single
+// candidate -- (dx, dy) = (R, R) -- that task is left out (one step less per
+// CTU) and the prep kernel seeds every CU's key with that candidate instead.
 struct SearchLayout {
   int32_t R, D, Q, G;           // range, group height, quads, groups
+  int32_t ntasks, corner;       // tasks searched; 1: the (R, R) task is left out
   int32_t nbands, total_steps;
-  int32_t band_g0[kMaxBands + 1];    // first group of each band (+ end)
+  int32_t band_g0[kMaxBands + 1];    // group of each band's first task
   int32_t band_step0[kMaxBands + 1]; // first global step of each band (+ end)
   int32_t win_rows_max, win_dwords;  // LDS window rows (largest band), dwords per row
 };
@@ -49,6 +54,8 @@ struct JobDesc {
   int32_t w, h, stride;
   int32_t w8, h8, ctus_w, ctus_h;
   int32_t R, D, Q, nbands;
+  int32_t ntasks;          // search tasks per CTU (see SearchLayout)
+  int32_t corner;          // 1: keys start at the (R, R) candidate's (prep kernel)
   int32_t win_dwords;      // LDS window row length in dwords: Q + 16 * strip
   int32_t strip;           // CTUs per search workgroup (one wavefront each)
   int32_t ctu_start;       // first flattened CTU index of this job in its batch

@@ -69,9 +69,16 @@ __device__ __forceinline__ uint32_t set_lane(uint32_t v, uint32_t u, int l) {
 
 // ---------------------------------------------------------------------------------- prep
 // One workgroup (256 threads) per CTU.
-__device__ void prep_ctu(cjob jb, int ctu) {
+__device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
   const int tid = threadIdx.x;
   const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
+  // With the (R, R) task left out of the search (see SearchLayout), every CU's
+  // key starts at that candidate's: csad[b] = its SAD on 8x8 block b (Z-order).
+  const bool corner = jb->corner != 0;  // uniform
+  if (corner) {
+    if (tid < 64) csad[tid] = 0;
+    __syncthreads();
+  }
   // 64 blocks x 16 dwords (row r, half c of block bz at dword bz * 16 + 2r + c).
   // Thread t reads dword t & 15 of CTU rows (t >> 4) + 16 i, i = 0..3, so a
   // wavefront reads 4 whole CTU rows: plain dword loads when the frame is
@@ -79,6 +86,8 @@ __device__ void prep_ctu(cjob jb, int ctu) {
   {
     uint32_t* dst = (uint32_t*)jb->curpack + (size_t)ctu * 1024;
     const int c16 = tid & 15, x0 = cx + 4 * c16;
+    const bool ref_fast = (((uintptr_t)jb->ref) & 3) == 0;
+    const uint32_t frame_bytes = (uint32_t)((jb->h - 1) * jb->stride + jb->w);
     const bool fast = ((jb->stride & 3) == 0) && ((((uintptr_t)jb->cur) & 3) == 0) &&
                       cx + 64 <= jb->w && cy + 64 <= jb->h;  // uniform
 #pragma unroll
@@ -97,8 +106,24 @@ __device__ void prep_ctu(cjob jb, int ctu) {
       const int bz = (bx & 1) | ((by & 1) << 1) | ((bx & 2) << 1) | ((by & 2) << 2) |
                      ((bx & 4) << 2) | ((by & 4) << 3);
       dst[bz * 16 + (ry & 7) * 2 + (c16 & 1)] = v;
+      if (corner) {
+        // Reference samples at (x + R, y + R), coordinates clamped to the picture.
+        const int R = jb->R, xr = x0 + R;
+        const uint32_t o = (uint32_t)(min(cy + ry + R, jb->h - 1) * jb->stride);
+        uint32_t rv;
+        if (ref_fast && xr + 3 < jb->w && o + (uint32_t)xr + 8u <= frame_bytes) {
+          const uint32_t* a = (const uint32_t*)(jb->ref + ((o + (uint32_t)xr) & ~3u));
+          rv = __builtin_amdgcn_alignbyte(a[1], a[0], (o + (uint32_t)xr) & 3u);
+        } else {
+          rv = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) rv |= (uint32_t)jb->ref[o + (uint32_t)min(xr + b, jb->w - 1)] << (8 * b);
+        }
+        atomicAdd(&csad[bz], __builtin_amdgcn_sad_u8(v, rv, 0u));
+      }
     }
   }
+  if (corner) __syncthreads();
   if (tid < kNodes) {
     const int d = tid == 0 ? 0 : tid < 5 ? 1 : tid < 21 ? 2 : 3;
     const int local = tid - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
@@ -121,7 +146,19 @@ __device__ void prep_ctu(cjob jb, int ctu) {
       }
     }
     jb->elig[(size_t)ctu * kNodes + tid] = e;
-    jb->keys[(size_t)ctu * kNodes + tid] = kKeyNone;
+    uint64_t key = kKeyNone;
+    if (corner) {
+      // The node's blocks are a Z-order run of 4^(3-d) blocks.
+      const int sh = 3 - d, cnt = 1 << (2 * sh);
+      const int z0 = ((lx << sh) & 1) | (((ly << sh) & 1) << 1) | (((lx << sh) & 2) << 1) |
+                     (((ly << sh) & 2) << 2) | (((lx << sh) & 4) << 2) | (((ly << sh) & 4) << 3);
+      uint32_t sad = 0;
+      for (int k = 0; k < cnt; ++k) sad += csad[z0 + k];
+      const int R = jb->R, span = 2 * R + 1;
+      const uint64_t J = (uint64_t)sad * 65536u + (uint64_t)jb->s * (uint64_t)(2 * se_bits_dev(4 * R));
+      key = (J << 17) | (uint64_t)(2 * R * span + 2 * R);  // raster index of (R, R)
+    }
+    jb->keys[(size_t)ctu * kNodes + tid] = key;
     // Eligibility as a bit mask: nodes 0..63 in the first wavefront, 64..84 in the second.
     const unsigned long long bits = __ballot(e != 0);
     if ((tid & 63) == 0) {
@@ -175,8 +212,8 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
                             uint32_t* ring) {
   const int lane = threadIdx.x & 63;
   const int Q = jb->Q, Wd = jb->win_dwords;
-  const int g0 = jb->band_g0[band], g1 = jb->band_g0[band + 1];
-  const int ntasks = (g1 - g0) * Q;
+  const int g0 = jb->band_g0[band];  // group of the band's first task: window row 0
+  const int ntasks = jb->ntasks;
   const int step0 = jb->band_step0[band];
   // Leaf-eligible nodes as an 85-bit mask in SGPRs (bit n of word n >> 5).
   const sptr32 eb = (sptr32)(jb->eligbits + (size_t)ctu * 4);
@@ -189,7 +226,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 
   for (int st = st_lo; st < st_hi; ++st) {
     const int gstep = step0 + st;
-    int task = st * kWaveSteps + lane;
+    int task = gstep * kWaveSteps + lane;
     if (task >= ntasks) task = ntasks - 1;  // idle lane: its table entries are invalid
     const int g = task / Q, qd = task - g * Q;
     uint32_t kq[D][4];
@@ -201,7 +238,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
         kq[j][0] = t.x, kq[j][1] = t.y, kq[j][2] = t.z, kq[j][3] = t.w;
       }
     }
-    const uint32_t* lbase = win + g * D * Wd + qd;
+    const uint32_t* lbase = win + (g - g0) * D * Wd + qd;
     uint32_t s16[D][4], s32[D][4], s64[D][4];
 #pragma unroll
     for (int j = 0; j < D; ++j)
@@ -741,8 +778,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_j
   const int flat = blockIdx.x;
   if (flat == 0 && threadIdx.x == 0) *counter = 0;  // work-queue head of the search kernel
   if (flat >= n_ctus) return;
+  __shared__ uint32_t csad[64];
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
-  prep_ctu(jobs + j, flat - jobs[j].ctu_start);
+  prep_ctu(jobs + j, flat - jobs[j].ctu_start, csad);
 }
 
 // Persistent search: each workgroup pops items until the queue is empty.  An
@@ -779,8 +817,10 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
       row = strip / spr, col0 = (strip % spr) * sw;
     }
     const cjob jb = jobs + job;
-    const int g0 = jb->band_g0[band], g1 = jb->band_g0[band + 1];
-    const int rows = (g1 - g0) * D + 63;
+    // Window rows of the groups the band's tasks touch.
+    const int g0 = jb->band_g0[band];
+    const int t_last = min(jb->band_step0[band + 1] * kWaveSteps, jb->ntasks) - 1;
+    const int rows = (t_last / jb->Q - g0 + 1) * D + 63;
     stage_window(jb, col0 * kCtu - jb->R, row * kCtu - jb->R + g0 * D, rows, win);
     __syncthreads();
     // This wavefront's current-CTU ring follows the largest window of the launch.

@@ -54,14 +54,25 @@ SearchLayout make_layout(int R, int D, int nbands) {
   L.D = D;
   L.Q = (span + 3) / 4;
   L.G = (span + D - 1) / D;
-  L.nbands = std::max(1, std::min(std::min(nbands, kMaxBands), L.G));
-  for (int b = 0; b <= L.nbands; ++b) L.band_g0[b] = (int)((int64_t)b * L.G / L.nbands);
-  for (int b = 0; b < L.nbands; ++b) {
-    const int B = L.band_g0[b + 1] - L.band_g0[b];
-    L.band_step0[b + 1] = L.band_step0[b] + (B * L.Q + kWaveSteps - 1) / kWaveSteps;
-    L.win_rows_max = std::max(L.win_rows_max, B * D + 63);
+  L.ntasks = L.Q * L.G;
+  // The last task is the one holding (R, R); it holds nothing else when 2R is a
+  // multiple of 4 and of D.  Leaving it out saves a step when it is alone in it.
+  if (R > 0 && (2 * R) % 4 == 0 && (2 * R) % D == 0 && L.ntasks % kWaveSteps == 1) {
+    L.corner = 1;
+    L.ntasks -= 1;
   }
-  L.total_steps = L.band_step0[L.nbands];
+  L.total_steps = (L.ntasks + kWaveSteps - 1) / kWaveSteps;
+  L.nbands = std::max(1, std::min(std::min(nbands, kMaxBands), L.total_steps));
+  for (int b = 0; b <= L.nbands; ++b)
+    L.band_step0[b] = (int)((int64_t)b * L.total_steps / L.nbands);
+  for (int b = 0; b < L.nbands; ++b) {
+    const int t0 = L.band_step0[b] * kWaveSteps;
+    const int t1 = std::min(L.band_step0[b + 1] * kWaveSteps, L.ntasks);
+    L.band_g0[b] = t0 / L.Q;
+    const int g_last = (t1 - 1) / L.Q;
+    L.win_rows_max = std::max(L.win_rows_max, (g_last - L.band_g0[b] + 1) * D + 63);
+  }
+  L.band_g0[L.nbands] = L.G;
   L.win_dwords = L.Q;  // + 16 * strip, added per job
   return L;
 }
@@ -72,11 +83,11 @@ size_t window_bytes(const SearchLayout& L, int strip) {
 
 int choose_bands(int R, int D, int strip, int ctus_w, int ctus_h, size_t lds_budget,
                  int min_items) {
-  const int span = 2 * R + 1, G = (span + D - 1) / D;
+  const int S = make_layout(R, D, 1).total_steps;
   int nb = 1;
-  while (nb < kMaxBands && nb < G && window_bytes(make_layout(R, D, nb), strip) > lds_budget) ++nb;
+  while (nb < kMaxBands && nb < S && window_bytes(make_layout(R, D, nb), strip) > lds_budget) ++nb;
   const int64_t strips = (int64_t)((ctus_w + strip - 1) / strip) * ctus_h;
-  while (min_items > 0 && nb < kMaxBands && strips * nb < min_items && (G + nb) / (nb + 1) >= 2)
+  while (min_items > 0 && nb < kMaxBands && strips * nb < min_items && (S + nb) / (nb + 1) >= 2)
     ++nb;
   return nb;
 }
@@ -88,10 +99,10 @@ static constexpr size_t kLdsBudget = 51 * 1024;
 // ----------------------------------------------------------------------- tables
 namespace {
 
-struct TableKey {
-  int device, qp, R, D, nbands;
+struct TableKey {  // the tables follow the global steps, whatever the band split
+  int device, qp, R, D;
   bool operator<(const TableKey& o) const {
-    return std::tie(device, qp, R, D, nbands) < std::tie(o.device, o.qp, o.R, o.D, o.nbands);
+    return std::tie(device, qp, R, D) < std::tie(o.device, o.qp, o.R, o.D);
   }
 };
 
@@ -116,22 +127,20 @@ void build_tables(int qp, const SearchLayout& L, std::vector<uint32_t>& q,
   dt.assign((size_t)L.total_steps * 2048, 0);
   std::vector<Cand> valid;
   std::vector<int> invalid;
-  for (int b = 0; b < L.nbands; ++b) {
-    const int g0 = L.band_g0[b], ntasks = (L.band_g0[b + 1] - g0) * L.Q;
-    for (int st = 0; st < L.band_step0[b + 1] - L.band_step0[b]; ++st) {
-      const int gstep = L.band_step0[b] + st;
+  {
+    for (int gstep = 0; gstep < L.total_steps; ++gstep) {
       valid.clear();
       invalid.clear();
       for (int lane = 0; lane < kWaveSteps; ++lane) {
-        const int task = st * kWaveSteps + lane;
+        const int task = gstep * kWaveSteps + lane;
         for (int j = 0; j < D; ++j)
           for (int k = 0; k < 4; ++k) {
             const int slot = lane * per_lane + j * 4 + k;
-            bool ok = task < ntasks;
+            bool ok = task < L.ntasks;
             int dx = 0, dy = 0;
             if (ok) {
               const int g = task / L.Q, qd = task % L.Q;
-              dy = -R + (g0 + g) * D + j;
+              dy = -R + g * D + j;
               dx = -R + 4 * qd + k;
               ok = dy <= R && dx <= R;
             }
@@ -165,7 +174,7 @@ void build_tables(int qp, const SearchLayout& L, std::vector<uint32_t>& q,
 int get_key_tables(int qp, const SearchLayout& L, KeyTables* out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MR_EHIP;
-  const TableKey key{dev, qp, L.R, L.D, L.nbands};
+  const TableKey key{dev, qp, L.R, L.D};
   std::lock_guard<std::mutex> lk(g_tab_mu);
   auto it = g_tables.find(key);
   if (it != g_tables.end()) {
@@ -372,6 +381,8 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     if (rc != MR_OK) return rc;
     jb.D = P->D;
     jb.Q = L.Q;
+    jb.ntasks = L.ntasks;
+    jb.corner = L.corner;
     jb.nbands = L.nbands;
     jb.strip = P->strip;
     jb.win_dwords = L.Q + 16 * P->strip;
