@@ -233,6 +233,23 @@ def test_partial_strips_bit_exact(mr, W, R, strip, nb):
     _compare(got, oracle.ctu_search(cur, ref, qp, R), W, H, label=f"W{W} R{R} strip{strip} nb{nb}")
 
 
+@pytest.mark.parametrize("W,H,R,qp,bounded", [
+    (200, 136, 64, 27, False), (136, 72, 60, 33, False), (203, 141, 64, 22, True),
+])
+def test_corner_candidate_left_to_prep_bit_exact(mr, W, H, R, qp, bounded):
+    """Ranges whose last search task holds only (R, R) (R 60, 64: 31^2 and 33^2 tasks, one more
+    than a multiple of 64): that candidate comes from the prep kernel's initial keys. Every
+    output, ragged frames whose windows reach past the picture, with and without bounds."""
+    ref, cur = _pair(0x6000 + W + R, W, H, 6, 40, 3)
+    b = None
+    if bounded:
+        rng = np.random.default_rng(R)
+        lo = rng.integers(0, 3, size=((H + 7) // 8, (W + 7) // 8)).astype(np.uint8)
+        b = np.stack([lo, np.minimum(lo + 1, 3)], -1)
+    _compare(_gpu(mr, cur, ref, qp, R, bounds=b), oracle.ctu_search(cur, ref, qp, R, bounds=b),
+             W, H, label=f"{W}x{H} R{R}")
+
+
 def test_padded_stride_and_unaligned_pointer(mr):
     """Frames inside larger buffers: stride > width and a base address not 4-byte aligned
     (the window staging falls back to byte loads); results equal the packed frames'."""
