@@ -557,6 +557,23 @@ def main():
         cpu = {"value": round(n / dt, 3), "unit": "CTUs/s", "cores": threads, "kind": "oracle",
                "sample": f"first {n} CTUs (raster order) of one 1920x1080 pair, R 64, QP 27; "
                          f"{dt:.1f} s"}
+        # The host, and the oracle on one thread over the whole small pair (416x240, R 16).
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f
+                              if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        small = synth.Scene(synth.SEED_BASE + 0, 416, 240, 6, 12, 0)
+        s0, s1 = small.render(0), small.render(1)
+        ta = time.perf_counter()
+        out = oracle.ctu_search(s1, s0, 32, 16, n_threads=1)
+        dt1 = time.perf_counter() - ta
+        cpu["host"] = {"cpu_model": model, "logical_cpus": os.cpu_count()}
+        cpu["one_thread_small"] = {"workload": "416x240 pair, R 16, QP 32 (28 CTUs)",
+                                   "ctus_per_s": round(out["cost"].size / dt1, 3),
+                                   "seconds": round(dt1, 3)}
 
     line = {
         "metric": "CTUs/s full vs ref-pruned CU search (bit-exact); p50/p99 frame latency",
