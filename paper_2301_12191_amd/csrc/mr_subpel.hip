@@ -44,6 +44,16 @@ __device__ __forceinline__ int dot2(uint32_t a, uint32_t b, int c) {
                                 c, false);
 }
 
+// The first product of a dot-product chain, with an inline-constant
+// accumulator in the three-operand encoding: the builtins select the
+// two-operand form, whose accumulator is its destination, and copy the
+// constant into it first.
+__device__ __forceinline__ int dot4_plus32(uint32_t a, uint32_t b) {
+  int r;
+  asm("v_dot4_i32_i8 %0, %1, %2, 32" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Sum over the aligned group of 4^(4-d) tiles of CU depth d (d >= 1: inside one
 // wavefront; d = 0: the whole workgroup through red[]).  Every lane of a group
 // receives the sum.
@@ -72,16 +82,16 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
   const int R = jb->R, span = 2 * R + 1;
   const uint64_t s = (uint64_t)jb->s;
   // Current tile (coded picture) from the packed CTU: block t >> 2, rows
-  // (t >> 1 & 1) * 4 + i, dword t & 1.
+  // (t >> 1 & 1) * 4 + i, dword t & 1; as sample - 128, like the predictions.
   int c[16];
   {
     const uint32_t* cp = jb->curpack + (size_t)ctu * 1024 + (t >> 2) * 16 + ((t >> 1) & 1) * 8 +
                          (t & 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const uint32_t w = cp[2 * i];
+      const uint32_t w = cp[2 * i] ^ 0x80808080u;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) c[4 * i + k] = (int)((w >> (8 * k)) & 0xFF);
+      for (int k = 0; k < 4; ++k) c[4 * i + k] = (int)(int8_t)((w >> (8 * k)) & 0xFF);
     }
   }
   const int pitch = jb->pad_pitch;
@@ -126,20 +136,27 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
         // Horizontal pass: h[r][k] for patch rows r = 0..11, tile columns k,
         // taps at patch bytes k + f + 1 .. k + f + 8; packed as 16-bit pairs of
         // consecutive rows Q[r][k] = (h[r][k], h[r + 1][k]).
+        //
+        // Offsets.  With samples as (sample - 128) each sum is the plain
+        // H.265 sum minus 128 * 64; it carries + 32 instead.  Every vertical
+        // filter's taps sum to 64, so the vertical sum is the plain one minus
+        // 128 * 4096 plus 2048, and the prediction (plain + 2048) >> 12 is that
+        // sum >> 12, plus 128.  The horizontal chains start from 32 and the
+        // vertical ones from 0, both inline constants.
+        const int o = f + 1;  // first tap of column 0 at patch byte o (0 or 1, per lane)
         uint32_t Q[12][4];  // Q[11] = (h[11], 0) pads the vertical window
         int hprev[4];
 #pragma unroll
         for (int r = 0; r < 12; ++r) {
+          // Patch row r from byte o on: a0 = bytes 0..3, a1 = 4..7, a2 = 8..10 (+1 unused).
+          const uint32_t a0 = __builtin_amdgcn_alignbyte(P[r][1], P[r][0], o);
+          const uint32_t a1 = __builtin_amdgcn_alignbyte(P[r][2], P[r][1], o);
+          const uint32_t a2 = __builtin_amdgcn_alignbyte(P[r][2], P[r][2], o);
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            const int sbyte = k + f + 1;  // 0..4
-            const uint32_t lo = sbyte == 4 ? P[r][1] : __builtin_amdgcn_alignbyte(P[r][1], P[r][0], sbyte);
-            const uint32_t hi = sbyte == 4 ? P[r][2] : __builtin_amdgcn_alignbyte(P[r][2], P[r][1], sbyte);
-            // sum of taps * (sample - 128), plus 128 * 64 for the offset (the
-            // first dot product's initial accumulator)
-            const int h = __builtin_amdgcn_sdot4((int)lo, (int)tlo,
-                                                 __builtin_amdgcn_sdot4((int)hi, (int)thi, 8192, false),
-                                                 false);
+            const uint32_t lo = k == 0 ? a0 : __builtin_amdgcn_alignbyte(a1, a0, k);
+            const uint32_t hi = k == 0 ? a1 : __builtin_amdgcn_alignbyte(a2, a1, k);
+            const int h = __builtin_amdgcn_sdot4((int)lo, (int)tlo, dot4_plus32(hi, thi), false);
             // (low halves of) hprev | h << 16 in one v_perm_b32
             if (r > 0) Q[r - 1][k] = __builtin_amdgcn_perm((uint32_t)h, (uint32_t)hprev[k], 0x05040100u);
             hprev[k] = h;
@@ -166,11 +183,12 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
           for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-              // (v >> 6) + 32 >> 6 == (v + 2048) >> 12 (arithmetic shifts)
-              int v = 2048;
+              // ((v >> 6) + 32) >> 6 == (v + 2048) >> 12 for the plain sum v
+              // (arithmetic shifts); here (v' >> 12) is that minus 128.
+              int v = 0;
 #pragma unroll
               for (int p = 0; p < 5; ++p) v = dot2(Q[i + 2 * p][k], tw[p], v);
-              const int pred = clampi(v >> 12, 0, 255);
+              const int pred = clampi(v >> 12, -128, 127);  // prediction - 128
               resid[4 * i + k] = c[4 * i + k] - pred;
             }
           }
