@@ -172,8 +172,11 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
 
 // -------------------------------------------------------------------------------- search
 // Stage rows [y0, y0 + rows) x dword columns [0, Wd) of the reference, with
-// coordinates clamped to the picture, into the LDS window (x origin x0).
-__device__ void stage_window(cjob jb, int x0, int y0, int rows, uint32_t* win) {
+// coordinates clamped to the picture, into the LDS window (x origin x0).  The
+// window is column-major with an odd pitch hs: dword column c, row r at
+// c * hs + r, so the rows a search lane walks are immediate offsets of its
+// column addresses, and lanes on consecutive columns hit distinct banks.
+__device__ void stage_window(cjob jb, int x0, int y0, int rows, int hs, uint32_t* win) {
   const int Wd = jb->win_dwords, w = jb->w, h = jb->h, stride = jb->stride;
   const uint8_t* ref = jb->ref;
   const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0) && ((x0 & 3) == 0);
@@ -190,7 +193,7 @@ __device__ void stage_window(cjob jb, int x0, int y0, int rows, uint32_t* win) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[clampi(x + b, 0, w - 1)] << (8 * b);
     }
-    win[i] = v;
+    win[(i - row * Wd) * hs + row] = v;
   }
 }
 
@@ -204,14 +207,14 @@ __device__ __forceinline__ void merge_keys(uint32_t vk, const uint64_t* __restri
 }
 
 // One wavefront: steps [st_lo, st_hi) of one (CTU, band); `win` points at
-// this CTU's column 0 of the staged window (dx = -R); `ring` is this
-// wavefront's 512-byte LDS ring for the current CTU (two 16x16 regions of 64
-// dwords).
+// this CTU's column 0 of the staged window (dx = -R), whose dword columns are
+// hs apart; `ring` is this wavefront's 512-byte LDS ring for the current CTU
+// (two 16x16 regions of 64 dwords).
 template <int D>
 __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, const uint32_t* win,
-                            uint32_t* ring) {
+                            int hs, uint32_t* ring) {
   const int lane = threadIdx.x & 63;
-  const int Q = jb->Q, Wd = jb->win_dwords;
+  const int Q = jb->Q;
   const int g0 = jb->band_g0[band];  // group of the band's first task: window row 0
   const int ntasks = jb->ntasks;
   const int step0 = jb->band_step0[band];
@@ -238,7 +241,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
         kq[j][0] = t.x, kq[j][1] = t.y, kq[j][2] = t.z, kq[j][3] = t.w;
       }
     }
-    const uint32_t* lbase = win + (g - g0) * D * Wd + qd;
+    const uint32_t* lbase = win + qd * hs + (g - g0) * D;  // row dy of window column qd
     uint32_t s16[D][4], s32[D][4], s64[D][4];
 #pragma unroll
     for (int j = 0; j < D; ++j)
@@ -253,6 +256,13 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
     for (int reg = 0; reg < 16; ++reg) {
       const uint32_t* rcur = ring + (reg & 1) * 64;
       uint32_t m8[4];  // per-lane minimum key of each 8x8 block of the region
+      // The region's window columns 4 zx(reg) + 0..4 from row 16 zy(reg): the
+      // left blocks read columns 0..2, the right ones 2..4, the lower ones 8
+      // rows further down (immediate offsets).
+      const uint32_t* cb[5];
+      cb[0] = lbase + 4 * zx(reg) * hs + 16 * zy(reg);
+#pragma unroll
+      for (int m = 1; m < 5; ++m) cb[m] = cb[m - 1] + hs;
 #pragma unroll
       for (int sub = 0; sub < 4; ++sub) {
         const int bz = reg * 4 + sub;
@@ -271,16 +281,17 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
         for (int j = 0; j < D; ++j)
 #pragma unroll
           for (int k = 0; k < 4; ++k) acc[j][k] = 0;
-        const uint32_t* rb = lbase + by * 8 * Wd + 2 * bx;
+        const uint32_t *c0 = cb[2 * (sub & 1)], *c1 = cb[2 * (sub & 1) + 1],
+                       *c2 = cb[2 * (sub & 1) + 2];
+        const int r0 = 8 * (sub >> 1);
         // Window rows are loaded one row ahead of their use, so each row's LDS
         // latency overlaps the previous row's SADs.
-        uint32_t n0 = rb[0], n1 = rb[1], n2 = rb[2];
+        uint32_t n0 = c0[r0], n1 = c1[r0], n2 = c2[r0];
 #pragma unroll
         for (int w = 0; w < D + 7; ++w) {
           const uint32_t d0 = n0, d1 = n1, d2 = n2;
           if (w + 1 < D + 7) {
-            const uint32_t* np = rb + (w + 1) * Wd;
-            n0 = np[0], n1 = np[1], n2 = np[2];
+            n0 = c0[r0 + w + 1], n1 = c1[r0 + w + 1], n2 = c2[r0 + w + 1];
           }
           __builtin_amdgcn_sched_barrier(0);
           uint32_t a0[4], a1[4];
@@ -821,7 +832,8 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
     const int g0 = jb->band_g0[band];
     const int t_last = min(jb->band_step0[band + 1] * kWaveSteps, jb->ntasks) - 1;
     const int rows = (t_last / jb->Q - g0 + 1) * D + 63;
-    stage_window(jb, col0 * kCtu - jb->R, row * kCtu - jb->R + g0 * D, rows, win);
+    const int hs = rows | 1;
+    stage_window(jb, col0 * kCtu - jb->R, row * kCtu - jb->R + g0 * D, rows, hs, win);
     __syncthreads();
     // This wavefront's current-CTU ring follows the largest window of the launch.
     uint32_t* ring = win + win_dwords_max + wave * (kCurRingBytes / 4);
@@ -831,7 +843,7 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
     const int hi = (wave + 1) * sw * nst / nw;
     while (lo < hi) {
       const int c = lo / nst, s0 = lo - c * nst, s1 = min(nst, s0 + (hi - lo));
-      search_wave<D>(jb, row * jb->ctus_w + col0 + c, band, s0, s1, win + 16 * c, ring);
+      search_wave<D>(jb, row * jb->ctus_w + col0 + c, band, s0, s1, win + 16 * c * hs, hs, ring);
       lo += s1 - s0;
     }
     __syncthreads();  // the window is restaged for the next item

@@ -77,8 +77,9 @@ SearchLayout make_layout(int R, int D, int nbands) {
   return L;
 }
 
+// The window is column-major with an odd pitch of (rows | 1) dwords.
 size_t window_bytes(const SearchLayout& L, int strip) {
-  return (size_t)L.win_rows_max * (L.Q + 16 * strip) * 4 + (size_t)kCurRingBytes * strip;
+  return (size_t)(L.win_rows_max | 1) * (L.Q + 16 * strip) * 4 + (size_t)kCurRingBytes * strip;
 }
 
 int choose_bands(int R, int D, int strip, int ctus_w, int ctus_h, size_t lds_budget,
