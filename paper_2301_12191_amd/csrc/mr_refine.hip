@@ -285,9 +285,21 @@ __device__ __forceinline__ void refine_body(const JobDesc* jobs_, const int* rli
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
   // eighth of the (CTU, depth) list so that its L2 holds one band of the
   // frames.  (A bijection on [0, gridDim.x) whatever the dispatch order.)
+  // Within its eighth an XCD runs the depth-0 items first and the depth-3
+  // items last: a 64x64 CU's cross-lane sums make its wavefront the longest,
+  // an 8x8 CU's the shortest, and the last of about three rounds of
+  // wavefronts per slot is only partly full.
   const int gx = gridDim.x, x = blockIdx.x;
   const int q = gx >> 3, rm = gx & 7, xcd = x & 7, k = x >> 3;
-  const int lin = xcd * q + min(xcd, rm) + k;
+  const int a = xcd * q + min(xcd, rm), len = q + (xcd < rm ? 1 : 0);  // this XCD's range
+  int lin = a, rest = k;
+#pragma unroll
+  for (int dd = 0; dd < 4; ++dd) {
+    const int first = a + ((dd - a) & 3);  // first index >= a of depth dd
+    const int cnt = first < a + len ? (a + len - first + 3) >> 2 : 0;
+    if (rest >= 0 && rest < cnt) lin = first + 4 * rest;
+    rest -= cnt;
+  }
   const int flat = lin >> 2, d = lin & 3;
   if (flat >= n_rctus) return;
   const int j = __builtin_amdgcn_readfirstlane(find_rjob(jobs, rlist, n_rjobs, flat));
