@@ -243,33 +243,36 @@ __device__ int find_rjob(cjob jobs, const int* rlist, int n_rjobs, int flat) {
   return rlist[lo];
 }
 
-// Padded reference of every job that has one (seeded or sub-pel): grid-stride
-// over those jobs in y and over each job's [h8 + 2 pad_y][pad_pitch] bytes, in
-// dwords, in x.
+// Padded reference of every job that has one (seeded or sub-pel): jobs in y,
+// rows of each job's [h8 + 2 pad_y][pad_pitch] bytes grid-strided in x, and
+// 8-byte pieces of a row over the threads (pad_pitch is a multiple of 8).
 __global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const int* plist,
                                                   int n_pjobs) {
   for (int k = blockIdx.y; k < n_pjobs; k += gridDim.y) {
     const cjob jb = (cjob)jobs_ + (plist ? plist[k] : 0);
     const int PY = jb->pad_y, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
-    const int dw = jb->pad_pitch >> 2;
-    const int64_t total = (int64_t)(jb->h8 + 2 * PY) * dw;
+    const int pitch = jb->pad_pitch, rows = jb->h8 + 2 * PY, pieces = pitch >> 3;
     const uint8_t* ref = jb->ref;
     const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0);
-    uint32_t* dst = (uint32_t*)jb->refpad;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-      const int row = (int)(i / dw), c = (int)(i - (int64_t)row * dw);
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
       const uint8_t* rp = ref + (size_t)clampi(row - PY, 0, h - 1) * stride;
-      const int x = 4 * c - P;
-      uint32_t v;
-      if (dword_ok && x >= 0 && x + 3 < w) {
-        v = *(const uint32_t*)(rp + x);
-      } else {
-        v = 0;
+      uint2* dst = (uint2*)(jb->refpad + (size_t)row * pitch);
+      for (int c = threadIdx.x; c < pieces; c += blockDim.x) {
+        uint32_t v[2];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[clampi(x + b, 0, w - 1)] << (8 * b);
+        for (int half = 0; half < 2; ++half) {
+          const int x = 8 * c + 4 * half - P;
+          if (dword_ok && x >= 0 && x + 3 < w) {
+            v[half] = *(const uint32_t*)(rp + x);
+          } else {
+            uint32_t u = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) u |= (uint32_t)rp[clampi(x + b, 0, w - 1)] << (8 * b);
+            v[half] = u;
+          }
+        }
+        dst[c] = make_uint2(v[0], v[1]);
       }
-      dst[i] = v;
     }
   }
 }
@@ -319,10 +322,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
   refine_body<2>(jobs_, rlist, n_rjobs, n_rctus);
 }
 
-hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int64_t max_dwords,
+hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int max_rows,
                       hipStream_t st) {
-  const int64_t blocks = std::min<int64_t>((max_dwords + 255) / 256, 2048);
-  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1),
+  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)std::max(1, std::min(max_rows, 65535)),
                                       (unsigned)std::min(n_pjobs, 65535)),
                      dim3(256), 0, st, jobs, plist, n_pjobs);
   return hipGetLastError();

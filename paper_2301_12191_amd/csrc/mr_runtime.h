@@ -54,12 +54,11 @@ struct Plan {
   std::vector<size_t> job_off;        // per-job scratch offset
   size_t scratch_bytes = 0;           // per-job scratch total (curpack, keys, elig, refpad)
   // Seeded jobs (refinement) in rctu_start order, sub-pel jobs in sctu_start
-  // order, jobs with a padded reference (seeded or sub-pel); largest padded
-  // reference in dwords.
+  // order, jobs with a padded reference (seeded or sub-pel).
   std::vector<int> rlist, slist, plist;
   int n_rjobs = 0, n_rctus = 0, max_r = 0;
   int n_sjobs = 0, n_sctus = 0;
-  int64_t max_pad_dwords = 0;
+  int max_pad_rows = 0;  // rows of the largest padded reference
 };
 
 // Build a plan.  seeds: null, or per job a seed (null entry = full search);
@@ -101,7 +100,7 @@ hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* co
 hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, int D, int strip,
                          int n_wg, size_t lds_bytes, uint32_t* counter, hipStream_t st);
 hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st);
-hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int64_t max_dwords,
+hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int max_rows,
                       hipStream_t st);
 hipError_t launch_subpel(const JobDesc* jobs, const int* slist, int n_sjobs, int n_sctus,
                          hipStream_t st);
