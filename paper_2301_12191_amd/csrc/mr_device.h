@@ -33,6 +33,10 @@ __device__ __forceinline__ uint32_t add_dpp(uint32_t v) {
   return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
+// max(|a|, |b|) = max(a, b, -a, -b) = max(a, b, -min(a, b)): a min, a
+// negation and a three-input max instead of two absolute values and a max.
+__device__ __forceinline__ int max_abs2(int a, int b) { return max(max(a, b), -min(a, b)); }
+
 // SATD of a 4x4 residual: sum |H d H^T| / 2 via butterflies.  The last
 // column stage is folded into |x + y| + |x - y| = 2 max(|x|, |y|).
 __device__ __forceinline__ uint32_t satd4x4(const int d[16]) {
@@ -48,7 +52,7 @@ __device__ __forceinline__ uint32_t satd4x4(const int d[16]) {
   for (int j = 0; j < 4; ++j) {  // columns
     const int a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
     const int a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
-    s += max(abs(a0), abs(a2)) + max(abs(a1), abs(a3));
+    s += max_abs2(a0, a2) + max_abs2(a1, a3);
   }
   return s;
 }
@@ -60,7 +64,12 @@ __device__ __forceinline__ uint32_t satd4x4(const int d[16]) {
 // each half's result within 16320.
 typedef short sh2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ sh2 pk_abs(sh2 x) { return __builtin_elementwise_max(x, (sh2)(0) - x); }
+// max(|a|, |b|) per 16-bit half, as max(max(a, b), -min(a, b)): four packed
+// operations instead of five.
+__device__ __forceinline__ sh2 pk_max_abs2(sh2 a, sh2 b) {
+  return __builtin_elementwise_max(__builtin_elementwise_max(a, b),
+                                   (sh2)(0) - __builtin_elementwise_min(a, b));
+}
 
 __device__ __forceinline__ uint32_t satd4x4_pair(const sh2 d[16]) {
   sh2 t[16];
@@ -75,8 +84,7 @@ __device__ __forceinline__ uint32_t satd4x4_pair(const sh2 d[16]) {
   for (int j = 0; j < 4; ++j) {  // columns
     const sh2 a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
     const sh2 a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
-    s += __builtin_elementwise_max(pk_abs(a0), pk_abs(a2)) +
-         __builtin_elementwise_max(pk_abs(a1), pk_abs(a3));
+    s += pk_max_abs2(a0, a2) + pk_max_abs2(a1, a3);
   }
   return __builtin_bit_cast(uint32_t, s);  // low half: d.x residual, high half: d.y
 }
@@ -96,7 +104,7 @@ __device__ __forceinline__ int hadamard_abs_sum(const int c[16], int& S) {
   for (int j = 0; j < 4; ++j) {
     const int a0 = t[j] + t[4 + j], a1 = t[j] - t[4 + j];
     const int a2 = t[8 + j] + t[12 + j], a3 = t[8 + j] - t[12 + j];
-    m += max(abs(a0), abs(a2)) + max(abs(a1), abs(a3));
+    m += max_abs2(a0, a2) + max_abs2(a1, a3);
     if (j == 0) S = a0 + a2;
   }
   return 2 * m;
