@@ -155,7 +155,7 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   for (int k = 0; k < NP; ++k) {
     const int p = pass * NP + k;  // window column of position k (valid: 0..2r)
     const int dx = cxm - r + p;
-    Ts[k][b] = p < ncand ? ((uint64_t)(s * se_len(4 * dx)) << 17) + (uint64_t)(dx + R)
+    Ts[k][b] = p < ncand ? ((uint64_t)__umul24(s, se_len(4 * dx)) << 17) + (uint64_t)(dx + R)
                          : (1ull << 62);
   }
   const uint32_t* src = (const uint32_t*)(jb->refpad +
@@ -193,32 +193,30 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
 #pragma unroll
       for (int row = 0; row < 8; ++row) {
         const int sl = (u + row) & 7;
+        // Every position, also past the window in a partial last pass: its
+        // samples are inside the padded reference and its key term is 2^62.
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          if (4 * q < rem) {
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
-              acc[4 * q + o] = __builtin_amdgcn_sad_u8(c[2 * row], S[sl][o][q], acc[4 * q + o]);
-              acc[4 * q + o] =
-                  __builtin_amdgcn_sad_u8(c[2 * row + 1], S[sl][o][q + 1], acc[4 * q + o]);
-            }
+          for (int o = 0; o < 4; ++o) {
+            acc[4 * q + o] = __builtin_amdgcn_sad_u8(c[2 * row], S[sl][o][q], acc[4 * q + o]);
+            acc[4 * q + o] =
+                __builtin_amdgcn_sad_u8(c[2 * row + 1], S[sl][o][q + 1], acc[4 * q + o]);
           }
         }
-        if (4 * NQ < rem) {
-          acc[4 * NQ] = __builtin_amdgcn_sad_u8(c[2 * row], S[sl][0][NQ], acc[4 * NQ]);
-          acc[4 * NQ] = __builtin_amdgcn_sad_u8(c[2 * row + 1], X[sl], acc[4 * NQ]);
-        }
+        acc[4 * NQ] = __builtin_amdgcn_sad_u8(c[2 * row], S[sl][0][NQ], acc[4 * NQ]);
+        acc[4 * NQ] = __builtin_amdgcn_sad_u8(c[2 * row + 1], X[sl], acc[4 * NQ]);
       }
       group_sums<NP>(acc, d);
       uint64_t rb = kKeyNone;
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
-        if (k < rem) {
-          const uint64_t key = Ts[k][b] + ((uint64_t)acc[k] << 33);
-          rb = key < rb ? key : rb;
-        }
+        const uint64_t key = Ts[k][b] + ((uint64_t)acc[k] << 33);  // >= 2^62 past the window
+        rb = key < rb ? key : rb;
       }
-      const uint64_t U = ((uint64_t)(s * se_len(4 * dy)) << 17) + (uint64_t)((dy + R) * span);
+      // s < 2^23 and se <= 21, (dy + R) and span <= 257: 24-bit products.
+      const uint64_t U = ((uint64_t)__umul24(s, se_len(4 * dy)) << 17) +
+                         (uint64_t)__umul24((uint32_t)(dy + R), (uint32_t)span);
       rb += U;
       best = rb < best ? rb : best;
       if (more) shifts<NQ>(nxt, shb, S[u], X[u]);
