@@ -30,11 +30,13 @@ __device__ __forceinline__ uint32_t taps8_lo(int ph) {
 __device__ __forceinline__ uint32_t taps8_hi(int ph) {
   return ph == 0 ? 0x00000000u : ph == 1 ? 0x0001FB11u : ph == 2 ? 0xFF04F528u : 0xFF04F63Au;
 }
-// Taps of phase ph as signed 16-bit pairs (2p, 2p + 1), p = 0..3.
+// Taps of phase ph times 16 as signed 16-bit pairs (2p, 2p + 1), p = 0..3: a
+// vertical sum then carries its prediction in its high 16 bits ((16 v) >> 16
+// == v >> 12), where one v_perm_b32 packs two candidates' predictions.
 __device__ __forceinline__ uint32_t taps16(int ph, int p) {
   const int t0 = (int)(int8_t)(((p < 2 ? taps8_lo(ph) : taps8_hi(ph)) >> (16 * (p & 1))) & 0xFF);
   const int t1 = (int)(int8_t)(((p < 2 ? taps8_lo(ph) : taps8_hi(ph)) >> (16 * (p & 1) + 8)) & 0xFF);
-  return ((uint32_t)t0 & 0xFFFFu) | ((uint32_t)t1 << 16);
+  return ((uint32_t)(16 * t0) & 0xFFFFu) | ((uint32_t)(16 * t1) << 16);
 }
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
@@ -82,8 +84,9 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
   const int R = jb->R, span = 2 * R + 1;
   const uint64_t s = (uint64_t)jb->s;
   // Current tile (coded picture) from the packed CTU: block t >> 2, rows
-  // (t >> 1 & 1) * 4 + i, dword t & 1; as sample - 128, like the predictions.
-  int c[16];
+  // (t >> 1 & 1) * 4 + i, dword t & 1; as sample - 128, like the predictions,
+  // in both 16-bit halves (c2) for the packed residuals of two candidates.
+  uint32_t c2[16];
   {
     const uint32_t* cp = jb->curpack + (size_t)ctu * 1024 + (t >> 2) * 16 + ((t >> 1) & 1) * 8 +
                          (t & 1);
@@ -91,7 +94,8 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
     for (int i = 0; i < 4; ++i) {
       const uint32_t w = cp[2 * i] ^ 0x80808080u;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) c[4 * i + k] = (int)(int8_t)((w >> (8 * k)) & 0xFF);
+      for (int k = 0; k < 4; ++k)
+        c2[4 * i + k] = ((uint32_t)(int)(int8_t)((w >> (8 * k)) & 0xFF) & 0xFFFFu) * 0x10001u;
     }
   }
   const int pitch = jb->pad_pitch;
@@ -164,46 +168,49 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) Q[11][k] = (uint32_t)hprev[k] & 0xFFFFu;
-        // Vertical pass of candidate row iy (qy = cqy + step (iy - 1)): the
-        // residual of each tile sample.
-        auto residual = [&](int iy, int resid[16]) {
+        // Vertical pass of candidate row iy (qy = cqy + step (iy - 1)): its
+        // per-lane taps, then per tile sample a sum v, 16 times the plain H.265
+        // sum minus 128 * 4096 plus 2048, so that v >> 16 is the prediction -
+        // 128 before clipping (((v >> 6) + 32) >> 6 == (v + 2048) >> 12 for the
+        // plain sum, arithmetic shifts).
+        auto vtaps = [&](int iy, uint32_t tw[5]) {
           const int qy = cqy + step * (iy - 1);
           const int fy = qy & 3, g = ((qy - fy) >> 2) - my;  // g in {-1, 0}
           // Filter tap j applies to patch row i + g + 1 + j.  Over the window
           // of rows i .. i + 9 (pairs Q[i + 2p], p = 0..4) that is window tap
           // j + g + 1: the taps move by one row for g = 0 instead of the rows.
-          uint32_t tw[5], prev = 0;
+          uint32_t prev = 0;
 #pragma unroll
           for (int p = 0; p < 5; ++p) {
             const uint32_t cur = p < 4 ? taps16(fy, p) : 0u;
             tw[p] = g == 0 ? __builtin_amdgcn_alignbyte(cur, prev, 2) : cur;
             prev = cur;
           }
+        };
+        auto vsum = [&](const uint32_t tw[5], int i, int k) {
+          int v = 0;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              // ((v >> 6) + 32) >> 6 == (v + 2048) >> 12 for the plain sum v
-              // (arithmetic shifts); here (v' >> 12) is that minus 128.
-              int v = 0;
-#pragma unroll
-              for (int p = 0; p < 5; ++p) v = dot2(Q[i + 2 * p][k], tw[p], v);
-              const int pred = clampi(v >> 12, -128, 127);  // prediction - 128
-              resid[4 * i + k] = c[4 * i + k] - pred;
-            }
-          }
+          for (int p = 0; p < 5; ++p) v = dot2(Q[i + 2 * p][k], tw[p], v);
+          return v;
         };
         // The quarter-pel stage's centre is the half-pel stage's best, whose
         // SATD is already known.  The first two candidates of the column share
         // one packed 16-bit transform.
         const bool centre_known = step == 1 && ix == 1;
         {
-          int ra[16], rb[16];
-          residual(0, ra);
-          residual(centre_known ? 2 : 1, rb);
+          uint32_t ta[5], tb[5];
+          vtaps(0, ta);
+          vtaps(centre_known ? 2 : 1, tb);
           sh2 pr[16];
 #pragma unroll
-          for (int i = 0; i < 16; ++i) pr[i] = (sh2){(short)ra[i], (short)rb[i]};
+          for (int i = 0; i < 16; ++i) {
+            const int va = vsum(ta, i >> 2, i & 3), vb = vsum(tb, i >> 2, i & 3);
+            // (va >> 16, vb >> 16) as 16-bit halves, clipped, subtracted from the sample
+            sh2 p = __builtin_bit_cast(sh2, __builtin_amdgcn_perm((uint32_t)vb, (uint32_t)va,
+                                                                  0x07060302u));
+            p = __builtin_elementwise_min(__builtin_elementwise_max(p, (sh2)(-128)), (sh2)(127));
+            pr[i] = __builtin_bit_cast(sh2, c2[i]) - p;
+          }
           const uint32_t pk = satd4x4_pair(pr);
           sat[ix] = pk & 0xFFFFu;
           if (centre_known) sat[6 + ix] = pk >> 16;
@@ -212,8 +219,12 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
         if (centre_known) {
           sat[4] = csatd_tile;
         } else {
+          uint32_t tc[5];
+          vtaps(2, tc);
           int rc[16];
-          residual(2, rc);
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            rc[i] = (int)(short)c2[i] - clampi(vsum(tc, i >> 2, i & 3) >> 16, -128, 127);
           sat[6 + ix] = satd4x4(rc);
         }
       }
