@@ -26,15 +26,32 @@ struct FrameRef {
   int stride;
 };
 
+// A batch's completion event, shared by the batch and its jobs' outputs.  A
+// later batch may wait for it on the device (its jobs' references); it is
+// destroyed with the last of them, after the reference outputs are freed, so
+// after every dependent batch, and so every wait on it, has completed.
+struct SharedEvent {
+  hipEvent_t ev = nullptr;
+  int refs = 0;
+};
+static void unref(SharedEvent* e) {
+  if (e && --e->refs == 0) {
+    (void)hipEventDestroy(e->ev);
+    delete e;
+  }
+}
+
 struct JobOut {
   uint8_t* mem = nullptr;  // one allocation: outputs then bounds
   mr_search_out out{};
   uint8_t* bounds = nullptr;
-  hipStream_t stream = nullptr;  // stream that wrote it
+  hipStream_t stream = nullptr;   // stream that wrote it
+  SharedEvent* batch = nullptr;   // its batch's completion event
+  bool batch_running = false;     // that batch not yet retired
 };
 
 struct BatchState {
-  hipEvent_t done = nullptr;
+  SharedEvent* done = nullptr;
   hipStream_t stream = nullptr;
 };
 
@@ -120,6 +137,21 @@ class GpuExecutor : public Executor {
   int launch(const std::vector<SchedJob*>& jobs, void** handle) override {
     hipStream_t st = streams_[next_++ & 1];
     const int n = (int)jobs.size();
+    // References whose batches still run (chain_on_launch): this batch waits
+    // for them on the device; on their own stream the order is given.
+    {
+      std::vector<hipEvent_t> waits;
+      for (SchedJob* j : jobs) {
+        if (!j->ref_job) continue;
+        const JobOut* ro = (const JobOut*)ref_state_(j->ref_job);
+        if (!ro) return MR_EDEPEND;
+        if (ro->batch && ro->batch_running && ro->stream != st &&
+            std::find(waits.begin(), waits.end(), ro->batch->ev) == waits.end())
+          waits.push_back(ro->batch->ev);
+      }
+      for (hipEvent_t ev : waits)
+        if (hipStreamWaitEvent(st, ev, 0) != hipSuccess) return MR_EHIP;
+    }
     std::vector<mr_frame> cur(n), ref(n);
     std::vector<mr_search_params> prm(n);
     std::vector<const uint8_t*> bnd(n, nullptr);
@@ -190,22 +222,28 @@ class GpuExecutor : public Executor {
       e = launch_plan(P, (JobDesc*)(mem + L.jobs), (const uint2*)(mem + L.items),
                       batch_lists(mem, L), (uint32_t*)(mem + L.counter), st, nullptr);
     const hipError_t ef = hipFreeAsync(mem, st);
+    hipEvent_t ev = nullptr;
+    if (e == hipSuccess) e = ef;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e != hipSuccess) {
+      if (ev) (void)hipEventDestroy(ev);
+      return MR_EHIP;
+    }
     BatchState* b = new BatchState();
     b->stream = st;
-    if (e == hipSuccess) e = ef;
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(b->done, st);
-    if (e != hipSuccess) {
-      if (b->done) (void)hipEventDestroy(b->done);
-      delete b;
-      return MR_EHIP;
+    b->done = new SharedEvent{ev, 1 + n};
+    for (SchedJob* j : jobs) {
+      JobOut* o = (JobOut*)j->exec_state;
+      o->batch = b->done;
+      o->batch_running = true;
     }
     *handle = b;
     return MR_OK;
   }
 
   int query(void* handle) override {
-    const hipError_t e = hipEventQuery(((BatchState*)handle)->done);
+    const hipError_t e = hipEventQuery(((BatchState*)handle)->done->ev);
     if (e == hipSuccess) return 1;
     if (e == hipErrorNotReady) return 0;
     return -1;
@@ -213,7 +251,9 @@ class GpuExecutor : public Executor {
 
   void finish(void* handle, const std::vector<SchedJob*>& jobs) override {
     BatchState* b = (BatchState*)handle;
-    (void)hipEventDestroy(b->done);
+    for (SchedJob* j : jobs)
+      if (j->exec_state) ((JobOut*)j->exec_state)->batch_running = false;
+    unref(b->done);
     delete b;
     for (SchedJob* j : jobs) j->status = MR_OK;
   }
@@ -222,6 +262,7 @@ class GpuExecutor : public Executor {
     JobOut* o = (JobOut*)j.exec_state;
     if (!o) return;
     (void)hipFreeAsync(o->mem, o->stream);
+    unref(o->batch);
     delete o;
   }
 
@@ -321,6 +362,7 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
   sc.max_inflight = cfg->max_inflight;
   sc.max_queue = cfg->max_queue;
   sc.max_batch_jobs = cfg->max_batch_jobs;
+  sc.chain_on_launch = true;  // dependents wait for their references on the device
   mr_ladder* l = new mr_ladder();
   l->cfg = sc;
   l->ex.reset(new GpuExecutor(sc));

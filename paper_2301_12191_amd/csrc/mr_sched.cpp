@@ -155,17 +155,27 @@ int Scheduler::step() {
     ex_->finish(running_[b].handle, running_[b].jobs);
     const int64_t t = ex_->now_ns();
     for (SchedJob* j : running_[b].jobs) {
-      complete(*j, q < 0 ? MR_EHIP : j->status, t);
+      int status = q < 0 ? MR_EHIP : j->status;
+      if (status == MR_OK && j->ref_job) {
+        // Launched behind a reference that has failed since (its batch is
+        // earlier in running_, so it was retired first).
+        auto it = jobs_.find(j->ref_job);
+        if (it != jobs_.end() && it->second->state == kFailed) status = MR_EDEPEND;
+      }
+      complete(*j, status, t);
       ++done;
     }
     running_.erase(running_.begin() + b);
   }
-  // 2. Dependents of finished references become ready (or fail with them).
+  // 2. Dependents of finished (with chain_on_launch: of launched) references
+  //    become ready, or fail with them.
   for (uint64_t id : queue_) {
     SchedJob& j = *jobs_[id];
-    if (j.state != kQueued) continue;
+    if ((j.state != kQueued && j.state != kReady) || !j.ref_job) continue;
     const SchedJob& r = *jobs_[j.ref_job];
-    if (r.state == kDone) j.state = kReady;
+    if (j.state == kQueued &&
+        (r.state == kDone || (cfg_.chain_on_launch && r.state == kRunning)))
+      j.state = kReady;
     if (r.state == kFailed) {
       j.state = kRunning;  // transient; completed below
       ++inflight_;

@@ -30,6 +30,10 @@ struct SchedConfig {
   int max_queue = 4096;       // submitted, not yet completed
   int max_batch_jobs = 64;    // jobs per device launch
   int max_batches_in_flight = 2;
+  // A dependent may launch once its reference's batch has been launched, not
+  // only once it is done: the executor orders the two batches on the device.
+  // A dependent whose reference then fails fails with it.
+  bool chain_on_launch = false;
 };
 
 struct SchedJob {
@@ -60,7 +64,8 @@ class Executor {
   virtual size_t footprint(const SchedJob& j) = 0;
   // Are both frames (frame and frame-1) of (stream, rung) resident?
   virtual bool frames_resident(int stream, int frame, int rung) = 0;
-  // Launch a batch; jobs' references (ref_job) are done.  Returns 0 or an mr_status.
+  // Launch a batch; jobs' references (ref_job) are done, or with chain_on_launch
+  // launched in an earlier batch.  Returns 0 or an mr_status.
   virtual int launch(const std::vector<SchedJob*>& jobs, void** handle) = 0;
   // 1 done, 0 still running, < 0 failed.
   virtual int query(void* handle) = 0;

@@ -285,7 +285,70 @@ static void test_dropped_frames_fail_alone() {
   CHECK(s.submit(0, 2, 0, &a) == MR_EINVAL);  // not resident any more
 }
 
+// chain_on_launch: a dependent launches in the batch after its reference's,
+// while that batch still runs; a reference that then fails takes the
+// already-launched dependent with it.
+static void test_chain_on_launch() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  add_frames(ex, 0, 3, 3);
+  SchedConfig cfg = ladder_cfg(1 << 20);
+  cfg.chain_on_launch = true;
+  {
+    Scheduler s(cfg, &ex);
+    uint64_t d = 0;
+    CHECK(s.submit(0, 1, 1, &d) == MR_OK);  // implies the rung-0 reference
+    const SchedJob* dj = s.job(d);
+    const SchedJob* rj = s.job(dj->ref_job);
+    s.step();  // the reference launches
+    CHECK(ex.launched.size() == 1 && ex.launched[0][0] == rj->id && rj->state == kRunning);
+    ex.t += 100000;
+    s.step();  // the dependent launches behind it, in its own batch
+    CHECK(ex.launched.size() == 2 && ex.launched[1].size() == 1 && ex.launched[1][0] == d);
+    CHECK(rj->state == kRunning && dj->state == kRunning);
+    run_until_idle(s, ex);
+    CHECK(rj->state == kDone && dj->state == kDone && dj->status == MR_OK);
+    CHECK(s.stats().completed == 2 && s.stats().failed == 0);
+  }
+  {
+    ex.launched.clear();
+    Scheduler s(cfg, &ex);
+    uint64_t d = 0;
+    CHECK(s.submit(0, 2, 1, &d) == MR_OK);
+    const SchedJob* dj = s.job(d);
+    const SchedJob* rj = s.job(dj->ref_job);
+    ex.fail_next = true;  // the reference batch fails when it completes
+    s.step();
+    ex.t += 100000;
+    s.step();
+    CHECK(ex.launched.size() == 2 && dj->state == kRunning);
+    run_until_idle(s, ex);
+    CHECK(rj->state == kFailed && rj->status == MR_EHIP);
+    CHECK(dj->state == kFailed && dj->status == MR_EDEPEND);
+    CHECK(s.stats().failed == 2 && s.stats().completed == 0);
+  }
+  {
+    // A dependent made ready by its running reference but not yet admitted
+    // (no batch slot) fails without a launch when the reference fails.
+    ex.launched.clear();
+    SchedConfig c1 = cfg;
+    c1.max_batches_in_flight = 1;
+    Scheduler s(c1, &ex);
+    uint64_t d = 0;
+    CHECK(s.submit(0, 2, 2, &d) == MR_OK);
+    const SchedJob* dj = s.job(d);
+    ex.fail_next = true;
+    s.step();  // reference launches and takes the only batch slot
+    ex.t += 100000;
+    s.step();
+    CHECK(ex.launched.size() == 1 && dj->state == kReady);
+    run_until_idle(s, ex);
+    CHECK(dj->state == kFailed && dj->status == MR_EDEPEND && ex.launched.size() == 1);
+  }
+}
+
 int main() {
+  test_chain_on_launch();
   test_dependency_and_implied_reference();
   test_missing_reference_frames();
   test_budget_admission_and_rejection();
