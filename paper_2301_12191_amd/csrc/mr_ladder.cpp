@@ -363,6 +363,7 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
   sc.max_queue = cfg->max_queue;
   sc.max_batch_jobs = cfg->max_batch_jobs;
   sc.chain_on_launch = true;  // dependents wait for their references on the device
+  sc.max_batches_in_flight = 4;  // a reference chain of up to 4 levels in flight
   mr_ladder* l = new mr_ladder();
   l->cfg = sc;
   l->ex.reset(new GpuExecutor(sc));
