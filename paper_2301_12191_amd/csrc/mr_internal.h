@@ -20,6 +20,14 @@ __host__ __device__ inline int refine_pad_x(int R) { return (R + 24 + 3) & ~3; }
 // Row margin: the refinement reaches R rows, the sub-pel patches R + 4.
 __host__ __device__ inline int refine_pad_y(int R) { return R + 8; }
 
+// One dependent's depth-bound computation (a batch of them is one launch).
+struct BoundsJob {
+  const uint8_t* ref_depth;  // device [ceil(ref_h / 8)][ceil(ref_w / 8)] depths
+  uint8_t* out;              // device [ceil(dep_h / 8)][ceil(dep_w / 8)][2] {lo, hi}
+  int ref_w, ref_h, dep_w, dep_h, dlo, dhi;
+};
+constexpr int kMaxBoundsJobs = 16;
+
 // Search work item of a batch: x = job, y = row << 16 | first CTU column << 4 | band.
 __host__ __device__ inline uint32_t pack_item_y(int row, int col0, int band) {
   return ((uint32_t)row << 16) | ((uint32_t)col0 << 4) | (uint32_t)band;

@@ -743,13 +743,11 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
 
 
 // ------------------------------------------------------------------------- depth bounds
-__global__ __launch_bounds__(256) void depth_bounds_kernel(const uint8_t* __restrict__ ref_depth,
-                                                           int ref_w, int ref_h, int dep_w,
-                                                           int dep_h, int dlo, int dhi,
-                                                           uint8_t* __restrict__ out) {
-  const int duw = (dep_w + 7) >> 3, duh = (dep_h + 7) >> 3;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= duw * duh) return;
+// Bounds of dependent unit i (of duw x duh) from the co-located reference unit.
+__device__ __forceinline__ void depth_bounds_unit(const uint8_t* __restrict__ ref_depth, int ref_w,
+                                                  int ref_h, int dep_w, int dep_h, int dlo,
+                                                  int dhi, uint8_t* __restrict__ out, int i) {
+  const int duw = (dep_w + 7) >> 3;
   const int ux = i % duw, uy = i / duw;
   const int64_t xr = min((int64_t)(8 * ux + 4) * ref_w / dep_w, (int64_t)ref_w - 1);
   const int64_t yr = min((int64_t)(8 * uy + 4) * ref_h / dep_h, (int64_t)ref_h - 1);
@@ -759,6 +757,26 @@ __global__ __launch_bounds__(256) void depth_bounds_kernel(const uint8_t* __rest
     if ((int64_t)(64 >> d) * ref_w <= (int64_t)(64 >> dr) * dep_w) ds = d;
   out[2 * i] = (uint8_t)max(0, ds - dlo);
   out[2 * i + 1] = (uint8_t)min(3, ds + dhi);
+}
+
+__global__ __launch_bounds__(256) void depth_bounds_kernel(const uint8_t* __restrict__ ref_depth,
+                                                           int ref_w, int ref_h, int dep_w,
+                                                           int dep_h, int dlo, int dhi,
+                                                           uint8_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ((dep_w + 7) >> 3) * ((dep_h + 7) >> 3)) return;
+  depth_bounds_unit(ref_depth, ref_w, ref_h, dep_w, dep_h, dlo, dhi, out, i);
+}
+
+// The bounds of up to kMaxBoundsJobs dependents in one launch: job blockIdx.y.
+struct BoundsBatch {
+  BoundsJob j[kMaxBoundsJobs];
+};
+__global__ __launch_bounds__(256) void depth_bounds_batch_kernel(BoundsBatch bb) {
+  const BoundsJob& b = bb.j[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ((b.dep_w + 7) >> 3) * ((b.dep_h + 7) >> 3)) return;
+  depth_bounds_unit(b.ref_depth, b.ref_w, b.ref_h, b.dep_w, b.dep_h, b.dlo, b.dhi, b.out, i);
 }
 
 }  // namespace mr
@@ -934,6 +952,23 @@ hipError_t launch_depth_bounds(const uint8_t* ref_depth, int ref_w, int ref_h, i
   hipLaunchKernelGGL(depth_bounds_kernel, dim3((n + 255) / 256), dim3(256), 0, st, ref_depth,
                      ref_w, ref_h, dep_w, dep_h, dlo, dhi, out);
   return hipGetLastError();
+}
+
+hipError_t launch_depth_bounds_batch(const BoundsJob* jobs, int n, hipStream_t st) {
+  for (int k0 = 0; k0 < n; k0 += kMaxBoundsJobs) {
+    const int m = std::min(kMaxBoundsJobs, n - k0);
+    BoundsBatch bb{};
+    int units = 1;
+    for (int k = 0; k < m; ++k) {
+      bb.j[k] = jobs[k0 + k];
+      units = std::max(units, ((bb.j[k].dep_w + 7) >> 3) * ((bb.j[k].dep_h + 7) >> 3));
+    }
+    hipLaunchKernelGGL(depth_bounds_batch_kernel, dim3((units + 255) / 256, m), dim3(256), 0, st,
+                       bb);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mr

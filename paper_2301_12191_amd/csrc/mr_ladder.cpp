@@ -158,6 +158,7 @@ class GpuExecutor : public Executor {
     std::vector<mr_search_out> outs(n);
     std::vector<mr_mv_seed> seeds(n);
     std::vector<const mr_mv_seed*> ps(n, nullptr);
+    std::vector<BoundsJob> bjobs;  // the dependents' depth bounds, one launch
     for (int i = 0; i < n; ++i) {
       SchedJob& j = *jobs[i];
       const RungCfg& r = cfg_.rungs[j.rung];
@@ -193,9 +194,8 @@ class GpuExecutor : public Executor {
         const RungCfg& rr = cfg_.rungs[r.ref_rung];
         const JobOut* ro = (const JobOut*)ref_state_(j.ref_job);
         if (!ro) return MR_EDEPEND;
-        if (launch_depth_bounds(ro->out.depth, rr.width, rr.height, r.width, r.height, r.dlo,
-                                r.dhi, o->bounds, st) != hipSuccess)
-          return MR_EHIP;
+        bjobs.push_back(BoundsJob{ro->out.depth, o->bounds, rr.width, rr.height, r.width,
+                                  r.height, r.dlo, r.dhi});
         bnd[i] = o->bounds;
         const int rr_refine = refine_of(r);
         if (rr_refine >= 0) {
@@ -205,6 +205,9 @@ class GpuExecutor : public Executor {
       }
       outs[i] = o->out;
     }
+    if (!bjobs.empty() &&
+        launch_depth_bounds_batch(bjobs.data(), (int)bjobs.size(), st) != hipSuccess)
+      return MR_EHIP;
     std::vector<const mr_frame*> pc(n), pr(n);
     std::vector<const mr_search_params*> pp(n);
     std::vector<const mr_search_out*> po(n);

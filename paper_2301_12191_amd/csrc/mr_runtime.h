@@ -108,6 +108,8 @@ hipError_t launch_refine(const JobDesc* jobs, const int* rlist, int n_rjobs, int
                          int max_r, hipStream_t st);
 hipError_t launch_depth_bounds(const uint8_t* ref_depth, int ref_w, int ref_h, int dep_w,
                                int dep_h, int dlo, int dhi, uint8_t* out, hipStream_t st);
+// Depth bounds of several dependents (one launch per kMaxBoundsJobs of them).
+hipError_t launch_depth_bounds_batch(const BoundsJob* jobs, int n, hipStream_t st);
 int search_occupancy(int D, int strip, size_t lds_bytes);
 
 // Stage profiling (mr_profile_*).
