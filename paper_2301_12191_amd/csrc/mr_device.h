@@ -63,6 +63,7 @@ __device__ __forceinline__ uint32_t satd4x4(const int d[16]) {
 // directly.  Residuals within +-255 keep every intermediate within +-2040 and
 // each half's result within 16320.
 typedef short sh2 __attribute__((ext_vector_type(2)));
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 
 // max(|a|, |b|) per 16-bit half, as max(max(a, b), -min(a, b)): four packed
 // operations instead of five.

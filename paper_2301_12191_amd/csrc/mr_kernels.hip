@@ -576,6 +576,12 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     // and S = the (0,0) coefficient (>= 0), SATD = (A - S + |S - 16 dc|) / 2.
     int S;
     const int A = hadamard_abs_sum(c, S);
+    // The tile's samples in pairs of a row, (c[4 j + 2 q], c[4 j + 2 q + 1]) as
+    // 16-bit halves: residuals and the planar prediction are packed 16-bit
+    // arithmetic, two samples per operation.
+    us2 cp[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) cp[m] = (us2){(unsigned short)c[2 * m], (unsigned short)c[2 * m + 1]};
 #pragma unroll
     for (int d = 3; d >= 0; --d) {
       const int n = kCtu >> d, lg = 6 - d;
@@ -584,8 +590,10 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       uint32_t v0 = 0, v1 = 0, v2 = 0;
       if (sh.elig[node]) {
         // Inter residual (zero with sub-pel refinement: that SATD comes from
-        // subres) in the low halves, planar residual in the high halves.
-        int ri[16];
+        // subres) in the low halves, planar residual in the high halves; both
+        // first as pairs of a row's samples (irp, prp), then regrouped per
+        // sample into pr.
+        sh2 irp[8];
         if (!jb->subpel) {
           const int mx = sh.mvx[node], my = sh.mvy[node];
           const uint8_t* __restrict__ rp = jb->ref;
@@ -595,51 +603,75 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
           for (int q = 0; q < 4; ++q)
             yo[q] = (uint32_t)(clampi(cy + ty * 4 + q + my, 0, jb->h - 1) * stride);
           // Rows needing no horizontal clamping: the two dwords around the 4
-          // samples (inside the frame) and one v_alignbyte.
+          // samples (inside the frame), one v_alignbyte and two byte-to-16-bit
+          // v_perm_b32.
           if (ref_aligned && xf >= 0 && xf + 3 < jb->w && yo[3] + (uint32_t)xf + 8u <= frame_bytes) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const uint32_t o = yo[q] + (uint32_t)xf;
               const uint32_t* a = (const uint32_t*)(rp + (o & ~3u));
               const uint32_t v = __builtin_amdgcn_alignbyte(a[1], a[0], o & 3u);
-#pragma unroll
-              for (int k = 0; k < 4; ++k) ri[4 * q + k] = c[4 * q + k] - (int)((v >> (8 * k)) & 0xFFu);
+              const us2 r0 = __builtin_bit_cast(us2, __builtin_amdgcn_perm(0u, v, 0x0c010c00u));
+              const us2 r1 = __builtin_bit_cast(us2, __builtin_amdgcn_perm(0u, v, 0x0c030c02u));
+              irp[2 * q] = __builtin_bit_cast(sh2, cp[2 * q] - r0);
+              irp[2 * q + 1] = __builtin_bit_cast(sh2, cp[2 * q + 1] - r1);
             }
           } else {
             uint32_t xo[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) xo[q] = (uint32_t)clampi(xf + q, 0, jb->w - 1);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) ri[i] = c[i] - (int)rp[yo[i >> 2] + xo[i & 3]];
+            for (int m = 0; m < 8; ++m) {
+              const us2 r = {(unsigned short)rp[yo[m >> 1] + xo[2 * (m & 1)]],
+                             (unsigned short)rp[yo[m >> 1] + xo[2 * (m & 1) + 1]]};
+              irp[m] = __builtin_bit_cast(sh2, cp[m] - r);
+            }
           }
         } else {
 #pragma unroll
-          for (int i = 0; i < 16; ++i) ri[i] = 0;
+          for (int m = 0; m < 8; ++m) irp[m] = (sh2)(0);
         }
         const int16_t* L = sh.refs + ref_offset(node);
         const int16_t* T = L + 2 * n + 1;
         const int px0 = tx * 4 - lx * n, py0 = ty * 4 - ly * n;  // position inside the CU
         // Planar: the horizontal part (n-1-px) L[py+1] + (px+1) T[n] is linear
         // in px along a row and the vertical part (n-1-py) T[px] + (py+1) L[n+1]
-        // linear in py along a column, so each tile row / column is set up once.
+        // linear in py along a column.  Both go in pairs of a row's samples:
+        // every true value lies in [0, 2^15), so the packed 16-bit sums (mod
+        // 2^16) and the unsigned shift are exact.
         const int Tn = T[n], Ln1 = L[n + 1];
-        int hr[4], dh[4], vc[4], dv[4];
+        us2 vp0, vp1, dv0, dv1;  // vertical parts of columns (0, 1) and (2, 3), their steps
+        {
+          int vc[4], dv[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int Tx = T[px0 + i];
+            vc[i] = (n - 1 - py0) * Tx + (py0 + 1) * Ln1, dv[i] = Ln1 - Tx;
+          }
+          vp0 = (us2){(unsigned short)vc[0], (unsigned short)vc[1]};
+          vp1 = (us2){(unsigned short)vc[2], (unsigned short)vc[3]};
+          dv0 = (us2){(unsigned short)dv[0], (unsigned short)dv[1]};
+          dv1 = (us2){(unsigned short)dv[2], (unsigned short)dv[3]};
+        }
+        const us2 sh_pl = (us2)(unsigned short)(lg + 1);
+        sh2 pr[16];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int Ly = L[py0 + j + 1];
-          hr[j] = (n - 1 - px0) * Ly + (px0 + 1) * Tn + n, dh[j] = Tn - Ly;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int Tx = T[px0 + i];
-          vc[i] = (n - 1 - py0) * Tx + (py0 + 1) * Ln1, dv[i] = Ln1 - Tx;
-        }
-        sh2 pr[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int i = k & 3, j = k >> 2;
-          const int p = (hr[j] + i * dh[j] + vc[i] + j * dv[i]) >> (lg + 1);
-          pr[k] = (sh2){(short)ri[k], (short)(c[k] - p)};
+          const int hr = (n - 1 - px0) * Ly + (px0 + 1) * Tn + n, dh = Tn - Ly;
+          const us2 h0 = {(unsigned short)hr, (unsigned short)(hr + dh)};
+          const us2 h1 = h0 + (us2)(unsigned short)(2 * dh);
+          const us2 p0 = (h0 + vp0) >> sh_pl, p1 = (h1 + vp1) >> sh_pl;
+          const uint32_t q0 = __builtin_bit_cast(uint32_t, cp[2 * j] - p0);
+          const uint32_t q1 = __builtin_bit_cast(uint32_t, cp[2 * j + 1] - p1);
+          const uint32_t i0 = __builtin_bit_cast(uint32_t, irp[2 * j]);
+          const uint32_t i1 = __builtin_bit_cast(uint32_t, irp[2 * j + 1]);
+          // sample (low half of the inter pair, low half of the planar pair), ...
+          pr[4 * j] = __builtin_bit_cast(sh2, __builtin_amdgcn_perm(q0, i0, 0x05040100u));
+          pr[4 * j + 1] = __builtin_bit_cast(sh2, __builtin_amdgcn_perm(q0, i0, 0x07060302u));
+          pr[4 * j + 2] = __builtin_bit_cast(sh2, __builtin_amdgcn_perm(q1, i1, 0x05040100u));
+          pr[4 * j + 3] = __builtin_bit_cast(sh2, __builtin_amdgcn_perm(q1, i1, 0x07060302u));
+          vp0 += dv0, vp1 += dv1;
         }
         const uint32_t pk = satd4x4_pair(pr);
         v0 = pk & 0xFFFFu, v1 = pk >> 16;
