@@ -20,6 +20,12 @@ __host__ __device__ inline int refine_pad_x(int R) { return (R + 24 + 3) & ~3; }
 // Row margin: the refinement reaches R rows, the sub-pel patches R + 4.
 __host__ __device__ inline int refine_pad_y(int R) { return R + 8; }
 
+// Search work queues, one per XCD: queue q holds items [off[q], off[q + 1]).
+constexpr int kQueues = 8;
+struct QueueOffsets {
+  int32_t off[kQueues + 1];
+};
+
 // One dependent's depth-bound computation (a batch of them is one launch).
 struct BoundsJob {
   const uint8_t* ref_depth;  // device [ceil(ref_h / 8)][ceil(ref_w / 8)] depths

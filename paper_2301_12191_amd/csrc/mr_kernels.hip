@@ -837,7 +837,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_j
                                                    uint32_t* counter) {
   const cjob jobs = (cjob)jobs_;
   const int flat = blockIdx.x;
-  if (flat == 0 && threadIdx.x == 0) *counter = 0;  // work-queue head of the search kernel
+  if (flat == 0 && threadIdx.x < kQueues) counter[threadIdx.x] = 0;  // search queue heads
   if (flat >= n_ctus) return;
   __shared__ uint32_t csad[64];
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
@@ -853,19 +853,39 @@ __global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_j
 // over several wavefronts instead of leaving some idle (partial results merge
 // through the same atomic minima as bands do).  items == null: one job, items
 // implicit.
+//
+// Queues: one per XCD, head counter[q], items [qo.off[q], qo.off[q + 1]).
+// Workgroups are dealt to the 8 XCDs round-robin, so a workgroup starts on
+// queue blockIdx.x mod 8 (its XCD's) and moves on to the next queue once that
+// one is empty; it ends when all are.  Every item is taken exactly once
+// whichever XCD a workgroup runs on.
 template <int D>
 __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const uint2* items_,
-                                                  int n_items, uint32_t* counter, uint32_t* win,
-                                                  int win_dwords_max) {
+                                                  const QueueOffsets& qo, uint32_t* counter,
+                                                  uint32_t* win, int win_dwords_max) {
   __shared__ int s_item;
   const cjob jobs = (cjob)jobs_;
   const sptr32 items = (sptr32)items_;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+  const int home = blockIdx.x & (kQueues - 1);
+  int empty = 0;  // thread 0: queues found empty, from the home queue on
   for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) {
+      int it = -1;
+      while (empty < kQueues) {
+        const int q = (home + empty) & (kQueues - 1);
+        const int k = (int)atomicAdd(&counter[q], 1u);
+        if (k < qo.off[q + 1] - qo.off[q]) {
+          it = qo.off[q] + k;
+          break;
+        }
+        ++empty;
+      }
+      s_item = it;
+    }
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(s_item);
-    if (it >= n_items) break;  // every wavefront of the workgroup sees the same value
+    if (it < 0) break;  // every wavefront of the workgroup sees the same value
     int job, row, col0, band;
     if (items_) {
       const uint32_t vx = items[2 * it], vy = items[2 * it + 1];
@@ -904,16 +924,17 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
 // larger register file at one or two.
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void search_kernel(
-    const JobDesc* jobs_, const uint2* items_, int n_items, uint32_t* counter, int win_dwords_max) {
+    const JobDesc* jobs_, const uint2* items_, QueueOffsets qo, uint32_t* counter,
+    int win_dwords_max) {
   extern __shared__ uint32_t win[];
-  search_persistent<D>(jobs_, items_, n_items, counter, win, win_dwords_max);
+  search_persistent<D>(jobs_, items_, qo, counter, win, win_dwords_max);
 }
 
 __global__ __launch_bounds__(256) void search_kernel_d8(const JobDesc* jobs_, const uint2* items_,
-                                                        int n_items, uint32_t* counter,
+                                                        QueueOffsets qo, uint32_t* counter,
                                                         int win_dwords_max) {
   extern __shared__ uint32_t win[];
-  search_persistent<8>(jobs_, items_, n_items, counter, win, win_dwords_max);
+  search_persistent<8>(jobs_, items_, qo, counter, win, win_dwords_max);
 }
 
 __global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus) {
@@ -959,15 +980,16 @@ int search_occupancy(int D, int strip, size_t lds_bytes) {
   return blocks;
 }
 
-hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, int D, int strip,
-                         int n_wg, size_t lds_bytes, uint32_t* counter, hipStream_t st) {
+hipError_t launch_search(const JobDesc* jobs, const uint2* items, const QueueOffsets& qoff,
+                         int D, int strip, int n_wg, size_t lds_bytes, uint32_t* counter,
+                         hipStream_t st) {
   const dim3 grid(n_wg), block(64 * strip);
   // LDS: window (lds_bytes minus the rings) then one ring per wavefront.
   const int win_dwords_max = (int)((lds_bytes - (size_t)kCurRingBytes * strip) / 4);
   switch (D) {
-    case 2: hipLaunchKernelGGL(search_kernel<2>, grid, block, lds_bytes, st, jobs, items, n_items, counter, win_dwords_max); break;
-    case 4: hipLaunchKernelGGL(search_kernel<4>, grid, block, lds_bytes, st, jobs, items, n_items, counter, win_dwords_max); break;
-    case 8: hipLaunchKernelGGL(search_kernel_d8, grid, block, lds_bytes, st, jobs, items, n_items, counter, win_dwords_max); break;
+    case 2: hipLaunchKernelGGL(search_kernel<2>, grid, block, lds_bytes, st, jobs, items, qoff, counter, win_dwords_max); break;
+    case 4: hipLaunchKernelGGL(search_kernel<4>, grid, block, lds_bytes, st, jobs, items, qoff, counter, win_dwords_max); break;
+    case 8: hipLaunchKernelGGL(search_kernel_d8, grid, block, lds_bytes, st, jobs, items, qoff, counter, win_dwords_max); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

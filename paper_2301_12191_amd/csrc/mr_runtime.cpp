@@ -317,7 +317,10 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     int64_t cost;
     uint32_t job, y;
   };
-  std::vector<Work> work;
+  // Per job, its items strip by strip (a strip's bands consecutive) and the
+  // strip's band count.
+  std::vector<std::vector<Work>> jwork(materialize_items ? n_jobs : 0);
+  std::vector<int> jnb(n_jobs, 1);
   for (int j = 0; j < n_jobs; ++j) {
     JobDesc& jb = P->jobs[j];
     std::memset(&jb, 0, sizeof(jb));
@@ -396,30 +399,64 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     P->lds_bytes = std::max(P->lds_bytes, window_bytes(L, P->strip));
     const int spr = (jb.ctus_w + P->strip - 1) / P->strip;
     total_items += (int64_t)spr * jb.ctus_h * L.nbands;
+    jnb[j] = L.nbands;
     if (materialize_items) {
-      for (int b = 0; b < L.nbands; ++b) {
-        const int steps = L.band_step0[b + 1] - L.band_step0[b];
-        const int rows = (L.band_g0[b + 1] - L.band_g0[b]) * P->D + 63;
-        for (int row = 0; row < jb.ctus_h; ++row)
-          for (int sidx = 0; sidx < spr; ++sidx) {
+      for (int row = 0; row < jb.ctus_h; ++row)
+        for (int sidx = 0; sidx < spr; ++sidx)
+          for (int b = 0; b < L.nbands; ++b) {
+            const int steps = L.band_step0[b + 1] - L.band_step0[b];
+            const int rows = (L.band_g0[b + 1] - L.band_g0[b]) * P->D + 63;
             // A partial strip spreads its CTUs' steps over all the strip's wavefronts.
             const int sw = std::min(P->strip, jb.ctus_w - sidx * P->strip);
             const int64_t span = ((int64_t)sw * steps + P->strip - 1) / P->strip;
             const int64_t cost = span * 4096 + rows;  // compute + staging
-            work.push_back(Work{cost, (uint32_t)j, pack_item_y(row, sidx * P->strip, b)});
+            jwork[j].push_back(Work{cost, (uint32_t)j, pack_item_y(row, sidx * P->strip, b)});
           }
-      }
     }
   }
   if (total_items > ((int64_t)1 << 30)) return MR_EINVAL;
   if (P->lds_bytes > device_lds_max()) return MR_EINVAL;  // a forced tile shape too large
   P->n_items = (int)total_items;
+  // One queue per XCD: workgroups are dealt to the 8 XCDs round-robin, and a
+  // workgroup starts on queue blockIdx.x mod 8, then takes from the others once
+  // its own is empty.  Each job's strips, every strip with all its bands, are
+  // cut into kQueues contiguous runs of equal cost, run q to queue q, so that
+  // one XCD's L2 holds the current CTUs and window rows of a region of every
+  // picture.  Each queue is in the order of one global queue: longest items
+  // first (heavy search ranges and long bands start early, small ones fill the
+  // tail).
   if (materialize_items) {
-    // Longest items first (LPT): heavy search ranges start early, small ones fill the tail.
-    std::stable_sort(work.begin(), work.end(),
-                     [](const Work& a, const Work& b) { return a.cost > b.cost; });
-    P->items.resize(work.size());
-    for (size_t i = 0; i < work.size(); ++i) P->items[i] = make_uint2(work[i].job, work[i].y);
+    std::vector<std::vector<Work>> qs(kQueues);
+    for (int j = 0; j < n_jobs; ++j) {
+      const std::vector<Work>& w = jwork[j];
+      const size_t nb = (size_t)jnb[j];
+      int64_t total = 0;
+      for (const Work& x : w) total += x.cost;
+      int64_t acc = 0;
+      for (size_t u = 0; u < w.size(); u += nb) {  // one strip and its bands
+        int64_t c = 0;
+        for (size_t k = 0; k < nb; ++k) c += w[u + k].cost;
+        const int q = total > 0 ? (int)std::min<int64_t>(kQueues - 1,
+                                                         (acc + c / 2) * kQueues / total)
+                                : 0;
+        qs[q].insert(qs[q].end(), w.begin() + u, w.begin() + u + nb);
+        acc += c;
+      }
+    }
+    P->items.clear();
+    P->items.reserve((size_t)total_items);
+    P->qoff.off[0] = 0;
+    for (int q = 0; q < kQueues; ++q) {
+      std::stable_sort(qs[q].begin(), qs[q].end(),
+                       [](const Work& a, const Work& b) { return a.cost > b.cost; });
+      for (const Work& x : qs[q]) P->items.push_back(make_uint2(x.job, x.y));
+      P->qoff.off[q + 1] = (int32_t)P->items.size();
+    }
+  } else {
+    // One job, items implicit (index = strip * bands + band): runs of whole strips.
+    const int64_t nb = jnb[0], strips = total_items / nb;
+    for (int q = 0; q < kQueues; ++q) P->qoff.off[q] = (int32_t)(strips * q / kQueues * nb);
+    P->qoff.off[kQueues] = (int32_t)total_items;
   }
   if (P->n_items > 0) {
     const int occ = std::max(1, search_occupancy(P->D, P->strip, P->lds_bytes));
@@ -459,7 +496,7 @@ hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, con
   if (e == hipSuccess && !P.plist.empty())
     e = launch_pad(jobs_d, L.plist, (int)P.plist.size(), P.max_pad_rows, st);
   if (e == hipSuccess && P.n_items > 0)
-    e = launch_search(jobs_d, items_d, P.n_items, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
+    e = launch_search(jobs_d, items_d, P.qoff, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
   if (e == hipSuccess && P.n_rjobs > 0)
     e = launch_refine(jobs_d, L.rlist, P.n_rjobs, P.n_rctus, P.max_r, st);
   if (e == hipSuccess && P.n_sjobs > 0)

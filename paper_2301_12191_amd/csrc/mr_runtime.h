@@ -59,6 +59,7 @@ struct Plan {
   int n_rjobs = 0, n_rctus = 0, max_r = 0;
   int n_sjobs = 0, n_sctus = 0;
   int max_pad_rows = 0;  // rows of the largest padded reference
+  QueueOffsets qoff{};   // search items of each per-XCD queue
 };
 
 // Build a plan.  seeds: null, or per job a seed (null entry = full search);
@@ -97,8 +98,9 @@ size_t device_lds_max();
 hipError_t launch_store_job(const JobDesc& jb, JobDesc* dst, hipStream_t st);
 hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* counter,
                        hipStream_t st);
-hipError_t launch_search(const JobDesc* jobs, const uint2* items, int n_items, int D, int strip,
-                         int n_wg, size_t lds_bytes, uint32_t* counter, hipStream_t st);
+hipError_t launch_search(const JobDesc* jobs, const uint2* items, const QueueOffsets& qoff,
+                         int D, int strip, int n_wg, size_t lds_bytes, uint32_t* counter,
+                         hipStream_t st);
 hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st);
 hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int max_rows,
                       hipStream_t st);

@@ -45,7 +45,7 @@ int time_search(const mr_search_job* jobs, int n, int reps, double* ms_out) {
     hipError_t e = launch_prep(jobs_d, n, P.n_ctus, ctr, nullptr);
     if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
     if (e == hipSuccess)
-      e = launch_search(jobs_d, items_d, P.n_items, P.D, P.strip, P.n_wg, P.lds_bytes, ctr,
+      e = launch_search(jobs_d, items_d, P.qoff, P.D, P.strip, P.n_wg, P.lds_bytes, ctr,
                         nullptr);
     if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
