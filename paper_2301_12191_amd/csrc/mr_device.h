@@ -12,6 +12,15 @@ typedef const __attribute__((address_space(4))) JobDesc* cjob;     // job descri
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Workgroups are dealt round-robin to the 8 XCDs: this maps blockIdx.x to an
+// index such that each XCD takes a contiguous eighth of [0, gridDim.x), so
+// neighbouring CTUs share one L2 (a bijection whatever the dispatch order).
+__device__ __forceinline__ int xcd_contiguous_index() {
+  const int gx = gridDim.x, x = blockIdx.x;
+  const int q = gx >> 3, rm = gx & 7, xcd = x & 7, k = x >> 3;
+  return xcd * q + min(xcd, rm) + k;
+}
+
 // Z-order (Morton) position -> (x, y) for 6-bit indices.
 __device__ __forceinline__ int zx(int z) { return (z & 1) | ((z >> 1) & 2) | ((z >> 2) & 4); }
 __device__ __forceinline__ int zy(int z) { return ((z >> 1) & 1) | ((z >> 2) & 2) | ((z >> 3) & 4); }

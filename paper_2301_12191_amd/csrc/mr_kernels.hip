@@ -836,7 +836,7 @@ __global__ void store_job_kernel(JobDesc jb, JobDesc* dst) {
 __global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus,
                                                    uint32_t* counter) {
   const cjob jobs = (cjob)jobs_;
-  const int flat = blockIdx.x;
+  const int flat = xcd_contiguous_index();
   if (flat == 0 && threadIdx.x < kQueues) counter[threadIdx.x] = 0;  // search queue heads
   if (flat >= n_ctus) return;
   __shared__ uint32_t csad[64];
@@ -940,7 +940,7 @@ __global__ __launch_bounds__(256) void search_kernel_d8(const JobDesc* jobs_, co
 __global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus) {
   __shared__ LeafShared sh;
   const cjob jobs = (cjob)jobs_;
-  const int flat = blockIdx.x;
+  const int flat = xcd_contiguous_index();
   if (flat >= n_ctus) return;
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
   leaf_ctu(jobs + j, flat - jobs[j].ctu_start, sh);

@@ -293,7 +293,7 @@ __device__ int find_sjob(cjob jobs, const int* slist, int n_sjobs, int flat) {
 __global__ __launch_bounds__(256) void subpel_kernel(const JobDesc* jobs_, const int* slist,
                                                      int n_sjobs, int n_sctus) {
   const cjob jobs = (cjob)jobs_;
-  const int flat = blockIdx.x;
+  const int flat = xcd_contiguous_index();
   if (flat >= n_sctus) return;
   const int j = __builtin_amdgcn_readfirstlane(find_sjob(jobs, slist, n_sjobs, flat));
   subpel_ctu(jobs + j, flat - jobs[j].sctu_start);
