@@ -197,17 +197,19 @@ int mr_batch_destroy(mr_batch* b);
  * work).  Frames stay resident in device memory (registered with
  * mr_ladder_put_frame, caller-owned).  A job (stream, frame, rung) searches
  * frame `frame` against `frame - 1` of that stream and rung.  A rung with
- * ref_rung >= 0 is a dependent: its job waits until the job of the reference
- * rung for the same (stream, frame) is done, then its depth search is bounded
- * by mr_depth_bounds(delta_lo, delta_hi) of that job's depth map.  Submitting
+ * ref_rung >= 0 is a dependent: its depth search is bounded by
+ * mr_depth_bounds(delta_lo, delta_hi) of the depth map of the job of the
+ * reference rung for the same (stream, frame).  It is launched once that job
+ * has been launched, in a later batch that waits for it on the device; if the
+ * reference job fails, the dependent fails with MR_EDEPEND.  Submitting
  * a dependent whose reference job does not exist creates it (an implied job)
  * if the reference rung's frames are resident, else fails with MR_EDEPEND.
  * A request loop (one host thread, two device streams of default priority)
  * admits ready jobs in arrival order while their device footprint (scratch +
  * outputs + bounds) fits hbm_budget_bytes and fewer than max_inflight jobs
  * run, batches up to max_batch_jobs of them into one persistent search launch,
- * keeps up to two batches in flight, and releases dependents as references
- * complete (continuous batching).  Done reference jobs stay resident for later
+ * keeps up to four batches in flight, and releases dependents as references
+ * are launched (continuous batching).  Done reference jobs stay resident for later
  * dependents until their memory is needed.  With reuse_mv, a dependent's
  * search is also seeded with its reference job's MV map.  Each rung may carry
  * its own policy (own_policy), so that one configuration holds both
