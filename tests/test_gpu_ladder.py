@@ -105,6 +105,22 @@ def test_mix_equals_alone(mr):
     assert st["p99_ms"] >= st["p50_ms"] > 0
 
 
+def test_many_dependents_per_batch_equal_alone(mr):
+    """Twelve streams' dependents submitted at once: a batch then carries more than 16
+    dependents, whose depth bounds the server computes in chunks of 16 per launch, each
+    launched behind its implied reference's running batch."""
+    fr = _frames(12, 2)
+    jobs = [(s, 1, r) for s in range(12) for r in (1, 2)]
+    got, st = _run_mix(mr, fr, jobs, max_batch_jobs=64)
+    assert st["completed"] == len(jobs) + st["implied"] and st["implied"] == 12
+    assert st["failed"] == 0
+    cache = {}
+    for key in jobs:
+        exp = _alone(mr, fr, *key, cache)
+        for k in FIELDS:
+            assert np.array_equal(got[key][k], exp[k]), (key, k)
+
+
 def test_dependent_only_submissions_imply_reference(mr):
     fr = _frames(2, 2)
     jobs = [(0, 1, 2), (1, 1, 1), (0, 1, 1)]
