@@ -177,7 +177,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the coding-tree "
-              "search has no cross-GPU step in this build", file=sys.stderr)
+              "search runs on one GPU (sharding jobs or CTU rows over GPUs is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
