@@ -76,20 +76,21 @@ PlanLists batch_lists(uint8_t* mem, const BatchLayout& L) {
                    (const int*)(mem + L.plist)};
 }
 
-// Upload the job array, items and job lists of a bound plan.
+// Upload the job array, items and job lists of a bound plan: one copy of a
+// host image of the head of the layout (they are contiguous, from offset 0 to
+// the counter).  A copy from pageable memory reads its source before it
+// returns, so the image may go out of scope.
 hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st) {
-  hipError_t e = hipMemcpyAsync(mem + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs,
-                                hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !P.items.empty())
-    e = hipMemcpyAsync(mem + L.items, P.items.data(), sizeof(uint2) * P.items.size(),
-                       hipMemcpyHostToDevice, st);
+  std::vector<uint8_t> img(L.counter, 0);
+  std::memcpy(img.data() + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs);
+  if (!P.items.empty())
+    std::memcpy(img.data() + L.items, P.items.data(), sizeof(uint2) * P.items.size());
   const std::pair<const std::vector<int>*, size_t> lists[3] = {
       {&P.rlist, L.rlist}, {&P.slist, L.slist}, {&P.plist, L.plist}};
   for (const auto& pl : lists)
-    if (e == hipSuccess && !pl.first->empty())
-      e = hipMemcpyAsync(mem + pl.second, pl.first->data(), sizeof(int) * pl.first->size(),
-                         hipMemcpyHostToDevice, st);
-  return e;
+    if (!pl.first->empty())
+      std::memcpy(img.data() + pl.second, pl.first->data(), sizeof(int) * pl.first->size());
+  return hipMemcpyAsync(mem, img.data(), img.size(), hipMemcpyHostToDevice, st);
 }
 
 }  // namespace mr
