@@ -104,7 +104,7 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
             groups = [order] if pipelined else [[x for x in order if x[0] == f]
                                                 for f in range(1, n_frames + 1)]
             for grp in groups:
-                ids = {lad.submit(0, f, i): (f, i) for f, i in grp}
+                ids = dict(zip(lad.submit_many([(0, f, i) for f, i in grp]), grp))
                 done, idle = 0, 0
                 while done < len(ids):
                     got = lad.poll(64, 200000)

@@ -288,6 +288,16 @@ int mr_ladder_drop_frames(mr_ladder* l, int32_t stream_id, int32_t before_frame)
 /* Errors: MR_EINVAL (ids, frames not resident), MR_EDEPEND, MR_EAGAIN (queue
  * full, or the job alone exceeds the budget), MR_ESTATE (closed). */
 int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id);
+/* Submits jobs[0..n) in order under one hold of the server's lock, so the
+ * scheduler sees them together (a frame's whole ladder, say) rather than as
+ * they trickle in one call at a time.  job_ids[i] receives job i's id.  Stops
+ * at the first job that mr_ladder_submit would refuse and returns that error;
+ * *n_submitted (always written when non-null) counts the jobs accepted before
+ * it, which stay submitted.  n = 0 is MR_OK.
+ * Errors: MR_EINVAL (null ladder or n_submitted, n < 0, null arrays with
+ * n > 0), else those of mr_ladder_submit. */
+int mr_ladder_submit_many(mr_ladder* l, const mr_job* jobs, int32_t n, uint64_t* job_ids,
+                          int32_t* n_submitted);
 /* Up to max completions, waiting up to timeout_us for the first one
  * (0 = do not wait).  MR_ETIMEOUT if none arrived. */
 int mr_ladder_poll(mr_ladder* l, mr_completion* out, int32_t max, int32_t timeout_us,

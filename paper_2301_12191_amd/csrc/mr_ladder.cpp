@@ -8,6 +8,7 @@
 #include <functional>
 #include <map>
 #include <mutex>
+#include <sys/prctl.h>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -300,6 +301,9 @@ struct mr_ladder {
 
 static void ladder_loop(mr_ladder* l) {
   (void)hipSetDevice(l->ex->device());
+  // The loop sleeps 20 us between steps; with Linux's default 50 us timer slack
+  // each sleep would last about three times that.  1 us of slack for this thread.
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(l->mu);
   while (!l->stop.load()) {
     const int done = l->sched->step();
@@ -407,6 +411,21 @@ int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id) {
   if (l->closed) return MR_ESTATE;
   const int rc = l->sched->submit(job->stream_id, job->frame_idx, job->rung, job_id);
   if (rc == MR_OK) l->cv_work.notify_all();
+  return rc;
+}
+
+int mr_ladder_submit_many(mr_ladder* l, const mr_job* jobs, int32_t n, uint64_t* job_ids,
+                          int32_t* n_submitted) {
+  if (n_submitted) *n_submitted = 0;
+  if (!l || n < 0 || !n_submitted || (n > 0 && (!jobs || !job_ids))) return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(l->mu);
+  if (l->closed) return MR_ESTATE;
+  int rc = MR_OK;
+  for (int32_t i = 0; i < n && rc == MR_OK; ++i) {
+    rc = l->sched->submit(jobs[i].stream_id, jobs[i].frame_idx, jobs[i].rung, &job_ids[i]);
+    if (rc == MR_OK) ++*n_submitted;
+  }
+  if (*n_submitted > 0) l->cv_work.notify_all();
   return rc;
 }
 

@@ -390,14 +390,17 @@ def _ladder_lib():
         L.mr_ladder_put_frame.argtypes = [vp, i32, i32, i32, vp, i32]
         L.mr_ladder_drop_frames.argtypes = [vp, i32, i32]
         L.mr_ladder_submit.argtypes = [vp, ctypes.POINTER(mr_job), ctypes.POINTER(ctypes.c_uint64)]
+        L.mr_ladder_submit_many.argtypes = [vp, ctypes.POINTER(mr_job), i32,
+                                            ctypes.POINTER(ctypes.c_uint64),
+                                            ctypes.POINTER(i32)]
         L.mr_ladder_poll.argtypes = [vp, ctypes.POINTER(mr_completion), i32, i32,
                                      ctypes.POINTER(i32)]
         L.mr_ladder_release.argtypes = [vp, ctypes.c_uint64]
         L.mr_ladder_get_stats.argtypes = [vp, ctypes.POINTER(mr_ladder_stats)]
         L.mr_ladder_close.argtypes = [vp]
         for f in ("mr_ladder_open", "mr_ladder_put_frame", "mr_ladder_drop_frames",
-                  "mr_ladder_submit", "mr_ladder_poll", "mr_ladder_release", "mr_ladder_get_stats",
-                  "mr_ladder_close"):
+                  "mr_ladder_submit", "mr_ladder_submit_many", "mr_ladder_poll",
+                  "mr_ladder_release", "mr_ladder_get_stats", "mr_ladder_close"):
             getattr(L, f).restype = ctypes.c_int
         L._ladder_bound = True
     return L
@@ -473,6 +476,22 @@ class Ladder:
         if rc != MR_OK:
             raise MRError(rc, "mr_ladder_submit")
         return jid.value
+
+    def submit_many(self, jobs) -> list:
+        """jobs: (stream_id, frame_idx, rung) tuples, submitted together in order. On a refusal
+        raises MRError whose `submitted` holds the ids of the jobs accepted before it."""
+        jobs = list(jobs)
+        n = len(jobs)
+        arr = (mr_job * max(n, 1))(*[mr_job(s, f, r) for s, f, r in jobs])
+        ids = (ctypes.c_uint64 * max(n, 1))()
+        done = ctypes.c_int32()
+        rc = _ladder_lib().mr_ladder_submit_many(self._h, arr, n, ids, ctypes.byref(done))
+        got = [ids[i] for i in range(done.value)]
+        if rc != MR_OK:
+            err = MRError(rc, "mr_ladder_submit_many")
+            err.submitted = got
+            raise err
+        return got
 
     def poll(self, max_n=64, timeout_us=0):
         arr = (mr_completion * max_n)()

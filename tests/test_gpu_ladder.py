@@ -61,15 +61,18 @@ def _alone(mr, fr, s, f, r, ref_cache, refine=None):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def _run_mix(mr, fr, jobs, **kw):
+def _run_mix(mr, fr, jobs, many=False, **kw):
     import torch
     lad = mr.Ladder(RUNGS, **kw)
     try:
         for (s, f, r), t in fr.items():
             lad.put_frame(s, f, r, t)
         ids = {}
-        for (s, f, r) in jobs:
-            ids[lad.submit(s, f, r)] = (s, f, r)
+        if many:
+            ids = dict(zip(lad.submit_many(jobs), jobs))
+        else:
+            for (s, f, r) in jobs:
+                ids[lad.submit(s, f, r)] = (s, f, r)
         got, seen = {}, 0
         deadline = 2000
         while seen < len(ids) and deadline > 0:
@@ -103,6 +106,48 @@ def test_mix_equals_alone(mr):
         for k in FIELDS:
             assert np.array_equal(got[key][k], exp[k]), (key, k)
     assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_submit_many_equals_alone(mr):
+    """The same shuffled mix as above, handed to the server in one mr_ladder_submit_many."""
+    fr = _frames(3, 3)
+    rng = np.random.default_rng(1)
+    jobs = [(int(s), int(f), int(r)) for s in range(3) for f in (1, 2) for r in range(3)]
+    rng.shuffle(jobs)
+    got, st = _run_mix(mr, fr, jobs, many=True, max_batch_jobs=64)
+    assert st["completed"] == len(jobs) + st["implied"] and st["failed"] == 0
+    cache = {}
+    for key in jobs:
+        exp = _alone(mr, fr, *key, cache)
+        for k in FIELDS:
+            assert np.array_equal(got[key][k], exp[k]), (key, k)
+
+
+def test_submit_many_stops_at_first_refusal(mr):
+    """A rung out of range in the middle: the jobs before it stay submitted and complete, the
+    rest are not submitted, and the error names how many were accepted."""
+    fr = _frames(1, 2)
+    lad = mr.Ladder(RUNGS)
+    try:
+        for (s, f, r), t in fr.items():
+            lad.put_frame(s, f, r, t)
+        assert lad.submit_many([]) == []
+        with pytest.raises(mr.MRError) as ei:
+            lad.submit_many([(0, 1, 0), (0, 1, 1), (0, 1, 7), (0, 1, 2)])
+        assert ei.value.code == mr.MR_EINVAL
+        accepted = ei.value.submitted
+        assert len(accepted) == 2
+        seen, deadline = set(), 2000
+        while len(seen) < 2 and deadline > 0:
+            for c in lad.poll(64, 100000):
+                assert c.status == 0 and c.rung in (0, 1) and not c.implied
+                seen.add(c.job_id)
+                lad.release(c.job_id)
+            deadline -= 1
+        assert seen == set(accepted)
+        assert lad.stats()["submitted"] == 2
+    finally:
+        lad.close()
 
 
 def test_many_dependents_per_batch_equal_alone(mr):

@@ -233,3 +233,14 @@ def test_host_lambda_and_bits_match_the_oracle():
         assert L.mr_sqrt_lambda_q16(qp) == oracle.sqrt_lambda_q16(qp), qp
     for v in range(-1100, 1101):
         assert L.mr_se_bits(v) == oracle.se_bits(v), v
+
+
+def test_ladder_submit_many_argument_errors(libmr):
+    from paper_2301_12191_amd import mr
+    L = mr._ladder_lib()
+    n = ctypes.c_int32(7)
+    jobs = (mr.mr_job * 1)(mr.mr_job(0, 1, 0))
+    ids = (ctypes.c_uint64 * 1)()
+    assert L.mr_ladder_submit_many(None, jobs, 1, ids, ctypes.byref(n)) == mr.MR_EINVAL
+    assert n.value == 0  # the count is written even when the call is refused
+    assert L.mr_ladder_submit_many(None, jobs, 1, ids, None) == mr.MR_EINVAL
