@@ -210,7 +210,9 @@ int mr_batch_destroy(mr_batch* b);
  * run, batches up to max_batch_jobs of them into one persistent search launch,
  * keeps up to four batches in flight, and releases dependents as references
  * are launched (continuous batching).  Done reference jobs stay resident for later
- * dependents until their memory is needed.  With reuse_mv, a dependent's
+ * dependents until their memory is needed.  The output blocks of finished jobs
+ * are kept for reuse by later jobs of the same size, up to 512 MiB beyond the
+ * admission budget, until mr_ladder_close.  With reuse_mv, a dependent's
  * search is also seeded with its reference job's MV map.  Each rung may carry
  * its own policy (own_policy), so that one configuration holds both
  * cross-resolution and same-resolution (multi-QP) edges, e.g. the

@@ -44,6 +44,7 @@ static void unref(SharedEvent* e) {
 
 struct JobOut {
   uint8_t* mem = nullptr;  // one allocation: outputs then bounds
+  size_t bytes = 0;
   mr_search_out out{};
   uint8_t* bounds = nullptr;
   hipStream_t stream = nullptr;   // stream that wrote it
@@ -68,6 +69,9 @@ class GpuExecutor : public Executor {
   }
 
   ~GpuExecutor() override {
+    // Cached blocks came from the stream-ordered allocator: free them the same way.
+    if (streams_[0])
+      for (auto& kv : pool_) (void)hipFreeAsync(kv.second, streams_[0]);
     for (auto& s : streams_)
       if (s) {
         (void)hipStreamSynchronize(s);
@@ -179,10 +183,12 @@ class GpuExecutor : public Executor {
       JobOut* o = new JobOut();
       size_t off[7];
       const size_t bytes = out_bytes(r, j.ref_job != 0, off);
-      if (hipMallocAsync((void**)&o->mem, bytes, st) != hipSuccess) {
+      o->mem = take_block(bytes);
+      if (!o->mem && hipMallocAsync((void**)&o->mem, bytes, st) != hipSuccess) {
         delete o;
         return MR_ENOMEM;
       }
+      o->bytes = bytes;
       o->stream = st;
       o->out = mr_search_out{o->mem + off[0], o->mem + off[1], (int16_t*)(o->mem + off[2]),
                              (int64_t*)(o->mem + off[3]), (int64_t*)(o->mem + off[4]),
@@ -262,10 +268,20 @@ class GpuExecutor : public Executor {
     for (SchedJob* j : jobs) j->status = MR_OK;
   }
 
+  // A job that succeeded and whose batch has retired is freed only once every
+  // dependent has completed, so no work in flight reads its block: the block
+  // goes to a per-size cache for later jobs (a serving loop allocates the same
+  // few sizes over and over) instead of back to the allocator.  Other blocks
+  // are freed in the order of the stream that wrote them.
   void free_job(SchedJob& j) override {
     JobOut* o = (JobOut*)j.exec_state;
     if (!o) return;
-    (void)hipFreeAsync(o->mem, o->stream);
+    if (j.state == kDone && !o->batch_running && pool_bytes_ + o->bytes <= kPoolMaxBytes) {
+      pool_.emplace(o->bytes, o->mem);
+      pool_bytes_ += o->bytes;
+    } else {
+      (void)hipFreeAsync(o->mem, o->stream);
+    }
     unref(o->batch);
     delete o;
   }
@@ -279,6 +295,19 @@ class GpuExecutor : public Executor {
 
  private:
   SchedConfig cfg_;
+  // A cached block of exactly `bytes`, or null.
+  uint8_t* take_block(size_t bytes) {
+    auto it = pool_.find(bytes);
+    if (it == pool_.end()) return nullptr;
+    uint8_t* m = it->second;
+    pool_.erase(it);
+    pool_bytes_ -= bytes;
+    return m;
+  }
+
+  static constexpr size_t kPoolMaxBytes = size_t(512) << 20;
+  std::multimap<size_t, uint8_t*> pool_;  // retired output blocks by size
+  size_t pool_bytes_ = 0;
   int device_ = 0;
   hipStream_t streams_[2] = {nullptr, nullptr};
   unsigned next_ = 0;
