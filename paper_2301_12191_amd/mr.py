@@ -106,6 +106,10 @@ def lib():
         L.mr_profile_enable.argtypes = [ctypes.c_int]
         L.mr_profile_read.restype = ctypes.c_int
         L.mr_profile_read.argtypes = [ctypes.POINTER(mr_profile), ctypes.c_int]
+        L.mr_sqrt_lambda_q16.restype = ctypes.c_int64
+        L.mr_sqrt_lambda_q16.argtypes = [i32]
+        L.mr_se_bits.restype = ctypes.c_int32
+        L.mr_se_bits.argtypes = [i32]
         _lib = L
     return _lib
 

@@ -37,6 +37,40 @@ def test_lambda_anchor_and_doubling():
     assert all(a < b for a, b in zip(s, s[1:]))
 
 
+def _sqrt_lambda_q16_exact(qp):
+    """round(sqrt(lambda) * 65536), lambda = 0.57 * 2^((QP - 12) / 3), in exact integer
+    arithmetic (no libm): x = sqrt(lambda) * 2^16 satisfies x^6 = 0.57^3 * 2^(QP - 12) * 2^96,
+    a rational number, so floor(2x) is an integer 6th root and round(x) = (floor(2x) + 1) // 2."""
+    num, den = 64 * 57 ** 3 * 2 ** (qp + 84), 10 ** 6  # (2x)^6 = num / den
+    lo, hi = 0, 1 << 30
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if mid ** 6 * den <= num:
+            lo = mid
+        else:
+            hi = mid - 1
+    return (lo + 1) // 2
+
+
+# The multipliers of the QPs the workloads use (QP 12 and the ladder's 22/27/30/32/35/37).
+S_TABLE = {12: 49479, 22: 157085, 27: 279893, 30: 395829, 32: 498713, 35: 705287, 37: 888606}
+
+
+def test_lambda_table_exact_all_qps():
+    """Every one of the 52 multipliers, in the oracle and in libmr's host code, equals the
+    exact integer rounding of sqrt(0.57 * 2^((QP - 12) / 3)) * 65536, so no libm difference
+    (pow vs exp2, float vs double) can shift an integer cost by one."""
+    from paper_2301_12191_amd import mr
+    L = mr.lib()
+    exact = [_sqrt_lambda_q16_exact(q) for q in range(52)]
+    for q, v in S_TABLE.items():
+        assert exact[q] == v, q
+    for q in range(52):
+        assert oracle.sqrt_lambda_q16(q) == exact[q], q
+        assert L.mr_sqrt_lambda_q16(q) == exact[q], q
+    assert L.mr_sqrt_lambda_q16(-1) == -1 and L.mr_sqrt_lambda_q16(52) == -1
+
+
 def _exp_golomb_lengths(limit):
     """Codeword lengths of ue(k), by enumerating the code tree: 2^L codewords of length 2L+1."""
     lengths = []
