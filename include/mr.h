@@ -59,7 +59,8 @@ typedef enum {
   MR_EDEPEND = -4,  /* ladder: reference job missing and not implied */
   MR_EHIP = -5,     /* a HIP runtime call failed */
   MR_ETIMEOUT = -6, /* ladder: poll timed out with no completion */
-  MR_ESTATE = -7    /* call not valid in the object's current state */
+  MR_ESTATE = -7,   /* call not valid in the object's current state */
+  MR_ESCRATCH = -8  /* mr_ctu_search_noalloc: the call needs more than its fixed scratch */
 } mr_status;
 
 /* One 8-bit luma picture: device pointer, width x height samples, row stride
@@ -149,6 +150,35 @@ typedef struct {
 int mr_ctu_search_seeded(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
                          const uint8_t* bounds, const mr_mv_seed* seed, mr_search_out* out,
                          void* hip_stream);
+
+/* Allocation-free variant of mr_ctu_search_seeded, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * hosts that forbid allocation): same arguments, checks, results and stream
+ * semantics, but every kernel's scratch (job descriptor, queue counters,
+ * arg-min key tables, packed CTUs, keys, eligibility, and for seeded or
+ * sub-pel searches the padded reference) lives in one file-scope device array
+ * of MR_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; the key
+ * tables are built on the device in each call.  No hipMalloc, hipFree,
+ * stream-ordered allocation or host-to-device copy is made, and stage
+ * profiling (mr_profile_enable) does not apply.  The caller still owns the
+ * frames, bounds, seed map and outputs.
+ * Every call on one GPU shares that GPU's array: calls on one stream run in
+ * order, but calls that overlap on one GPU (different streams or host
+ * threads without ordering) race and corrupt each other's results.  The
+ * array keeps the last call's contents; what must start at zero is cleared
+ * by the call's own kernels.
+ * Size: under 1 KiB of descriptor and counters; the key tables of a full or
+ * bounded search (at most 1.4 MiB, at R 128); per 64x64 CTU about 4.8 KiB
+ * (+ 680 bytes with sub-pel); and (H8 + 2R + 16) x (W8 + 2P) bytes for a
+ * seeded or sub-pel search (P as for mr_ctu_search_seeded).  A 3840x2160
+ * search at R 128 fits with or without sub-pel or seed (23 MB at most);
+ * larger requests are refused.
+ * Errors: those of mr_ctu_search_seeded (without MR_ENOMEM), and MR_ESCRATCH
+ * (before any launch) when the request does not fit the array. */
+#define MR_NOALLOC_SCRATCH_BYTES ((uint64_t)24 << 20)
+int mr_ctu_search_noalloc(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
+                          const uint8_t* bounds, const mr_mv_seed* seed, mr_search_out* out,
+                          void* hip_stream);
 
 /* One frame pair of a batch (same meaning as the mr_ctu_search_seeded
  * arguments; seed points to host memory and NULL means full search). */

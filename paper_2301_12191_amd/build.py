@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmr.so")
-SOURCES = ["mr_kernels.hip", "mr_refine.hip", "mr_subpel.hip", "mr_runtime.cpp", "mr_batch.cpp", "mr_tune.cpp", "mr_sched.cpp",
+SOURCES = ["mr_kernels.hip", "mr_refine.hip", "mr_subpel.hip", "mr_noalloc.hip", "mr_runtime.cpp", "mr_batch.cpp", "mr_tune.cpp", "mr_sched.cpp",
            "mr_ladder.cpp"]
 
 HIPCC_FLAGS = [

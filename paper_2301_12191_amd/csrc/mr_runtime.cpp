@@ -380,9 +380,11 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     TileConfig tj;
     if (get_tile_override(R, &tj) && tj.D == P->D && tj.nbands) nb = tj.nbands;
     const SearchLayout L = make_layout(R, P->D, nb);
-    KeyTables kt;
-    const int rc = get_key_tables(p[j]->qp, L, &kt);
-    if (rc != MR_OK) return rc;
+    KeyTables kt{nullptr, nullptr};
+    if (!P->defer_tables) {
+      const int rc = get_key_tables(p[j]->qp, L, &kt);
+      if (rc != MR_OK) return rc;
+    }
     jb.D = P->D;
     jb.Q = L.Q;
     jb.ntasks = L.ntasks;
@@ -553,6 +555,7 @@ const char* mr_status_str(int status) {
     case MR_EHIP: return "MR_EHIP: HIP runtime error";
     case MR_ETIMEOUT: return "MR_ETIMEOUT: timed out";
     case MR_ESTATE: return "MR_ESTATE: invalid state for this call";
+    case MR_ESCRATCH: return "MR_ESCRATCH: request exceeds the fixed scratch of the allocation-free search";
     default: return "unknown mr_status";
   }
 }

@@ -60,6 +60,9 @@ struct Plan {
   int n_sjobs = 0, n_sctus = 0;
   int max_pad_rows = 0;  // rows of the largest padded reference
   QueueOffsets qoff{};   // search items of each per-XCD queue
+  // Input to make_plan: true leaves the jobs' key tables (qtab, dtab) null
+  // for the caller to place and fill, instead of the cached device copies.
+  bool defer_tables = false;
 };
 
 // Build a plan.  seeds: null, or per job a seed (null entry = full search);

@@ -18,6 +18,9 @@ _lib = None
 
 MR_OK, MR_EINVAL, MR_ENOMEM, MR_EAGAIN, MR_EDEPEND, MR_EHIP, MR_ETIMEOUT, MR_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
+MR_ESCRATCH = -8
+# Size of the per-GPU device array of mr_ctu_search_noalloc.
+NOALLOC_SCRATCH_BYTES = 24 << 20
 
 
 class MRError(RuntimeError):
@@ -83,6 +86,8 @@ def lib():
                                            ctypes.POINTER(mr_search_params), vp,
                                            ctypes.POINTER(mr_mv_seed),
                                            ctypes.POINTER(mr_search_out), vp]
+        L.mr_ctu_search_noalloc.restype = ctypes.c_int
+        L.mr_ctu_search_noalloc.argtypes = L.mr_ctu_search_seeded.argtypes
         L.mr_depth_bounds.restype = ctypes.c_int
         L.mr_depth_bounds.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
         L.mr_ctu_search_batch.restype = ctypes.c_int
@@ -205,6 +210,25 @@ def mr_ctu_search(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: i
         where = "mr_ctu_search_seeded"
     if rc != MR_OK:
         raise MRError(rc, where)
+    return out
+
+
+def mr_ctu_search_noalloc(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: int,
+                          out: dict, bounds: torch.Tensor | None = None, stream=None,
+                          seed: dict | None = None, subpel: bool = False):
+    """The allocation-free search (mr_ctu_search_noalloc in include/mr.h): the caller passes
+    the outputs; the library allocates nothing.  Same arguments and results as
+    mr_ctu_search."""
+    fc, fr = _frame(cur, "cur"), _frame(ref, "ref")
+    prm = mr_search_params(qp, search_range, 1 if subpel else 0)
+    o = _out_struct(out)
+    bp = None if bounds is None else _dev_ptr(bounds, torch.uint8, "bounds")
+    sd = _seed_struct(seed)
+    rc = lib().mr_ctu_search_noalloc(ctypes.byref(fc), ctypes.byref(fr), ctypes.byref(prm), bp,
+                                     None if sd is None else ctypes.byref(sd), ctypes.byref(o),
+                                     _stream_handle(stream))
+    if rc != MR_OK:
+        raise MRError(rc, "mr_ctu_search_noalloc")
     return out
 
 

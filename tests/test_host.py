@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol(libmr):
 
 def test_status_strings(libmr):
     from paper_2301_12191_amd import mr
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         assert mr.mr_status_str(code).startswith("MR_")
     assert "unknown" in mr.mr_status_str(-99)
 
@@ -85,6 +85,28 @@ def test_search_rejects_invalid_arguments_before_launch(libmr, case):
     rc = libmr.mr_ctu_search(ctypes.byref(cur), ctypes.byref(ref), ctypes.byref(prm), None,
                              ctypes.byref(out), None)
     assert rc == mr.MR_EINVAL
+    rc = libmr.mr_ctu_search_noalloc(ctypes.byref(cur), ctypes.byref(ref), ctypes.byref(prm),
+                                     None, None, ctypes.byref(out), None)
+    assert rc == mr.MR_EINVAL
+
+
+@pytest.mark.parametrize("w,h,R,subpel,seeded", [
+    (8192, 4320, 128, 0, False),  # 8,704 CTUs of packed current samples alone exceed the array
+    (4608, 2592, 128, 1, False),  # 14.4 MB of CTU scratch fits; the padded reference of
+    (4608, 2592, 64, 0, True),    # sub-pel or a seed (over 13 MB) does not
+])
+def test_noalloc_rejects_requests_beyond_its_scratch(libmr, w, h, R, subpel, seeded):
+    """The allocation-free search refuses (MR_ESCRATCH) a request whose scratch exceeds its
+    fixed array, before touching the device (the frame pointers here are never read)."""
+    from paper_2301_12191_amd import mr
+    cur, ref = _fake_frame(mr, w, h), _fake_frame(mr, w, h)
+    prm = mr.mr_search_params(30, R, subpel)
+    seed = mr.mr_mv_seed(ctypes.c_void_p(0x3000), w // 2, h // 2, 4, 0) if seeded else None
+    rc = libmr.mr_ctu_search_noalloc(ctypes.byref(cur), ctypes.byref(ref), ctypes.byref(prm),
+                                     None, ctypes.byref(seed) if seed else None,
+                                     ctypes.byref(_fake_out(mr)), None)
+    assert rc == mr.MR_ESCRATCH
+    assert "scratch" in mr.mr_status_str(rc)
 
 
 def test_search_rejects_null_structs(libmr):
