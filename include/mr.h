@@ -361,21 +361,31 @@ int mr_depth_bounds(const uint8_t* ref_depth, int32_t ref_w, int32_t ref_h, int3
                     void* hip_stream);
 
 /* Tile override for one search range R (an autotuner knob): the search
- * kernel gives each lane 4 horizontal x d vertical candidate shifts (d = 2, 4
- * or 8) and splits the search window into nbands dy bands (1..8), one
+ * kernel gives each lane 4 horizontal x d vertical candidate shifts (d = 2, 4,
+ * 5, 6 or 8) and splits the search window into nbands dy bands (1..8), one
  * workgroup per (CTU, band).  d = 0 removes the override (built-in choice).
  * Results are identical for every setting; only speed changes.
- * Errors: MR_EINVAL (R outside 0..128, d not 0/2/4/8, nbands outside 1..8). */
+ * Errors: MR_EINVAL (R outside 0..128, d not 0/2/4/5/6/8, nbands outside
+ * 1..8). */
 int mr_set_tiles(int32_t search_range, int32_t d, int32_t nbands);
 /* Same with the strip width (CTUs per workgroup, 1..4; 0 = built-in). */
 int mr_set_tiles3(int32_t search_range, int32_t d, int32_t nbands, int32_t strip);
+/* Same with the work split: split = 1 gives each wavefront a whole CTU (a
+ * workgroup searches a strip of CTUs), split = 2 gives the four wavefronts of
+ * a workgroup the four 32x32 quadrants of one CTU (the 64x64 SAD is summed
+ * across them in LDS), which spreads small search ranges over four times as
+ * many wavefronts; 0 = built-in (split for R <= 64).  nbands 0 = built-in.
+ * A batch with split jobs runs strips of 4 for its other jobs.
+ * Errors: MR_EINVAL (as mr_set_tiles3, nbands 0..8, split outside 0..2). */
+int mr_set_tiles4(int32_t search_range, int32_t d, int32_t nbands, int32_t strip, int32_t split);
 
 /* Autotuner.  Times tile shapes of the search kernel on the given batch (the
  * jobs a later mr_batch_create / mr_ctu_search_batch will run) and installs
  * the fastest as the tile override of the batch's dominant search range (the
- * job with the most candidate work).  Coarse-to-fine: d in {2, 4, 8} at the
- * built-in band count, then nbands 1..8 for the best d, then strip (CTUs per
- * workgroup) in {1, 2, 3, 4}.  Each shape is run once to warm up and then `reps`
+ * job with the most candidate work).  Coarse-to-fine: d in {2, 4, 5, 6, 8} x split
+ * in {1, 2} (mr_set_tiles4) at the built-in band count, then nbands 1..8 for
+ * the best pair, then, for split = 1, strip (CTUs per workgroup) in
+ * {1, 2, 3, 4}.  Each shape is run once to warm up and then `reps`
  * times (1..20) with HIP events around the search kernel; the minimum counts.
  * Blocking; overwrites the jobs' outputs.  *out receives the choice.
  * Errors: MR_EINVAL, MR_ENOMEM, MR_EHIP. */
@@ -384,6 +394,7 @@ typedef struct {
   double search_ms;  /* best measured search-kernel time */
   double default_ms; /* time of the built-in choice */
   int32_t tried;     /* shapes measured */
+  int32_t split;     /* 1 whole CTU, 2 quadrant per wavefront (mr_set_tiles4) */
 } mr_tune_result;
 int mr_autotune(const mr_search_job* jobs, int32_t n_jobs, int32_t reps, mr_tune_result* out);
 

@@ -13,6 +13,11 @@ constexpr uint32_t kCinv = 1050000u;  // cost field of candidates outside the wi
 constexpr uint64_t kKeyNone = ~0ull;
 constexpr int kMaxStrip = 4;        // CTUs (wavefronts) per search workgroup
 constexpr int kCurRingBytes = 512;  // per wavefront: two 16x16 regions of the current CTU
+constexpr int kSplitWaves = 4;      // wavefronts of a split search item (one per quadrant)
+
+// LDS dwords of the 64x64 SAD exchange of a split search item: two buffers
+// (alternate steps) of three wavefronts x 64 lanes x 4D candidate sums.
+__host__ __device__ constexpr int xch_dwords(int D) { return 2 * 3 * 64 * 4 * D; }
 
 // Column margin of the padded reference of a seeded job with range R: the
 // refinement loads reach 3 bytes left of -R and 20 bytes right of w8 - 8 + R.
@@ -71,7 +76,9 @@ struct JobDesc {
   int32_t ntasks;          // search tasks per CTU (see SearchLayout)
   int32_t corner;          // 1: keys start at the (R, R) candidate's (prep kernel)
   int32_t win_dwords;      // LDS window row length in dwords: Q + 16 * strip
-  int32_t strip;           // CTUs per search workgroup (one wavefront each)
+  int32_t strip;           // CTUs per search workgroup (one wavefront each); 1 if split
+  int32_t split;           // 1: a search item is one CTU whose quadrants go to the
+                           // workgroup's four wavefronts
   int32_t ctu_start;       // first flattened CTU index of this job in its batch
   int32_t band_g0[kMaxBands + 1];
   int32_t band_step0[kMaxBands + 1];

@@ -176,24 +176,45 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
 // window is column-major with an odd pitch hs: dword column c, row r at
 // c * hs + r, so the rows a search lane walks are immediate offsets of its
 // column addresses, and lanes on consecutive columns hit distinct banks.
+// Each thread owns one dword column and every per-th row of it (per = the
+// workgroup's threads / Wd, at least 1), so the column's clamping is decided
+// once; four rows are loaded before any is stored, keeping four loads in
+// flight per thread.
 __device__ void stage_window(cjob jb, int x0, int y0, int rows, int hs, uint32_t* win) {
   const int Wd = jb->win_dwords, w = jb->w, h = jb->h, stride = jb->stride;
   const uint8_t* ref = jb->ref;
   const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0) && ((x0 & 3) == 0);
-  const int total = rows * Wd;
-  for (int i = threadIdx.x; i < total; i += blockDim.x) {
-    const int row = i / Wd, c4 = (i - row * Wd) * 4;
-    const uint8_t* rp = ref + (size_t)clampi(y0 + row, 0, h - 1) * stride;
-    const int x = x0 + c4;
-    uint32_t v;
+  const int nthr = blockDim.x;
+  const int per = max(1, nthr / Wd);
+  for (int pair = threadIdx.x; pair < per * Wd; pair += nthr) {
+    const int p = pair / Wd, c = pair - p * Wd;
+    const int x = x0 + 4 * c;
+    uint32_t* dst = win + c * hs;
     if (dword_ok && x >= 0 && x + 3 < w) {
-      v = *(const uint32_t*)(rp + x);
-    } else {
-      v = 0;
+      const uint8_t* base = ref + x;
+      int r = p;
+      for (; r + 3 * per < rows; r += 4 * per) {
+        uint32_t v[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[clampi(x + b, 0, w - 1)] << (8 * b);
+        for (int u = 0; u < 4; ++u)
+          v[u] = *(const uint32_t*)(base + (size_t)clampi(y0 + r + u * per, 0, h - 1) * stride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dst[r + u * per] = v[u];
+      }
+      for (; r < rows; r += per)
+        dst[r] = *(const uint32_t*)(base + (size_t)clampi(y0 + r, 0, h - 1) * stride);
+    } else {
+      int xb[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) xb[b] = clampi(x + b, 0, w - 1);
+      for (int r = p; r < rows; r += per) {
+        const uint8_t* rp = ref + (size_t)clampi(y0 + r, 0, h - 1) * stride;
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v |= (uint32_t)rp[xb[b]] << (8 * b);
+        dst[r] = v;
+      }
     }
-    win[(i - row * Wd) * hs + row] = v;
   }
 }
 
@@ -210,9 +231,18 @@ __device__ __forceinline__ void merge_keys(uint32_t vk, const uint64_t* __restri
 // this CTU's column 0 of the staged window (dx = -R), whose dword columns are
 // hs apart; `ring` is this wavefront's 512-byte LDS ring for the current CTU
 // (two 16x16 regions of 64 dwords).
-template <int D>
+//
+// SPLIT: the workgroup's four wavefronts take the four 32x32 quadrants of one
+// CTU (quadrant = wavefront index), each over the same steps, so a CTU's work
+// is spread over four SIMDs instead of one.  The 8x8..32x32 CUs lie inside a
+// quadrant; the 64x64 CU's SAD per candidate is the sum of the four quadrant
+// SADs, exchanged through LDS (`xch`, two buffers alternating by step, so one
+// barrier per step suffices) and keyed by wavefront 0.
+template <int D, bool SPLIT>
 __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, const uint32_t* win,
-                            int hs, uint32_t* ring) {
+                            int hs, uint32_t* ring, int quad, uint32_t* xch) {
+  constexpr int NREG = SPLIT ? 4 : 16;
+  const int reg0 = SPLIT ? 4 * quad : 0;
   const int lane = threadIdx.x & 63;
   const int Q = jb->Q;
   const int g0 = jb->band_g0[band];  // group of the band's first task: window row 0
@@ -248,13 +278,15 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
       for (int k = 0; k < 4; ++k) s64[j][k] = 0;
     uint32_t vk8 = 0xFFFFFFFFu, vkB = 0xFFFFFFFFu;
-    // Region 0 of the current CTU into the ring; later regions are fetched one
-    // region ahead (global load now, LDS write after the region's compute).
-    ring[lane] = cur[lane];
-    uint32_t pre = cur[64 + lane];
+    // The first region of the current CTU into the ring; later regions are
+    // fetched one region ahead (global load now, LDS write after the region's
+    // compute).
+    ring[lane] = cur[reg0 * 64 + lane];
+    uint32_t pre = cur[(reg0 + 1) * 64 + lane];
 
-    for (int reg = 0; reg < 16; ++reg) {
-      const uint32_t* rcur = ring + (reg & 1) * 64;
+    for (int rr = 0; rr < NREG; ++rr) {
+      const int reg = reg0 + rr;
+      const uint32_t* rcur = ring + (rr & 1) * 64;
       uint32_t m8[4];  // per-lane minimum key of each 8x8 block of the region
       // The region's window columns 4 zx(reg) + 0..4 from row 16 zy(reg): the
       // left blocks read columns 0..2, the right ones 2..4, the lower ones 8
@@ -335,9 +367,9 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
         vk8 = (lane >> 2) == reg ? r : vk8;
       }
       // Next-but-one region into the slot this region used.
-      if (reg < 15) {
-        ring[((reg + 1) & 1) * 64 + lane] = pre;
-        if (reg < 14) pre = cur[(reg + 2) * 64 + lane];
+      if (rr < NREG - 1) {
+        ring[((rr + 1) & 1) * 64 + lane] = pre;
+        if (rr < NREG - 2) pre = cur[(reg + 2) * 64 + lane];
       }
       {  // 16x16 CU of this region (nodes 5..20)
         const int lx = zx(reg), ly = zy(reg);
@@ -372,13 +404,42 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
           const uint32_t mk = wave_min(m);
           vkB = set_lane(vkB, mk, 16 + qz);
         }
+        if (!SPLIT) {
 #pragma unroll
-        for (int j = 0; j < D; ++j)
+          for (int j = 0; j < D; ++j)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) s64[j][k] += s32[j][k];
+            for (int k = 0; k < 4; ++k) s64[j][k] += s32[j][k];
+        }
       }
     }
-    if (em0 & 1u) {  // 64x64 CU (node 0)
+    if (SPLIT) {
+      // s32 holds this quadrant's SADs; the 64x64 SAD is the sum over the
+      // four wavefronts.  The condition is uniform over the workgroup.
+      if (em0 & 1u) {
+        uint32_t* xb = xch + (st & 1) * (3 * 64 * 4 * D);
+        if (quad != 0) {
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) xb[((quad - 1) * 4 * D + j * 4 + k) * 64 + lane] = s32[j][k];
+        }
+        __syncthreads();
+        if (quad == 0) {
+          uint32_t m = 0xFFFFFFFFu;
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int jk = j * 4 + k;
+              const uint32_t t = s32[j][k] + xb[jk * 64 + lane] + xb[(4 * D + jk) * 64 + lane] +
+                                 xb[(8 * D + jk) * 64 + lane];
+              m = min(m, t * 2048u + kq[j][k]);
+            }
+          const uint32_t mk = wave_min(m);
+          vkB = set_lane(vkB, mk, 20);
+        }
+      }
+    } else if (em0 & 1u) {  // 64x64 CU (node 0)
       uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
       for (int j = 0; j < D; ++j)
@@ -907,14 +968,23 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
     __syncthreads();
     // This wavefront's current-CTU ring follows the largest window of the launch.
     uint32_t* ring = win + win_dwords_max + wave * (kCurRingBytes / 4);
-    const int nw = jb->strip, sw = min(nw, jb->ctus_w - col0);
     const int nst = jb->band_step0[band + 1] - jb->band_step0[band];
-    int lo = wave * sw * nst / nw;
-    const int hi = (wave + 1) * sw * nst / nw;
-    while (lo < hi) {
-      const int c = lo / nst, s0 = lo - c * nst, s1 = min(nst, s0 + (hi - lo));
-      search_wave<D>(jb, row * jb->ctus_w + col0 + c, band, s0, s1, win + 16 * c * hs, hs, ring);
-      lo += s1 - s0;
+    if (jb->split) {
+      // One CTU; the four wavefronts take its quadrants over all the band's
+      // steps.  The 64x64 exchange sits at the end of the window area, past
+      // this job's window (the plan sizes the area for both).
+      search_wave<D, true>(jb, row * jb->ctus_w + col0, band, 0, nst, win, hs, ring, wave,
+                           win + win_dwords_max - xch_dwords(D));
+    } else {
+      const int nw = jb->strip, sw = min(nw, jb->ctus_w - col0);
+      int lo = wave * sw * nst / nw;
+      const int hi = (wave + 1) * sw * nst / nw;
+      while (lo < hi) {
+        const int c = lo / nst, s0 = lo - c * nst, s1 = min(nst, s0 + (hi - lo));
+        search_wave<D, false>(jb, row * jb->ctus_w + col0 + c, band, s0, s1, win + 16 * c * hs,
+                              hs, ring, 0, nullptr);
+        lo += s1 - s0;
+      }
     }
     __syncthreads();  // the window is restaged for the next item
   }
@@ -961,6 +1031,8 @@ static const void* search_fn(int D) {
   switch (D) {
     case 2: return (const void*)search_kernel<2>;
     case 4: return (const void*)search_kernel<4>;
+    case 5: return (const void*)search_kernel<5>;
+    case 6: return (const void*)search_kernel<6>;
     case 8: return (const void*)search_kernel_d8;
     default: return nullptr;
   }
@@ -989,6 +1061,8 @@ hipError_t launch_search(const JobDesc* jobs, const uint2* items, const QueueOff
   switch (D) {
     case 2: hipLaunchKernelGGL(search_kernel<2>, grid, block, lds_bytes, st, jobs, items, qoff, counter, win_dwords_max); break;
     case 4: hipLaunchKernelGGL(search_kernel<4>, grid, block, lds_bytes, st, jobs, items, qoff, counter, win_dwords_max); break;
+    case 5: hipLaunchKernelGGL(search_kernel<5>, grid, block, lds_bytes, st, jobs, items, qoff, counter, win_dwords_max); break;
+    case 6: hipLaunchKernelGGL(search_kernel<6>, grid, block, lds_bytes, st, jobs, items, qoff, counter, win_dwords_max); break;
     case 8: hipLaunchKernelGGL(search_kernel_d8, grid, block, lds_bytes, st, jobs, items, qoff, counter, win_dwords_max); break;
     default: return hipErrorInvalidValue;
   }

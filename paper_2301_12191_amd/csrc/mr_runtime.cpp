@@ -28,12 +28,15 @@ TileConfig g_tile_override[129];  // D == 0: none
 }  // namespace
 
 int set_tile_override(int R, const TileConfig& tc) {
-  if (R < 0 || R > 128 || !(tc.D == 0 || tc.D == 2 || tc.D == 4 || tc.D == 8)) return MR_EINVAL;
+  if (R < 0 || R > 128 ||
+      !(tc.D == 0 || tc.D == 2 || tc.D == 4 || tc.D == 5 || tc.D == 6 || tc.D == 8))
+    return MR_EINVAL;
   if (tc.D != 0 && (tc.nbands < 0 || tc.nbands > kMaxBands || tc.strip < 0 ||
                     tc.strip > kMaxStrip))
     return MR_EINVAL;
+  if (tc.split < 0 || tc.split > 2) return MR_EINVAL;
   std::lock_guard<std::mutex> lk(g_tile_mu);
-  g_tile_override[R] = tc.D ? tc : TileConfig{0, 0, 0};
+  g_tile_override[R] = tc.D ? tc : TileConfig{0, 0, 0, 0};
   return MR_OK;
 }
 
@@ -44,7 +47,16 @@ bool get_tile_override(int R, TileConfig* tc) {
   return true;
 }
 
-static int default_D(int R) { return R < 20 ? 2 : 4; }
+// Vertical shifts per lane when nothing overrides them, by the batch's
+// dominant range R and its CTU count: the D whose steps waste the fewest
+// lanes on candidates outside the window, where its registers allow three
+// wavefronts per SIMD.  A small single picture at R < 20 keeps D = 2: three
+// steps per CTU give its few CTUs three times as many work items.
+int default_D(int R, int64_t ctus) {
+  if (R < 20) return ctus < 256 ? 2 : 5;
+  if (R >= 40 && R <= 56) return 5;
+  return 4;
+}
 
 SearchLayout make_layout(int R, int D, int nbands) {
   SearchLayout L;
@@ -83,15 +95,18 @@ size_t window_bytes(const SearchLayout& L, int strip) {
 }
 
 int choose_bands(int R, int D, int strip, int ctus_w, int ctus_h, size_t lds_budget,
-                 int min_items) {
+                 int min_items, int min_steps_per_band) {
   const int S = make_layout(R, D, 1).total_steps;
   int nb = 1;
   while (nb < kMaxBands && nb < S && window_bytes(make_layout(R, D, nb), strip) > lds_budget) ++nb;
   const int64_t strips = (int64_t)((ctus_w + strip - 1) / strip) * ctus_h;
-  while (min_items > 0 && nb < kMaxBands && strips * nb < min_items && (S + nb) / (nb + 1) >= 2)
+  while (min_items > 0 && nb < kMaxBands && strips * nb < min_items &&
+         (S + nb) / (nb + 1) >= min_steps_per_band)
     ++nb;
   return nb;
 }
+
+bool default_split(int R) { return R <= 64; }
 
 // LDS budget per search workgroup: three workgroups per CU (the window plus
 // a 512-byte current-CTU ring per wavefront).
@@ -294,10 +309,26 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     if (work > heavy_work) heavy_work = work, heavy = j;
     max_ctus_w = std::max(max_ctus_w, ((cur[j]->width + 7) / 8 * 8 + 63) / 64);
   }
-  TileConfig tc{0, 0, 0};
+  TileConfig tc{0, 0, 0, 0};
   const bool ov = get_tile_override(p[heavy]->search_range, &tc);
-  P->D = ov ? tc.D : default_D(p[heavy]->search_range);
+  int64_t fs_ctus = 0;  // CTUs of the full-search jobs
+  for (int j = 0; j < n_jobs; ++j)
+    if (!seed_of(j))
+      fs_ctus += (int64_t)(((cur[j]->width + 7) / 8 * 8 + 63) / 64) *
+                 (((cur[j]->height + 7) / 8 * 8 + 63) / 64);
+  P->D = ov ? tc.D : default_D(p[heavy]->search_range, fs_ctus);
   P->strip = (ov && tc.strip) ? tc.strip : std::min(kMaxStrip, max_ctus_w);
+  // Split jobs need a workgroup of four wavefronts; a batch with some keeps
+  // strips of four for its other jobs.
+  auto split_of = [&](int R) {
+    TileConfig t;
+    const int sp = get_tile_override(R, &t) ? t.split : 0;
+    return sp == 2 || (sp == 0 && default_split(R));
+  };
+  bool any_split = false;
+  for (int j = 0; j < n_jobs; ++j)
+    if (!seed_of(j) && split_of(p[j]->search_range)) any_split = true;
+  if (any_split) P->strip = kMaxStrip;
   P->n_jobs = n_jobs;
   P->jobs.assign(n_jobs, JobDesc{});
   P->job_off.assign(n_jobs, 0);
@@ -376,7 +407,14 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
       P->max_r = std::max(P->max_r, jb.seed_r);
       continue;
     }
-    int nb = choose_bands(R, P->D, P->strip, jb.ctus_w, jb.ctus_h, kLdsBudget, min_items);
+    // A split job is searched one CTU per workgroup (window of one CTU) and
+    // its bands may be single steps: each item is a quarter CTU per wavefront.
+    const bool split = split_of(R);
+    const size_t xch_bytes = split ? (size_t)xch_dwords(P->D) * 4 : 0;
+    const size_t ring_extra = split ? (size_t)kCurRingBytes * (kSplitWaves - 1) : 0;
+    int nb = split ? choose_bands(R, P->D, 1, jb.ctus_w, jb.ctus_h,
+                                  kLdsBudget - xch_bytes - ring_extra, min_items, 1)
+                   : choose_bands(R, P->D, P->strip, jb.ctus_w, jb.ctus_h, kLdsBudget, min_items);
     TileConfig tj;
     if (get_tile_override(R, &tj) && tj.D == P->D && tj.nbands) nb = tj.nbands;
     const SearchLayout L = make_layout(R, P->D, nb);
@@ -390,16 +428,20 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     jb.ntasks = L.ntasks;
     jb.corner = L.corner;
     jb.nbands = L.nbands;
-    jb.strip = P->strip;
-    jb.win_dwords = L.Q + 16 * P->strip;
+    jb.split = split ? 1 : 0;
+    jb.strip = split ? 1 : P->strip;
+    jb.win_dwords = L.Q + 16 * jb.strip;
     for (int b = 0; b <= kMaxBands; ++b) {
       jb.band_g0[b] = L.band_g0[b];
       jb.band_step0[b] = L.band_step0[b];
     }
     jb.qtab = kt.qtab;
     jb.dtab = kt.dtab;
-    P->lds_bytes = std::max(P->lds_bytes, window_bytes(L, P->strip));
-    const int spr = (jb.ctus_w + P->strip - 1) / P->strip;
+    // LDS: the window (plus, split, the 64x64 exchange after it), then one
+    // ring per wavefront of the launch.
+    P->lds_bytes = std::max(P->lds_bytes, split ? window_bytes(L, 1) + xch_bytes + ring_extra
+                                                : window_bytes(L, P->strip));
+    const int spr = (jb.ctus_w + jb.strip - 1) / jb.strip;
     total_items += (int64_t)spr * jb.ctus_h * L.nbands;
     jnb[j] = L.nbands;
     if (materialize_items) {
@@ -408,11 +450,12 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
           for (int b = 0; b < L.nbands; ++b) {
             const int steps = L.band_step0[b + 1] - L.band_step0[b];
             const int rows = (L.band_g0[b + 1] - L.band_g0[b]) * P->D + 63;
-            // A partial strip spreads its CTUs' steps over all the strip's wavefronts.
-            const int sw = std::min(P->strip, jb.ctus_w - sidx * P->strip);
-            const int64_t span = ((int64_t)sw * steps + P->strip - 1) / P->strip;
-            const int64_t cost = span * 4096 + rows;  // compute + staging
-            jwork[j].push_back(Work{cost, (uint32_t)j, pack_item_y(row, sidx * P->strip, b)});
+            // A partial strip spreads its CTUs' steps over all the strip's
+            // wavefronts; a split item gives each wavefront a quarter CTU.
+            const int sw = std::min(jb.strip, jb.ctus_w - sidx * jb.strip);
+            const int64_t span = ((int64_t)sw * steps + jb.strip - 1) / jb.strip;
+            const int64_t cost = span * (split ? 1024 : 4096) + rows;  // compute + staging
+            jwork[j].push_back(Work{cost, (uint32_t)j, pack_item_y(row, sidx * jb.strip, b)});
           }
     }
   }
@@ -600,13 +643,21 @@ int32_t mr_se_bits(int32_t v) {
 
 int mr_set_tiles(int32_t search_range, int32_t d, int32_t nbands) {
   if (d != 0 && (nbands < 1 || nbands > kMaxBands)) return MR_EINVAL;
-  return set_tile_override(search_range, TileConfig{d, nbands, 0});
+  return set_tile_override(search_range, TileConfig{d, nbands, 0, 0});
 }
 
 int mr_set_tiles3(int32_t search_range, int32_t d, int32_t nbands, int32_t strip) {
   if (d != 0 && (nbands < 1 || nbands > kMaxBands || strip < 0 || strip > kMaxStrip))
     return MR_EINVAL;
-  return set_tile_override(search_range, TileConfig{d, nbands, strip});
+  return set_tile_override(search_range, TileConfig{d, nbands, strip, 0});
+}
+
+int mr_set_tiles4(int32_t search_range, int32_t d, int32_t nbands, int32_t strip,
+                  int32_t split) {
+  if (d != 0 && (nbands < 0 || nbands > kMaxBands || strip < 0 || strip > kMaxStrip ||
+                 split < 0 || split > 2))
+    return MR_EINVAL;
+  return set_tile_override(search_range, TileConfig{d, nbands, strip, split});
 }
 
 int mr_profile_enable(int on) {

@@ -20,6 +20,7 @@ struct TileConfig {
   int D;       // vertical shifts per lane (2, 4 or 8)
   int nbands;  // dy bands the window is split into (1..kMaxBands); 0 = derive
   int strip;   // CTUs per workgroup (1..kMaxStrip); 0 = derive
+  int split;   // 0 = derive, 1 = a wavefront searches a whole CTU, 2 = its quadrant
 };
 // Tile override for one search range (autotuner / user knob); D == 0 clears it.
 int set_tile_override(int R, const TileConfig& tc);
@@ -29,7 +30,13 @@ SearchLayout make_layout(int R, int D, int nbands);
 // Bands for a job: smallest count whose window fits the LDS budget, raised until
 // the job alone has at least min_items items (when min_items > 0).
 int choose_bands(int R, int D, int strip, int ctus_w, int ctus_h, size_t lds_budget,
-                 int min_items);
+                 int min_items, int min_steps_per_band = 2);
+// Whether full-search jobs of range R run split (a CTU's quadrants on four
+// wavefronts) when nothing overrides it.
+bool default_split(int R);
+// Vertical shifts per lane when nothing overrides them, for a batch whose
+// dominant range is R with `ctus` CTUs of full search.
+int default_D(int R, int64_t ctus);
 size_t window_bytes(const SearchLayout& L, int strip);
 
 // Device tables of the rank-ordered arg-min keys for (qp, layout); cached per device.

@@ -78,7 +78,13 @@ extern "C" int mr_autotune(const mr_search_job* jobs, int32_t n_jobs, int32_t re
     if (w > hw) hw = w, heavy = j;
   }
   const int R = jobs[heavy].params.search_range;
-  TileConfig saved{0, 0, 0};
+  int64_t ctus = 0;
+  for (int j = 0; j < n_jobs; ++j)
+    if (!jobs[j].seed)
+      ctus += (int64_t)(((jobs[j].cur.width + 7) / 8 * 8 + 63) / 64) *
+              (((jobs[j].cur.height + 7) / 8 * 8 + 63) / 64);
+  const int builtin_D = default_D(R, ctus);
+  TileConfig saved{0, 0, 0, 0};
   const bool had = get_tile_override(R, &saved);
   out->search_range = R;
   out->tried = 0;
@@ -91,30 +97,31 @@ extern "C" int mr_autotune(const mr_search_job* jobs, int32_t n_jobs, int32_t re
     return rc;
   };
   // Built-in choice first (no override).
-  int rc = set_tile_override(R, TileConfig{0, 0, 0});
+  int rc = set_tile_override(R, TileConfig{0, 0, 0, 0});
   double def_ms = DBL_MAX;
   if (rc == MR_OK) rc = time_search(jobs, n_jobs, reps, &def_ms);
   ++out->tried;
-  TileConfig best{0, 0, 0};
+  TileConfig best{0, 0, 0, 0};
   double best_ms = def_ms;
-  if (rc == MR_OK) {
-    // 1. D at the built-in bands (nbands 0 = derive) and strip.
-    for (int D : {2, 4, 8}) {
-      double ms;
-      rc = measure(TileConfig{D, 0, 0}, &ms);
+  // 1. D x split (whole CTU or quadrant per wavefront) at the built-in bands
+  //    (nbands 0 = derive) and strip.
+  for (int sp : {1, 2})
+    for (int D : {2, 4, 5, 6, 8}) {
       if (rc != MR_OK) break;
-      if (ms < best_ms) best_ms = ms, best = TileConfig{D, 0, 0};
+      double ms;
+      rc = measure(TileConfig{D, 0, 0, sp}, &ms);
+      if (rc == MR_OK && ms < best_ms) best_ms = ms, best = TileConfig{D, 0, 0, sp};
     }
-  }
-  const int bestD = best.D ? best.D : (R < 20 ? 2 : 4);
-  // 2. bands, 3. strip.
+  const int bestD = best.D ? best.D : builtin_D;
+  const int bestSp = best.D ? best.split : (default_split(R) ? 2 : 1);
+  // 2. bands, 3. strip (CTUs per workgroup, whole-CTU wavefronts only).
   for (int nb = 1; rc == MR_OK && nb <= kMaxBands; ++nb) {
     double ms;
-    rc = measure(TileConfig{bestD, nb, 0}, &ms);
-    if (rc == MR_OK && ms < best_ms) best_ms = ms, best = TileConfig{bestD, nb, 0};
+    rc = measure(TileConfig{bestD, nb, 0, bestSp}, &ms);
+    if (rc == MR_OK && ms < best_ms) best_ms = ms, best = TileConfig{bestD, nb, 0, bestSp};
   }
   for (int sw : {1, 2, 3, 4}) {
-    if (rc != MR_OK || !best.D) break;
+    if (rc != MR_OK || !best.D || best.split == 2) break;
     double ms;
     TileConfig tc = best;
     tc.strip = sw;
@@ -122,13 +129,14 @@ extern "C" int mr_autotune(const mr_search_job* jobs, int32_t n_jobs, int32_t re
     if (rc == MR_OK && ms < best_ms) best_ms = ms, best = tc;
   }
   if (rc != MR_OK) {
-    (void)set_tile_override(R, had ? saved : TileConfig{0, 0, 0});
+    (void)set_tile_override(R, had ? saved : TileConfig{0, 0, 0, 0});
     return rc;
   }
   (void)set_tile_override(R, best);
-  out->d = best.D ? best.D : (R < 20 ? 2 : 4);
+  out->d = best.D ? best.D : builtin_D;
   out->nbands = best.nbands;
   out->strip = best.strip;
+  out->split = best.D ? best.split : (default_split(R) ? 2 : 1);
   out->search_ms = best_ms;
   out->default_ms = def_ms;
   return MR_OK;

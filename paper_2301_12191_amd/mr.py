@@ -60,7 +60,7 @@ class mr_tune_result(ctypes.Structure):
     _fields_ = [("search_range", ctypes.c_int32), ("d", ctypes.c_int32),
                 ("nbands", ctypes.c_int32), ("strip", ctypes.c_int32),
                 ("search_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
-                ("tried", ctypes.c_int32)]
+                ("tried", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class mr_profile(ctypes.Structure):
@@ -105,6 +105,8 @@ def lib():
                                   ctypes.POINTER(mr_tune_result)]
         L.mr_set_tiles3.restype = ctypes.c_int
         L.mr_set_tiles3.argtypes = [i32, i32, i32, i32]
+        L.mr_set_tiles4.restype = ctypes.c_int
+        L.mr_set_tiles4.argtypes = [i32, i32, i32, i32, i32]
         L.mr_set_tiles.restype = ctypes.c_int
         L.mr_set_tiles.argtypes = [i32, i32, i32]
         L.mr_profile_enable.restype = ctypes.c_int
@@ -354,6 +356,12 @@ def mr_set_tiles3(search_range: int, d: int, nbands: int, strip: int) -> None:
     rc = lib().mr_set_tiles3(search_range, d, nbands, strip)
     if rc != MR_OK:
         raise MRError(rc, "mr_set_tiles3")
+
+
+def mr_set_tiles4(search_range: int, d: int, nbands: int, strip: int, split: int) -> None:
+    rc = lib().mr_set_tiles4(search_range, d, nbands, strip, split)
+    if rc != MR_OK:
+        raise MRError(rc, "mr_set_tiles4")
 
 
 def mr_autotune(jobs, reps: int = 3) -> dict:

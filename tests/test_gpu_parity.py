@@ -225,12 +225,67 @@ def test_partial_strips_bit_exact(mr, W, R, strip, nb):
     at the right edge, whose (CTU, step) pairs are dealt over all the workgroup's wavefronts."""
     H, qp = 136, 30
     ref, cur = _pair(0x5700 + 7 * W + strip, W, H, 5, 12, 2)
-    mr.mr_set_tiles3(R, 4, nb, strip)
+    mr.mr_set_tiles4(R, 4, nb, strip, 1)  # whole CTUs per wavefront
     try:
         got = _gpu(mr, cur, ref, qp, R)
     finally:
         mr.mr_set_tiles(R, 0, 1)
     _compare(got, oracle.ctu_search(cur, ref, qp, R), W, H, label=f"W{W} R{R} strip{strip} nb{nb}")
+
+
+@pytest.mark.parametrize("W,H,R,D,nb,bounded", [
+    (200, 136, 16, 2, 1, False),   # 4x3 CTUs, partial bottom row
+    (200, 136, 16, 5, 1, True),    # one step per CTU, bounds
+    (264, 200, 24, 4, 3, False),   # three single-step bands
+    (330, 130, 32, 6, 0, True),    # built-in bands, bounds
+    (136, 72, 8, 8, 1, False),
+    (203, 141, 64, 4, 5, True),    # the (R, R) corner left to prep, ragged
+    (72, 40, 40, 5, 2, False),     # 2x1 CTUs, both partial
+    (64, 64, 0, 2, 1, False),      # one candidate
+])
+def test_split_quadrants_bit_exact(mr, W, H, R, D, nb, bounded):
+    """Split search: the four wavefronts of a workgroup take the four 32x32 quadrants of one
+    CTU and sum the 64x64 SADs through LDS, on ragged pictures (edge CTUs whose 64x64 node is
+    absent), with bounds (nodes that may not be leaves skip their keys and the exchange),
+    and at each lane shape D."""
+    qp = 31
+    ref, cur = _pair(0x5A00 + W + 3 * R + D, W, H, 6, max(4, R), 2)
+    b = None
+    if bounded:
+        rng = np.random.default_rng(W + R)
+        lo = rng.integers(0, 4, size=((H + 7) // 8, (W + 7) // 8), dtype=np.uint8)
+        hi = np.maximum(lo, rng.integers(0, 4, size=lo.shape, dtype=np.uint8))
+        b = np.stack([lo, hi], axis=-1)
+    mr.mr_set_tiles4(R, D, nb, 0, 2)
+    try:
+        got = _gpu(mr, cur, ref, qp, R, bounds=b)
+    finally:
+        mr.mr_set_tiles(R, 0, 1)
+    _compare(got, oracle.ctu_search(cur, ref, qp, R, bounds=b), W, H,
+             label=f"split W{W} H{H} R{R} D{D} nb{nb}")
+
+
+def test_split_and_whole_jobs_in_one_batch(mr):
+    """One batch mixing split jobs (R 16, 24) and whole-CTU jobs (R 40 forced whole): each
+    job's outputs equal the oracle's."""
+    import torch
+    specs = [(200, 136, 16), (264, 136, 24), (330, 200, 40), (136, 72, 16)]
+    jobs, host = [], []
+    for i, (W, H, R) in enumerate(specs):
+        ref, cur = _pair(0x5B00 + i, W, H, 6, R, 2)
+        host.append((cur, ref, R))
+        jobs.append(dict(cur=torch.from_numpy(cur).cuda(), ref=torch.from_numpy(ref).cuda(),
+                         qp=30 + i, search_range=R))
+    mr.mr_set_tiles4(40, 4, 0, 0, 1)
+    try:
+        outs = mr.mr_ctu_search_batch(jobs)
+        torch.cuda.synchronize()
+    finally:
+        mr.mr_set_tiles(40, 0, 1)
+    for i, ((cur, ref, R), o) in enumerate(zip(host, outs)):
+        H, W = cur.shape
+        got = {k: v.cpu().numpy() for k, v in o.items()}
+        _compare(got, oracle.ctu_search(cur, ref, 30 + i, R), W, H, label=f"mixed job {i}")
 
 
 @pytest.mark.parametrize("W,H,R,qp,bounded", [

@@ -242,6 +242,14 @@ def test_tile_override_validation(libmr):
     assert libmr.mr_set_tiles(64, 4, 0) == mr.MR_EINVAL
     assert libmr.mr_set_tiles(64, 4, 9) == mr.MR_EINVAL
     assert libmr.mr_set_tiles(64, 0, 1) == mr.MR_OK
+    assert libmr.mr_set_tiles(64, 5, 1) == mr.MR_OK and libmr.mr_set_tiles(64, 6, 2) == mr.MR_OK
+    assert libmr.mr_set_tiles(64, 7, 1) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles4(64, 4, 0, 0, 3) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles4(64, 4, 0, 0, -1) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles4(64, 4, 9, 0, 1) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles4(64, 4, 0, 5, 1) == mr.MR_EINVAL
+    assert libmr.mr_set_tiles4(64, 4, 0, 0, 2) == mr.MR_OK
+    assert libmr.mr_set_tiles(64, 0, 1) == mr.MR_OK
 
 
 def test_host_lambda_and_bits_match_the_oracle():
