@@ -4,12 +4,15 @@
 //   prep   : pack the current CTUs into 8x8-block-linear dwords (coded picture,
 //            edge-replicated), reset the arg-min keys, mark leaf-eligible nodes
 //            (inside the picture and allowed by the depth bounds);
-//   search : integer full-search ME.  One workgroup per (CTU, dy band) stages
-//            the reference window in LDS; each lane owns 4 horizontal x D
-//            vertical candidate shifts, computes the 64 8x8 SADs per candidate
-//            with v_sad_u8 (current block read through SGPRs, reference
-//            dwords re-aligned with v_alignbyte), sums them into 16/32/64 SADs
-//            and keeps an exact first-minimum arg-min for all 85 CUs;
+//   search : integer full-search ME.  Persistent workgroups take (strip of
+//            CTUs, dy band) items -- or, at small ranges, one CTU whose
+//            quadrants go to the four wavefronts -- and stage the reference
+//            window in LDS; each lane owns 4 horizontal x D vertical candidate
+//            shifts and computes the 64 8x8 SADs per candidate with
+//            v_qsad_pk_u16_u8 (the 4 horizontal shifts of a window dword pair
+//            in one instruction, as packed 16-bit sums; current block from an
+//            LDS ring), sums them into 16/32/64 SADs and keeps an exact
+//            first-minimum arg-min for all 85 CUs;
 //   leaf   : SATD (4x4 Hadamard) of the inter residual at the best MV and of
 //            the intra DC / planar residuals, leaf mode choice, bottom-up
 //            quad-tree decision with optional depth bounds, outputs.
@@ -227,6 +230,19 @@ __device__ __forceinline__ void merge_keys(uint32_t vk, const uint64_t* __restri
   }
 }
 
+// Field k (0..3) of four packed 16-bit values, times m (< 2^16, uniform), plus
+// a: one v_mad_u32_u16 whose op_sel picks the high half of the dword holding
+// the field, instead of an extract and a multiply-add.
+__device__ __forceinline__ uint32_t field_mad(uint64_t v, int k, uint32_t m, uint32_t a) {
+  const uint32_t x = (uint32_t)(v >> (32 * (k >> 1)));
+  uint32_t r;
+  if (k & 1)
+    asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(r) : "v"(x), "s"(m), "v"(a));
+  else
+    asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(m), "v"(a));
+  return r;
+}
+
 // One wavefront: steps [st_lo, st_hi) of one (CTU, band); `win` points at
 // this CTU's column 0 of the staged window (dx = -R), whose dword columns are
 // hs apart; `ring` is this wavefront's 512-byte LDS ring for the current CTU
@@ -272,7 +288,10 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
       }
     }
     const uint32_t* lbase = win + qd * hs + (g - g0) * D;  // row dy of window column qd
-    uint32_t s16[D][4], s32[D][4], s64[D][4];
+    // s16q[j]: the 16x16 SADs of the 4 horizontal shifts of vertical shift j,
+    // packed as 16-bit fields (at most 4 x 16320 < 2^16, so packed adds are exact).
+    uint64_t s16q[D];
+    uint32_t s32[D][4], s64[D][4];
 #pragma unroll
     for (int j = 0; j < D; ++j)
 #pragma unroll
@@ -308,11 +327,15 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
             cw[4 * i] = t.x, cw[4 * i + 1] = t.y, cw[4 * i + 2] = t.z, cw[4 * i + 3] = t.w;
           }
         }
-        uint32_t acc[D][4];
+        // acq[j]: the block's SADs at the 4 horizontal shifts k of vertical
+        // shift j, as 16-bit fields k (at most 64 x 255 = 16320).  One
+        // v_qsad_pk_u16_u8 takes 8 window bytes (two dwords) and one current
+        // dword and adds the 4 SADs of the dword against the window bytes
+        // k .. k + 3, k = 0..3: the horizontal shifts without re-aligning the
+        // window.  The two dwords of an 8-sample row are two such steps.
+        uint64_t acq[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc[j][k] = 0;
+        for (int j = 0; j < D; ++j) acq[j] = 0;
         const uint32_t *c0 = cb[2 * (sub & 1)], *c1 = cb[2 * (sub & 1) + 1],
                        *c2 = cb[2 * (sub & 1) + 2];
         const int r0 = 8 * (sub >> 1);
@@ -326,22 +349,13 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
             n0 = c0[r0 + w + 1], n1 = c1[r0 + w + 1], n2 = c2[r0 + w + 1];
           }
           __builtin_amdgcn_sched_barrier(0);
-          uint32_t a0[4], a1[4];
-          a0[0] = d0, a1[0] = d1;
-#pragma unroll
-          for (int k = 1; k < 4; ++k) {
-            a0[k] = __builtin_amdgcn_alignbyte(d1, d0, k);
-            a1[k] = __builtin_amdgcn_alignbyte(d2, d1, k);
-          }
+          const uint64_t p0 = ((uint64_t)d1 << 32) | d0, p1 = ((uint64_t)d2 << 32) | d1;
 #pragma unroll
           for (int j = 0; j < D; ++j) {
             const int r = w - j;
             if (r < 0 || r > 7) continue;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              acc[j][k] = __builtin_amdgcn_sad_u8(a0[k], cw[2 * r], acc[j][k]);
-              acc[j][k] = __builtin_amdgcn_sad_u8(a1[k], cw[2 * r + 1], acc[j][k]);
-            }
+            acq[j] = __builtin_amdgcn_qsad_pk_u16_u8(p0, cw[2 * r], acq[j]);
+            acq[j] = __builtin_amdgcn_qsad_pk_u16_u8(p1, cw[2 * r + 1], acq[j]);
           }
         }
         const int n8 = 21 + by * 8 + bx;  // 21..84
@@ -352,13 +366,11 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
           for (int j = 0; j < D; ++j)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) m = min(m, acc[j][k] * 2048u + kq[j][k]);
+            for (int k = 0; k < 4; ++k) m = min(m, field_mad(acq[j], k, 2048u, kq[j][k]));
           m8[sub] = m;
         }
 #pragma unroll
-        for (int j = 0; j < D; ++j)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) s16[j][k] = sub == 0 ? acc[j][k] : s16[j][k] + acc[j][k];
+        for (int j = 0; j < D; ++j) s16q[j] = sub == 0 ? acq[j] : s16q[j] + acq[j];
       }
       // The region's four 8x8 CUs are blocks 4 reg .. 4 reg + 3, i.e. lanes
       // whose low two bits name the block: one joint wavefront reduction.
@@ -378,7 +390,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
           for (int j = 0; j < D; ++j)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) m = min(m, s16[j][k] * 2048u + kq[j][k]);
+            for (int k = 0; k < 4; ++k) m = min(m, field_mad(s16q[j], k, 2048u, kq[j][k]));
           const uint32_t mk = wave_min(m);
           vkB = set_lane(vkB, mk, reg);
         }
@@ -391,7 +403,7 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
 #pragma unroll
         for (int j = 0; j < D; ++j)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) s32[j][k] += s16[j][k];
+          for (int k = 0; k < 4; ++k) s32[j][k] = field_mad(s16q[j], k, 1u, s32[j][k]);
       }
       if ((reg & 3) == 3) {  // 32x32 CU (nodes 1..4)
         const int qz = reg >> 2, lx = qz & 1, ly = qz >> 1;

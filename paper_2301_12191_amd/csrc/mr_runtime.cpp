@@ -50,11 +50,13 @@ bool get_tile_override(int R, TileConfig* tc) {
 // Vertical shifts per lane when nothing overrides them, by the batch's
 // dominant range R and its CTU count: the D whose steps waste the fewest
 // lanes on candidates outside the window, where its registers allow three
-// wavefronts per SIMD.  A small single picture at R < 20 keeps D = 2: three
-// steps per CTU give its few CTUs three times as many work items.
+// wavefronts per SIMD; at R >= 96 D = 8 (two wavefronts per SIMD), whose rows
+// serve twice as many vertical shifts.  A small single picture at R < 20 keeps
+// D = 2: three steps per CTU give its few CTUs three times as many work items.
 int default_D(int R, int64_t ctus) {
   if (R < 20) return ctus < 256 ? 2 : 5;
   if (R >= 40 && R <= 56) return 5;
+  if (R >= 96) return 8;
   return 4;
 }
 
