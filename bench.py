@@ -177,7 +177,7 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
 
     def serve(pipelined):
         lad = mr.Ladder(rungs, max_batch_jobs=64)
-        j_dag, lat, held = {}, [], []
+        j_dag, lat, held, first_launch = {}, [], [], []
         try:
             for f in range(n_frames + 1):
                 for i, r in enumerate(rungs):
@@ -188,7 +188,7 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
                                                 for f in range(1, n_frames + 1)]
             for grp in groups:
                 ids = dict(zip(lad.submit_many([(0, f, i) for f, i in grp]), grp))
-                done, idle = 0, 0
+                done, idle, starts = 0, 0, []
                 while done < len(ids):
                     got = lad.poll(64, 200000)
                     idle = 0 if got else idle + 1
@@ -201,21 +201,27 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
                             done += 1
                             f, i = ids[c.job_id]
                             lat.append((c.t_done_ns - c.t_arrive_ns) * 1e-6)
+                            starts.append((c.t_start_ns - c.t_arrive_ns) * 1e-6)
                             if f == 1:  # read after the timed region (no device sync here)
                                 held.append((i, c))
                                 continue
                         lad.release(c.job_id)
+                first_launch.append(min(starts))  # submission -> the group's first launch
             t1 = time.perf_counter()
+            st = lad.stats()
             for i, c in held:
                 j_dag[i] = int(lad.outputs(c)["cost"].sum().item())
                 lad.release(c.job_id)
         finally:
             lad.close()
-        return (t1 - t0) * 1e3 / n_frames, j_dag, sorted(lat)
+        host = {"batches": st["batches"],
+                "host_ms_per_batch": round(st["host_launch_ms"] / max(1, st["batches"]), 4),
+                "submit_to_first_launch_ms": round(sorted(first_launch)[len(first_launch) // 2], 4)}
+        return (t1 - t0) * 1e3 / n_frames, j_dag, sorted(lat), host
 
     serve(True)  # warm-up (plans, key tables, allocator)
-    seq_ms, _, _ = serve(False)
-    pipe_ms, j_dag, lat = serve(True)
+    seq_ms, _, _, seq_host = serve(False)
+    pipe_ms, j_dag, lat, pipe_host = serve(True)
     rd = {}
     for li, (w, h, _) in enumerate(sizes):
         jf = sum(j_full[5 * li:5 * li + 5])
@@ -235,6 +241,7 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
         "pipelining_gain": round(seq_ms / pipe_ms, 3),
         "pipelined_ctus_per_s": round(n_ctus / (pipe_ms * 1e-3), 1),
         "job_latency_p50_ms": round(pct(0.5), 3), "job_latency_p99_ms": round(pct(0.99), 3),
+        "host_frame_by_frame": seq_host, "host_pipelined": pipe_host,
         "rd_cost_increase_pct_frame1": rd}
 
 

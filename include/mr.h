@@ -60,7 +60,8 @@ typedef enum {
   MR_EHIP = -5,     /* a HIP runtime call failed */
   MR_ETIMEOUT = -6, /* ladder: poll timed out with no completion */
   MR_ESTATE = -7,   /* call not valid in the object's current state */
-  MR_ESCRATCH = -8  /* mr_ctu_search_noalloc: the call needs more than its fixed scratch */
+  MR_ESCRATCH = -8, /* mr_ctu_search_noalloc: the call needs more than its fixed scratch */
+  MR_ECANCELED = -9 /* ladder: the job was cancelled before its launch */
 } mr_status;
 
 /* One 8-bit luma picture: device pointer, width x height samples, row stride
@@ -212,6 +213,8 @@ int mr_ctu_search_batch(const mr_search_job* jobs, int32_t n_jobs, void* hip_str
  *     largest half-width re-records the graph (host-blocking).
  *   mr_batch_launch : replay on hip_stream (with stage profiling enabled, the
  *     three kernels are launched directly between timing events instead).
+ *     Launches of one batch share its scratch, so each launch waits on the
+ *     device for the batch's previous one, whatever stream either is on.
  *   mr_batch_destroy: waits for the last launch, frees everything (NULL ok).
  * Errors: MR_EINVAL, MR_ENOMEM, MR_EHIP. */
 typedef struct mr_batch mr_batch;
@@ -241,9 +244,11 @@ int mr_batch_destroy(mr_batch* b);
  * keeps up to four batches in flight, and releases dependents as references
  * are launched (continuous batching).  Done reference jobs stay resident for later
  * dependents until their memory is needed.  The output blocks of finished jobs
- * are kept for reuse by later jobs of the same size, up to 512 MiB beyond the
- * admission budget, until mr_ladder_close.  With reuse_mv, a dependent's
- * search is also seeded with its reference job's MV map.  Each rung may carry
+ * are kept for reuse by later jobs of the same size, outside the admission
+ * budget but capped at a quarter of it (at most 512 MiB; mr_ladder_stats
+ * reports them), until mr_ladder_close; a device allocation that fails first
+ * empties that cache and retries.  With reuse_mv, a dependent's search is
+ * also seeded with its reference job's MV map.  Each rung may carry
  * its own policy (own_policy), so that one configuration holds both
  * cross-resolution and same-resolution (multi-QP) edges, e.g. the
  * multi-encoding scheme whose per-resolution median-QP masters chain
@@ -277,6 +282,12 @@ typedef struct {
                                   their reference job's MVs */
   int32_t refine_range;        /* r of seeded dependents, 0..128 (capped at each
                                   rung's search_range); ignored when reuse_mv = 0 */
+  int32_t job_timeout_us;      /* >= 0; a job still waiting for its launch this long
+                                  after its submission (for its reference, for memory
+                                  or for a batch slot) completes with MR_ETIMEOUT and
+                                  its dependents with MR_EDEPEND; 0 = no limit.  A
+                                  launched job runs to completion (device work is not
+                                  interrupted). */
 } mr_ladder_config;
 
 typedef struct {
@@ -299,7 +310,11 @@ typedef struct {
   int64_t submitted, implied, completed, failed, rejected, batches, ctus_done;
   double p50_ms, p99_ms, mean_ms, max_ms; /* arrival -> completion of completed jobs */
   double ctus_per_s;                      /* ctus_done / (last done - first start) */
-  uint64_t bytes_in_use, peak_bytes;
+  uint64_t bytes_in_use, peak_bytes;      /* footprint of admitted jobs (the budget's) */
+  int64_t cancelled, timed_out;           /* of the failed ones */
+  uint64_t cached_bytes;                  /* retired output blocks kept for reuse */
+  double host_launch_ms;                  /* server thread's time in batch launches
+                                             (plan, allocation, upload, kernel launches) */
 } mr_ladder_stats;
 
 typedef struct mr_ladder mr_ladder;
@@ -334,6 +349,11 @@ int mr_ladder_submit_many(mr_ladder* l, const mr_job* jobs, int32_t n, uint64_t*
  * (0 = do not wait).  MR_ETIMEOUT if none arrived. */
 int mr_ladder_poll(mr_ladder* l, mr_completion* out, int32_t max, int32_t timeout_us,
                    int32_t* n_out);
+/* Cancel a job that has not been launched yet (waiting for its reference,
+ * for memory or for a batch slot): it completes with MR_ECANCELED, and its
+ * dependents fail with MR_EDEPEND.  Errors: MR_EINVAL (null ladder, unknown
+ * id), MR_ESTATE (already launched or completed: device work runs to its end). */
+int mr_ladder_cancel(mr_ladder* l, uint64_t job_id);
 /* Give a completed job's outputs back (MR_ESTATE if not completed yet).  Once
  * a job is released, handed out by mr_ladder_poll and needed by no dependent,
  * the server forgets it (its id then gives MR_EINVAL). */

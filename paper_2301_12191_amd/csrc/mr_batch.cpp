@@ -239,6 +239,10 @@ int mr_batch_launch(mr_batch* b, void* hip_stream) {
   if (!b) return MR_EINVAL;
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e;
+  // Every launch of a batch uses the batch's one scratch (packed CTUs, keys,
+  // queue counters): a launch on another stream than the previous one waits
+  // for it on the device instead of overlapping it.
+  if (b->launched && hipStreamWaitEvent(st, b->last, 0) != hipSuccess) return MR_EHIP;
   if (profile_on()) {
     StageEvents ev{};
     if (profile_begin(&ev, st) != MR_OK) return MR_EHIP;

@@ -31,13 +31,17 @@ struct FrameRef {
 // later batch may wait for it on the device (its jobs' references); it is
 // destroyed with the last of them, after the reference outputs are freed, so
 // after every dependent batch, and so every wait on it, has completed.
+// The event goes back to its executor's pool (it has completed by then)
+// instead of being destroyed: creating one costs tens of microseconds.
 struct SharedEvent {
   hipEvent_t ev = nullptr;
   int refs = 0;
+  std::vector<hipEvent_t>* pool = nullptr;
 };
 static void unref(SharedEvent* e) {
   if (e && --e->refs == 0) {
-    (void)hipEventDestroy(e->ev);
+    if (e->pool) e->pool->push_back(e->ev);
+    else (void)hipEventDestroy(e->ev);
     delete e;
   }
 }
@@ -55,11 +59,14 @@ struct JobOut {
 struct BatchState {
   SharedEvent* done = nullptr;
   hipStream_t stream = nullptr;
+  uint8_t* scratch = nullptr;  // the batch's device scratch (back to the cache when done)
+  size_t scratch_bytes = 0;
 };
 
 class GpuExecutor : public Executor {
  public:
-  explicit GpuExecutor(const SchedConfig& cfg) : cfg_(cfg) {}
+  explicit GpuExecutor(const SchedConfig& cfg)
+      : cfg_(cfg), pool_max_(std::min<size_t>(kPoolMaxBytes, cfg.budget_bytes / 4)) {}
 
   int init() {
     if (hipGetDevice(&device_) != hipSuccess) return MR_EHIP;
@@ -70,13 +77,16 @@ class GpuExecutor : public Executor {
 
   ~GpuExecutor() override {
     // Cached blocks came from the stream-ordered allocator: free them the same way.
-    if (streams_[0])
+    if (streams_[0]) {
       for (auto& kv : pool_) (void)hipFreeAsync(kv.second, streams_[0]);
+      for (auto& kv : scratch_free_) (void)hipFreeAsync(kv.second, streams_[0]);
+    }
     for (auto& s : streams_)
       if (s) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
       }
+    for (hipEvent_t ev : events_) (void)hipEventDestroy(ev);
   }
 
   int device() const { return device_; }
@@ -184,7 +194,7 @@ class GpuExecutor : public Executor {
       size_t off[7];
       const size_t bytes = out_bytes(r, j.ref_job != 0, off);
       o->mem = take_block(bytes);
-      if (!o->mem && hipMallocAsync((void**)&o->mem, bytes, st) != hipSuccess) {
+      if (!o->mem && !alloc(&o->mem, bytes, st)) {
         delete o;
         return MR_ENOMEM;
       }
@@ -224,25 +234,36 @@ class GpuExecutor : public Executor {
                        &P);
     if (rc != MR_OK) return rc;
     const BatchLayout L = batch_layout(P);
-    uint8_t* mem = nullptr;
-    if (hipMallocAsync((void**)&mem, L.total, st) != hipSuccess) return MR_ENOMEM;
+    size_t mem_bytes = 0;
+    uint8_t* mem = take_scratch(L.total, &mem_bytes);
+    if (!mem) {
+      // Sizes rounded up to 1 MiB so that later batches of similar size reuse it.
+      mem_bytes = (L.total + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+      if (!alloc(&mem, mem_bytes, st)) return MR_ENOMEM;
+    }
     bind_scratch(P, mem + L.scratch);
     hipError_t e = batch_upload(P, mem, L, st);
     if (e == hipSuccess)
       e = launch_plan(P, (JobDesc*)(mem + L.jobs), (const uint2*)(mem + L.items),
                       batch_lists(mem, L), (uint32_t*)(mem + L.counter), st, nullptr);
-    const hipError_t ef = hipFreeAsync(mem, st);
     hipEvent_t ev = nullptr;
-    if (e == hipSuccess) e = ef;
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (!events_.empty()) {
+      ev = events_.back();
+      events_.pop_back();
+    } else if (e == hipSuccess) {
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipEventRecord(ev, st);
     if (e != hipSuccess) {
       if (ev) (void)hipEventDestroy(ev);
+      (void)hipFreeAsync(mem, st);
       return MR_EHIP;
     }
     BatchState* b = new BatchState();
     b->stream = st;
-    b->done = new SharedEvent{ev, 1 + n};
+    b->scratch = mem;
+    b->scratch_bytes = mem_bytes;
+    b->done = new SharedEvent{ev, 1 + n, &events_};
     for (SchedJob* j : jobs) {
       JobOut* o = (JobOut*)j->exec_state;
       o->batch = b->done;
@@ -263,6 +284,13 @@ class GpuExecutor : public Executor {
     BatchState* b = (BatchState*)handle;
     for (SchedJob* j : jobs)
       if (j->exec_state) ((JobOut*)j->exec_state)->batch_running = false;
+    // The batch has finished on the device: its scratch may serve the next one.
+    if (pool_bytes_ + scratch_free_bytes_ + b->scratch_bytes <= pool_max_) {
+      scratch_free_.emplace(b->scratch_bytes, b->scratch);
+      scratch_free_bytes_ += b->scratch_bytes;
+    } else {
+      (void)hipFreeAsync(b->scratch, b->stream);
+    }
     unref(b->done);
     delete b;
     for (SchedJob* j : jobs) j->status = MR_OK;
@@ -276,7 +304,8 @@ class GpuExecutor : public Executor {
   void free_job(SchedJob& j) override {
     JobOut* o = (JobOut*)j.exec_state;
     if (!o) return;
-    if (j.state == kDone && !o->batch_running && pool_bytes_ + o->bytes <= kPoolMaxBytes) {
+    if (j.state == kDone && !o->batch_running &&
+        pool_bytes_ + scratch_free_bytes_ + o->bytes <= pool_max_) {
       pool_.emplace(o->bytes, o->mem);
       pool_bytes_ += o->bytes;
     } else {
@@ -293,8 +322,34 @@ class GpuExecutor : public Executor {
     for (auto& s : streams_) (void)hipStreamSynchronize(s);
   }
 
+  size_t cached_bytes() const { return pool_bytes_ + scratch_free_bytes_; }
+
  private:
   SchedConfig cfg_;
+  // Stream-ordered allocation; when it fails, the cached output blocks go back
+  // to the allocator (in the order of `st`, so a retry on `st` may reuse them)
+  // and it is tried once more.
+  bool alloc(uint8_t** p, size_t bytes, hipStream_t st) {
+    if (hipMallocAsync((void**)p, bytes, st) == hipSuccess) return true;
+    (void)hipGetLastError();
+    if (pool_.empty() && scratch_free_.empty()) return false;
+    for (auto& kv : pool_) (void)hipFreeAsync(kv.second, st);
+    for (auto& kv : scratch_free_) (void)hipFreeAsync(kv.second, st);
+    pool_.clear();
+    scratch_free_.clear();
+    pool_bytes_ = scratch_free_bytes_ = 0;
+    return hipMallocAsync((void**)p, bytes, st) == hipSuccess;
+  }
+  // A cached scratch block of at least `bytes` (and at most twice that), or null.
+  uint8_t* take_scratch(size_t bytes, size_t* got) {
+    auto it = scratch_free_.lower_bound(bytes);
+    if (it == scratch_free_.end() || it->first > 2 * bytes + ((size_t)1 << 20)) return nullptr;
+    uint8_t* m = it->second;
+    *got = it->first;
+    scratch_free_bytes_ -= it->first;
+    scratch_free_.erase(it);
+    return m;
+  }
   // A cached block of exactly `bytes`, or null.
   uint8_t* take_block(size_t bytes) {
     auto it = pool_.find(bytes);
@@ -307,7 +362,11 @@ class GpuExecutor : public Executor {
 
   static constexpr size_t kPoolMaxBytes = size_t(512) << 20;
   std::multimap<size_t, uint8_t*> pool_;  // retired output blocks by size
+  size_t pool_max_ = 0;  // cache cap (outputs and scratch): a quarter of the budget, <= 512 MiB
   size_t pool_bytes_ = 0;
+  std::multimap<size_t, uint8_t*> scratch_free_;  // scratch of finished batches by size
+  size_t scratch_free_bytes_ = 0;
+  std::vector<hipEvent_t> events_;                // completed batch events for reuse
   int device_ = 0;
   hipStream_t streams_[2] = {nullptr, nullptr};
   unsigned next_ = 0;
@@ -368,7 +427,8 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
       !policy_ok(cfg->delta_lo, cfg->delta_hi, cfg->reuse_mv, cfg->refine_range) ||
       cfg->hbm_budget_bytes == 0 ||
       cfg->max_inflight < 1 || cfg->max_inflight > 65536 || cfg->max_queue < 1 ||
-      cfg->max_queue > (1 << 20) || cfg->max_batch_jobs < 1 || cfg->max_batch_jobs > 4096)
+      cfg->max_queue > (1 << 20) || cfg->max_batch_jobs < 1 || cfg->max_batch_jobs > 4096 ||
+      cfg->job_timeout_us < 0)
     return MR_EINVAL;
   SchedConfig sc;
   for (int r = 0; r < cfg->n_rungs; ++r) {
@@ -398,6 +458,7 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
   sc.max_inflight = cfg->max_inflight;
   sc.max_queue = cfg->max_queue;
   sc.max_batch_jobs = cfg->max_batch_jobs;
+  sc.job_timeout_ns = (int64_t)cfg->job_timeout_us * 1000;
   sc.chain_on_launch = true;  // dependents wait for their references on the device
   sc.max_batches_in_flight = 4;  // a reference chain of up to 4 levels in flight
   mr_ladder* l = new mr_ladder();
@@ -488,6 +549,14 @@ int mr_ladder_poll(mr_ladder* l, mr_completion* out, int32_t max, int32_t timeou
   return MR_OK;
 }
 
+int mr_ladder_cancel(mr_ladder* l, uint64_t job_id) {
+  if (!l) return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(l->mu);
+  const int rc = l->sched->cancel(job_id);
+  if (rc == MR_OK) l->cv_done.notify_all();
+  return rc;
+}
+
 int mr_ladder_release(mr_ladder* l, uint64_t job_id) {
   if (!l) return MR_EINVAL;
   std::lock_guard<std::mutex> lk(l->mu);
@@ -506,6 +575,9 @@ int mr_ladder_get_stats(mr_ladder* l, mr_ladder_stats* out) {
   const double span = (s.last_done_ns - s.first_start_ns) * 1e-9;
   out->ctus_per_s = span > 0 ? s.ctus_done / span : 0.0;
   out->bytes_in_use = s.bytes_in_use, out->peak_bytes = s.peak_bytes;
+  out->cancelled = s.cancelled, out->timed_out = s.timed_out;
+  out->cached_bytes = l->ex->cached_bytes();
+  out->host_launch_ms = s.host_launch_ns * 1e-6;
   return MR_OK;
 }
 

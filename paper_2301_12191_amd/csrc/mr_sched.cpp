@@ -145,9 +145,17 @@ int Scheduler::step() {
   int done = 0;
   retire_finished();
   const int64_t now = ex_->now_ns();
-  // 1. Retire finished batches.
+  // 1. Retire finished batches.  A batch holding a dependent whose reference's
+  //    batch has not been retired yet waits for it (chain_on_launch): the
+  //    reference's outcome decides the dependent's.
   for (size_t b = 0; b < running_.size();) {
-    const int q = ex_->query(running_[b].handle);
+    bool ref_running = false;
+    for (const SchedJob* j : running_[b].jobs) {
+      if (!j->ref_job) continue;
+      auto it = jobs_.find(j->ref_job);
+      if (it != jobs_.end() && it->second->state == kRunning) ref_running = true;
+    }
+    const int q = ref_running ? 0 : ex_->query(running_[b].handle);
     if (q == 0) {
       ++b;
       continue;
@@ -157,8 +165,8 @@ int Scheduler::step() {
     for (SchedJob* j : running_[b].jobs) {
       int status = q < 0 ? MR_EHIP : j->status;
       if (status == MR_OK && j->ref_job) {
-        // Launched behind a reference that has failed since (its batch is
-        // earlier in running_, so it was retired first).
+        // Launched behind a reference that has failed since (its batch was
+        // retired first, see above).
         auto it = jobs_.find(j->ref_job);
         if (it != jobs_.end() && it->second->state == kFailed) status = MR_EDEPEND;
       }
@@ -181,6 +189,19 @@ int Scheduler::step() {
       ++inflight_;
       complete(j, MR_EDEPEND, now);
       ++done;
+    }
+  }
+  // Jobs that waited longer than the timeout without a launch give up.
+  if (cfg_.job_timeout_ns > 0) {
+    for (uint64_t id : queue_) {
+      SchedJob& j = *jobs_[id];
+      if ((j.state == kQueued || j.state == kReady) && now - j.t_arrive > cfg_.job_timeout_ns) {
+        j.state = kRunning;  // transient; completed below
+        ++inflight_;
+        complete(j, MR_ETIMEOUT, now);
+        ++st_.timed_out;
+        ++done;
+      }
     }
   }
   queue_.erase(std::remove_if(queue_.begin(), queue_.end(),
@@ -231,8 +252,10 @@ int Scheduler::step() {
                               [&](uint64_t id) { return jobs_[id]->state == kRunning; }),
                queue_.end());
   void* handle = nullptr;
+  const int64_t t0 = ex_->now_ns();
   const int rc = ex_->launch(batch, &handle);
   const int64_t t = ex_->now_ns();
+  st_.host_launch_ns += t - t0;
   if (rc != MR_OK) {
     for (SchedJob* j : batch) {
       complete(*j, rc, t);
@@ -273,6 +296,19 @@ int Scheduler::release(uint64_t id) {
   j.released = true;
   maybe_free(j);
   retire_check_.push_back(id);
+  return MR_OK;
+}
+
+int Scheduler::cancel(uint64_t id) {
+  auto it = jobs_.find(id);
+  if (it == jobs_.end()) return MR_EINVAL;
+  SchedJob& j = *it->second;
+  if (j.state != kQueued && j.state != kReady) return MR_ESTATE;
+  j.state = kRunning;  // transient, as for the other failures before a launch
+  ++inflight_;
+  complete(j, MR_ECANCELED, ex_->now_ns());
+  ++st_.cancelled;
+  queue_.erase(std::remove(queue_.begin(), queue_.end(), id), queue_.end());
   return MR_OK;
 }
 

@@ -34,6 +34,10 @@ struct SchedConfig {
   // only once it is done: the executor orders the two batches on the device.
   // A dependent whose reference then fails fails with it.
   bool chain_on_launch = false;
+  // A job not launched within this time of its arrival completes with
+  // MR_ETIMEOUT (0: no limit).  Launched jobs run to completion: device work
+  // is not interrupted.
+  int64_t job_timeout_ns = 0;
 };
 
 struct SchedJob {
@@ -78,7 +82,9 @@ class Executor {
 struct SchedStats {
   int64_t submitted = 0, implied = 0, completed = 0, failed = 0, rejected = 0;
   int64_t batches = 0, ctus_done = 0;
+  int64_t cancelled = 0, timed_out = 0;
   int64_t first_start_ns = 0, last_done_ns = 0;
+  int64_t host_launch_ns = 0;  // host time spent in Executor::launch
   double p50_ms = 0, p99_ms = 0, mean_ms = 0, max_ms = 0;
   uint64_t bytes_in_use = 0, peak_bytes = 0;
 };
@@ -98,6 +104,10 @@ class Scheduler {
   // forgets it, so the tables hold live jobs only.
   const SchedJob* job(uint64_t id) const;
   int release(uint64_t id);
+  // Cancel a job that has not been launched: it completes with MR_ECANCELED
+  // (its dependents then fail with MR_EDEPEND).  MR_ESTATE once launched or
+  // finished, MR_EINVAL for an unknown id.
+  int cancel(uint64_t id);
   bool idle() const;  // nothing queued or running
   SchedStats stats() const;
   int batches_in_flight() const { return (int)running_.size(); }

@@ -19,6 +19,7 @@ _lib = None
 MR_OK, MR_EINVAL, MR_ENOMEM, MR_EAGAIN, MR_EDEPEND, MR_EHIP, MR_ETIMEOUT, MR_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 MR_ESCRATCH = -8
+MR_ECANCELED = -9
 # Size of the per-GPU device array of mr_ctu_search_noalloc.
 NOALLOC_SCRATCH_BYTES = 24 << 20
 
@@ -392,7 +393,7 @@ class mr_ladder_config(ctypes.Structure):
                 ("delta_hi", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_int32), ("max_queue", ctypes.c_int32),
                 ("max_batch_jobs", ctypes.c_int32), ("reuse_mv", ctypes.c_int32),
-                ("refine_range", ctypes.c_int32)]
+                ("refine_range", ctypes.c_int32), ("job_timeout_us", ctypes.c_int32)]
 
 
 class mr_job(ctypes.Structure):
@@ -415,7 +416,9 @@ class mr_ladder_stats(ctypes.Structure):
                 ("ctus_done", ctypes.c_int64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("ctus_per_s", ctypes.c_double),
-                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64)]
+                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("cancelled", ctypes.c_int64), ("timed_out", ctypes.c_int64),
+                ("cached_bytes", ctypes.c_uint64), ("host_launch_ms", ctypes.c_double)]
 
 
 def _ladder_lib():
@@ -432,11 +435,13 @@ def _ladder_lib():
         L.mr_ladder_poll.argtypes = [vp, ctypes.POINTER(mr_completion), i32, i32,
                                      ctypes.POINTER(i32)]
         L.mr_ladder_release.argtypes = [vp, ctypes.c_uint64]
+        L.mr_ladder_cancel.argtypes = [vp, ctypes.c_uint64]
         L.mr_ladder_get_stats.argtypes = [vp, ctypes.POINTER(mr_ladder_stats)]
         L.mr_ladder_close.argtypes = [vp]
         for f in ("mr_ladder_open", "mr_ladder_put_frame", "mr_ladder_drop_frames",
                   "mr_ladder_submit", "mr_ladder_submit_many", "mr_ladder_poll",
-                  "mr_ladder_release", "mr_ladder_get_stats", "mr_ladder_close"):
+                  "mr_ladder_release", "mr_ladder_cancel", "mr_ladder_get_stats",
+                  "mr_ladder_close"):
             getattr(L, f).restype = ctypes.c_int
         L._ladder_bound = True
     return L
@@ -458,7 +463,7 @@ class Ladder:
     """mr_ladder_* handle: continuous-batching server of ladder frame-pair jobs."""
 
     def __init__(self, rungs, delta_lo=0, delta_hi=1, budget_bytes=8 << 30, max_inflight=256,
-                 max_queue=8192, max_batch_jobs=64, refine_range=None):
+                 max_queue=8192, max_batch_jobs=64, refine_range=None, job_timeout_us=0):
         L = _ladder_lib()
         cfg = mr_ladder_config()
         if not 1 <= len(rungs) <= MR_MAX_RUNGS:
@@ -481,6 +486,7 @@ class Ladder:
         # their reference job's MVs (refinement half-width r).
         cfg.reuse_mv = 0 if refine_range is None else 1
         cfg.refine_range = 0 if refine_range is None else refine_range
+        cfg.job_timeout_us = job_timeout_us
         self.rungs = rungs
         self._h = ctypes.c_void_p()
         self._frames = {}
@@ -550,6 +556,12 @@ class Ladder:
                     cost=_tensor_view(c.out.ctu_cost, (th, tw), torch.int64, device),
                     dist=_tensor_view(c.out.ctu_dist, (th, tw), torch.int64, device),
                     bits=_tensor_view(c.out.ctu_bits, (th, tw), torch.int64, device))
+
+    def cancel(self, job_id):
+        """Cancel a job not launched yet (MRError with MR_ESTATE once it has been)."""
+        rc = _ladder_lib().mr_ladder_cancel(self._h, job_id)
+        if rc != MR_OK:
+            raise MRError(rc, "mr_ladder_cancel")
 
     def release(self, job_id):
         rc = _ladder_lib().mr_ladder_release(self._h, job_id)

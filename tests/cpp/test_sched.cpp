@@ -32,6 +32,7 @@ struct FakeBatch {
 struct FakeExec : Executor {
   int64_t t = 0;                       // fake clock (ns), advanced by the test
   int64_t batch_ns = 1000000;          // every batch takes 1 ms
+  std::vector<int64_t> next_ns;        // durations of the next launches (then batch_ns)
   std::set<std::tuple<int, int, int>> frames;
   std::map<int, size_t> fp;            // per-rung footprint
   std::vector<std::vector<uint64_t>> launched;
@@ -54,7 +55,9 @@ struct FakeExec : Executor {
       j->n_ctus = 10;
     }
     launched.push_back(ids);
-    FakeBatch* fb = new FakeBatch{t + batch_ns, fail_next};
+    int64_t ns = batch_ns;
+    if (!next_ns.empty()) ns = next_ns.front(), next_ns.erase(next_ns.begin());
+    FakeBatch* fb = new FakeBatch{t + ns, fail_next};
     live.insert(fb);
     *h = fb;
     fail_next = false;
@@ -347,7 +350,109 @@ static void test_chain_on_launch() {
   }
 }
 
+// A dependent's batch that finishes before its reference's batch is not
+// retired first: the reference's failure still reaches it.
+static void test_dependent_batch_done_first() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  add_frames(ex, 0, 3, 3);
+  SchedConfig cfg = ladder_cfg(1 << 20);
+  cfg.chain_on_launch = true;
+  Scheduler s(cfg, &ex);
+  uint64_t d = 0;
+  CHECK(s.submit(0, 1, 1, &d) == MR_OK);
+  const SchedJob* dj = s.job(d);
+  const SchedJob* rj = s.job(dj->ref_job);
+  ex.next_ns = {3000000, 500000};  // reference batch 3 ms, dependent batch 0.5 ms
+  ex.fail_next = true;             // and the reference batch fails
+  s.step();                        // reference launches
+  ex.t += 100000;
+  s.step();                        // dependent launches behind it
+  CHECK(ex.launched.size() == 2 && dj->state == kRunning);
+  ex.t += 1000000;                 // the dependent's batch reports done, the reference's not
+  s.step();
+  CHECK(dj->state == kRunning && rj->state == kRunning);
+  CHECK(s.stats().completed == 0 && s.stats().failed == 0);
+  run_until_idle(s, ex);
+  CHECK(rj->state == kFailed && rj->status == MR_EHIP);
+  CHECK(dj->state == kFailed && dj->status == MR_EDEPEND);
+  // An independent batch that finishes early is not held back.
+  ex.launched.clear();
+  Scheduler s2(cfg, &ex);
+  uint64_t a = 0, b = 0;
+  add_frames(ex, 1, 3, 3);
+  ex.next_ns = {3000000, 500000};
+  CHECK(s2.submit(0, 1, 0, &a) == MR_OK);
+  s2.step();
+  ex.t += 100000;
+  CHECK(s2.submit(1, 1, 0, &b) == MR_OK);
+  s2.step();
+  ex.t += 1000000;
+  s2.step();
+  CHECK(s2.job(b)->state == kDone && s2.job(a)->state == kRunning);
+  run_until_idle(s2, ex);
+}
+
+static void test_cancel() {
+  FakeExec ex;
+  ex.fp = {{0, 600}, {1, 1}, {2, 1}};
+  add_frames(ex, 0, 3, 3);
+  add_frames(ex, 1, 3, 3);
+  Scheduler s(ladder_cfg(1000), &ex);
+  uint64_t a = 0, b = 0, d = 0;
+  CHECK(s.submit(0, 1, 0, &a) == MR_OK);
+  CHECK(s.submit(1, 1, 0, &b) == MR_OK);   // waits: 600 + 600 > 1000
+  CHECK(s.submit(1, 1, 1, &d) == MR_OK);   // dependent of b
+  s.step();
+  CHECK(ex.launched.size() == 1 && ex.launched[0][0] == a);
+  CHECK(s.cancel(a) == MR_ESTATE);         // launched: runs to its end
+  CHECK(s.cancel(b) == MR_OK);             // waiting for memory
+  CHECK(s.job(b)->state == kFailed && s.job(b)->status == MR_ECANCELED);
+  CHECK(s.cancel(b) == MR_ESTATE && s.cancel(999) == MR_EINVAL);
+  run_until_idle(s, ex);
+  CHECK(s.job(d)->state == kFailed && s.job(d)->status == MR_EDEPEND);
+  CHECK(s.job(a)->state == kDone);
+  CHECK(ex.launched.size() == 1);          // neither b nor its dependent ran
+  const SchedStats st = s.stats();
+  CHECK(st.cancelled == 1 && st.failed == 2 && st.completed == 1);
+  std::vector<uint64_t> c = s.take_completions(10);
+  CHECK(c.size() == 3);
+  for (uint64_t id : c) CHECK(s.release(id) == MR_OK);
+  s.step();
+}
+
+static void test_timeout() {
+  FakeExec ex;
+  ex.fp = {{0, 600}, {1, 1}, {2, 1}};
+  add_frames(ex, 0, 3, 3);
+  add_frames(ex, 1, 3, 3);
+  SchedConfig cfg = ladder_cfg(1000);
+  cfg.job_timeout_ns = 2000000;  // 2 ms
+  Scheduler s(cfg, &ex);
+  ex.batch_ns = 5000000;         // the running job holds the memory for 5 ms
+  uint64_t a = 0, b = 0, d = 0;
+  CHECK(s.submit(0, 1, 0, &a) == MR_OK);
+  CHECK(s.submit(1, 1, 0, &b) == MR_OK);
+  s.step();                       // a launches; b cannot fit
+  ex.t += 1000000;
+  CHECK(s.submit(1, 1, 2, &d) == MR_OK);  // a dependent of b, 1 ms later
+  s.step();
+  CHECK(s.job(b)->state == kReady && s.job(d)->state == kQueued);
+  ex.t += 1500000;                // 2.5 ms after arrival
+  s.step();
+  CHECK(s.job(b)->state == kFailed && s.job(b)->status == MR_ETIMEOUT);
+  CHECK(s.job(a)->state == kRunning);  // launched jobs are not timed out
+  run_until_idle(s, ex);
+  CHECK(s.job(a)->state == kDone && s.job(a)->status == MR_OK);
+  CHECK(s.job(d)->state == kFailed && s.job(d)->status == MR_EDEPEND);
+  CHECK(s.stats().timed_out == 1 && s.stats().failed == 2);
+  CHECK(ex.launched.size() == 1);
+}
+
 int main() {
+  test_dependent_batch_done_first();
+  test_cancel();
+  test_timeout();
   test_chain_on_launch();
   test_dependency_and_implied_reference();
   test_missing_reference_frames();

@@ -153,6 +153,27 @@ def test_graph_replays_match_eager(mr):
         batch.close()
 
 
+def test_launches_on_two_streams_are_ordered(mr):
+    """Launches of one batch on two streams back to back: the second waits on the device for
+    the first (they share the batch's scratch), so the outputs equal the eager search."""
+    import torch
+    jobs = _ladder_jobs(mr, 1)[:5]
+    eager = [_np(o) for o in mr.mr_ctu_search_batch([dict(j) for j in jobs])]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    batch = mr.Batch(jobs)
+    try:
+        for rep in range(3):
+            batch.launch(s1)
+            outs = batch.launch(s2)
+            batch.launch(s1)
+            torch.cuda.synchronize()
+            for o, e in zip(outs, eager):
+                _same(_np(o), e, f"two streams, round {rep}")
+    finally:
+        batch.close()
+
+
 def test_batch_set_jobs_swaps_frames(mr):
     import torch
     sc = synth.Scene(55, 320, 192, 6, 10, 2)

@@ -212,8 +212,73 @@ def test_ladder_errors(mr):
         assert lad.poll(4, 1000) == []
     finally:
         lad.close()
+    lad = mr.Ladder(RUNGS)
+    try:
+        for (s, f, r), t in fr.items():
+            lad.put_frame(s, f, r, t)
+        with pytest.raises(mr.MRError) as e:
+            lad.cancel(12345)  # unknown job
+        assert e.value.code == mr.MR_EINVAL
+        jid = lad.submit(0, 1, 0)
+        seen = []
+        for _ in range(200):
+            seen += lad.poll(4, 100000)
+            if seen:
+                break
+        assert seen and seen[0].job_id == jid and seen[0].status == mr.MR_OK
+        with pytest.raises(mr.MRError) as e:
+            lad.cancel(jid)  # completed: nothing to cancel
+        assert e.value.code == mr.MR_ESTATE
+        lad.release(jid)
+    finally:
+        lad.close()
     with pytest.raises(mr.MRError):
         mr.Ladder([dict(width=64, height=64, qp=30, search_range=8, ref_rung=0)])  # self-reference
+    with pytest.raises(mr.MRError):
+        mr.Ladder(RUNGS, job_timeout_us=-1)
+
+
+def test_output_blocks_recycled_across_equal_rungs(mr):
+    """Two root rungs of the same size (QP 30 and 35) served frame by frame: the output
+    blocks of released jobs are cached and handed to the next jobs of either rung. Every
+    job equals its search alone, and the cache stays within a quarter of the budget."""
+    import torch
+    rungs = [dict(width=320, height=180, qp=30, search_range=16, ref_rung=-1),
+             dict(width=320, height=180, qp=35, search_range=16, ref_rung=-1)]
+    src = synth.Scene(synth.SEED_BASE + 77, 1920, 1080, 12, 30, 4)
+    imgs = [torch.from_numpy(synth.box_downscale(src.render(f), 6, 320, 180)).cuda()
+            for f in range(7)]
+    budget = 4 << 20
+    lad = mr.Ladder(rungs, budget_bytes=budget)
+    got, cached = {}, []
+    try:
+        for f, img in enumerate(imgs):
+            lad.put_frame(0, f, 0, img)
+            lad.put_frame(0, f, 1, img)
+        for f in range(1, 7):
+            ids = {lad.submit(0, f, r): r for r in ((0, 1) if f % 2 else (1, 0))}
+            left = dict(ids)
+            for _ in range(200):
+                for c in lad.poll(8, 100000):
+                    assert c.status == 0
+                    torch.cuda.synchronize()
+                    got[(f, left.pop(c.job_id))] = {k: v.cpu().numpy()
+                                                    for k, v in lad.outputs(c).items()}
+                    lad.release(c.job_id)
+                if not left:
+                    break
+            assert not left
+            cached.append(lad.stats()["cached_bytes"])
+        st = lad.stats()
+    finally:
+        lad.close()
+    assert st["completed"] == 12 and st["failed"] == 0
+    assert max(cached) > 0 and max(cached) <= budget // 4
+    for (f, r), g in got.items():
+        exp = mr.mr_ctu_search(imgs[f], imgs[f - 1], rungs[r]["qp"], 16)
+        torch.cuda.synchronize()
+        for k in FIELDS:
+            assert np.array_equal(g[k], exp[k].cpu().numpy()), ((f, r), k)
 
 
 def test_streaming_with_dropped_frames_and_forgotten_jobs(mr):
