@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 NODE_FIELDS = ("kind", "mode", "mx", "my", "sad", "satd_inter", "satd_planar", "satd_dc",
-               "leaf_j", "leaf_d", "leaf_r", "qmx", "qmy")
+               "leaf_j", "leaf_d", "leaf_r", "qmx", "qmy", "satd_angular_best")
 
 
 def build(force: bool = True) -> str:
@@ -136,24 +136,26 @@ def mv_centre(seed: Seed, cur_w, cur_h, R, x0, y0, n):
 
 
 def ctu_nodes(cur, ref, qp, R, ctu_x, ctu_y, seed: Seed | None = None,
-              subpel: bool = False) -> np.ndarray:
-    """(85, 13) int64 per-node leaf evaluation of one CTU (fields: NODE_FIELDS)."""
+              subpel: bool = False, angular: bool = False) -> np.ndarray:
+    """(85, 14) int64 per-node leaf evaluation of one CTU (fields: NODE_FIELDS)."""
     c = np.ascontiguousarray(cur, dtype=np.uint8)
     r = np.ascontiguousarray(ref, dtype=np.uint8)
     rec = np.zeros((85, len(NODE_FIELDS)), dtype=np.int64)
     sa = seed.args() if seed is not None else _NO_SEED
     rc = lib().orc_ctu_nodes(_p(c), _p(r), c.shape[1], c.shape[0], c.shape[1], qp, R,
-                             1 if subpel else 0, ctu_x, ctu_y, *sa, _p(rec))
+                             (1 if subpel else 0) | (2 if angular else 0), ctu_x, ctu_y, *sa,
+                             _p(rec))
     if rc != 0:
         raise ValueError("orc_ctu_nodes: invalid arguments")
     return rec
 
 
 def ctu_search(cur, ref, qp, R, bounds=None, ctu_list=None, n_threads=0,
-               seed: Seed | None = None, subpel: bool = False):
+               seed: Seed | None = None, subpel: bool = False, angular: bool = False):
     """Coding-tree search of a frame pair (all CTUs or a listed subset); seeded when ``seed``
     is given; with ``subpel`` the inter MVs are refined to quarter-pel (and output in
-    quarter-pel units).
+    quarter-pel units); with ``angular`` the 33 angular intra modes are searched beside
+    planar and DC (mode codes 3..35 = 1 + the H.265 mode).
 
     Returns a dict of numpy arrays: depth, mode ([H8/8, W8/8] u8), mv ([H8/8, W8/8, 2] i16),
     cost, dist, bits ([ceil(H/64), ceil(W/64)] i64).  Units of CTUs outside the list keep 0.
@@ -175,7 +177,8 @@ def ctu_search(cur, ref, qp, R, bounds=None, ctu_list=None, n_threads=0,
     if ctu_list is not None:
         lst = np.ascontiguousarray(np.asarray(ctu_list, dtype=np.int32))
     sa = seed.args() if seed is not None else _NO_SEED
-    rc = lib().orc_ctu_search(_p(c), _p(r), W, H, W, qp, R, 1 if subpel else 0, _p(b), *sa,
+    rc = lib().orc_ctu_search(_p(c), _p(r), W, H, W, qp, R,
+                              (1 if subpel else 0) | (2 if angular else 0), _p(b), *sa,
                               _p(out["depth"]),
                               _p(out["mode"]), _p(out["mv"]), _p(out["cost"]), _p(out["dist"]),
                               _p(out["bits"]), _p(lst), 0 if lst is None else len(lst),

@@ -29,6 +29,15 @@
  *     formulas are the H.265 ones) from original neighbouring samples.
  *     READING: a neighbour is available iff it lies inside the coded picture;
  *     H.265 reference substitution; no reference smoothing, no DC edge filter.
+ *   - Optionally the 33 angular modes (same section), H.265 angular
+ *     prediction from the same substituted neighbours.  READING: no
+ *     reference smoothing and no edge filter for the pure horizontal and
+ *     vertical modes (as for DC); mode bits from the H.265 most-probable-mode
+ *     list of a block whose neighbours are unavailable, {planar, DC,
+ *     vertical}: 1 (prediction mode) + 1 (MPM flag) + 1 or 2 (MPM index) for
+ *     planar (3), DC (4) and vertical (4), 1 + 1 + 5 (fixed-length remainder)
+ *     = 7 for the other 32; ties in the order inter < planar < DC < angular by
+ *     mode number.  Mode codes: 0 inter, 1 + the H.265 intra mode otherwise.
  *   - Bottom-up quad-tree decision with optional per-8x8 depth bounds; the
  *     bounds implement depth-bound reuse (related-work section: search only
  *     depths up to the co-located reference depth) generalised to scaled
@@ -148,9 +157,29 @@ int64_t satd_block(const int* resid, int stride, int n) {
   return total;
 }
 
-// Intra prediction (mode 1 planar, 2 DC) of the n x n block at (x0, y0) of the
-// coded current picture.  Neighbours: left column p[-1][y], y = -1..2n-1
-// (corner included) and top row p[x][-1], x = 0..2n-1.
+// H.265 intraPredAngle of intra modes 2..34 (index = mode), and invAngle of
+// the modes with a negative angle (11..25): 8192 / angle rounded to nearest.
+const int kIntraAngle[35] = {0,   0,   32,  26,  21,  17,  13,  9,   5,   2,   0,   -2,
+                             -5,  -9,  -13, -17, -21, -26, -32, -26, -21, -17, -13, -9,
+                             -5,  -2,  0,   2,   5,   9,   13,  17,  21,  26,  32};
+int inv_angle(int angle) {
+  switch (angle) {
+    case -2: return -4096;
+    case -5: return -1638;
+    case -9: return -910;
+    case -13: return -630;
+    case -17: return -482;
+    case -21: return -390;
+    case -26: return -315;
+    case -32: return -256;
+    default: return 0;
+  }
+}
+
+// Intra prediction (mode code 1 planar, 2 DC, 1 + m for the angular mode m in
+// 2..34) of the n x n block at (x0, y0) of the coded current picture.
+// Neighbours: left column p[-1][y], y = -1..2n-1 (corner included) and top
+// row p[x][-1], x = 0..2n-1.
 void intra_predict(const Pic& c, int x0, int y0, int n, int mode, int* pred) {
   std::vector<int> left(2 * n + 1), top(2 * n);  // left[y + 1] = p[-1][y]
   std::vector<char> lav(2 * n + 1), tav(2 * n);
@@ -186,6 +215,41 @@ void intra_predict(const Pic& c, int x0, int y0, int n, int mode, int* pred) {
   }
   int lg = 0;
   while ((1 << lg) < n) ++lg;
+  if (mode >= 3) {  // angular: H.265 mode m = mode - 1
+    const int m = mode - 1, angle = kIntraAngle[m];
+    const bool vertical = m >= 18;
+    // main[k], k = 0..2n: the corner then the samples along the prediction's
+    // own side (top row for vertical modes, left column for horizontal ones);
+    // side[k] likewise along the other side.  left[k] = p[-1][k - 1].
+    std::vector<int> main_(2 * n + 1), side(2 * n + 1);
+    for (int k = 0; k <= 2 * n; ++k) {
+      const int t = k == 0 ? left[0] : top[k - 1];
+      const int l = left[k];
+      main_[k] = vertical ? t : l;
+      side[k] = vertical ? l : t;
+    }
+    // ref[k] for k = -n..2n at ref[k + n]: main for k >= 0; for a negative
+    // angle reaching past the corner, the other side projected onto the main
+    // line: ref[k] = side[(k * invAngle + 128) >> 8].
+    std::vector<int> ref(3 * n + 1, 0);
+    for (int k = 0; k <= 2 * n; ++k) ref[k + n] = main_[k];
+    if (angle < 0 && ((n * angle) >> 5) < -1) {
+      const int inv = inv_angle(angle);
+      for (int k = (n * angle) >> 5; k <= -1; ++k) ref[k + n] = side[(k * inv + 128) >> 8];
+    }
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        // Along the prediction direction: the row (vertical) or column
+        // (horizontal) distance from the reference line, and the position
+        // across it.
+        const int along = vertical ? y : x, across = vertical ? x : y;
+        const int pos = (along + 1) * angle;
+        const int idx = pos >> 5, fact = pos & 31;
+        const int a = ref[across + idx + 1 + n];
+        pred[y * n + x] = fact ? ((32 - fact) * a + fact * ref[across + idx + 2 + n] + 16) >> 5 : a;
+      }
+    return;
+  }
   if (mode == 1) {  // planar
     for (int y = 0; y < n; ++y)
       for (int x = 0; x < n; ++x)
@@ -207,7 +271,8 @@ struct Node {
   int qmx, qmy;        // final MV in quarter-pel units (4 mx, 4 my without sub-pel refinement)
   int64_t sad;
   int64_t satd_inter, satd_planar, satd_dc;
-  int mode;            // 0 inter, 1 planar, 2 DC
+  int64_t satd_angular_best;  // smallest SATD over the angular modes (-1: not evaluated)
+  int mode;            // 0 inter, 1 planar, 2 DC, 3..35 angular (1 + H.265 mode)
   int64_t leaf_j;      // J of the best mode, without the split flag
   int64_t leaf_d, leaf_r;
   int evaluated;
@@ -344,7 +409,7 @@ void subpel_refine(const Pic& cur, const Pic& ref, int x0, int y0, int n, int mx
 }
 
 void evaluate_leaf(const Pic& cur, const Pic& ref, int x0, int y0, int n, int R, int64_t s,
-                   const Seed* seed, bool subpel, Node* nd) {
+                   const Seed* seed, bool subpel, bool angular, Node* nd) {
   if (seed) {
     int cx, cy;
     mv_centre(*seed, cur.w, cur.h, R, x0, y0, n, &cx, &cy);
@@ -378,6 +443,19 @@ void evaluate_leaf(const Pic& cur, const Pic& ref, int x0, int y0, int n, int R,
   nd->mode = 0, nd->leaf_j = j_inter, nd->leaf_d = nd->satd_inter, nd->leaf_r = r_inter;
   if (j_pl < nd->leaf_j) nd->mode = 1, nd->leaf_j = j_pl, nd->leaf_d = nd->satd_planar, nd->leaf_r = r_pl;
   if (j_dc < nd->leaf_j) nd->mode = 2, nd->leaf_j = j_dc, nd->leaf_d = nd->satd_dc, nd->leaf_r = r_dc;
+  // Angular modes 2..34 (codes 3..35): 4 bits for vertical (26, an MPM), 7 for the others.
+  nd->satd_angular_best = -1;
+  if (angular) {
+    for (int m = 2; m <= 34; ++m) {
+      intra_predict(cur, x0, y0, n, m + 1, pred.data());
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) resid[j * n + i] = coded(cur, x0 + i, y0 + j) - pred[j * n + i];
+      const int64_t sd = satd_block(resid.data(), n, n), r_a = m == 26 ? 4 : 7;
+      const int64_t j_a = sd * 65536 + s * r_a;
+      if (nd->satd_angular_best < 0 || sd < nd->satd_angular_best) nd->satd_angular_best = sd;
+      if (j_a < nd->leaf_j) nd->mode = m + 1, nd->leaf_j = j_a, nd->leaf_d = sd, nd->leaf_r = r_a;
+    }
+  }
   nd->evaluated = 1;
 }
 
@@ -395,6 +473,7 @@ struct CtuJob {
   const uint8_t* bounds;  // [h8/8][w8/8][2] or null
   const Seed* seed;       // null for the full search
   bool subpel;            // half- and quarter-pel refinement of the inter MV
+  bool angular;           // the 33 angular intra modes beside planar and DC
   int cx, cy;             // CTU origin in pixels
   Node nodes[85];
 };
@@ -453,7 +532,8 @@ Result best_tree(CtuJob& job, int d, int lx, int ly, bool* choose_leaf) {
   Result leaf{INT64_MAX, 0, 0};
   if (leaf_ok) {
     if (!nd.evaluated)
-      evaluate_leaf(*job.cur, *job.ref, x0, y0, n, job.R, job.s, job.seed, job.subpel, &nd);
+      evaluate_leaf(*job.cur, *job.ref, x0, y0, n, job.R, job.s, job.seed, job.subpel,
+                    job.angular, &nd);
     int flag = d < 3 ? 1 : 0;
     leaf = Result{nd.leaf_j + job.s * flag, nd.leaf_d, nd.leaf_r + flag};
   }
@@ -513,10 +593,11 @@ int64_t orc_satd(const int32_t* resid, int stride, int n) {
   return satd_block(r.data(), n, n);
 }
 
-// Intra prediction of the n x n block at (x0, y0); mode 1 planar, 2 DC.
+// Intra prediction of the n x n block at (x0, y0); mode 1 planar, 2 DC,
+// 3..35 the angular mode (mode - 1).
 int orc_intra_predict(const uint8_t* cur, int w, int h, int stride, int x0, int y0, int n,
                       int mode, int32_t* pred) {
-  if (!valid_pic(cur, w, h, stride) || (mode != 1 && mode != 2) || n < 4) return -1;
+  if (!valid_pic(cur, w, h, stride) || mode < 1 || mode > 35 || n < 4) return -1;
   Pic c = make_pic(cur, w, h, stride);
   std::vector<int> p(n * n);
   intra_predict(c, x0, y0, n, mode, p.data());
@@ -582,20 +663,23 @@ int orc_mv_centre(const int16_t* ref_mv, int ref_w, int ref_h, int cur_w, int cu
 
 // Per-node leaf evaluation of one CTU (all 85 nodes, no bounds); record layout
 // per node: kind, mode, mx, my, sad, satd_inter, satd_planar, satd_dc, leaf_j,
-// leaf_d, leaf_r, qmx, qmy (13 int64; mx, my integer ME, qmx, qmy the final MV
-// in quarter-pel units).  Used to check the decision against enumeration.
+// leaf_d, leaf_r, qmx, qmy, satd_angular_best (14 int64; mx, my integer ME,
+// qmx, qmy the final MV in quarter-pel units).  Used to check the decision
+// against enumeration.  flags: bit 0 sub-pel refinement, bit 1 angular modes.
 int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int qp,
-                  int R, int subpel, int ctu_x, int ctu_y, const int16_t* ref_mv, int ref_w,
+                  int R, int flags, int ctu_x, int ctu_y, const int16_t* ref_mv, int ref_w,
                   int ref_h, int refine_r, int seed_qpel, int64_t* rec) {
   Seed sd{};
-  if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || qp < 0 || qp > 51 || subpel < 0 ||
-      subpel > 1 || !make_seed(ref_mv, ref_w, ref_h, refine_r, R, seed_qpel, &sd))
+  if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || qp < 0 || qp > 51 || flags < 0 ||
+      flags > 3 || !make_seed(ref_mv, ref_w, ref_h, refine_r, R, seed_qpel, &sd))
     return -1;
+  const bool subpel = (flags & 1) != 0, angular = (flags & 2) != 0;
   Pic c = make_pic(cur, w, h, stride), r = make_pic(ref, w, h, stride);
   CtuJob* job = new CtuJob();
   job->cur = &c, job->ref = &r, job->R = R, job->s = sqrt_lambda_q16(qp), job->bounds = nullptr;
   job->seed = ref_mv ? &sd : nullptr;
-  job->subpel = subpel != 0;
+  job->subpel = subpel;
+  job->angular = angular;
   job->cx = ctu_x * kCtu, job->cy = ctu_y * kCtu;
   for (int d = 0; d < 4; ++d)
     for (int ly = 0; ly < (1 << d); ++ly)
@@ -607,9 +691,10 @@ int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stri
         else if (x0 + n > c.w8 || y0 + n > c.h8) nd.kind = 1;
         else {
           nd.kind = 2;
-          evaluate_leaf(c, r, x0, y0, n, R, job->s, job->seed, job->subpel, &nd);
+          evaluate_leaf(c, r, x0, y0, n, R, job->s, job->seed, job->subpel, job->angular, &nd);
         }
-        int64_t* o = rec + 13 * node_index(d, lx, ly);
+        int64_t* o = rec + 14 * node_index(d, lx, ly);
+        o[13] = nd.satd_angular_best;
         o[0] = nd.kind, o[1] = nd.mode, o[2] = nd.mx, o[3] = nd.my, o[4] = nd.sad;
         o[11] = nd.qmx, o[12] = nd.qmy;
         o[5] = nd.satd_inter, o[6] = nd.satd_planar, o[7] = nd.satd_dc, o[8] = nd.leaf_j;
@@ -625,16 +710,18 @@ int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stri
 //   ctu_cost/dist/bits: [ceil(h/64)][ceil(w/64)] i64.
 // bounds: null for full search, else [h8/8][w8/8][2] {lo, hi}.
 // ref_mv: null for full search, else a seeded search (see make_seed).
+// flags: bit 0 sub-pel refinement, bit 1 angular intra modes.
 int orc_ctu_search(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int qp,
-                   int R, int subpel, const uint8_t* bounds, const int16_t* ref_mv, int ref_w,
+                   int R, int flags, const uint8_t* bounds, const int16_t* ref_mv, int ref_w,
                    int ref_h, int refine_r, int seed_qpel, uint8_t* depth, uint8_t* mode,
                    int16_t* mv, int64_t* ctu_cost, int64_t* ctu_dist, int64_t* ctu_bits,
                    const int32_t* ctu_list, int n_list, int n_threads) {
   Seed sd{};
   if (!valid_pic(cur, w, h, stride) || !ref || R < 0 || R > 128 || qp < 0 || qp > 51 ||
-      subpel < 0 || subpel > 1 || !depth || !mode || !mv || !ctu_cost || !ctu_dist ||
+      flags < 0 || flags > 3 || !depth || !mode || !mv || !ctu_cost || !ctu_dist ||
       !ctu_bits || !make_seed(ref_mv, ref_w, ref_h, refine_r, R, seed_qpel, &sd))
     return -1;
+  const bool subpel = (flags & 1) != 0, angular = (flags & 2) != 0;
   const Seed* seed = ref_mv ? &sd : nullptr;
   Pic c = make_pic(cur, w, h, stride), r = make_pic(ref, w, h, stride);
   int ctw = (c.w8 + kCtu - 1) / kCtu, cth = (c.h8 + kCtu - 1) / kCtu;
@@ -658,7 +745,8 @@ int orc_ctu_search(const uint8_t* cur, const uint8_t* ref, int w, int h, int str
       *job = CtuJob{};
       job->cur = &c, job->ref = &r, job->R = R, job->s = s, job->bounds = bounds;
       job->seed = seed;
-      job->subpel = subpel != 0;
+      job->subpel = subpel;
+      job->angular = angular;
       job->cx = (t % ctw) * kCtu, job->cy = (t / ctw) * kCtu;
       bool leaf;
       Result root = best_tree(*job, 0, 0, 0, &leaf);

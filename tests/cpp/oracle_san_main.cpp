@@ -24,10 +24,10 @@ int orc_subpel_refine(const uint8_t* cur, const uint8_t* ref, int w, int h, int 
 int orc_mv_centre(const int16_t* ref_mv, int ref_w, int ref_h, int cur_w, int cur_h, int R,
                   int r, int qpel, int x0, int y0, int n, int32_t* cx, int32_t* cy);
 int orc_ctu_nodes(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int qp,
-                  int R, int subpel, int ctu_x, int ctu_y, const int16_t* ref_mv, int ref_w,
+                  int R, int flags, int ctu_x, int ctu_y, const int16_t* ref_mv, int ref_w,
                   int ref_h, int refine_r, int seed_qpel, int64_t* rec);
 int orc_ctu_search(const uint8_t* cur, const uint8_t* ref, int w, int h, int stride, int qp,
-                   int R, int subpel, const uint8_t* bounds, const int16_t* ref_mv, int ref_w,
+                   int R, int flags, const uint8_t* bounds, const int16_t* ref_mv, int ref_w,
                    int ref_h, int refine_r, int seed_qpel, uint8_t* depth, uint8_t* mode,
                    int16_t* mv, int64_t* ctu_cost, int64_t* ctu_dist, int64_t* ctu_bits,
                    const int32_t* ctu_list, int n_list, int n_threads);
@@ -63,7 +63,7 @@ static std::vector<uint8_t> picture(int w, int h, int stride, int shift) {
   return p;
 }
 
-static void search_case(int w, int h, int stride, int qp, int R, int subpel, bool bounded,
+static void search_case(int w, int h, int stride, int qp, int R, int flags, bool bounded,
                         int seed_r, int qpel, int threads) {
   const std::vector<uint8_t> ref = picture(w, h, stride, 0), cur = picture(w, h, stride, 3);
   const int uw = (w + 7) / 8, uh = (h + 7) / 8, tw = (uw * 8 + 63) / 64, th = (uh * 8 + 63) / 64;
@@ -82,7 +82,7 @@ static void search_case(int w, int h, int stride, int qp, int R, int subpel, boo
     seed.resize((size_t)((sw + 7) / 8) * ((sh + 7) / 8) * 2);
     for (auto& v : seed) v = (int16_t)((int)(rnd() % (2u * 40 + 1)) - 40);
   }
-  const int rc = orc_ctu_search(cur.data(), ref.data(), w, h, stride, qp, R, subpel,
+  const int rc = orc_ctu_search(cur.data(), ref.data(), w, h, stride, qp, R, flags,
                                 bounded ? bounds.data() : nullptr,
                                 seed_r >= 0 ? seed.data() : nullptr, sw, sh,
                                 seed_r >= 0 ? seed_r : 0, qpel, depth.data(), mode.data(),
@@ -90,14 +90,15 @@ static void search_case(int w, int h, int stride, int qp, int R, int subpel, boo
   CHECK(rc == 0);
   const int64_t s = orc_sqrt_lambda_q16(qp);
   for (size_t t = 0; t < J.size(); ++t) CHECK(J[t] == D[t] * 65536 + s * B[t]);
-  for (size_t u = 0; u < depth.size(); ++u) CHECK(depth[u] <= 3 && mode[u] <= 2);
+  const int max_mode = (flags & 2) ? 35 : 2;  // bit 1: angular modes
+  for (size_t u = 0; u < depth.size(); ++u) CHECK(depth[u] <= 3 && mode[u] <= max_mode);
   // A listed subset (last CTU first) gives the same results for those CTUs.
   if (J.size() > 1) {
     std::vector<int64_t> J2(J.size()), D2(J.size()), B2(J.size());
     std::vector<uint8_t> d2(depth.size()), m2(depth.size());
     std::vector<int16_t> v2(mv.size());
     const int32_t list[2] = {(int32_t)J.size() - 1, 0};
-    CHECK(orc_ctu_search(cur.data(), ref.data(), w, h, stride, qp, R, subpel,
+    CHECK(orc_ctu_search(cur.data(), ref.data(), w, h, stride, qp, R, flags,
                          bounded ? bounds.data() : nullptr, seed_r >= 0 ? seed.data() : nullptr,
                          sw, sh, seed_r >= 0 ? seed_r : 0, qpel, d2.data(), m2.data(), v2.data(),
                          J2.data(), D2.data(), B2.data(), list, 2, 2) == 0);
@@ -122,7 +123,7 @@ int main() {
     const std::vector<uint8_t> c = picture(w, h, w, 1);
     std::vector<int32_t> pred(64 * 64);
     for (int n : {8, 16, 32})
-      for (int mode : {1, 2})
+      for (int mode = 1; mode <= 35; ++mode)
         for (int y0 : {0, 8, 24})
           for (int x0 : {0, 16, 32}) CHECK(orc_intra_predict(c.data(), w, h, w, x0, y0, n, mode, pred.data()) == 0);
   }
@@ -141,8 +142,9 @@ int main() {
     const std::vector<int16_t> seed(6 * 4 * 2, 100);
     int32_t cx, cy;
     CHECK(orc_mv_centre(seed.data(), 41, 30, 90, 61, 16, 3, 0, 80, 56, 8, &cx, &cy) == 0);
-    std::vector<int64_t> rec(85 * 13);
+    std::vector<int64_t> rec(85 * 14);
     CHECK(orc_ctu_nodes(a.data(), b.data(), w, h, w, 27, 6, 1, 0, 0, nullptr, 0, 0, 0, 0, rec.data()) == 0);
+    CHECK(orc_ctu_nodes(a.data(), b.data(), w, h, w, 27, 6, 3, 0, 0, nullptr, 0, 0, 0, 0, rec.data()) == 0);
   }
 
   // Whole searches: sub-unit and ragged pictures, padded strides, every search form.
@@ -153,6 +155,8 @@ int main() {
     search_case(z.w, z.h, z.stride, 0, 8, 1, false, -1, 0, 2);
     search_case(z.w, z.h, z.stride, 27, 8, 0, true, 2, 0, 4);
     search_case(z.w, z.h, z.stride, 22, 6, 1, false, 6, 1, 2);
+    search_case(z.w, z.h, z.stride, 37, 4, 2, true, -1, 0, 3);   // angular intra modes
+    search_case(z.w, z.h, z.stride, 30, 4, 3, false, 3, 0, 2);   // angular + sub-pel, seeded
   }
 
   // Depth bounds at dyadic and odd ratios, up and down.
