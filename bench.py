@@ -21,6 +21,8 @@ Beside it the JSON line carries:
                  (refinement r = 4), and the refinement kernel's absdiff rate;
   subpel       : the 1080p workload with quarter-pel refinement (SATD, H.265 interpolation):
                  time, the refinement's share and operation rate, RD-cost change;
+  angular      : the 1080p workload with the 33 angular intra modes: time, the leaf kernel's
+                 operation rate, the share of angular CUs' units, RD-cost change;
   multi_qp     : one 1920x1080 pair at QPs 22/26/30/34/38 with the median QP as master
                  (same-resolution sharing): speedup and RD-cost increase per QP;
   dag          : the multi-encoding scheme (3 resolutions x 5 QPs, median-QP masters chained
@@ -32,8 +34,8 @@ Beside it the JSON line carries:
                  and the oracle on the whole first 1920x1080 pair, compared likewise.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-single]
-                      [--no-small] [--no-pruned] [--no-subpel] [--no-multi-qp] [--no-dag]
-                      [--no-serving] [--serve-seconds S]
+                      [--no-small] [--no-pruned] [--no-subpel] [--no-angular] [--no-multi-qp]
+                      [--no-dag] [--no-serving] [--serve-seconds S]
 """
 import argparse
 import json
@@ -428,6 +430,45 @@ def run_subpel(mr, torch, frames, jobs_int, args, int_search_ms):
         "rd_cost_change_pct": round(100.0 * (j_sp - j_int) / j_int, 6)}
 
 
+def angular_ops(w, h):
+    """Algorithmic operations the angular modes add to the leaf kernel: for each of the 33
+    modes and every 4x4 tile of every inside node, 16 predicted samples (two products, two
+    additions and a shift each) and the tile's SATD."""
+    return 33 * inside_tiles(w, h) * (16 * 5 + SATD4_OPS)
+
+
+def run_angular(mr, torch, frames, jobs_int, args):
+    """The 1080p workload with the 33 angular intra modes scored beside planar and DC."""
+    QP, R, NP = 27, 64, len(jobs_int)
+    jobs_a = [dict(cur=frames[k + 1], ref=frames[k], qp=QP, search_range=R, angular=True)
+              for k in range(NP)]
+    stream = torch.cuda.current_stream()
+    ba = mr.Batch(jobs_a)
+    elapsed, pst = timed_launches(mr, torch, lambda: ba.launch(stream), args.steps,
+                                  max(1, args.warmup))
+    j_int = sum(int(j["out"]["cost"].sum().item()) for j in jobs_int)
+    j_a = sum(int(j["out"]["cost"].sum().item()) for j in jobs_a)
+    modes = torch.cat([j["out"]["mode"].flatten() for j in jobs_a])
+    ang_units = int((modes >= 3).sum().item())
+    ms = elapsed * 1e3 / args.steps
+    stage = stage_avg(pst)
+    ops = (leaf_ops(1920, 1080) + angular_ops(1920, 1080)) * NP
+    ctus = jobs_int[0]["out"]["cost"].numel() * NP
+    ba.close()
+    return {
+        "workload": "the 1080p 8 pairs (1920x1080, R 64, QP 27) with the 33 angular intra modes "
+                    "(H.265 angular prediction) scored beside planar and DC",
+        "ms_per_step": round(ms, 4), "ctus_per_s": round(ctus / (ms * 1e-3), 1),
+        "stage_avg_ms": stage,
+        "leaf_roofline": {
+            "bound": "alu", "unit": "T int16 ops/s", "ops_per_launch": ops,
+            "achieved": round(ops / (stage["leaf"] * 1e-3) / 1e12, 3),
+            "peak": round(PEAK_OPS16 / 1e12, 3),
+            "frac": round(ops / (stage["leaf"] * 1e-3) / PEAK_OPS16, 4)},
+        "angular_unit_share": round(ang_units / modes.numel(), 4),
+        "rd_cost_change_pct": round(100.0 * (j_a - j_int) / j_int, 6)}
+
+
 def run_pruned(mr, synth, torch, dev):
     log("rendering 3840x2160 source pair")
     src = synth.Scene(synth.SEED_BASE + 2, 3840, 2160, 24, 96, 8)
@@ -733,6 +774,7 @@ def main():
     ap.add_argument("--no-pruned", action="store_true")
     ap.add_argument("--no-multi-qp", action="store_true")
     ap.add_argument("--no-subpel", action="store_true")
+    ap.add_argument("--no-angular", action="store_true")
     ap.add_argument("--no-dag", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
@@ -768,7 +810,7 @@ def main():
     value, ms_per_step, config, roofline, head_outs, head_host = run_headline(
         mr, synth, torch, dev, args)
 
-    single = subpel = small = pruned = multi_qp = dag = serving = cpu = None
+    single = subpel = angular = small = pruned = multi_qp = dag = serving = cpu = None
     single_cpu = None
     if not args.no_single:
         single, frames, jobs, gpu0, host0 = run_single_res(mr, synth, torch, dev, args)
@@ -778,6 +820,9 @@ def main():
             subpel = run_subpel(mr, torch, frames, jobs, args,
                                 single["roofline"]["stage_avg_ms"]["search"])
             log(f"subpel: {subpel}")
+        if not args.no_angular:
+            angular = run_angular(mr, torch, frames, jobs, args)
+            log(f"angular: {angular}")
         del frames, jobs
     if not args.no_small:
         small = run_small(mr, synth, torch, dev)
@@ -803,7 +848,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": config, "roofline": roofline, "cpu_baseline": cpu, "single_res": single,
-        "small": small, "subpel": subpel, "pruned": pruned, "multi_qp": multi_qp, "dag": dag,
+        "small": small, "subpel": subpel, "angular": angular, "pruned": pruned,
+        "multi_qp": multi_qp, "dag": dag,
         "serving": serving, "thesis_context": THESIS_CONTEXT,
     }
     print(json.dumps(line), flush=True)

@@ -82,18 +82,27 @@ typedef struct {
  * neighbours at the stage's step, J = SATD * 65536 + s * (se(qx) + se(qy))
  * with (qx, qy) in quarter-pel units, the centre keeping ties, then raster
  * order (dy outer).  The leaf's inter candidate is then that MV and SATD, and
- * out.mv holds quarter-pel units. */
+ * out.mv holds quarter-pel units.
+ * angular: 0 = intra DC and planar only; 1 = also the 33 angular intra modes
+ * (HEVC background section: DC, planar and angular modes), H.265 angular
+ * prediction from the same substituted neighbours, no reference smoothing and
+ * no edge filters, each scored by its SATD with 4 mode bits for vertical
+ * (mode 26) and 7 for the others (most-probable-mode list of a block with
+ * unavailable neighbours: planar, DC, vertical); ties in the order inter <
+ * planar < DC < angular by mode number; out.mode then holds 1 + the H.265
+ * mode (3..35) for angular CUs. */
 typedef struct {
   int32_t qp;
   int32_t search_range;
   int32_t subpel;
+  int32_t angular;
 } mr_search_params;
 
 /* Outputs (device, caller-allocated).  With U = ceil(H/8) rows and
  * V = ceil(W/8) columns of 8x8 units, and T = ceil(H/64) x ceil(W/64) CTUs in
  * raster order:
  *   depth[U][V]   u8: depth 0..3 of the CU covering the unit (CU size 64 >> d)
- *   mode[U][V]    u8: 0 inter, 1 planar, 2 DC
+ *   mode[U][V]    u8: 0 inter, 1 planar, 2 DC, 3..35 angular (1 + H.265 mode)
  *   mv[U][V][2]  i16: (mx, my) best integer MV of that CU (also for intra CUs)
  *   ctu_cost[T], ctu_dist[T], ctu_bits[T] i64: J, D and R of each CTU, with
  *     J == D * 65536 + s * R. */
@@ -112,7 +121,8 @@ typedef struct {
  * a node at depth d covering units S may stop (be a leaf) iff
  * d >= min_S lo or it may not split, and may split iff d < 3 and
  * d < max_S hi.  Scratch memory is allocated stream-ordered on hip_stream.
- * Errors: MR_EINVAL (null pointers, sizes, qp, R, subpel), MR_ENOMEM, MR_EHIP. */
+ * Errors: MR_EINVAL (null pointers, sizes, qp, R, subpel, angular), MR_ENOMEM,
+ * MR_EHIP. */
 int mr_ctu_search(const mr_frame* cur, const mr_frame* ref, const mr_search_params* p,
                   const uint8_t* bounds, mr_search_out* out, void* hip_stream);
 

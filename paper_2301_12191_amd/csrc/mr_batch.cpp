@@ -201,7 +201,8 @@ int mr_batch_set_jobs(mr_batch* b, const mr_search_job* jobs, int32_t n_jobs) {
     if (rc != MR_OK) return rc;
     if (q.cur.width != jd.w || q.cur.height != jd.h || q.params.search_range != jd.R ||
         sqrt_lambda_q16(q.params.qp) != jd.s || (q.bounds != nullptr) != (jd.bounds != nullptr) ||
-        (q.seed != nullptr) != (jd.seed_mv != nullptr) || q.params.subpel != jd.subpel)
+        (q.seed != nullptr) != (jd.seed_mv != nullptr) || q.params.subpel != jd.subpel ||
+        q.params.angular != jd.angular)
       return MR_EINVAL;
   }
   if (b->launched && hipEventSynchronize(b->last) != hipSuccess) return MR_EHIP;

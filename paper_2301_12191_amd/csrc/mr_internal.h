@@ -97,6 +97,7 @@ struct JobDesc {
   int32_t seed_r;          // refinement half-width r
   int32_t seed_qpel;       // 1: seed_mv in quarter-pel units
   int32_t rctu_start;      // first CTU of this job among the seeded jobs' CTUs
+  int32_t angular;         // 1: the leaf also scores the 33 angular intra modes
   // Sub-pel refinement: per node {quarter-pel MV (qx | qy << 16), SATD}.
   int32_t subpel;
   int32_t sctu_start;      // first CTU of this job among the sub-pel jobs' CTUs

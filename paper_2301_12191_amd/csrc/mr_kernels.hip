@@ -504,7 +504,61 @@ struct LeafShared {
   uint8_t mode[kNodes];
   int64_t lj[kNodes], ld[kNodes], lr[kNodes];
   uint8_t split_ok[kNodes], leaf_ok[kNodes];
+  // Angular modes: per node the best (J, SATD, mode code); node 0's per-mode
+  // SATDs arrive as per-wave partial sums.
+  int64_t angj[kNodes];
+  uint32_t angd[kNodes];
+  uint8_t angm[kNodes];
+  uint32_t ang0[4][33];
 };
+
+// H.265 intraPredAngle of intra modes 2..34 (index = mode) and, for the
+// negative angles, invAngle = 8192 / angle rounded (index = -angle).
+__constant__ int8_t kAngle[35] = {0,   0,   32,  26,  21,  17,  13,  9,   5,   2,   0,   -2,
+                                  -5,  -9,  -13, -17, -21, -26, -32, -26, -21, -17, -13, -9,
+                                  -5,  -2,  0,   2,   5,   9,   13,  17,  21,  26,  32};
+__constant__ int16_t kInvAngle[33] = {0, 0, -4096, 0, 0, -1638, 0, 0, 0, -910, 0,
+                                      0, 0, -630, 0, 0, 0, -482, 0, 0, 0, -390,
+                                      0, 0, 0, 0, -315, 0, 0, 0, 0, 0, -256};
+
+// Reference sample k (-n <= k <= 2n) of the angular prediction of a node
+// whose neighbours R hold p[-1][i - 1] at R[i] (i = 0..2n, R[0] the corner)
+// and p[i][-1] at R[2n + 1 + i] (i = 0..2n-1): along the top row for vertical
+// modes, the left column for horizontal ones, and for k < 0 the other side
+// projected onto that line (sample (k * invAngle + 128) >> 8 of it).
+__device__ __forceinline__ int ang_ref(const int16_t* R, int n, bool vertical, int inv, int k) {
+  if (k >= 0) return vertical ? R[k == 0 ? 0 : 2 * n + k] : R[k];
+  const int j = (k * inv + 128) >> 8;
+  return vertical ? R[j] : R[2 * n + j];
+}
+
+// The 16 predicted samples (row-major) of the 4x4 tile at (px0, py0) inside an
+// n x n node for angular mode m: along the prediction direction, the row
+// (vertical modes) or column (horizontal modes) q of the tile is (q + 1) *
+// angle / 32 samples ahead of the reference line, split into an integer step
+// and a 1/32 fraction shared by the four samples across it, which take
+// ((32 - f) a + f b + 16) >> 5 of two neighbouring reference samples.
+__device__ __forceinline__ void angular_tile(const int16_t* R, int n, int m, int px0, int py0,
+                                             int pred[16]) {
+  const int angle = kAngle[m];
+  const bool vertical = m >= 18;
+  const int inv = angle < 0 ? kInvAngle[-angle] : 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int along = (vertical ? py0 : px0) + q;
+    const int pos = (along + 1) * angle, idx = pos >> 5, f = pos & 31;
+    const int base = (vertical ? px0 : py0) + idx + 1;
+    int r[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) r[i] = ang_ref(R, n, vertical, inv, min(base + i, 2 * n));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = f ? ((32 - f) * r[i] + f * r[i + 1] + 16) >> 5 : r[i];
+      if (vertical) pred[q * 4 + i] = v;
+      else pred[i * 4 + q] = v;
+    }
+  }
+}
 
 // Sum over aligned groups of `width` lanes (4, 16 or 64; a compile-time
 // constant after unrolling), every lane of a group receiving it: DPP adds
@@ -519,6 +573,9 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t v, int width) {
   return v;
 }
 
+// ANG: the angular-mode instantiation (a separate kernel, so that the default
+// one keeps its register budget); a job's own flag still decides.
+template <bool ANG>
 __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
@@ -601,9 +658,11 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   // (entries 2n + 1 .. 3n + 1) only, so just those 2n + 2 are computed: the
   // closed form gives each one directly.
   const int stride = jb->stride;
+  const bool angular = ANG && jb->angular != 0;  // uniform
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    const int n = kCtu >> d, len = 2 * n + 2, tpn = 256 >> (2 * d);
+    // Angular prediction reads every entry: all 4n + 1 then.
+    const int n = kCtu >> d, len = angular ? 4 * n + 1 : 2 * n + 2, tpn = 256 >> (2 * d);
     const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + (tid >> (8 - 2 * d));
     const int j = tid & (tpn - 1);
     if (sh.elig[node]) {
@@ -611,7 +670,8 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       int16_t* R = sh.refs + ref_offset(node);
       int dcs = 0;
       for (int m = j; m < len; m += tpn) {
-        const int off = m <= n ? m + 1 : n + m;  // 1 .. n + 1, then 2n + 1 .. 3n + 1
+        // 1 .. n + 1, then 2n + 1 .. 3n + 1 (planar, DC), or every entry (angular)
+        const int off = angular ? m : (m <= n ? m + 1 : n + m);
         int v = 128;
         if (a <= b) {
           const int k = clampi(off <= 2 * n ? 2 * n - off : off, a, b);
@@ -760,9 +820,59 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       } else if (lane == 0) {
         sh.part0[wave][0] = v0, sh.part0[wave][1] = v1, sh.part0[wave][2] = v2;
       }
+      if (angular) {
+        // Modes 2..34 two at a time (one packed SATD for both); the group's
+        // first lane keeps the node's first minimum of J in mode order.
+        const bool e = sh.elig[node] != 0;
+        const int16_t* L = sh.refs + ref_offset(node);
+        const int px0 = tx * 4 - lx * n, py0 = ty * 4 - ly * n;
+        int64_t bj = INT64_MAX;
+        uint32_t bd = 0;
+        int bm = 0;
+        for (int ma = 2; ma <= 34; ma += 2) {
+          const int mb = ma < 34 ? ma + 1 : ma;
+          uint32_t sa = 0, sb = 0;
+          if (e) {
+            int pa[16], pb[16];
+            angular_tile(L, n, ma, px0, py0, pa);
+            angular_tile(L, n, mb, px0, py0, pb);
+            sh2 pr[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) pr[i] = (sh2){(short)(c[i] - pa[i]), (short)(c[i] - pb[i])};
+            const uint32_t pk = satd4x4_pair(pr);
+            sa = pk & 0xFFFFu, sb = pk >> 16;
+          }
+          sa = group_sum(sa, w), sb = group_sum(sb, w);
+          if (d == 0) {
+            if (lane == 0) {
+              sh.ang0[wave][ma - 2] = sa;
+              if (mb != ma) sh.ang0[wave][mb - 2] = sb;
+            }
+          } else {
+            const int64_t ja = (int64_t)sa * 65536 + jb->s * (ma == 26 ? 4 : 7);
+            if (ja < bj) bj = ja, bd = sa, bm = ma + 1;
+            const int64_t jbb = (int64_t)sb * 65536 + jb->s * (mb == 26 ? 4 : 7);
+            if (mb != ma && jbb < bj) bj = jbb, bd = sb, bm = mb + 1;
+          }
+        }
+        if (d > 0 && (lane & (w - 1)) == 0)
+          sh.angj[node] = bj, sh.angd[node] = bd, sh.angm[node] = (uint8_t)bm;
+      }
     }
   }
   __syncthreads();
+  if (angular && tid == 0 && sh.elig[0]) {
+    int64_t bj = INT64_MAX;
+    uint32_t bd = 0;
+    int bm = 0;
+    for (int m = 2; m <= 34; ++m) {
+      const uint32_t sd = sh.ang0[0][m - 2] + sh.ang0[1][m - 2] + sh.ang0[2][m - 2] +
+                          sh.ang0[3][m - 2];
+      const int64_t j = (int64_t)sd * 65536 + jb->s * (m == 26 ? 4 : 7);
+      if (j < bj) bj = j, bd = sd, bm = m + 1;
+    }
+    sh.angj[0] = bj, sh.angd[0] = bd, sh.angm[0] = (uint8_t)bm;
+  }
   const int64_t s = jb->s;
   if (tid < kNodes) {
     const int node = tid;
@@ -784,6 +894,8 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     if (jp < j) j = jp, dd = sh.satd[node][1], rr = 3, m = 1;
     const int64_t jd = (int64_t)sh.satd[node][2] * 65536 + s * 4;
     if (jd < j) j = jd, dd = sh.satd[node][2], rr = 4, m = 2;
+    if (angular && sh.angj[node] < j)
+      j = sh.angj[node], dd = sh.angd[node], rr = sh.angm[node] == 27 ? 4 : 7, m = sh.angm[node];
     sh.lj[node] = j, sh.ld[node] = dd, sh.lr[node] = rr, sh.mode[node] = m;
   }
   __syncthreads();
@@ -1019,13 +1131,14 @@ __global__ __launch_bounds__(256) void search_kernel_d8(const JobDesc* jobs_, co
   search_persistent<8>(jobs_, items_, qo, counter, win, win_dwords_max);
 }
 
+template <bool ANG>
 __global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus) {
   __shared__ LeafShared sh;
   const cjob jobs = (cjob)jobs_;
   const int flat = xcd_contiguous_index();
   if (flat >= n_ctus) return;
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
-  leaf_ctu(jobs + j, flat - jobs[j].ctu_start, sh);
+  leaf_ctu<ANG>(jobs + j, flat - jobs[j].ctu_start, sh);
 }
 
 hipError_t launch_store_job(const JobDesc& jb, JobDesc* dst, hipStream_t st) {
@@ -1081,8 +1194,12 @@ hipError_t launch_search(const JobDesc* jobs, const uint2* items, const QueueOff
   return hipGetLastError();
 }
 
-hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st) {
-  hipLaunchKernelGGL(leaf_kernel, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus);
+hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, bool angular,
+                       hipStream_t st) {
+  if (angular)
+    hipLaunchKernelGGL(leaf_kernel<true>, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus);
+  else
+    hipLaunchKernelGGL(leaf_kernel<false>, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus);
   return hipGetLastError();
 }
 

@@ -236,7 +236,7 @@ int validate_job(const mr_frame* cur, const mr_frame* ref, const mr_search_param
   if (cur->width != ref->width || cur->height != ref->height || cur->stride != ref->stride)
     return MR_EINVAL;
   if (p->qp < 0 || p->qp > 51 || p->search_range < 0 || p->search_range > 128 || p->subpel < 0 ||
-      p->subpel > 1)
+      p->subpel > 1 || p->angular < 0 || p->angular > 1)
     return MR_EINVAL;
   if (!out->depth || !out->mode || !out->mv || !out->ctu_cost || !out->ctu_dist ||
       !out->ctu_bits)
@@ -341,6 +341,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
   P->n_rjobs = P->n_rctus = P->max_r = 0;
   P->n_sjobs = P->n_sctus = 0;
   P->max_pad_rows = 0;
+  P->any_angular = false;
   P->n_ctus = 0;
   P->scratch_bytes = 0;
   P->lds_bytes = 0;
@@ -383,6 +384,8 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
                         up256((size_t)n_ctus * kNodes) + up256((size_t)n_ctus * 16);
     P->n_ctus += n_ctus;
     jb.subpel = p[j]->subpel;
+    jb.angular = p[j]->angular;
+    if (jb.angular) P->any_angular = true;
     if (jb.subpel) {
       jb.sctu_start = P->n_sctus;
       P->scratch_bytes += up256((size_t)n_ctus * kNodes * 8);  // subres
@@ -549,7 +552,7 @@ hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, con
   if (e == hipSuccess && P.n_sjobs > 0)
     e = launch_subpel(jobs_d, L.slist, P.n_sjobs, P.n_sctus, st);
   if (ev) profile_mark(ev, 2, st);
-  if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, st);
+  if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, P.any_angular, st);
   if (ev) profile_mark(ev, 3, st);
   return e;
 }

@@ -66,6 +66,7 @@ struct Plan {
   int n_rjobs = 0, n_rctus = 0, max_r = 0;
   int n_sjobs = 0, n_sctus = 0;
   int max_pad_rows = 0;  // rows of the largest padded reference
+  bool any_angular = false;  // some job scores the angular intra modes
   QueueOffsets qoff{};   // search items of each per-XCD queue
   // Input to make_plan: true leaves the jobs' key tables (qtab, dtab) null
   // for the caller to place and fill, instead of the cached device copies.
@@ -111,7 +112,8 @@ hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* co
 hipError_t launch_search(const JobDesc* jobs, const uint2* items, const QueueOffsets& qoff,
                          int D, int strip, int n_wg, size_t lds_bytes, uint32_t* counter,
                          hipStream_t st);
-hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, hipStream_t st);
+hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, bool angular,
+                       hipStream_t st);
 hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int max_rows,
                       hipStream_t st);
 hipError_t launch_subpel(const JobDesc* jobs, const int* slist, int n_sjobs, int n_sctus,

@@ -37,7 +37,7 @@ class mr_frame(ctypes.Structure):
 
 class mr_search_params(ctypes.Structure):
     _fields_ = [("qp", ctypes.c_int32), ("search_range", ctypes.c_int32),
-                ("subpel", ctypes.c_int32)]
+                ("subpel", ctypes.c_int32), ("angular", ctypes.c_int32)]
 
 
 class mr_search_out(ctypes.Structure):
@@ -185,15 +185,16 @@ def _seed_struct(seed):
 
 def mr_ctu_search(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: int,
                   bounds: torch.Tensor | None = None, out: dict | None = None, stream=None,
-                  seed: dict | None = None, subpel: bool = False):
+                  seed: dict | None = None, subpel: bool = False, angular: bool = False):
     """Coding-tree search of one frame pair (see mr_ctu_search and mr_ctu_search_seeded in
     include/mr.h); seeded when ``seed`` is given; with ``subpel`` the MVs are refined to
-    quarter-pel and returned in quarter-pel units."""
+    quarter-pel and returned in quarter-pel units; with ``angular`` the 33 angular intra
+    modes are scored beside planar and DC."""
     H, W = cur.shape
     if out is None:
         out = alloc_outputs(W, H, cur.device)
     fc, fr = _frame(cur, "cur"), _frame(ref, "ref")
-    prm = mr_search_params(qp, search_range, 1 if subpel else 0)
+    prm = mr_search_params(qp, search_range, 1 if subpel else 0, 1 if angular else 0)
     o = mr_search_out(_dev_ptr(out["depth"], torch.uint8, "depth"),
                       _dev_ptr(out["mode"], torch.uint8, "mode"),
                       _dev_ptr(out["mv"], torch.int16, "mv"),
@@ -218,12 +219,12 @@ def mr_ctu_search(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: i
 
 def mr_ctu_search_noalloc(cur: torch.Tensor, ref: torch.Tensor, qp: int, search_range: int,
                           out: dict, bounds: torch.Tensor | None = None, stream=None,
-                          seed: dict | None = None, subpel: bool = False):
+                          seed: dict | None = None, subpel: bool = False, angular: bool = False):
     """The allocation-free search (mr_ctu_search_noalloc in include/mr.h): the caller passes
     the outputs; the library allocates nothing.  Same arguments and results as
     mr_ctu_search."""
     fc, fr = _frame(cur, "cur"), _frame(ref, "ref")
-    prm = mr_search_params(qp, search_range, 1 if subpel else 0)
+    prm = mr_search_params(qp, search_range, 1 if subpel else 0, 1 if angular else 0)
     o = _out_struct(out)
     bp = None if bounds is None else _dev_ptr(bounds, torch.uint8, "bounds")
     sd = _seed_struct(seed)
@@ -261,7 +262,8 @@ def _job_array(jobs):
             sp = ctypes.pointer(sd)
         arr[i] = mr_search_job(_frame(cur, "cur"), _frame(j["ref"], "ref"),
                                mr_search_params(j["qp"], j["search_range"],
-                                                1 if j.get("subpel") else 0),
+                                                1 if j.get("subpel") else 0,
+                                                1 if j.get("angular") else 0),
                                None if b is None else _dev_ptr(b, torch.uint8, "bounds"),
                                _out_struct(j["out"]), sp)
     return arr

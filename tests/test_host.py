@@ -50,7 +50,8 @@ def _fake_out(mr):
 
 @pytest.mark.parametrize("case", ["qp_low", "qp_high", "range_neg", "range_big", "null_cur",
                                   "size_mismatch", "stride_small", "zero_width", "huge",
-                                  "null_out_field", "subpel_2", "subpel_neg", "offsets_32bit"])
+                                  "null_out_field", "subpel_2", "subpel_neg", "offsets_32bit",
+                                  "angular_2"])
 def test_search_rejects_invalid_arguments_before_launch(libmr, case):
     from paper_2301_12191_amd import mr
     cur, ref = _fake_frame(mr), _fake_frame(mr)
@@ -80,6 +81,8 @@ def test_search_rejects_invalid_arguments_before_launch(libmr, case):
         prm.subpel = 2
     elif case == "subpel_neg":
         prm.subpel = -1
+    elif case == "angular_2":
+        prm.angular = 2
     elif case == "offsets_32bit":  # stride * (height - 1) + width must stay below 2^31
         cur, ref = _fake_frame(mr, 64, 8192, 300000), _fake_frame(mr, 64, 8192, 300000)
     rc = libmr.mr_ctu_search(ctypes.byref(cur), ctypes.byref(ref), ctypes.byref(prm), None,
