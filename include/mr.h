@@ -275,6 +275,7 @@ typedef struct {
                          1: this rung's four fields below (same ranges) */
   int32_t delta_lo, delta_hi;
   int32_t reuse_mv, refine_range;
+  int32_t angular;    /* this rung's jobs also score the angular intra modes (mr_search_params) */
 } mr_rung;
 
 #define MR_MAX_RUNGS 16

@@ -189,7 +189,7 @@ class GpuExecutor : public Executor {
       }
       cur[i] = mr_frame{fc.luma, r.width, r.height, fc.stride};
       ref[i] = mr_frame{fr.luma, r.width, r.height, fr.stride};
-      prm[i] = mr_search_params{r.qp, r.search_range, r.subpel};
+      prm[i] = mr_search_params{r.qp, r.search_range, r.subpel, r.angular};
       JobOut* o = new JobOut();
       size_t off[7];
       const size_t bytes = out_bytes(r, j.ref_job != 0, off);
@@ -438,9 +438,10 @@ int mr_ladder_open(const mr_ladder_config* cfg, mr_ladder** out) {
         g.ref_rung >= cfg->n_rungs || g.ref_rung == r || g.own_policy < 0 || g.own_policy > 1 ||
         (g.own_policy && !policy_ok(g.delta_lo, g.delta_hi, g.reuse_mv, g.refine_range)))
       return MR_EINVAL;
-    if (g.subpel < 0 || g.subpel > 1) return MR_EINVAL;
+    if (g.subpel < 0 || g.subpel > 1 || g.angular < 0 || g.angular > 1) return MR_EINVAL;
     RungCfg rc{g.width, g.height, g.qp, g.search_range, g.ref_rung};
     rc.subpel = g.subpel;
+    rc.angular = g.angular;
     const bool own = g.own_policy != 0;
     rc.dlo = own ? g.delta_lo : cfg->delta_lo;
     rc.dhi = own ? g.delta_hi : cfg->delta_hi;

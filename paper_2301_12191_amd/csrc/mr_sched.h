@@ -21,6 +21,7 @@ struct RungCfg {
   int dlo = 0, dhi = 1;  // depth-bound policy of this rung as a dependent
   int refine = -1;       // refinement half-width of its seed, -1: not seeded
   int subpel = 0;        // quarter-pel refinement of its MVs
+  int angular = 0;       // angular intra modes
 };
 
 struct SchedConfig {

@@ -386,7 +386,7 @@ class mr_rung(ctypes.Structure):
                 ("search_range", ctypes.c_int32), ("ref_rung", ctypes.c_int32),
                 ("subpel", ctypes.c_int32), ("own_policy", ctypes.c_int32), ("delta_lo", ctypes.c_int32),
                 ("delta_hi", ctypes.c_int32), ("reuse_mv", ctypes.c_int32),
-                ("refine_range", ctypes.c_int32)]
+                ("refine_range", ctypes.c_int32), ("angular", ctypes.c_int32)]
 
 
 class mr_ladder_config(ctypes.Structure):
@@ -480,7 +480,7 @@ class Ladder:
                                    r.get("ref_rung", -1), 1 if r.get("subpel") else 0,
                                    1 if own else 0, r.get("delta_lo", 0),
                                    r.get("delta_hi", 1), 0 if rr is None else 1,
-                                   0 if rr is None else rr)
+                                   0 if rr is None else rr, 1 if r.get("angular") else 0)
         cfg.delta_lo, cfg.delta_hi = delta_lo, delta_hi
         cfg.hbm_budget_bytes = budget_bytes
         cfg.max_inflight, cfg.max_queue, cfg.max_batch_jobs = max_inflight, max_queue, max_batch_jobs

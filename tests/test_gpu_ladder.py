@@ -108,6 +108,49 @@ def test_mix_equals_alone(mr):
     assert st["p99_ms"] >= st["p50_ms"] > 0
 
 
+def test_angular_rungs_equal_alone(mr):
+    """Rungs whose jobs score the angular intra modes (the reference rung and one
+    dependent) beside a plain dependent: each job equals its angular / plain search alone."""
+    import torch
+    rungs = [dict(RUNGS[0], angular=True), dict(RUNGS[1], angular=True), dict(RUNGS[2])]
+    fr = _frames(2, 2)
+    jobs = [(s, 1, r) for s in range(2) for r in (2, 1, 0)]
+    lad = mr.Ladder(rungs)
+    got = {}
+    try:
+        for (s, f, r), t in fr.items():
+            lad.put_frame(s, f, r, t)
+        ids = {lad.submit(*j): j for j in jobs}
+        for _ in range(2000):
+            for c in lad.poll(64, 100000):
+                assert c.status == 0
+                if c.job_id in ids:
+                    torch.cuda.synchronize()
+                    got[ids[c.job_id]] = {k: v.cpu().numpy() for k, v in lad.outputs(c).items()}
+                lad.release(c.job_id)
+            if len(got) == len(ids):
+                break
+    finally:
+        lad.close()
+    assert len(got) == len(jobs)
+    for (s, f, r) in jobs:
+        ref_out = mr.mr_ctu_search(fr[(s, f, 0)], fr[(s, f - 1, 0)], RUNGS[0]["qp"],
+                                   RUNGS[0]["search_range"], angular=True)
+        cfg = RUNGS[r]
+        if r == 0:
+            exp = ref_out
+        else:
+            b = mr.mr_depth_bounds(ref_out["depth"], RUNGS[0]["width"], RUNGS[0]["height"],
+                                   cfg["width"], cfg["height"], 0, 1)
+            exp = mr.mr_ctu_search(fr[(s, f, r)], fr[(s, f - 1, r)], cfg["qp"],
+                                   cfg["search_range"], bounds=b, angular=(r == 1))
+        torch.cuda.synchronize()
+        for k in FIELDS:
+            assert np.array_equal(got[(s, f, r)][k], exp[k].cpu().numpy()), ((s, f, r), k)
+        if r < 2:
+            assert got[(s, f, r)]["mode"].max() >= 3
+
+
 def test_submit_many_equals_alone(mr):
     """The same shuffled mix as above, handed to the server in one mr_ladder_submit_many."""
     fr = _frames(3, 3)
