@@ -14,6 +14,8 @@ Beside it the JSON line carries:
                  leaf kernel of the same launch as algorithmic 16-bit SATD operations;
   single_res   : 1920x1080, 8 consecutive pairs, R 64, QP 27 (its own roofline);
   small        : the 416x240 pair (R 16, QP 32): GPU latency of one call and of a graph replay;
+  small_ranges : the ladder's 426x240 / 640x360 / 960x540 rungs (R 16 / 24 / 32), 16 pairs each:
+                 search time and fraction of peak per rung;
   pruned       : multi-resolution pruning on a 3840x2160 source: 960x540 reference (QP 32,
                  R 32) bounds 1920x1080 (QP 27, R 64) and 3840x2160 (QP 22, R 128), refine
                  depths n..n+1; speedup of pruned over full search and the exact RD-cost
@@ -34,7 +36,8 @@ Beside it the JSON line carries:
                  and the oracle on the whole first 1920x1080 pair, compared likewise.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-single]
-                      [--no-small] [--no-pruned] [--no-subpel] [--no-angular] [--no-multi-qp]
+                      [--no-small] [--no-small-ranges] [--no-pruned] [--no-subpel]
+                      [--no-angular] [--no-multi-qp]
                       [--no-dag] [--no-serving] [--serve-seconds S]
 """
 import argparse
@@ -398,6 +401,32 @@ def run_small(mr, synth, torch, dev):
             "graph_replay_ms_p99": round(pct_of(lg, 0.99), 4),
             "stage_avg_ms": stage_avg(prof),
             "search_frac_of_peak": round(absdiff / search_s / PEAK_ABSDIFF, 4)}
+
+
+def run_small_ranges(mr, synth, torch, dev, args):
+    """The ladder's three smallest rungs (426x240 R 16, 640x360 R 24, 960x540 R 32), 16
+    consecutive pairs each from the ladder source, one batch per rung at the built-in tiles:
+    search time and fraction of peak where few wavefronts carry the work."""
+    nf = 16
+    src = synth.Scene(synth.SEED_BASE + 3, 3840, 2160, 24, 96, 8)
+    srcs = [src.render(t) for t in range(nf + 1)]
+    stream = torch.cuda.current_stream()
+    res = {}
+    for (w, h, n, qp) in synth.LADDER[:3]:
+        R = synth.search_range_for_width(w)
+        rung = [torch.from_numpy(synth.box_downscale(f, n, w, h)).to(dev) for f in srcs]
+        jobs = [dict(cur=rung[k], ref=rung[k - 1], qp=qp, search_range=R)
+                for k in range(1, nf + 1)]
+        b = mr.Batch(jobs)
+        _, prof = timed_launches(mr, torch, lambda: b.launch(stream), max(5, args.steps),
+                                 max(1, args.warmup))
+        b.close()
+        search_s = prof["search"][0] / 1e3 / max(1, prof["search"][1])
+        absdiff = search_absdiff(w, h, R) * nf
+        res[f"{w}x{h}"] = {"R": R, "pairs": nf, "ctus": jobs[0]["out"]["cost"].numel() * nf,
+                           "search_ms": round(search_s * 1e3, 4),
+                           "frac_of_peak": round(absdiff / search_s / PEAK_ABSDIFF, 4)}
+    return res
 
 
 def run_subpel(mr, torch, frames, jobs_int, args, int_search_ms):
@@ -771,6 +800,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-small-ranges", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
     ap.add_argument("--no-multi-qp", action="store_true")
     ap.add_argument("--no-subpel", action="store_true")
@@ -810,7 +840,8 @@ def main():
     value, ms_per_step, config, roofline, head_outs, head_host = run_headline(
         mr, synth, torch, dev, args)
 
-    single = subpel = angular = small = pruned = multi_qp = dag = serving = cpu = None
+    single = subpel = angular = small = small_ranges = pruned = multi_qp = dag = None
+    serving = cpu = None
     single_cpu = None
     if not args.no_single:
         single, frames, jobs, gpu0, host0 = run_single_res(mr, synth, torch, dev, args)
@@ -827,6 +858,9 @@ def main():
     if not args.no_small:
         small = run_small(mr, synth, torch, dev)
         log(f"small: {small}")
+    if not args.no_small_ranges:
+        small_ranges = run_small_ranges(mr, synth, torch, dev, args)
+        log(f"small_ranges: {small_ranges}")
     if not args.no_pruned:
         pruned = run_pruned(mr, synth, torch, dev)
     if not args.no_multi_qp:
@@ -848,7 +882,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": config, "roofline": roofline, "cpu_baseline": cpu, "single_res": single,
-        "small": small, "subpel": subpel, "angular": angular, "pruned": pruned,
+        "small": small, "small_ranges": small_ranges, "subpel": subpel, "angular": angular,
+        "pruned": pruned,
         "multi_qp": multi_qp, "dag": dag,
         "serving": serving, "thesis_context": THESIS_CONTEXT,
     }
