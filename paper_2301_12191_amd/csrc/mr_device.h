@@ -36,6 +36,19 @@ __device__ __forceinline__ int se_bits_dev(int v) {
   return 2 * (31 - __builtin_clz(k + 1u)) + 1;
 }
 
+// Field k (0..3) of four packed 16-bit values, times m (< 2^16, uniform), plus
+// a: one v_mad_u32_u16 whose op_sel picks the high half of the dword holding
+// the field, instead of an extract and a multiply-add.
+__device__ __forceinline__ uint32_t field_mad(uint64_t v, int k, uint32_t m, uint32_t a) {
+  const uint32_t x = (uint32_t)(v >> (32 * (k >> 1)));
+  uint32_t r;
+  if (k & 1)
+    asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(r) : "v"(x), "s"(m), "v"(a));
+  else
+    asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(m), "v"(a));
+  return r;
+}
+
 // v plus the value of another lane (DPP permutation CTRL) in one v_add_u32.
 template <int CTRL>
 __device__ __forceinline__ uint32_t add_dpp(uint32_t v) {

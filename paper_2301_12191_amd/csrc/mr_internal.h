@@ -25,6 +25,23 @@ __host__ __device__ inline int refine_pad_x(int R) { return (R + 24 + 3) & ~3; }
 // Row margin: the refinement reaches R rows, the sub-pel patches R + 4.
 __host__ __device__ inline int refine_pad_y(int R) { return R + 8; }
 
+// Refinement key tables of a seeded job, built by the pad kernel in the job's
+// scratch.  With c(v) = s * se(4 v) (the MV-bit term of one component, < 2^28)
+// and i = v + R in [0, 2R]:
+//   rk[i] = (c(dx) >> 16) * 2^9 + rank(i), rank ordering the 2R + 1 columns by
+//           (c(dx) & 0xFFFF, i) over the whole range;
+//   rd[rank(i)] = (c(dx) & 0xFFFF) * 2^17 + i;
+//   ru[i] = c(dy) * 2^17 + i * (2R + 1).
+// Within one window row, (SAD + (c >> 16)) * 2^9 + rank orders the candidates
+// as their 64-bit keys do, and the row minimum m decodes to the key
+// (m >> 9) * 2^33 + rd[m & 511] + ru[dy + R].
+constexpr int kRtabSpan = 257;  // 2R + 1 for R <= 128
+constexpr int kRankBitsR = 9;
+constexpr size_t kRtabRk = 0;
+constexpr size_t kRtabRd = 1056;                   // after rk, 8-byte aligned
+constexpr size_t kRtabRu = kRtabRd + 8 * kRtabSpan;
+constexpr size_t kRtabBytes = kRtabRu + 8 * kRtabSpan;
+
 // Search work queues, one per XCD: queue q holds items [off[q], off[q + 1]).
 constexpr int kQueues = 8;
 struct QueueOffsets {
@@ -97,6 +114,7 @@ struct JobDesc {
   int32_t seed_r;          // refinement half-width r
   int32_t seed_qpel;       // 1: seed_mv in quarter-pel units
   int32_t rctu_start;      // first CTU of this job among the seeded jobs' CTUs
+  uint8_t* rtab;           // refinement key tables (kRtabBytes), seeded jobs only
   int32_t angular;         // 1: the leaf also scores the 33 angular intra modes
   // Sub-pel refinement: per node {quarter-pel MV (qx | qy << 16), SATD}.
   int32_t subpel;

@@ -230,19 +230,6 @@ __device__ __forceinline__ void merge_keys(uint32_t vk, const uint64_t* __restri
   }
 }
 
-// Field k (0..3) of four packed 16-bit values, times m (< 2^16, uniform), plus
-// a: one v_mad_u32_u16 whose op_sel picks the high half of the dword holding
-// the field, instead of an extract and a multiply-add.
-__device__ __forceinline__ uint32_t field_mad(uint64_t v, int k, uint32_t m, uint32_t a) {
-  const uint32_t x = (uint32_t)(v >> (32 * (k >> 1)));
-  uint32_t r;
-  if (k & 1)
-    asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(r) : "v"(x), "s"(m), "v"(a));
-  else
-    asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(m), "v"(a));
-  return r;
-}
-
 // One wavefront: steps [st_lo, st_hi) of one (CTU, band); `win` points at
 // this CTU's column 0 of the staged window (dx = -R), whose dword columns are
 // hs apart; `ring` is this wavefront's 512-byte LDS ring for the current CTU

@@ -25,33 +25,6 @@ __device__ __forceinline__ int scale_round_dev(int m, int num, int den) {
   return m < 0 ? -q : q;
 }
 
-// Sums of acc[k] over aligned groups of 4^(3-d) lanes (d = 3: none; 2: quads;
-// 1: rows of 16; 0: the wavefront), every lane of a group receiving its sum.
-// d is uniform; independent DPP adds are interleaved across k.
-template <int NP>
-__device__ __forceinline__ void group_sums(uint32_t (&acc)[NP], int d) {
-  if (d < 3) {
-#pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0xB1>(acc[k]);  // quad_perm [1,0,3,2]
-#pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x4E>(acc[k]);  // quad_perm [2,3,0,1]
-  }
-  if (d < 2) {
-#pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x141>(acc[k]);  // row_half_mirror
-#pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x140>(acc[k]);  // row_mirror
-  }
-  if (d == 0) {
-#pragma unroll
-    for (int k = 0; k < NP; ++k)
-      acc[k] = (uint32_t)(__builtin_amdgcn_readlane((int)acc[k], 0) +
-                          __builtin_amdgcn_readlane((int)acc[k], 16) +
-                          __builtin_amdgcn_readlane((int)acc[k], 32) +
-                          __builtin_amdgcn_readlane((int)acc[k], 48));
-  }
-}
-
 // Signed Exp-Golomb length of v without a branch on the sign.
 __device__ __forceinline__ uint32_t se_len(int v) {
   const uint32_t k = 2u * (uint32_t)(v < 0 ? -v : v) - (v > 0 ? 1u : 0u);
@@ -59,23 +32,77 @@ __device__ __forceinline__ uint32_t se_len(int v) {
 }
 
 // A reference row segment of NQ + 3 dwords, re-aligned on this lane's first
-// window column (byte sh of raw[0], per lane), as the four byte shifts of its
-// first NQ + 1 dwords plus one more plain dword:
-// out[o][j] = window bytes 4j + o .. 4j + o + 3 (j = 0..NQ), x = bytes
-// 4 NQ + 4 .. 4 NQ + 7.
+// window column (byte sh of raw[0], per lane), as NQ + 1 overlapping dword
+// pairs: P[q] = window bytes 4q .. 4q + 7.
 template <int NQ>
-__device__ __forceinline__ void shifts(const uint32_t (&raw)[NQ + 3], int sh,
-                                       uint32_t (&out)[4][NQ + 1], uint32_t& x) {
+__device__ __forceinline__ void align_pairs(const uint32_t (&raw)[NQ + 3], int sh,
+                                            uint64_t (&P)[NQ + 1]) {
   uint32_t e[NQ + 2];
 #pragma unroll
   for (int m = 0; m < NQ + 2; ++m) e[m] = __builtin_amdgcn_alignbyte(raw[m + 1], raw[m], sh);
 #pragma unroll
-  for (int j = 0; j <= NQ; ++j) {
-    out[0][j] = e[j];
+  for (int q = 0; q <= NQ; ++q) P[q] = ((uint64_t)e[q + 1] << 32) | e[q];
+}
+
+// The minimum 32-bit key SAD * 2^9 + Ks[k] over a window row's NP = 4 NQ + 1
+// candidates, whose block SADs this lane holds as NQ packed quads (16-bit
+// fields k = positions 4q + k) and one 32-bit SAD (position 4 NQ).  The SADs
+// are first summed over aligned groups of 4^(3-d) lanes (d = 3: none; 2: quads;
+// 1: rows of 16; 0: the wavefront) with DPP adds; d is uniform.  For d >= 1
+// every lane of a group receives its sums; for d = 0 the lanes of the last row
+// (48..63) do: after the row sums, row 1 adds row 0 (row_bcast:15 into rows 1
+// and 3) and rows 2 and 3 add lane 31 (row_bcast:31).  A field holds an 8x8
+// SAD (<= 16320) and, after the quad level, a 16x16 SAD (<= 65280): below
+// 2^16, so 32-bit adds on two fields are exact.  Larger CUs are unpacked after
+// the quad level.
+template <int NQ>
+__device__ __forceinline__ uint32_t row_min_key(uint64_t (&aq)[NQ], uint32_t a8, int d,
+                                                const uint32_t (*Ks)[64], int b) {
+  constexpr int NP = 4 * NQ + 1;
+  uint32_t w[2 * NQ + 1];
 #pragma unroll
-    for (int o = 1; o < 4; ++o) out[o][j] = __builtin_amdgcn_alignbyte(e[j + 1], e[j], o);
+  for (int q = 0; q < NQ; ++q) w[2 * q] = (uint32_t)aq[q], w[2 * q + 1] = (uint32_t)(aq[q] >> 32);
+  w[2 * NQ] = a8;
+  if (d < 3) {
+#pragma unroll
+    for (int i = 0; i <= 2 * NQ; ++i) w[i] = add_dpp<0xB1>(w[i]);  // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int i = 0; i <= 2 * NQ; ++i) w[i] = add_dpp<0x4E>(w[i]);  // quad_perm [2,3,0,1]
   }
-  x = e[NQ + 1];
+  uint32_t m = 0xFFFFFFFFu;
+  if (d >= 2) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const uint64_t v = ((uint64_t)w[2 * q + 1] << 32) | w[2 * q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) m = min(m, field_mad(v, k, 1u << kRankBitsR, Ks[4 * q + k][b]));
+    }
+    m = min(m, (w[2 * NQ] << kRankBitsR) + Ks[4 * NQ][b]);
+  } else {
+    uint32_t acc[NP];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      acc[4 * q] = w[2 * q] & 0xFFFFu, acc[4 * q + 1] = w[2 * q] >> 16;
+      acc[4 * q + 2] = w[2 * q + 1] & 0xFFFFu, acc[4 * q + 3] = w[2 * q + 1] >> 16;
+    }
+    acc[4 * NQ] = w[2 * NQ];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x141>(acc[k]);  // row_half_mirror
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x140>(acc[k]);  // row_mirror
+    if (d == 0) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+        acc[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)acc[k], 0x142, 0xA, 0xF, false);
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+        acc[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)acc[k], 0x143, 0xC, 0xF, false);
+    }
+    // SAD < 2^21: SAD * 2^9 + Ks stays below 2^32, also past the window.
+#pragma unroll
+    for (int k = 0; k < NP; ++k) m = min(m, (acc[k] << kRankBitsR) + Ks[k][b]);
+  }
+  return m;
 }
 
 // One wavefront: the CUs of depth d (uniform) of one CTU, one pass of
@@ -83,24 +110,30 @@ __device__ __forceinline__ void shifts(const uint32_t (&raw)[NQ + 3], int sh,
 // 8x8 block at Z-order position b; the lanes of one CU sum their block SADs per
 // candidate.
 //
-// Keys.  The arg-min key J * 2^17 + idx of candidate (dx, dy) is split as
-//   T(dx) + SAD * 2^33 + U(dy),  T = s * se(4dx) * 2^17 + dx + R,
-//   U = s * se(4dy) * 2^17 + (dy + R) * (2R + 1),
-// so a window row is reduced with T alone and U is added once per row
-// (s * se < 2^28 and every key < 2^54).
+// Keys.  A candidate's arg-min key J * 2^17 + idx is
+//   (SAD + (c(dx) >> 16)) * 2^33 + rd[rank(dx + R)] + ru[dy + R]
+// with the job's tables (c = s * se(4 v); rank orders the columns of the
+// whole range by (c & 0xFFFF, dx)), so inside one window row the 32-bit
+// (SAD + (c(dx) >> 16)) * 2^9 + rank(dx + R) = SAD * 2^9 + rk[dx + R] orders the
+// candidates exactly as their keys do: one shift-add and a minimum per
+// candidate, and one 64-bit decode per row.  Columns past the window (last
+// pass only, uniform) get rk = 2^31, above every valid row key (< 2^30).
 // Columns.  Pass p covers window columns p NP .. p NP + NP - 1.  Every new
 // reference row is re-aligned on this lane's first column of the pass (a
-// per-lane byte shift), so position k = 4q + o reads the pre-shifted dwords
-// S[o][q] and S[o][q + 1], and position 4 NQ reads S[0][NQ] and X.  Columns
-// past the window (last pass only, uniform) are skipped or get T = 2^62.
-// Rows.  The 8 reference rows of the current dy are a ring of pre-shifted rows
-// S[slot][o][j]; step u of a group of 8 uses slot (u + row) & 7 for window row
+// per-lane byte shift) and kept as NQ + 1 dword pairs P[q] (bytes 4q .. 4q + 7).
+// One v_qsad_pk_u16_u8 of P[q] and a current dword adds that dword's SADs at
+// the 4 byte shifts 4q .. 4q + 3 into 16-bit fields, so positions 0 .. 4 NQ - 1
+// take 2 NQ of them per row and position 4 NQ two v_sad_u8.  The ring of 8
+// rows then holds 16 (NQ + 1) registers instead of 13 NQ + 8 pre-shifted ones:
+// more wavefronts per SIMD.
+// Rows.  The 8 reference rows of the current dy are a ring of aligned rows
+// P[slot][q]; step u of a group of 8 uses slot (u + row) & 7 for window row
 // `row`, and the row loaded during step u (8 rows below) replaces slot u, which
 // step u + 1 no longer needs: the ring turns by renaming, one new row per step,
-// loaded one step ahead.
+// loaded one step ahead.  A row's two table loads are used one step later.
 template <int NQ>
 __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nband,
-                            uint64_t (*Ts)[64]) {
+                            uint32_t (*Ks)[64]) {
   constexpr int NP = 4 * NQ + 1, NDW = NQ + 3;
   const int n = kCtu >> d, sh3 = 3 - d;
   const int b = threadIdx.x & 63;
@@ -108,10 +141,7 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   const int ctu_x = (ctu % jb->ctus_w) * kCtu, ctu_y = (ctu / jb->ctus_w) * kCtu;
   const int lx = bx >> sh3, ly = by >> sh3;
   const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
-  const bool e = jb->elig[(size_t)ctu * kNodes + node] != 0;
-  if (__ballot(e) == 0) return;  // no CU of this depth may be a leaf
-
-  const int R = jb->R, r = jb->seed_r, lim = R - r, span = 2 * R + 1;
+  const int R = jb->R, r = jb->seed_r, lim = R - r;
   const int ncand = 2 * r + 1;
   const int rem = ncand - pass * NP;  // window columns left for this pass (uniform)
   if (rem <= 0) return;
@@ -119,21 +149,18 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   const int iy0 = band * bh, iy1 = min(ncand, iy0 + bh);
   if (iy0 >= iy1) return;
   const int W = jb->w, H = jb->h;
-  // Search centre of this lane's CU (all products < 2^27).
-  int cxm, cym;
+  // The eligibility flags, the reference MV at this lane's CU centre and the
+  // current block are loaded together: the wavefront's first global loads.
+  const bool e = jb->elig[(size_t)ctu * kNodes + node] != 0;
+  const uint32_t sw = jb->seed_w, shh = jb->seed_h;
+  int16_t m0, m1;
   {
     const uint32_t px = ctu_x + lx * n + n / 2, py = ctu_y + ly * n + n / 2;
-    const uint32_t sw = jb->seed_w, shh = jb->seed_h;
     const uint32_t xr = min(px * sw / (uint32_t)W, sw - 1);
     const uint32_t yr = min(py * shh / (uint32_t)H, shh - 1);
     const int16_t* m = jb->seed_mv + 2 * ((yr >> 3) * ((sw + 7) >> 3) + (xr >> 3));
-    const int qs = 2 * jb->seed_qpel;  // quarter-pel maps: 4 map units per pixel
-    cxm = clampi(scale_round_dev(m[0], W, sw << qs), -lim, lim);
-    cym = clampi(scale_round_dev(m[1], H, shh << qs), -lim, lim);
+    m0 = m[0], m1 = m[1];
   }
-  // This lane's block (blocks outside the coded picture belong to CUs that are
-  // not searched; their loads are kept inside the padded reference).
-  const int X0 = min(ctu_x + 8 * bx, jb->w8 - 8), Y0 = min(ctu_y + 8 * by, jb->h8 - 8);
   uint32_t c[16];
   {
     const uint4* cp = (const uint4*)(jb->curpack + (size_t)ctu * 1024 + b * 16);
@@ -143,35 +170,54 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
       c[4 * i] = v.x, c[4 * i + 1] = v.y, c[4 * i + 2] = v.z, c[4 * i + 3] = v.w;
     }
   }
+  // Consume every load here, so that the compiler keeps them above the exit
+  // test (one round of latency instead of three).
+  asm volatile("" ::"v"(m0), "v"(m1), "v"(c[0]), "v"(c[4]), "v"(c[8]), "v"(c[12]));
+  if (__ballot(e) == 0) return;  // no CU of this depth may be a leaf
+  // Search centre of this lane's CU (all products < 2^27).
+  const int qs = 2 * jb->seed_qpel;  // quarter-pel maps: 4 map units per pixel
+  const int cxm = clampi(scale_round_dev(m0, W, sw << qs), -lim, lim);
+  const int cym = clampi(scale_round_dev(m1, H, shh << qs), -lim, lim);
+  // This lane's block (blocks outside the coded picture belong to CUs that are
+  // not searched; their loads are kept inside the padded reference).
+  const int X0 = min(ctu_x + 8 * bx, jb->w8 - 8), Y0 = min(ctu_y + 8 * by, jb->h8 - 8);
   const int pitch = jb->pad_pitch;
-  const uint32_t s = (uint32_t)jb->s;
+  const uint32_t* __restrict__ rk = (const uint32_t*)(jb->rtab + kRtabRk);
+  const uint64_t* __restrict__ rd = (const uint64_t*)(jb->rtab + kRtabRd);
+  const uint64_t* __restrict__ ru = (const uint64_t*)(jb->rtab + kRtabRu);
   // This pass's first window column in the padded reference, the dword-aligned
   // column at or left of it and its byte in that dword (0..3, per lane).
   const int xs = X0 + cxm - r + jb->pad_x + pass * NP;
   const int shb = xs & 3;
   // Column key terms, one LDS slot per (position, lane): kept out of the
   // register file, which the ring of pre-shifted rows fills.
+  {
+    // All loads first (indices clamped into the table), then the selects.
+    uint32_t kv[NP];
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const int p = pass * NP + k;  // window column of position k (valid: 0..2r)
-    const int dx = cxm - r + p;
-    Ts[k][b] = p < ncand ? ((uint64_t)__umul24(s, se_len(4 * dx)) << 17) + (uint64_t)(dx + R)
-                         : (1ull << 62);
+    for (int k = 0; k < NP; ++k) kv[k] = rk[min(cxm - r + pass * NP + k + R, 2 * R)];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)  // window column pass NP + k (valid: 0..2r)
+      Ks[k][b] = pass * NP + k < ncand ? kv[k] : 0x80000000u;
   }
   const uint32_t* src = (const uint32_t*)(jb->refpad +
                                           (size_t)(Y0 + cym - r + iy0 + jb->pad_y) * pitch +
                                           (xs - shb));
   const int dwp = pitch >> 2;
-  uint32_t S[8][4][NQ + 1], X[8];
+  uint64_t P[8][NQ + 1];
 #pragma unroll
   for (int row = 0; row < 8; ++row) {
     uint32_t raw[NDW];
 #pragma unroll
     for (int j = 0; j < NDW; ++j) raw[j] = src[row * dwp + j];
-    shifts<NQ>(raw, shb, S[row], X[row]);
+    align_pairs<NQ>(raw, shb, P[row]);
   }
   const int nrow = iy1 - iy0;
   uint64_t best = kKeyNone;
+  // The previous row's minimum and its table entries.  Before the first row:
+  // a key above every real one (< 2^54) and below kKeyNone.
+  uint32_t pm = 0xFFFFFFFFu;
+  uint64_t pd = 0, pu = 0;
   for (int g = 0; g < nrow; g += 8) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -187,43 +233,41 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
 #pragma unroll
         for (int j = 0; j < NDW; ++j) nxt[j] = src[(t + 8) * dwp + j];
       }
-      uint32_t acc[NP];
+      // Every position, also past the window in a partial last pass: its
+      // samples are inside the padded reference and its key term is 2^31.
+      uint64_t aq[NQ];
 #pragma unroll
-      for (int k = 0; k < NP; ++k) acc[k] = 0;
+      for (int q = 0; q < NQ; ++q) aq[q] = 0;
+      uint32_t a8 = 0;
 #pragma unroll
       for (int row = 0; row < 8; ++row) {
         const int sl = (u + row) & 7;
-        // Every position, also past the window in a partial last pass: its
-        // samples are inside the padded reference and its key term is 2^62.
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-          for (int o = 0; o < 4; ++o) {
-            acc[4 * q + o] = __builtin_amdgcn_sad_u8(c[2 * row], S[sl][o][q], acc[4 * q + o]);
-            acc[4 * q + o] =
-                __builtin_amdgcn_sad_u8(c[2 * row + 1], S[sl][o][q + 1], acc[4 * q + o]);
-          }
+          aq[q] = __builtin_amdgcn_qsad_pk_u16_u8(P[sl][q], c[2 * row], aq[q]);
+          aq[q] = __builtin_amdgcn_qsad_pk_u16_u8(P[sl][q + 1], c[2 * row + 1], aq[q]);
         }
-        acc[4 * NQ] = __builtin_amdgcn_sad_u8(c[2 * row], S[sl][0][NQ], acc[4 * NQ]);
-        acc[4 * NQ] = __builtin_amdgcn_sad_u8(c[2 * row + 1], X[sl], acc[4 * NQ]);
+        a8 = __builtin_amdgcn_sad_u8(c[2 * row], (uint32_t)P[sl][NQ], a8);
+        a8 = __builtin_amdgcn_sad_u8(c[2 * row + 1], (uint32_t)(P[sl][NQ] >> 32), a8);
       }
-      group_sums<NP>(acc, d);
-      uint64_t rb = kKeyNone;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        const uint64_t key = Ts[k][b] + ((uint64_t)acc[k] << 33);  // >= 2^62 past the window
-        rb = key < rb ? key : rb;
+      const uint32_t m = row_min_key<NQ>(aq, a8, d, Ks, b);
+      {
+        const uint64_t K = ((uint64_t)(pm >> kRankBitsR) << 33) + pd + pu;
+        best = K < best ? K : best;
       }
-      // s < 2^23 and se <= 21, (dy + R) and span <= 257: 24-bit products.
-      const uint64_t U = ((uint64_t)__umul24(s, se_len(4 * dy)) << 17) +
-                         (uint64_t)__umul24((uint32_t)(dy + R), (uint32_t)span);
-      rb += U;
-      best = rb < best ? rb : best;
-      if (more) shifts<NQ>(nxt, shb, S[u], X[u]);
+      pm = m;
+      pd = rd[m & ((1u << kRankBitsR) - 1)];
+      pu = ru[dy + R];
+      if (more) align_pairs<NQ>(nxt, shb, P[u]);
     }
   }
-  // Passes and bands of one CU meet in its key (reset to all ones by prep).
-  if (e && (b & ((1 << (2 * sh3)) - 1)) == 0)
+  {
+    const uint64_t K = ((uint64_t)(pm >> kRankBitsR) << 33) + pd + pu;
+    best = K < best ? K : best;
+  }
+  // Passes and bands of one CU meet in its key (reset to all ones by prep),
+  // from the lane that holds the CU's sums: its first lane, lane 63 for d = 0.
+  if (e && (d == 0 ? b == 63 : (b & ((1 << (2 * sh3)) - 1)) == 0))
     atomicMin((unsigned long long*)&jb->keys[(size_t)ctu * kNodes + node],
               (unsigned long long)best);
 }
@@ -241,6 +285,44 @@ __device__ int find_rjob(cjob jobs, const int* rlist, int n_rjobs, int flat) {
   return rlist[lo];
 }
 
+// The refinement key tables of a seeded job (layout with kRtabBytes): one
+// 256-thread block.  Ranks are counts of smaller (c & 0xFFFF, i) keys, read
+// from LDS (the same address in every lane).
+__device__ void build_refine_tables(cjob jb) {
+  constexpr int NQ4 = (kRtabSpan + 3) / 4;
+  __shared__ uint4 key4[NQ4];
+  uint32_t* key = (uint32_t*)key4;
+  const int R = jb->R, n = 2 * R + 1, nq = (n + 3) >> 2;
+  const uint32_t s = (uint32_t)jb->s;
+  uint32_t* rk = (uint32_t*)(jb->rtab + kRtabRk);
+  uint64_t* rd = (uint64_t*)(jb->rtab + kRtabRd);
+  uint64_t* ru = (uint64_t*)(jb->rtab + kRtabRu);
+  for (int i = threadIdx.x; i < 4 * nq; i += blockDim.x) {
+    if (i < n) {
+      const uint32_t c = __umul24(s, se_len(4 * (i - R)));  // s < 2^23, se <= 21
+      key[i] = ((c & 0xFFFFu) << kRankBitsR) | (uint32_t)i;  // < 2^25
+      ru[i] = ((uint64_t)c << 17) + (uint64_t)(i * n);
+    } else {
+      key[i] = 0xFFFFFFFFu;  // padding: never below a key
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t ki = key[i];
+    uint32_t rank = 0;
+#pragma unroll 8
+    for (int q = 0; q < nq; ++q) {
+      const uint4 v = key4[q];
+      rank += (v.x < ki ? 1u : 0u) + (v.y < ki ? 1u : 0u) + (v.z < ki ? 1u : 0u) +
+              (v.w < ki ? 1u : 0u);
+    }
+    const uint32_t c = __umul24(s, se_len(4 * (i - R)));
+    rk[i] = ((c >> 16) << kRankBitsR) + rank;
+    rd[rank] = ((uint64_t)(c & 0xFFFFu) << 17) | (uint64_t)i;
+  }
+  __syncthreads();
+}
+
 // Padded reference of every job that has one (seeded or sub-pel): jobs in y,
 // rows of each job's [h8 + 2 pad_y][pad_pitch] bytes grid-strided in x, and
 // 8-byte pieces of a row over the threads (pad_pitch is a multiple of 8).
@@ -248,11 +330,15 @@ __global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const in
                                                   int n_pjobs) {
   for (int k = blockIdx.y; k < n_pjobs; k += gridDim.y) {
     const cjob jb = (cjob)jobs_ + (plist ? plist[k] : 0);
+    if (blockIdx.x == 0) {  // the first block to start builds the key tables
+      if (jb->seed_mv) build_refine_tables(jb);
+      continue;
+    }
     const int PY = jb->pad_y, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
     const int pitch = jb->pad_pitch, rows = jb->h8 + 2 * PY, pieces = pitch >> 3;
     const uint8_t* ref = jb->ref;
     const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0);
-    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+    for (int row = blockIdx.x - 1; row < rows; row += gridDim.x - 1) {
       const uint8_t* rp = ref + (size_t)clampi(row - PY, 0, h - 1) * stride;
       uint2* dst = (uint2*)(jb->refpad + (size_t)row * pitch);
       for (int c = threadIdx.x; c < pieces; c += blockDim.x) {
@@ -281,15 +367,14 @@ __global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const in
 template <int NQ>
 __device__ __forceinline__ void refine_body(const JobDesc* jobs_, const int* rlist, int n_rjobs,
                                             int n_rctus) {
-  __shared__ uint64_t Ts[4 * NQ + 1][64];
+  __shared__ uint32_t Ks[4 * NQ + 1][64];
   const cjob jobs = (cjob)jobs_;
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
   // eighth of the (CTU, depth) list so that its L2 holds one band of the
   // frames.  (A bijection on [0, gridDim.x) whatever the dispatch order.)
   // Within its eighth an XCD runs the depth-0 items first and the depth-3
   // items last: a 64x64 CU's cross-lane sums make its wavefront the longest,
-  // an 8x8 CU's the shortest, and the last of about three rounds of
-  // wavefronts per slot is only partly full.
+  // an 8x8 CU's the shortest, so the last wavefronts to start are short.
   const int gx = gridDim.x, x = blockIdx.x;
   const int q = gx >> 3, rm = gx & 7, xcd = x & 7, k = x >> 3;
   const int a = xcd * q + min(xcd, rm), len = q + (xcd < rm ? 1 : 0);  // this XCD's range
@@ -301,28 +386,28 @@ __device__ __forceinline__ void refine_body(const JobDesc* jobs_, const int* rli
     if (rest >= 0 && rest < cnt) lin = first + 4 * rest;
     rest -= cnt;
   }
-  const int flat = lin >> 2, d = lin & 3;
+  const int flat = lin >> 2, d = __builtin_amdgcn_readfirstlane(lin & 3);
   if (flat >= n_rctus) return;
   const int j = __builtin_amdgcn_readfirstlane(find_rjob(jobs, rlist, n_rjobs, flat));
-  refine_wave<NQ>(jobs + j, flat - jobs[j].rctu_start, d, blockIdx.y, blockIdx.z, gridDim.z, Ts);
+  refine_wave<NQ>(jobs + j, flat - jobs[j].rctu_start, d, blockIdx.y, blockIdx.z, gridDim.z, Ks);
 }
 
-// 5 columns per pass: four wavefronts per SIMD (register budget 128).
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel_q1(
-    const JobDesc* jobs_, const int* rlist, int n_rjobs, int n_rctus) {
+// 5 columns per pass.
+__global__ __launch_bounds__(64) void refine_kernel_q1(const JobDesc* jobs_, const int* rlist,
+                                                       int n_rjobs, int n_rctus) {
   refine_body<1>(jobs_, rlist, n_rjobs, n_rctus);
 }
 
-// 9 columns per pass: the ring of 8 pre-shifted rows takes 104 registers;
-// three wavefronts per SIMD (register budget 168).
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void refine_kernel_q2(
+// 9 columns per pass: the ring of 8 aligned rows takes 48 registers; four
+// wavefronts per SIMD (register budget 128).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel_q2(
     const JobDesc* jobs_, const int* rlist, int n_rjobs, int n_rctus) {
   refine_body<2>(jobs_, rlist, n_rjobs, n_rctus);
 }
 
 hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int max_rows,
                       hipStream_t st) {
-  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)std::max(1, std::min(max_rows, 65535)),
+  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)std::max(1, std::min(max_rows, 65534)) + 1,
                                       (unsigned)std::min(n_pjobs, 65535)),
                      dim3(256), 0, st, jobs, plist, n_pjobs);
   return hipGetLastError();

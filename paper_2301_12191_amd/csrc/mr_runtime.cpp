@@ -405,6 +405,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     if (seed_of(j)) {
       // Seeded: refinement around reference MVs instead of the full search.
       set_job_seed(jb, seed_of(j));
+      P->scratch_bytes += up256(kRtabBytes);
       jb.rctu_start = P->n_rctus;
       P->rlist.push_back(j);
       P->n_rjobs += 1;
@@ -534,6 +535,11 @@ void bind_scratch(Plan& P, uint8_t* base) {
     if (jb.subpel) {
       jb.subres = (uint32_t*)sp;
       sp += up256((size_t)n_ctus * kNodes * 8);
+    }
+    jb.rtab = nullptr;
+    if (jb.seed_mv) {
+      jb.rtab = sp;
+      sp += up256(kRtabBytes);
     }
     jb.refpad = (jb.seed_mv || jb.subpel) ? sp : nullptr;
   }
