@@ -646,6 +646,13 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   // closed form gives each one directly.
   const int stride = jb->stride;
   const bool angular = ANG && jb->angular != 0;  // uniform
+  // Planar and DC read p[-1][0..n] and p[0..n][-1] of a node at (x0, y0):
+  // with x0, y0 >= 1, x0 + n <= W8 - 1 and y0 + n <= H8 - 1 all of them are
+  // available (a <= n - 1 and b >= 3n + 1 above), which holds for every node
+  // of a CTU with cx, cy >= 1 and cx + 64, cy + 64 inside the coded picture:
+  // then each entry is read straight from its position.
+  const bool interior = !angular && cx >= 1 && cy >= 1 && cx + kCtu <= W8 - 1 &&
+                        cy + kCtu <= H8 - 1;  // uniform
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     // Angular prediction reads every entry: all 4n + 1 then.
@@ -656,22 +663,37 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       const int x0 = sh.nx0[node], y0 = sh.ny0[node], a = sh.na[node], b = sh.nb[node];
       int16_t* R = sh.refs + ref_offset(node);
       int dcs = 0;
-      for (int m = j; m < len; m += tpn) {
-        // 1 .. n + 1, then 2n + 1 .. 3n + 1 (planar, DC), or every entry (angular)
-        const int off = angular ? m : (m <= n ? m + 1 : n + m);
-        int v = 128;
-        if (a <= b) {
-          const int k = clampi(off <= 2 * n ? 2 * n - off : off, a, b);
-          int x, y;
-          if (k <= 2 * n) x = x0 - 1, y = y0 - 1 + (2 * n - k);  // left column / corner
-          else x = x0 + (k - 2 * n - 1), y = y0 - 1;             // top row
+      if (interior) {
+        for (int m = j; m < len; m += tpn) {
+          // m <= n: p[-1][m] (entry m + 1); m > n: p[m - n - 1][-1] (entry n + m)
+          const bool left = m <= n;
+          const int x = left ? x0 - 1 : x0 + m - n - 1, y = left ? y0 + m : y0 - 1;
           const int lx = x - cx, ly = y - cy;
+          int v;
           if ((unsigned)lx < 64u && (unsigned)ly < 64u) v = sh.cur[ly * 64 + lx];
           else v = jb->cur[(uint32_t)(min(y, jb->h - 1) * stride + min(x, jb->w - 1))];
+          R[left ? m + 1 : n + m] = (int16_t)v;
+          // DC: p[-1][0..n-1] (m < n) and p[0..n-1][-1] (n < m <= 2n).
+          if (m != n && m <= 2 * n) dcs += v;
         }
-        R[off] = (int16_t)v;
-        // DC: p[0..n-1][-1] (off 2n+1 .. 3n) and p[-1][0..n-1] (off 1 .. n).
-        if ((off >= 1 && off <= n) || (off > 2 * n && off <= 3 * n)) dcs += v;
+      } else {
+        for (int m = j; m < len; m += tpn) {
+          // 1 .. n + 1, then 2n + 1 .. 3n + 1 (planar, DC), or every entry (angular)
+          const int off = angular ? m : (m <= n ? m + 1 : n + m);
+          int v = 128;
+          if (a <= b) {
+            const int k = clampi(off <= 2 * n ? 2 * n - off : off, a, b);
+            int x, y;
+            if (k <= 2 * n) x = x0 - 1, y = y0 - 1 + (2 * n - k);  // left column / corner
+            else x = x0 + (k - 2 * n - 1), y = y0 - 1;             // top row
+            const int lx = x - cx, ly = y - cy;
+            if ((unsigned)lx < 64u && (unsigned)ly < 64u) v = sh.cur[ly * 64 + lx];
+            else v = jb->cur[(uint32_t)(min(y, jb->h - 1) * stride + min(x, jb->w - 1))];
+          }
+          R[off] = (int16_t)v;
+          // DC: p[0..n-1][-1] (off 2n+1 .. 3n) and p[-1][0..n-1] (off 1 .. n).
+          if ((off >= 1 && off <= n) || (off > 2 * n && off <= 3 * n)) dcs += v;
+        }
       }
       const int g = tpn < 64 ? tpn : 64;  // the node's threads within this wavefront
       dcs = (int)group_sum((uint32_t)dcs, g);
@@ -760,27 +782,26 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
         // every true value lies in [0, 2^15), so the packed 16-bit sums (mod
         // 2^16) and the unsigned shift are exact.
         const int Tn = T[n], Ln1 = L[n + 1];
-        us2 vp0, vp1, dv0, dv1;  // vertical parts of columns (0, 1) and (2, 3), their steps
-        {
-          int vc[4], dv[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int Tx = T[px0 + i];
-            vc[i] = (n - 1 - py0) * Tx + (py0 + 1) * Ln1, dv[i] = Ln1 - Tx;
-          }
-          vp0 = (us2){(unsigned short)vc[0], (unsigned short)vc[1]};
-          vp1 = (us2){(unsigned short)vc[2], (unsigned short)vc[3]};
-          dv0 = (us2){(unsigned short)dv[0], (unsigned short)dv[1]};
-          dv1 = (us2){(unsigned short)dv[2], (unsigned short)dv[3]};
-        }
+        // Vertical parts of columns (0, 1) and (2, 3) at the tile's first row,
+        // (n - 1 - py0) T[px] + (py0 + 1) L[n + 1], and their steps per row,
+        // L[n + 1] - T[px]: packed multiply-adds (every value below 2^15).
+        const us2 t01 = {(unsigned short)T[px0], (unsigned short)T[px0 + 1]};
+        const us2 t23 = {(unsigned short)T[px0 + 2], (unsigned short)T[px0 + 3]};
+        const us2 kv = (us2)(unsigned short)(n - 1 - py0);
+        const us2 cv = (us2)(unsigned short)((py0 + 1) * Ln1), l1 = (us2)(unsigned short)Ln1;
+        us2 vp0 = t01 * kv + cv, vp1 = t23 * kv + cv;
+        const us2 dv0 = l1 - t01, dv1 = l1 - t23;
         const us2 sh_pl = (us2)(unsigned short)(lg + 1);
+        const us2 x01 = {0, 1}, x23 = {2, 3};
+        const int hc = (px0 + 1) * Tn + n;
         sh2 pr[16];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+          // Horizontal part of row j at columns px0 + i: hr + i dh.
           const int Ly = L[py0 + j + 1];
-          const int hr = (n - 1 - px0) * Ly + (px0 + 1) * Tn + n, dh = Tn - Ly;
-          const us2 h0 = {(unsigned short)hr, (unsigned short)(hr + dh)};
-          const us2 h1 = h0 + (us2)(unsigned short)(2 * dh);
+          const int hr = (n - 1 - px0) * Ly + hc, dh = Tn - Ly;
+          const us2 dd = (us2)(unsigned short)dh, hh = (us2)(unsigned short)hr;
+          const us2 h0 = dd * x01 + hh, h1 = dd * x23 + hh;
           const us2 p0 = (h0 + vp0) >> sh_pl, p1 = (h1 + vp1) >> sh_pl;
           const uint32_t q0 = __builtin_bit_cast(uint32_t, cp[2 * j] - p0);
           const uint32_t q1 = __builtin_bit_cast(uint32_t, cp[2 * j + 1] - p1);
