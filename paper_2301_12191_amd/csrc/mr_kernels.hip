@@ -740,17 +740,18 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
           const int mx = sh.mvx[node], my = sh.mvy[node];
           const uint8_t* __restrict__ rp = jb->ref;
           const int xf = cx + tx * 4 + mx;  // first reference column of the tile
-          uint32_t yo[4];  // sample offsets (the library keeps them below 2^31)
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            yo[q] = (uint32_t)(clampi(cy + ty * 4 + q + my, 0, jb->h - 1) * stride);
-          // Rows needing no horizontal clamping: the two dwords around the 4
-          // samples (inside the frame), one v_alignbyte and two byte-to-16-bit
-          // v_perm_b32.
-          if (ref_aligned && xf >= 0 && xf + 3 < jb->w && yo[3] + (uint32_t)xf + 8u <= frame_bytes) {
+          const int yf = cy + ty * 4 + my;  // and row
+          // A tile whose 4 x 4 reference samples lie inside the frame: per
+          // row the two dwords around its 4 samples (the last row's second
+          // dword inside the frame too), one v_alignbyte and two
+          // byte-to-16-bit v_perm_b32; row offsets (below 2^31) one stride
+          // apart.
+          const uint32_t o0 = (uint32_t)yf * (uint32_t)stride + (uint32_t)xf;
+          if (ref_aligned && xf >= 0 && xf + 3 < jb->w && yf >= 0 && yf + 3 < jb->h &&
+              ((o0 + 3u * (uint32_t)stride) & ~3u) + 8u <= frame_bytes) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const uint32_t o = yo[q] + (uint32_t)xf;
+              const uint32_t o = o0 + (uint32_t)(q * stride);
               const uint32_t* a = (const uint32_t*)(rp + (o & ~3u));
               const uint32_t v = __builtin_amdgcn_alignbyte(a[1], a[0], o & 3u);
               const us2 r0 = __builtin_bit_cast(us2, __builtin_amdgcn_perm(0u, v, 0x0c010c00u));
@@ -759,9 +760,12 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
               irp[2 * q + 1] = __builtin_bit_cast(sh2, cp[2 * q + 1] - r1);
             }
           } else {
-            uint32_t xo[4];
+            uint32_t yo[4], xo[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) xo[q] = (uint32_t)clampi(xf + q, 0, jb->w - 1);
+            for (int q = 0; q < 4; ++q) {
+              yo[q] = (uint32_t)(clampi(yf + q, 0, jb->h - 1) * stride);
+              xo[q] = (uint32_t)clampi(xf + q, 0, jb->w - 1);
+            }
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
               const us2 r = {(unsigned short)rp[yo[m >> 1] + xo[2 * (m & 1)]],
