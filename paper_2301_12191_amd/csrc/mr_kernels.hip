@@ -1051,11 +1051,13 @@ __global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_j
 // through the same atomic minima as bands do).  items == null: one job, items
 // implicit.
 //
-// Queues: one per XCD, head counter[q], items [qo.off[q], qo.off[q + 1]).
-// Workgroups are dealt to the 8 XCDs round-robin, so a workgroup starts on
-// queue blockIdx.x mod 8 (its XCD's) and moves on to the next queue once that
-// one is empty; it ends when all are.  Every item is taken exactly once
-// whichever XCD a workgroup runs on.
+// Queues: one per XCD, items [qo.off[q], qo.off[q + 1]).  Workgroups are
+// dealt to the 8 XCDs round-robin, so a workgroup starts on queue
+// blockIdx.x mod 8 (its XCD's): its first item is that queue's item
+// blockIdx.x / 8, and the items past the first G_q of queue q (G_q workgroups
+// start on it) are popped through the head counter[q].  A workgroup moves on
+// to the next queue once its own is empty and ends when all are.  Every item
+// is taken exactly once whichever XCD a workgroup runs on.
 template <int D>
 __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const uint2* items_,
                                                   const QueueOffsets& qo, uint32_t* counter,
@@ -1066,15 +1068,30 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int home = blockIdx.x & (kQueues - 1);
   int empty = 0;  // thread 0: queues found empty, from the home queue on
+  bool first = true;
   for (;;) {
     if (threadIdx.x == 0) {
       int it = -1;
-      while (empty < kQueues) {
+      // The first G_q items of queue q (G_q: the workgroups that start on it)
+      // are taken without an atomic, one per workgroup; the rest through
+      // counter[q].  A queue with no more items than that needs no atomic at
+      // all: device-scope atomics on the counters serialise across the XCDs,
+      // which in a short launch costs more than the search.
+      if (first) {
+        first = false;
+        const int k = blockIdx.x >> 3;
+        if (k < qo.off[home + 1] - qo.off[home]) it = qo.off[home] + k;
+      }
+      while (it < 0 && empty < kQueues) {
         const int q = (home + empty) & (kQueues - 1);
-        const int k = (int)atomicAdd(&counter[q], 1u);
-        if (k < qo.off[q + 1] - qo.off[q]) {
-          it = qo.off[q] + k;
-          break;
+        const int len = qo.off[q + 1] - qo.off[q];
+        const int G = ((int)gridDim.x - q + kQueues - 1) / kQueues;
+        if (len > G) {
+          const int k = G + (int)atomicAdd(&counter[q], 1u);
+          if (k < len) {
+            it = qo.off[q] + k;
+            break;
+          }
         }
         ++empty;
       }
