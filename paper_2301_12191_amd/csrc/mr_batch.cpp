@@ -66,7 +66,7 @@ BatchLayout batch_layout(const Plan& P) {
   L.slist = L.rlist + up256(sizeof(int) * P.rlist.size());
   L.plist = L.slist + up256(sizeof(int) * P.slist.size());
   L.counter = L.plist + up256(sizeof(int) * P.plist.size());
-  L.scratch = L.counter + 256;
+  L.scratch = L.counter + kCounterBytes;
   L.total = L.scratch + P.scratch_bytes;
   return L;
 }

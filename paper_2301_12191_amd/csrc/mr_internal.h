@@ -43,7 +43,11 @@ constexpr size_t kRtabRu = kRtabRd + 8 * kRtabSpan;
 constexpr size_t kRtabBytes = kRtabRu + 8 * kRtabSpan;
 
 // Search work queues, one per XCD: queue q holds items [off[q], off[q + 1]).
+// Their head counters are 256 bytes apart (kCounterStride words), so that
+// atomics on different queues do not meet on one memory line.
 constexpr int kQueues = 8;
+constexpr int kCounterStride = 64;
+constexpr size_t kCounterBytes = (size_t)kQueues * kCounterStride * 4;
 struct QueueOffsets {
   int32_t off[kQueues + 1];
 };

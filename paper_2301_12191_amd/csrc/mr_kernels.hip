@@ -1034,7 +1034,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_j
                                                    uint32_t* counter) {
   const cjob jobs = (cjob)jobs_;
   const int flat = xcd_contiguous_index();
-  if (flat == 0 && threadIdx.x < kQueues) counter[threadIdx.x] = 0;  // search queue heads
+  if (flat == 0 && threadIdx.x < kQueues) counter[threadIdx.x * kCounterStride] = 0;  // queue heads
   if (flat >= n_ctus) return;
   __shared__ uint32_t csad[64];
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
@@ -1086,8 +1086,12 @@ __device__ __forceinline__ void search_persistent(const JobDesc* jobs_, const ui
         const int q = (home + empty) & (kQueues - 1);
         const int len = qo.off[q + 1] - qo.off[q];
         const int G = ((int)gridDim.x - q + kQueues - 1) / kQueues;
-        if (len > G) {
-          const int k = G + (int)atomicAdd(&counter[q], 1u);
+        uint32_t* head = counter + q * kCounterStride;
+        // A head only grows: on the other queues (the end of the launch) a
+        // device-scope read that already shows the queue empty saves the atomic.
+        if (len > G && (empty == 0 || G + (int)__hip_atomic_load(head, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT) < len)) {
+          const int k = G + (int)atomicAdd(head, 1u);
           if (k < len) {
             it = qo.off[q] + k;
             break;

@@ -122,7 +122,7 @@ extern "C" int mr_ctu_search_noalloc(const mr_frame* cur, const mr_frame* ref,
   JobDesc& jb = P.jobs[0];
   const bool full = jb.seed_mv == nullptr;  // the full (or bounded) search needs key tables
   const int steps = full ? (jb.ntasks + kWaveSteps - 1) / kWaveSteps : 0;
-  const size_t head = up256(sizeof(JobDesc)) + 256;  // descriptor, queue counters
+  const size_t head = up256(sizeof(JobDesc)) + kCounterBytes;  // descriptor, queue counters
   const size_t qbytes = up256((size_t)steps * kWaveSteps * 4 * jb.D * 4);
   const size_t dbytes = up256((size_t)steps * 2048 * 8);
   if (head + qbytes + dbytes + P.scratch_bytes > kNoAllocBytes) return MR_ESCRATCH;

@@ -623,7 +623,7 @@ int mr_ctu_search_seeded(const mr_frame* cur, const mr_frame* ref, const mr_sear
   int rc = make_plan(&cur, &ref, &p, &bounds, &o, &seed, 1, false, &P);
   if (rc != MR_OK) return rc;
   // Scratch: job descriptor, queue counter, per-job buffers.
-  const size_t head = up256(sizeof(JobDesc)) + 256;
+  const size_t head = up256(sizeof(JobDesc)) + kCounterBytes;
   uint8_t* scratch = nullptr;
   if (hipMallocAsync((void**)&scratch, head + P.scratch_bytes, st) != hipSuccess) return MR_ENOMEM;
   bind_scratch(P, scratch + head);
