@@ -369,6 +369,12 @@ int mr_ladder_cancel(mr_ladder* l, uint64_t job_id);
  * a job is released, handed out by mr_ladder_poll and needed by no dependent,
  * the server forgets it (its id then gives MR_EINVAL). */
 int mr_ladder_release(mr_ladder* l, uint64_t job_id);
+/* mr_ladder_release of ids[0 .. n - 1] under one lock (a client that handles
+ * a poll's completions together saves a call per job).  Stops at the first id
+ * that fails and returns its status; *n_released = the ids released before it
+ * (n_released may be NULL).  Errors: MR_EINVAL (null ids with n > 0, n < 0),
+ * then those of mr_ladder_release. */
+int mr_ladder_release_many(mr_ladder* l, const uint64_t* ids, int32_t n, int32_t* n_released);
 int mr_ladder_get_stats(mr_ladder* l, mr_ladder_stats* out);
 /* Waits for in-flight work, frees everything the ladder owns (NULL ok). */
 int mr_ladder_close(mr_ladder* l);

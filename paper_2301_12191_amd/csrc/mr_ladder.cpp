@@ -564,6 +564,18 @@ int mr_ladder_release(mr_ladder* l, uint64_t job_id) {
   return l->sched->release(job_id);
 }
 
+int mr_ladder_release_many(mr_ladder* l, const uint64_t* ids, int32_t n, int32_t* n_released) {
+  if (n_released) *n_released = 0;
+  if (!l || n < 0 || (n > 0 && !ids)) return MR_EINVAL;
+  std::lock_guard<std::mutex> lk(l->mu);
+  for (int32_t i = 0; i < n; ++i) {
+    const int rc = l->sched->release(ids[i]);
+    if (rc != MR_OK) return rc;
+    if (n_released) *n_released = i + 1;
+  }
+  return MR_OK;
+}
+
 int mr_ladder_get_stats(mr_ladder* l, mr_ladder_stats* out) {
   if (!l || !out) return MR_EINVAL;
   std::lock_guard<std::mutex> lk(l->mu);

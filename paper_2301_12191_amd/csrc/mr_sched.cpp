@@ -175,6 +175,14 @@ int Scheduler::step() {
     }
     running_.erase(running_.begin() + b);
   }
+  // 2, 3: with chain_on_launch a launch makes its dependents ready at once, so
+  // the next batch of a reference chain goes out in the same step.
+  while (launch_ready(now, done)) {
+  }
+  return done;
+}
+
+int Scheduler::launch_ready(int64_t now, int& done) {
   // 2. Dependents of finished (with chain_on_launch: of launched) references
   //    become ready, or fail with them.
   for (uint64_t id : queue_) {
@@ -209,7 +217,7 @@ int Scheduler::step() {
                queue_.end());
   // 3. Admit ready jobs in arrival order (head of line blocks: no starvation of
   //    large jobs) and launch them as one batch.
-  if ((int)running_.size() >= cfg_.max_batches_in_flight) return done;
+  if ((int)running_.size() >= cfg_.max_batches_in_flight) return 0;
   std::vector<SchedJob*> batch;
   for (uint64_t id : queue_) {
     SchedJob& j = *jobs_[id];
@@ -246,7 +254,7 @@ int Scheduler::step() {
   queue_.erase(std::remove_if(queue_.begin(), queue_.end(),
                               [&](uint64_t id) { return jobs_[id]->state == kFailed; }),
                queue_.end());
-  if (batch.empty()) return done;
+  if (batch.empty()) return 0;
   for (SchedJob* j : batch) j->state = kRunning;
   queue_.erase(std::remove_if(queue_.begin(), queue_.end(),
                               [&](uint64_t id) { return jobs_[id]->state == kRunning; }),
@@ -261,13 +269,13 @@ int Scheduler::step() {
       complete(*j, rc, t);
       ++done;
     }
-    return done;
+    return 0;
   }
   for (SchedJob* j : batch) j->t_start = t;
   if (!st_.first_start_ns) st_.first_start_ns = t;
   ++st_.batches;
   running_.push_back(Batch{handle, batch});
-  return done;
+    return 1;
 }
 
 std::vector<uint64_t> Scheduler::take_completions(int max) {

@@ -125,6 +125,9 @@ class Scheduler {
   void maybe_free(SchedJob& j);
   void complete(SchedJob& j, int status, int64_t t);
   void retire_finished();
+  // Phases 2 and 3 of step(): dependents become ready (or fail), timeouts,
+  // then one batch is admitted and launched.  1 if a batch was launched.
+  int launch_ready(int64_t now, int& done);
   SchedConfig cfg_;
   Executor* ex_;
   uint64_t next_id_ = 1;

@@ -437,12 +437,15 @@ def _ladder_lib():
         L.mr_ladder_poll.argtypes = [vp, ctypes.POINTER(mr_completion), i32, i32,
                                      ctypes.POINTER(i32)]
         L.mr_ladder_release.argtypes = [vp, ctypes.c_uint64]
+        L.mr_ladder_release_many.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32,
+                                             ctypes.POINTER(i32)]
         L.mr_ladder_cancel.argtypes = [vp, ctypes.c_uint64]
         L.mr_ladder_get_stats.argtypes = [vp, ctypes.POINTER(mr_ladder_stats)]
         L.mr_ladder_close.argtypes = [vp]
         for f in ("mr_ladder_open", "mr_ladder_put_frame", "mr_ladder_drop_frames",
                   "mr_ladder_submit", "mr_ladder_submit_many", "mr_ladder_poll",
-                  "mr_ladder_release", "mr_ladder_cancel", "mr_ladder_get_stats",
+                  "mr_ladder_release", "mr_ladder_release_many", "mr_ladder_cancel",
+                  "mr_ladder_get_stats",
                   "mr_ladder_close"):
             getattr(L, f).restype = ctypes.c_int
         L._ladder_bound = True
@@ -569,6 +572,17 @@ class Ladder:
         rc = _ladder_lib().mr_ladder_release(self._h, job_id)
         if rc != MR_OK:
             raise MRError(rc, "mr_ladder_release")
+
+    def release_many(self, job_ids):
+        """Release several completed jobs in one call (stops at the first failure)."""
+        ids = list(job_ids)
+        if not ids:
+            return
+        arr = (ctypes.c_uint64 * len(ids))(*ids)
+        n = ctypes.c_int32(0)
+        rc = _ladder_lib().mr_ladder_release_many(self._h, arr, len(ids), ctypes.byref(n))
+        if rc != MR_OK:
+            raise MRError(rc, f"mr_ladder_release_many (released {n.value} of {len(ids)})")
 
     def stats(self) -> dict:
         s = mr_ladder_stats()

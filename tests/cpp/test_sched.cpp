@@ -289,8 +289,8 @@ static void test_dropped_frames_fail_alone() {
 }
 
 // chain_on_launch: a dependent launches in the batch after its reference's,
-// while that batch still runs; a reference that then fails takes the
-// already-launched dependent with it.
+// in the same step, while that batch still runs; a reference that then fails
+// takes the already-launched dependent with it.
 static void test_chain_on_launch() {
   FakeExec ex;
   ex.fp = {{0, 1}, {1, 1}, {2, 1}};
@@ -303,11 +303,9 @@ static void test_chain_on_launch() {
     CHECK(s.submit(0, 1, 1, &d) == MR_OK);  // implies the rung-0 reference
     const SchedJob* dj = s.job(d);
     const SchedJob* rj = s.job(dj->ref_job);
-    s.step();  // the reference launches
-    CHECK(ex.launched.size() == 1 && ex.launched[0][0] == rj->id && rj->state == kRunning);
-    ex.t += 100000;
-    s.step();  // the dependent launches behind it, in its own batch
-    CHECK(ex.launched.size() == 2 && ex.launched[1].size() == 1 && ex.launched[1][0] == d);
+    s.step();  // the reference launches, and the dependent behind it in its own batch
+    CHECK(ex.launched.size() == 2 && ex.launched[0][0] == rj->id && rj->state == kRunning);
+    CHECK(ex.launched[1].size() == 1 && ex.launched[1][0] == d);
     CHECK(rj->state == kRunning && dj->state == kRunning);
     run_until_idle(s, ex);
     CHECK(rj->state == kDone && dj->state == kDone && dj->status == MR_OK);

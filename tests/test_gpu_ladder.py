@@ -272,7 +272,9 @@ def test_ladder_errors(mr):
         with pytest.raises(mr.MRError) as e:
             lad.cancel(jid)  # completed: nothing to cancel
         assert e.value.code == mr.MR_ESTATE
-        lad.release(jid)
+        with pytest.raises(mr.MRError) as e:
+            lad.release_many([jid, 987654321])  # the first released, the unknown id refused
+        assert e.value.code == mr.MR_EINVAL and "released 1 of 2" in str(e.value)
     finally:
         lad.close()
     with pytest.raises(mr.MRError):

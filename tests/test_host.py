@@ -277,3 +277,13 @@ def test_ladder_submit_many_argument_errors(libmr):
     assert L.mr_ladder_submit_many(None, jobs, 1, ids, ctypes.byref(n)) == mr.MR_EINVAL
     assert n.value == 0  # the count is written even when the call is refused
     assert L.mr_ladder_submit_many(None, jobs, 1, ids, None) == mr.MR_EINVAL
+
+
+def test_ladder_release_many_argument_errors(libmr):
+    from paper_2301_12191_amd import mr
+    L = mr._ladder_lib()
+    n = ctypes.c_int32(7)
+    ids = (ctypes.c_uint64 * 2)(1, 2)
+    assert L.mr_ladder_release_many(None, ids, 2, ctypes.byref(n)) == mr.MR_EINVAL
+    assert n.value == 0  # the count is written even when the call is refused
+    assert L.mr_ladder_release_many(None, ids, 2, None) == mr.MR_EINVAL
