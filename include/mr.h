@@ -326,6 +326,9 @@ typedef struct {
   uint64_t cached_bytes;                  /* retired output blocks kept for reuse */
   double host_launch_ms;                  /* server thread's time in batch launches
                                              (plan, allocation, upload, kernel launches) */
+  int64_t device_allocs;                  /* device allocations made by the server
+                                             (outputs and batch scratch not served from
+                                             its caches) */
 } mr_ladder_stats;
 
 typedef struct mr_ladder mr_ladder;

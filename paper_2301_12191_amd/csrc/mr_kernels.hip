@@ -20,6 +20,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <utility>
+
 #include "mr_device.h"
 
 namespace mr {
@@ -1196,17 +1201,35 @@ static const void* search_fn(int D) {
   }
 }
 
+// Cached per (device, D, strip, LDS bytes): the occupancy query costs tens of
+// microseconds of host time, every batch launch asks.  A kernel's dynamic-LDS
+// limit (above 64 KB) is only ever raised, so a cached answer stays valid.
 int search_occupancy(int D, int strip, size_t lds_bytes) {
   const void* fn = search_fn(D);
   if (!fn) return 0;
-  if (lds_bytes > 64 * 1024 &&
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, size_t>, int> cache;
+  static std::map<std::pair<int, const void*>, size_t> lds_limit;
+  std::lock_guard<std::mutex> lk(mu);
+  if (lds_bytes > 64 * 1024) {
+    size_t& lim = lds_limit[{dev, fn}];
+    if (lds_bytes > lim) {
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
           hipSuccess)
-    return 0;
+        return 0;
+      lim = lds_bytes;
+    }
+  }
+  const auto key = std::make_tuple(dev, D, strip, lds_bytes);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64 * strip, lds_bytes) !=
       hipSuccess)
     return 0;
+  cache[key] = blocks;
   return blocks;
 }
 

@@ -323,6 +323,7 @@ class GpuExecutor : public Executor {
   }
 
   size_t cached_bytes() const { return pool_bytes_ + scratch_free_bytes_; }
+  int64_t device_allocs() const { return allocs_; }
 
  private:
   SchedConfig cfg_;
@@ -330,6 +331,7 @@ class GpuExecutor : public Executor {
   // to the allocator (in the order of `st`, so a retry on `st` may reuse them)
   // and it is tried once more.
   bool alloc(uint8_t** p, size_t bytes, hipStream_t st) {
+    ++allocs_;
     if (hipMallocAsync((void**)p, bytes, st) == hipSuccess) return true;
     (void)hipGetLastError();
     if (pool_.empty() && scratch_free_.empty()) return false;
@@ -367,6 +369,7 @@ class GpuExecutor : public Executor {
   std::multimap<size_t, uint8_t*> scratch_free_;  // scratch of finished batches by size
   size_t scratch_free_bytes_ = 0;
   std::vector<hipEvent_t> events_;                // completed batch events for reuse
+  int64_t allocs_ = 0;                            // calls of alloc()
   int device_ = 0;
   hipStream_t streams_[2] = {nullptr, nullptr};
   unsigned next_ = 0;
@@ -590,6 +593,7 @@ int mr_ladder_get_stats(mr_ladder* l, mr_ladder_stats* out) {
   out->bytes_in_use = s.bytes_in_use, out->peak_bytes = s.peak_bytes;
   out->cancelled = s.cancelled, out->timed_out = s.timed_out;
   out->cached_bytes = l->ex->cached_bytes();
+  out->device_allocs = l->ex->device_allocs();
   out->host_launch_ms = s.host_launch_ns * 1e-6;
   return MR_OK;
 }

@@ -74,13 +74,28 @@ int Scheduler::submit(int stream, int frame, int rung, uint64_t* id) {
   return MR_OK;
 }
 
+// A done job of a later frame of the same stream and rung?
+bool Scheduler::superseded(const SchedJob& j) const {
+  for (auto it = latest_.lower_bound(std::make_tuple(j.stream, j.frame + 1, 0));
+       it != latest_.end() && std::get<0>(it->first) == j.stream; ++it) {
+    if (std::get<2>(it->first) != j.rung) continue;
+    auto jt = jobs_.find(it->second);
+    if (jt != jobs_.end() && jt->second->state == kDone) return true;
+  }
+  return false;
+}
+
 void Scheduler::maybe_free(SchedJob& j) {
   if (!j.exec_state) return;
   if (j.state != kDone && j.state != kFailed) return;
   if (!j.released || j.pending_dependents > 0) return;
   // A done reference job stays resident (its depth map serves later
-  // dependents) until admission needs its memory; see step().
-  if (j.state == kDone && is_reference_rung(cfg_, j.rung)) return;
+  // dependents of its frame) until admission needs its memory (see step()) or
+  // a later frame's job of its stream and rung is done: a dependent submitted
+  // for its frame after that gets a new reference job.  So a stream's
+  // references of past frames do not hold memory, and their blocks serve the
+  // next frames' jobs.
+  if (j.state == kDone && is_reference_rung(cfg_, j.rung) && !superseded(j)) return;
   ex_->free_job(j);
   j.exec_state = nullptr;
   if (j.admitted) st_.bytes_in_use -= j.footprint, j.admitted = false;
@@ -138,6 +153,19 @@ void Scheduler::complete(SchedJob& j, int status, int64_t t) {
       maybe_free(*it->second);
       retire_check_.push_back(j.ref_job);
     }
+  }
+  // A reference of this stream and rung from an earlier frame is superseded.
+  if (status == MR_OK && is_reference_rung(cfg_, j.rung)) {
+    std::vector<SchedJob*> older;
+    for (auto it = latest_.lower_bound(std::make_tuple(j.stream, 0, 0));
+         it != latest_.end() && std::get<0>(it->first) == j.stream &&
+         std::get<1>(it->first) < j.frame;
+         ++it) {
+      if (std::get<2>(it->first) != j.rung) continue;
+      auto jt = jobs_.find(it->second);
+      if (jt != jobs_.end()) older.push_back(jt->second.get());
+    }
+    for (SchedJob* r : older) maybe_free(*r);
   }
 }
 

@@ -122,6 +122,7 @@ class Scheduler {
     std::vector<SchedJob*> jobs;
   };
   SchedJob* find_ref(int stream, int frame, int ref_rung);
+  bool superseded(const SchedJob& j) const;
   void maybe_free(SchedJob& j);
   void complete(SchedJob& j, int status, int64_t t);
   void retire_finished();

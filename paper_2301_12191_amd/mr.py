@@ -420,7 +420,8 @@ class mr_ladder_stats(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("ctus_per_s", ctypes.c_double),
                 ("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
                 ("cancelled", ctypes.c_int64), ("timed_out", ctypes.c_int64),
-                ("cached_bytes", ctypes.c_uint64), ("host_launch_ms", ctypes.c_double)]
+                ("cached_bytes", ctypes.c_uint64), ("host_launch_ms", ctypes.c_double),
+                ("device_allocs", ctypes.c_int64)]
 
 
 def _ladder_lib():

@@ -270,6 +270,35 @@ static void test_finished_jobs_are_forgotten() {
   CHECK(ex.freed > before);
 }
 
+// A released reference of a stream's earlier frame is freed once a later
+// frame's job of its rung is done, without budget pressure; a dependent of
+// that earlier frame submitted afterwards gets a new (implied) reference.
+static void test_superseded_references_freed() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  add_frames(ex, 0, 6, 3);
+  Scheduler s(ladder_cfg(1 << 20), &ex);
+  for (int f = 1; f <= 5; ++f) {
+    uint64_t a = 0;
+    CHECK(s.submit(0, f, 0, &a) == MR_OK);
+    run_until_idle(s, ex);
+    for (uint64_t id : s.take_completions(100)) CHECK(s.release(id) == MR_OK);
+    s.step();
+    // the newest reference stays resident, every earlier one is freed
+    CHECK(ex.freed == f - 1);
+    CHECK(s.jobs_known() == 1);
+  }
+  uint64_t d = 0;
+  CHECK(s.submit(0, 2, 1, &d) == MR_OK);  // frame 2's reference is gone: implied again
+  CHECK(s.stats().implied == 1 && s.job(s.job(d)->ref_job)->implied);
+  run_until_idle(s, ex);
+  CHECK(s.job(d)->state == kDone && s.job(d)->status == MR_OK);
+  // the frame-5 reference is still resident: a frame-5 dependent reuses it
+  uint64_t d5 = 0;
+  CHECK(s.submit(0, 5, 2, &d5) == MR_OK);
+  CHECK(s.stats().implied == 1 && !s.job(s.job(d5)->ref_job)->implied);
+}
+
 static void test_dropped_frames_fail_alone() {
   FakeExec ex;
   ex.fp = {{0, 1}, {1, 1}, {2, 1}};
@@ -460,6 +489,7 @@ int main() {
   test_continuous_batching_and_latency();
   test_finished_jobs_are_forgotten();
   test_dropped_frames_fail_alone();
+  test_superseded_references_freed();
   if (g_fail) {
     std::fprintf(stderr, "%d checks failed\n", g_fail);
     return 1;
