@@ -90,8 +90,10 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
   // 64 blocks x 16 dwords (row r, half c of block bz at dword bz * 16 + 2r + c).
   // Thread t reads dword t & 15 of CTU rows (t >> 4) + 16 i, i = 0..3, so a
   // wavefront reads 4 whole CTU rows: plain dword loads when the frame is
-  // dword-aligned and the CTU lies inside it, else clamped byte loads.
-  {
+  // dword-aligned and the CTU lies inside it, else clamped byte loads.  A job
+  // that shares another job's packed copy only reads, for the corner SADs.
+  const bool pack = jb->pack_cur != 0;  // uniform
+  if (pack || corner) {
     uint32_t* dst = (uint32_t*)jb->curpack + (size_t)ctu * 1024;
     const int c16 = tid & 15, x0 = cx + 4 * c16;
     const bool ref_fast = (((uintptr_t)jb->ref) & 3) == 0;
@@ -113,7 +115,7 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
       const int bx = c16 >> 1, by = ry >> 3;
       const int bz = (bx & 1) | ((by & 1) << 1) | ((bx & 2) << 1) | ((by & 2) << 2) |
                      ((bx & 4) << 2) | ((by & 4) << 3);
-      dst[bz * 16 + (ry & 7) * 2 + (c16 & 1)] = v;
+      if (pack) dst[bz * 16 + (ry & 7) * 2 + (c16 & 1)] = v;
       if (corner) {
         // Reference samples at (x + R, y + R), coordinates clamped to the picture.
         const int R = jb->R, xr = x0 + R;

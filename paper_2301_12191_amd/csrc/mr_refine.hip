@@ -324,8 +324,11 @@ __device__ void build_refine_tables(cjob jb) {
 }
 
 // Padded reference of every job that has one (seeded or sub-pel): jobs in y,
-// rows of each job's [h8 + 2 pad_y][pad_pitch] bytes grid-strided in x, and
-// 8-byte pieces of a row over the threads (pad_pitch is a multiple of 8).
+// rows of each job's [h8 + 2 pad_y][pad_pitch] bytes grid-strided over blocks
+// 1.. in x, and 8-byte pieces of a row over the threads (pad_pitch is a
+// multiple of 8); a job whose reference another job of the batch pads (same
+// frame and margins) shares that copy.  Block 0 builds the seeded jobs' key
+// tables.
 __global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const int* plist,
                                                   int n_pjobs) {
   for (int k = blockIdx.y; k < n_pjobs; k += gridDim.y) {
@@ -334,6 +337,7 @@ __global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const in
       if (jb->seed_mv) build_refine_tables(jb);
       continue;
     }
+    if (!jb->pad_rows) continue;  // another job of the batch pads the same frame
     const int PY = jb->pad_y, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
     const int pitch = jb->pad_pitch, rows = jb->h8 + 2 * PY, pieces = pitch >> 3;
     const uint8_t* ref = jb->ref;

@@ -289,6 +289,12 @@ size_t device_lds_max() {
   return cached[dev];
 }
 
+// Two frame descriptors of the same picture memory and geometry.
+static bool same_frame(const mr_frame* a, const mr_frame* b) {
+  return a->luma == b->luma && a->width == b->width && a->height == b->height &&
+         a->stride == b->stride;
+}
+
 int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
               const mr_search_params* const* p, const uint8_t* const* bounds,
               const mr_search_out* const* out, const mr_mv_seed* const* seeds, int n_jobs,
@@ -334,6 +340,8 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
   P->n_jobs = n_jobs;
   P->jobs.assign(n_jobs, JobDesc{});
   P->job_off.assign(n_jobs, 0);
+  P->cur_owner.assign(n_jobs, -1);
+  P->pad_owner.assign(n_jobs, -1);
   P->items.clear();
   P->rlist.clear();
   P->slist.clear();
@@ -380,8 +388,18 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     jb.ctu_dist = out[j]->ctu_dist;
     jb.ctu_bits = out[j]->ctu_bits;
     P->job_off[j] = P->scratch_bytes;
-    P->scratch_bytes += up256((size_t)n_ctus * 4096) + up256((size_t)n_ctus * kNodes * 8) +
-                        up256((size_t)n_ctus * kNodes) + up256((size_t)n_ctus * 16);
+    // Jobs that read the same current frame (e.g. one pair at several QPs)
+    // share one packed copy of its CTUs.
+    P->cur_owner[j] = -1;
+    for (int i = 0; i < j; ++i)
+      if (P->cur_owner[i] < 0 && same_frame(cur[i], cur[j])) {
+        P->cur_owner[j] = i;
+        break;
+      }
+    jb.pack_cur = P->cur_owner[j] < 0 ? 1 : 0;
+    P->scratch_bytes += (jb.pack_cur ? up256((size_t)n_ctus * 4096) : 0) +
+                        up256((size_t)n_ctus * kNodes * 8) + up256((size_t)n_ctus * kNodes) +
+                        up256((size_t)n_ctus * 16);
     P->n_ctus += n_ctus;
     jb.subpel = p[j]->subpel;
     jb.angular = p[j]->angular;
@@ -393,12 +411,21 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
       P->n_sjobs += 1;
       P->n_sctus += n_ctus;
     }
+    P->pad_owner[j] = -1;
     if (seed_of(j) || jb.subpel) {
       jb.pad_x = refine_pad_x(R);
       jb.pad_y = refine_pad_y(R);
       jb.pad_pitch = jb.w8 + 2 * jb.pad_x;
+      // The same reference frame with the same margins (same R): one copy.
+      for (int i = 0; i < j; ++i)
+        if (P->pad_owner[i] < 0 && P->jobs[i].pad_pitch != 0 && same_frame(ref[i], ref[j]) &&
+            P->jobs[i].pad_x == jb.pad_x && P->jobs[i].pad_y == jb.pad_y) {
+          P->pad_owner[j] = i;
+          break;
+        }
+      jb.pad_rows = P->pad_owner[j] < 0 ? 1 : 0;
       const int64_t pad_bytes = (int64_t)(jb.h8 + 2 * jb.pad_y) * jb.pad_pitch;
-      P->scratch_bytes += up256((size_t)pad_bytes);
+      if (jb.pad_rows) P->scratch_bytes += up256((size_t)pad_bytes);
       P->max_pad_rows = std::max(P->max_pad_rows, jb.h8 + 2 * jb.pad_y);
       P->plist.push_back(j);
     }
@@ -523,8 +550,12 @@ void bind_scratch(Plan& P, uint8_t* base) {
     JobDesc& jb = P.jobs[j];
     const int n_ctus = jb.ctus_w * jb.ctus_h;
     uint8_t* sp = base + P.job_off[j];
-    jb.curpack = (const uint32_t*)sp;
-    sp += up256((size_t)n_ctus * 4096);
+    if (P.cur_owner[j] < 0) {
+      jb.curpack = (const uint32_t*)sp;
+      sp += up256((size_t)n_ctus * 4096);
+    } else {
+      jb.curpack = P.jobs[P.cur_owner[j]].curpack;  // owners come first
+    }
     jb.keys = (uint64_t*)sp;
     sp += up256((size_t)n_ctus * kNodes * 8);
     jb.elig = sp;
@@ -541,7 +572,9 @@ void bind_scratch(Plan& P, uint8_t* base) {
       jb.rtab = sp;
       sp += up256(kRtabBytes);
     }
-    jb.refpad = (jb.seed_mv || jb.subpel) ? sp : nullptr;
+    jb.refpad = nullptr;
+    if (jb.seed_mv || jb.subpel)
+      jb.refpad = P.pad_owner[j] < 0 ? sp : P.jobs[P.pad_owner[j]].refpad;
   }
 }
 

@@ -59,6 +59,10 @@ struct Plan {
   std::vector<JobDesc> jobs;
   std::vector<uint2> items;           // empty when implicit (single job)
   std::vector<size_t> job_off;        // per-job scratch offset
+  // Per job, the earlier job of the batch whose packed current CTUs (cur_owner)
+  // or padded reference (pad_owner) it shares: same frame, size and stride (and
+  // margins), or -1 for its own copy.
+  std::vector<int> cur_owner, pad_owner;
   size_t scratch_bytes = 0;           // per-job scratch total (curpack, keys, elig, refpad)
   // Seeded jobs (refinement) in rctu_start order, sub-pel jobs in sctu_start
   // order, jobs with a padded reference (seeded or sub-pel).

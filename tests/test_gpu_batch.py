@@ -69,6 +69,40 @@ def test_batch_mixed_jobs_equal_single_calls(mr):
         _same(_np(o), exp, "oracle")
 
 
+def test_jobs_sharing_frames_equal_single_calls(mr):
+    """One frame pair at several QPs and search forms in one batch: the jobs share the packed
+    current CTUs, and those with equal margins the padded reference; each equals its own
+    launch."""
+    import torch
+    sc = synth.Scene(11, 360, 200, 6, 14, 2)
+    cur = torch.from_numpy(sc.render(1)).cuda()
+    ref = torch.from_numpy(sc.render(0)).cuda()
+    other = torch.from_numpy(sc.render(2)).cuda()
+    half = synth.Scene(12, 180, 100, 6, 14, 2)
+    seed_mv = mr.mr_ctu_search(torch.from_numpy(half.render(1)).cuda(),
+                               torch.from_numpy(half.render(0)).cuda(), 30, 8)["mv"]
+    seed = dict(ref_mv=seed_mv, ref_w=180, ref_h=100, r=2)
+    b = torch.randint(0, 2, (25, 45, 2), dtype=torch.uint8)
+    b[..., 1] += b[..., 0] + 1
+    jobs = [dict(cur=cur, ref=ref, qp=37, search_range=16),
+            dict(cur=cur, ref=ref, qp=22, search_range=16),               # shares the packed CTUs
+            dict(cur=cur, ref=ref, qp=30, search_range=16, bounds=b.cuda()),
+            dict(cur=cur, ref=ref, qp=27, search_range=16, seed=seed),    # pads the reference
+            dict(cur=cur, ref=ref, qp=34, search_range=16, seed=seed),    # shares that copy
+            dict(cur=cur, ref=ref, qp=32, search_range=16, subpel=True),  # and so does this one
+            dict(cur=cur, ref=ref, qp=32, search_range=24, seed=seed),    # other margins: own copy
+            dict(cur=cur, ref=other, qp=27, search_range=16, seed=seed),  # other reference
+            dict(cur=other, ref=cur, qp=30, search_range=16)]             # other current frame
+    outs = mr.mr_ctu_search_batch(jobs)
+    torch.cuda.synchronize()
+    for k, (j, o) in enumerate(zip(jobs, outs)):
+        single = mr.mr_ctu_search(j["cur"], j["ref"], j["qp"], j["search_range"],
+                                  bounds=j.get("bounds"), seed=j.get("seed"),
+                                  subpel=j.get("subpel", False))
+        torch.cuda.synchronize()
+        _same(_np(o), _np(single), f"job {k}")
+
+
 def test_ladder_batch_equals_per_rung_launches(mr):
     """Six rungs x 2 frame pairs in one persistent launch == separate launches per pair."""
     import torch
