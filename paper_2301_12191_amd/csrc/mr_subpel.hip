@@ -14,9 +14,12 @@
 // 4x4 tile at Z-order position t, so the tiles of one CU are consecutive
 // lanes (4, 16, 64 or 256 of them).  For each CU depth a thread loads a 12x12
 // patch of the padded reference around its tile at the CU's integer MV, which
-// covers both stages (|qx - 4 mx| <= 3).  A stage shares the horizontal pass
-// among the 3 candidates of each column and does the vertical pass with
-// packed 16-bit dot products.
+// covers both stages (|qx - 4 mx| <= 3), into its own column of an LDS array
+// (read back row by row in every horizontal pass).  A stage shares the
+// horizontal pass among the 3 candidates of each column and does the vertical
+// pass with packed 16-bit dot products; its columns are a loop, not unrolled.
+// Patch in LDS and one column's sums live at a time keep the kernel at 168
+// registers: three wavefronts per SIMD instead of two.
 #include <hip/hip_runtime.h>
 
 #include "mr_device.h"
@@ -74,6 +77,7 @@ __device__ __forceinline__ uint32_t tile_group_sum(uint32_t v, int d, uint32_t* 
 
 __device__ void subpel_ctu(cjob jb, int ctu) {
   __shared__ uint32_t red[4][9];
+  __shared__ uint32_t Ps[12][3][256];  // patch dwords: [row][dword][thread], conflict-free
   const int t = threadIdx.x, wave = t >> 6;
   const int tx = (t & 1) | ((t >> 1) & 2) | ((t >> 2) & 4) | ((t >> 3) & 8);
   const int ty = ((t >> 1) & 1) | ((t >> 2) & 2) | ((t >> 3) & 4) | ((t >> 4) & 8);
@@ -112,8 +116,8 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
       my = idx / span - R;
       mx = idx - (my + R) * span - R;
     }
-    // 12x12 patch at (X + mx - 4, Y + my - 4), as signed bytes (sample - 128).
-    uint32_t P[12][3];
+    // 12x12 patch at (X + mx - 4, Y + my - 4), as signed bytes (sample - 128),
+    // into this thread's column of Ps (no other thread reads it).
     {
       const int col = X + mx - 4 + jb->pad_x;
       const int sb = col & 3;
@@ -122,9 +126,9 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
       for (int r = 0; r < 12; ++r) {
         const uint32_t* rp = (const uint32_t*)(base + (size_t)r * pitch);
         const uint32_t d0 = rp[0], d1 = rp[1], d2 = rp[2], d3 = rp[3];
-        P[r][0] = __builtin_amdgcn_alignbyte(d1, d0, sb) ^ 0x80808080u;
-        P[r][1] = __builtin_amdgcn_alignbyte(d2, d1, sb) ^ 0x80808080u;
-        P[r][2] = __builtin_amdgcn_alignbyte(d3, d2, sb) ^ 0x80808080u;
+        Ps[r][0][t] = __builtin_amdgcn_alignbyte(d1, d0, sb) ^ 0x80808080u;
+        Ps[r][1][t] = __builtin_amdgcn_alignbyte(d2, d1, sb) ^ 0x80808080u;
+        Ps[r][2][t] = __builtin_amdgcn_alignbyte(d3, d2, sb) ^ 0x80808080u;
       }
     }
     int cqx = 4 * mx, cqy = 4 * my;
@@ -132,7 +136,7 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
 #pragma unroll 1
     for (int step = 2; step >= 1; --step) {
       uint32_t sat[9];
-#pragma unroll
+#pragma unroll 1
       for (int ix = 0; ix < 3; ++ix) {
         const int qx = cqx + step * (ix - 1);
         const int fx = qx & 3, f = ((qx - fx) >> 2) - mx;  // f in {-1, 0}
@@ -153,9 +157,10 @@ __device__ void subpel_ctu(cjob jb, int ctu) {
 #pragma unroll
         for (int r = 0; r < 12; ++r) {
           // Patch row r from byte o on: a0 = bytes 0..3, a1 = 4..7, a2 = 8..10 (+1 unused).
-          const uint32_t a0 = __builtin_amdgcn_alignbyte(P[r][1], P[r][0], o);
-          const uint32_t a1 = __builtin_amdgcn_alignbyte(P[r][2], P[r][1], o);
-          const uint32_t a2 = __builtin_amdgcn_alignbyte(P[r][2], P[r][2], o);
+          const uint32_t p0 = Ps[r][0][t], p1 = Ps[r][1][t], p2 = Ps[r][2][t];
+          const uint32_t a0 = __builtin_amdgcn_alignbyte(p1, p0, o);
+          const uint32_t a1 = __builtin_amdgcn_alignbyte(p2, p1, o);
+          const uint32_t a2 = __builtin_amdgcn_alignbyte(p2, p2, o);
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const uint32_t lo = k == 0 ? a0 : __builtin_amdgcn_alignbyte(a1, a0, k);
@@ -290,8 +295,8 @@ __device__ int find_sjob(cjob jobs, const int* slist, int n_sjobs, int flat) {
   return slist[lo];
 }
 
-__global__ __launch_bounds__(256) void subpel_kernel(const JobDesc* jobs_, const int* slist,
-                                                     int n_sjobs, int n_sctus) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void subpel_kernel(
+    const JobDesc* jobs_, const int* slist, int n_sjobs, int n_sctus) {
   const cjob jobs = (cjob)jobs_;
   const int flat = xcd_contiguous_index();
   if (flat >= n_sctus) return;
