@@ -439,15 +439,17 @@ typedef struct {
 int mr_autotune(const mr_search_job* jobs, int32_t n_jobs, int32_t reps, mr_tune_result* out);
 
 /* Stage timing, a profiling aid for benchmarks.  While enabled, every
- * mr_ctu_search call records HIP events on its stream around its three
- * kernels: 0 prep (pack current CTUs, reset keys), 1 search (motion search
- * and arg-min), 2 leaf (SATD, intra, quad-tree decision).  mr_profile_read
- * waits for the recorded events, adds their elapsed times (milliseconds) and
- * counts per stage into *out and, if reset != 0, forgets them.
+ * mr_ctu_search call records HIP events on its stream around its four
+ * stages: 0 prep (pack current CTUs, reset keys), 1 search (padded
+ * reference, motion search or refinement, arg-min), 2 subpel (quarter-pel
+ * refinement; about 0 ms when no job of the call has it), 3 leaf (SATD,
+ * intra, quad-tree decision).  mr_profile_read waits for the recorded events,
+ * adds their elapsed times (milliseconds) and counts per stage into *out and,
+ * if reset != 0, forgets them.
  * Errors: MR_EINVAL (out NULL), MR_EHIP. */
 typedef struct {
-  double ms[3];
-  int64_t launches[3];
+  double ms[4];
+  int64_t launches[4];
 } mr_profile;
 
 int mr_profile_enable(int on);

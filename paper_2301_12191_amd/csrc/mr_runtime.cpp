@@ -588,11 +588,12 @@ hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, con
     e = launch_search(jobs_d, items_d, P.qoff, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
   if (e == hipSuccess && P.n_rjobs > 0)
     e = launch_refine(jobs_d, L.rlist, P.n_rjobs, P.n_rctus, P.max_r, st);
+  if (ev) profile_mark(ev, 2, st);
   if (e == hipSuccess && P.n_sjobs > 0)
     e = launch_subpel(jobs_d, L.slist, P.n_sjobs, P.n_sctus, st);
-  if (ev) profile_mark(ev, 2, st);
-  if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, P.any_angular, st);
   if (ev) profile_mark(ev, 3, st);
+  if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, P.any_angular, st);
+  if (ev) profile_mark(ev, 4, st);
   return e;
 }
 
@@ -602,8 +603,8 @@ struct ProfileState {
   std::mutex mu;
   bool on = false;
   std::vector<StageEvents> pending;
-  double ms[3] = {0, 0, 0};
-  int64_t n[3] = {0, 0, 0};
+  double ms[4] = {0, 0, 0, 0};
+  int64_t n[4] = {0, 0, 0, 0};
 };
 ProfileState g_prof;
 }  // namespace
@@ -715,8 +716,8 @@ int mr_profile_read(mr_profile* out, int reset) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   int rc = MR_OK;
   for (auto& ev : g_prof.pending) {
-    if (hipEventSynchronize(ev.e[3]) != hipSuccess) rc = MR_EHIP;
-    for (int k = 0; k < 3; ++k) {
+    if (hipEventSynchronize(ev.e[4]) != hipSuccess) rc = MR_EHIP;
+    for (int k = 0; k < 4; ++k) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev.e[k], ev.e[k + 1]) != hipSuccess) rc = MR_EHIP;
       g_prof.ms[k] += ms;
@@ -725,7 +726,7 @@ int mr_profile_read(mr_profile* out, int reset) {
     for (auto& x : ev.e) (void)hipEventDestroy(x);
   }
   g_prof.pending.clear();
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     out->ms[k] = g_prof.ms[k];
     out->launches[k] = g_prof.n[k];
     if (reset) g_prof.ms[k] = 0, g_prof.n[k] = 0;

@@ -133,7 +133,7 @@ int search_occupancy(int D, int strip, size_t lds_bytes);
 // Stage profiling (mr_profile_*).
 bool profile_on();
 struct StageEvents {
-  hipEvent_t e[4];
+  hipEvent_t e[5];  // start, after prep, after search, after sub-pel, after leaf
 };
 int profile_begin(StageEvents* ev, hipStream_t st);
 void profile_mark(StageEvents* ev, int k, hipStream_t st);

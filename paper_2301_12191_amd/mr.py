@@ -65,7 +65,7 @@ class mr_tune_result(ctypes.Structure):
 
 
 class mr_profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 3), ("launches", ctypes.c_int64 * 3)]
+    _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
 
 
 def lib():
@@ -330,7 +330,7 @@ def mr_depth_bounds(ref_depth: torch.Tensor, ref_w: int, ref_h: int, dep_w: int,
     return out
 
 
-STAGES = ("prep", "search", "leaf")
+STAGES = ("prep", "search", "subpel", "leaf")
 
 
 def mr_profile_enable(on: bool) -> None:

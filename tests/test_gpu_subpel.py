@@ -241,3 +241,30 @@ def test_subpel_ladder_reference_rung(mr):
         for r, o in enumerate((o0, o1, o2)):
             for k in FIELDS:
                 assert np.array_equal(got[(f, r)][k], o[k].cpu().numpy()), ((f, r), k)
+
+
+def test_stage_profile_times_subpel_on_its_own(mr):
+    """The stage events put the quarter-pel refinement in a stage of its own: it takes time in
+    a call with sub-pel and next to none in one without; every stage counts every call."""
+    import torch
+    sc = synth.Scene(21, 640, 360, 6, 14, 2)
+    cur, ref = _dev(sc.render(1)), _dev(sc.render(0))
+    mr.mr_ctu_search(cur, ref, 30, 16, subpel=True)  # warm-up (plans, tables)
+    torch.cuda.synchronize()
+    mr.mr_profile_read(reset=True)
+    mr.mr_profile_enable(True)
+    try:
+        for _ in range(3):
+            mr.mr_ctu_search(cur, ref, 30, 16, subpel=True)
+        torch.cuda.synchronize()
+        with_sp = mr.mr_profile_read(reset=True)
+        for _ in range(3):
+            mr.mr_ctu_search(cur, ref, 30, 16)
+        torch.cuda.synchronize()
+        without = mr.mr_profile_read(reset=True)
+    finally:
+        mr.mr_profile_enable(False)
+    assert set(with_sp) == {"prep", "search", "subpel", "leaf"}
+    assert all(n == 3 for _, n in with_sp.values()) and all(n == 3 for _, n in without.values())
+    assert with_sp["subpel"][0] > 0.01 * 3  # a 640x360 refinement takes well over 10 us
+    assert without["subpel"][0] < with_sp["subpel"][0] / 5
