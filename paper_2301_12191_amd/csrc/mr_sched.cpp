@@ -74,9 +74,9 @@ int Scheduler::submit(int stream, int frame, int rung, uint64_t* id) {
   return MR_OK;
 }
 
-// A done job of a later frame of the same stream and rung?
+// A done job of the same stream and rung kKeepFrames or more frames later?
 bool Scheduler::superseded(const SchedJob& j) const {
-  for (auto it = latest_.lower_bound(std::make_tuple(j.stream, j.frame + 1, 0));
+  for (auto it = latest_.lower_bound(std::make_tuple(j.stream, j.frame + kKeepFrames, 0));
        it != latest_.end() && std::get<0>(it->first) == j.stream; ++it) {
     if (std::get<2>(it->first) != j.rung) continue;
     auto jt = jobs_.find(it->second);
@@ -91,10 +91,11 @@ void Scheduler::maybe_free(SchedJob& j) {
   if (!j.released || j.pending_dependents > 0) return;
   // A done reference job stays resident (its depth map serves later
   // dependents of its frame) until admission needs its memory (see step()) or
-  // a later frame's job of its stream and rung is done: a dependent submitted
-  // for its frame after that gets a new reference job.  So a stream's
-  // references of past frames do not hold memory, and their blocks serve the
-  // next frames' jobs.
+  // a job of its stream and rung kKeepFrames frames later is done: a
+  // dependent submitted for its frame after that gets a new reference job.  So
+  // a stream that moves forward keeps the references of its last frames only,
+  // and the older ones' blocks serve the next frames' jobs; clients that
+  // revisit the last frames still find theirs.
   if (j.state == kDone && is_reference_rung(cfg_, j.rung) && !superseded(j)) return;
   ex_->free_job(j);
   j.exec_state = nullptr;
@@ -154,12 +155,13 @@ void Scheduler::complete(SchedJob& j, int status, int64_t t) {
       retire_check_.push_back(j.ref_job);
     }
   }
-  // A reference of this stream and rung from an earlier frame is superseded.
+  // References of this stream and rung kKeepFrames or more frames earlier are
+  // superseded.
   if (status == MR_OK && is_reference_rung(cfg_, j.rung)) {
     std::vector<SchedJob*> older;
     for (auto it = latest_.lower_bound(std::make_tuple(j.stream, 0, 0));
          it != latest_.end() && std::get<0>(it->first) == j.stream &&
-         std::get<1>(it->first) < j.frame;
+         std::get<1>(it->first) <= j.frame - kKeepFrames;
          ++it) {
       if (std::get<2>(it->first) != j.rung) continue;
       auto jt = jobs_.find(it->second);

@@ -16,6 +16,11 @@ namespace mr {
 
 enum JobState { kQueued = 0, kReady = 1, kRunning = 2, kDone = 3, kFailed = 4 };
 
+// A done reference job is kept for later dependents of its frame until a job
+// of its stream and rung this many frames later is done (or admission needs
+// its memory).
+constexpr int kKeepFrames = 2;
+
 struct RungCfg {
   int width, height, qp, search_range, ref_rung;  // ref_rung -1: a root (no dependency)
   int dlo = 0, dhi = 1;  // depth-bound policy of this rung as a dependent

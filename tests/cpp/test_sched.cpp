@@ -270,9 +270,10 @@ static void test_finished_jobs_are_forgotten() {
   CHECK(ex.freed > before);
 }
 
-// A released reference of a stream's earlier frame is freed once a later
-// frame's job of its rung is done, without budget pressure; a dependent of
-// that earlier frame submitted afterwards gets a new (implied) reference.
+// A released reference of a stream's frame is freed once a job of its rung
+// kKeepFrames frames later is done, without budget pressure; a dependent of
+// that frame submitted afterwards gets a new (implied) reference, one of the
+// last kKeepFrames frames still finds its reference.
 static void test_superseded_references_freed() {
   FakeExec ex;
   ex.fp = {{0, 1}, {1, 1}, {2, 1}};
@@ -284,19 +285,21 @@ static void test_superseded_references_freed() {
     run_until_idle(s, ex);
     for (uint64_t id : s.take_completions(100)) CHECK(s.release(id) == MR_OK);
     s.step();
-    // the newest reference stays resident, every earlier one is freed
-    CHECK(ex.freed == f - 1);
-    CHECK(s.jobs_known() == 1);
+    // the references of the last kKeepFrames frames stay resident, earlier ones are freed
+    CHECK(ex.freed == std::max(0, f - kKeepFrames));
+    CHECK((int)s.jobs_known() == std::min(f, kKeepFrames));
   }
   uint64_t d = 0;
   CHECK(s.submit(0, 2, 1, &d) == MR_OK);  // frame 2's reference is gone: implied again
   CHECK(s.stats().implied == 1 && s.job(s.job(d)->ref_job)->implied);
   run_until_idle(s, ex);
   CHECK(s.job(d)->state == kDone && s.job(d)->status == MR_OK);
-  // the frame-5 reference is still resident: a frame-5 dependent reuses it
-  uint64_t d5 = 0;
+  // the frame-4 and frame-5 references are still resident: their dependents reuse them
+  uint64_t d4 = 0, d5 = 0;
+  CHECK(s.submit(0, 4, 2, &d4) == MR_OK);
   CHECK(s.submit(0, 5, 2, &d5) == MR_OK);
-  CHECK(s.stats().implied == 1 && !s.job(s.job(d5)->ref_job)->implied);
+  CHECK(s.stats().implied == 1 && !s.job(s.job(d4)->ref_job)->implied &&
+        !s.job(s.job(d5)->ref_job)->implied);
 }
 
 static void test_dropped_frames_fail_alone() {
