@@ -65,7 +65,8 @@ BatchLayout batch_layout(const Plan& P) {
   L.rlist = L.items + up256(sizeof(uint2) * P.items.size());
   L.slist = L.rlist + up256(sizeof(int) * P.rlist.size());
   L.plist = L.slist + up256(sizeof(int) * P.slist.size());
-  L.counter = L.plist + up256(sizeof(int) * P.plist.size());
+  L.llist = L.plist + up256(sizeof(int) * P.plist.size());
+  L.counter = L.llist + up256(sizeof(int) * P.llist.size());
   L.scratch = L.counter + kCounterBytes;
   L.total = L.scratch + P.scratch_bytes;
   return L;
@@ -73,7 +74,7 @@ BatchLayout batch_layout(const Plan& P) {
 
 PlanLists batch_lists(uint8_t* mem, const BatchLayout& L) {
   return PlanLists{(const int*)(mem + L.rlist), (const int*)(mem + L.slist),
-                   (const int*)(mem + L.plist)};
+                   (const int*)(mem + L.plist), (const int*)(mem + L.llist)};
 }
 
 // Upload the job array, items and job lists of a bound plan: one copy of a
@@ -85,8 +86,8 @@ hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipSt
   std::memcpy(img.data() + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs);
   if (!P.items.empty())
     std::memcpy(img.data() + L.items, P.items.data(), sizeof(uint2) * P.items.size());
-  const std::pair<const std::vector<int>*, size_t> lists[3] = {
-      {&P.rlist, L.rlist}, {&P.slist, L.slist}, {&P.plist, L.plist}};
+  const std::pair<const std::vector<int>*, size_t> lists[4] = {
+      {&P.rlist, L.rlist}, {&P.slist, L.slist}, {&P.plist, L.plist}, {&P.llist, L.llist}};
   for (const auto& pl : lists)
     if (!pl.first->empty())
       std::memcpy(img.data() + pl.second, pl.first->data(), sizeof(int) * pl.first->size());

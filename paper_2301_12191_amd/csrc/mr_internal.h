@@ -123,6 +123,16 @@ struct JobDesc {
   int32_t rctu_start;      // first CTU of this job among the seeded jobs' CTUs
   uint8_t* rtab;           // refinement key tables (kRtabBytes), seeded jobs only
   int32_t angular;         // 1: the leaf also scores the 33 angular intra modes
+  // Intra SATDs shared by jobs of a batch with the same current frame (none of
+  // them angular): the first such job's leaf writes, per node of every CTU,
+  // {planar SATD, DC SATD} of every node inside the picture to `intra`
+  // ([ctus][85][2]; null when no other job shares them); the others' leaf
+  // (a later launch) reads them from `intra_src` and computes the inter SATDs
+  // only.
+  uint32_t* intra;
+  const uint32_t* intra_src;
+  int32_t lctu_start;      // with shared intra SATDs: first CTU of this job among the
+                           // CTUs of its leaf launch (jobs taking them, or the others)
   // Sub-pel refinement: per node {quarter-pel MV (qx | qy << 16), SATD}.
   int32_t subpel;
   int32_t sctu_start;      // first CTU of this job among the sub-pel jobs' CTUs

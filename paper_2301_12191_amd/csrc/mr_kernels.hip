@@ -567,9 +567,52 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t v, int width) {
   return v;
 }
 
+// Inter residual of a 4x4 tile whose reference samples start at (xf, yf):
+// cp minus those samples, as pairs of a row's samples (16-bit halves).
+__device__ __forceinline__ void inter_rows(cjob jb, int xf, int yf, const us2 (&cp)[8],
+                                           bool ref_aligned, uint32_t frame_bytes,
+                                           sh2 (&irp)[8]) {
+  const uint8_t* __restrict__ rp = jb->ref;
+  const int stride = jb->stride;
+  // A tile whose 4 x 4 reference samples lie inside the frame: per row the two
+  // dwords around its 4 samples (the last row's second dword inside the frame
+  // too), one v_alignbyte and two byte-to-16-bit v_perm_b32; row offsets
+  // (below 2^31) one stride apart.
+  const uint32_t o0 = (uint32_t)yf * (uint32_t)stride + (uint32_t)xf;
+  if (ref_aligned && xf >= 0 && xf + 3 < jb->w && yf >= 0 && yf + 3 < jb->h &&
+      ((o0 + 3u * (uint32_t)stride) & ~3u) + 8u <= frame_bytes) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t o = o0 + (uint32_t)(q * stride);
+      const uint32_t* a = (const uint32_t*)(rp + (o & ~3u));
+      const uint32_t v = __builtin_amdgcn_alignbyte(a[1], a[0], o & 3u);
+      const us2 r0 = __builtin_bit_cast(us2, __builtin_amdgcn_perm(0u, v, 0x0c010c00u));
+      const us2 r1 = __builtin_bit_cast(us2, __builtin_amdgcn_perm(0u, v, 0x0c030c02u));
+      irp[2 * q] = __builtin_bit_cast(sh2, cp[2 * q] - r0);
+      irp[2 * q + 1] = __builtin_bit_cast(sh2, cp[2 * q + 1] - r1);
+    }
+  } else {
+    uint32_t yo[4], xo[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      yo[q] = (uint32_t)(clampi(yf + q, 0, jb->h - 1) * stride);
+      xo[q] = (uint32_t)clampi(xf + q, 0, jb->w - 1);
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const us2 r = {(unsigned short)rp[yo[m >> 1] + xo[2 * (m & 1)]],
+                     (unsigned short)rp[yo[m >> 1] + xo[2 * (m & 1) + 1]]};
+      irp[m] = __builtin_bit_cast(sh2, cp[m] - r);
+    }
+  }
+}
+
 // ANG: the angular-mode instantiation (a separate kernel, so that the default
 // one keeps its register budget); a job's own flag still decides.
-template <bool ANG>
+// SHARED: a job that takes its planar and DC SATDs from another job of the
+// batch with the same current frame (intra_src): no neighbours, and its inter
+// SATDs two depths at a time ((3, 2) and (1, 0)) in one packed transform.
+template <bool ANG, bool SHARED>
 __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
@@ -653,6 +696,9 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   // closed form gives each one directly.
   const int stride = jb->stride;
   const bool angular = ANG && jb->angular != 0;  // uniform
+  // A job whose intra SATDs serve other jobs computes them for every node
+  // inside the picture, eligible here or not.
+  const bool own = !SHARED && jb->intra != nullptr;  // uniform
   // Planar and DC read p[-1][0..n] and p[0..n][-1] of a node at (x0, y0):
   // with x0, y0 >= 1, x0 + n <= W8 - 1 and y0 + n <= H8 - 1 all of them are
   // available (a <= n - 1 and b >= 3n + 1 above), which holds for every node
@@ -662,11 +708,12 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
                         cy + kCtu <= H8 - 1;  // uniform
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
+    if (SHARED) break;
     // Angular prediction reads every entry: all 4n + 1 then.
     const int n = kCtu >> d, len = angular ? 4 * n + 1 : 2 * n + 2, tpn = 256 >> (2 * d);
     const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + (tid >> (8 - 2 * d));
     const int j = tid & (tpn - 1);
-    if (sh.elig[node]) {
+    if (sh.elig[node] || (own && sh.kind[node] == 2)) {
       const int x0 = sh.nx0[node], y0 = sh.ny0[node], a = sh.na[node], b = sh.nb[node];
       int16_t* R = sh.refs + ref_offset(node);
       int dcs = 0;
@@ -719,6 +766,55 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     int c[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) c[i] = sh.cur[(ty * 4 + (i >> 2)) * 64 + tx * 4 + (i & 3)];
+    if (SHARED) {
+      // Inter SATDs only, depths (3, 2) and (1, 0) as the low and high halves
+      // of one packed transform.
+      us2 cp[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) cp[m] = (us2){(unsigned short)c[2 * m], (unsigned short)c[2 * m + 1]};
+#pragma unroll
+      for (int dp = 0; dp < 2; ++dp) {
+        int nd[2];
+        sh2 ir[2][8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int d = 3 - 2 * dp - h, lg = 6 - d;
+          const int lx = (tx * 4) >> lg, ly = (ty * 4) >> lg;
+          nd[h] = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
+          if (!jb->subpel && sh.elig[nd[h]]) {
+            inter_rows(jb, cx + tx * 4 + sh.mvx[nd[h]], cy + ty * 4 + sh.mvy[nd[h]], cp,
+                       ref_aligned, frame_bytes, ir[h]);
+          } else {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) ir[h][m] = (sh2)(0);
+          }
+        }
+        // Per sample: (depth 3 - 2 dp residual, depth 2 - 2 dp residual).
+        sh2 pr[16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const uint32_t a = __builtin_bit_cast(uint32_t, ir[0][2 * j + q]);
+            const uint32_t b = __builtin_bit_cast(uint32_t, ir[1][2 * j + q]);
+            pr[4 * j + 2 * q] = __builtin_bit_cast(sh2, __builtin_amdgcn_perm(b, a, 0x05040100u));
+            pr[4 * j + 2 * q + 1] = __builtin_bit_cast(sh2, __builtin_amdgcn_perm(b, a, 0x07060302u));
+          }
+        }
+        const uint32_t pk = satd4x4_pair(pr);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int d = 3 - 2 * dp - h;
+          const int width = 4 << (2 * (3 - d)), w = width > 64 ? 64 : width;
+          const uint32_t v = group_sum(h == 0 ? (pk & 0xFFFFu) : (pk >> 16), w);
+          if (d > 0) {
+            if ((lane & (w - 1)) == 0) sh.satd[nd[h]][0] = v;
+          } else if (lane == 0) {
+            sh.part0[wave][0] = v;
+          }
+        }
+      }
+    } else {
     // The transform is linear and a constant block only moves its (0,0)
     // coefficient (by 16 times the constant), so the DC SATD of this tile at
     // any node follows from the tile's own coefficients: with A = sum |coef|
@@ -737,49 +833,15 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       const int lx = (tx * 4) >> lg, ly = (ty * 4) >> lg;
       const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
       uint32_t v0 = 0, v1 = 0, v2 = 0;
-      if (sh.elig[node]) {
+      if (sh.elig[node] || (own && sh.kind[node] == 2)) {
         // Inter residual (zero with sub-pel refinement: that SATD comes from
         // subres) in the low halves, planar residual in the high halves; both
         // first as pairs of a row's samples (irp, prp), then regrouped per
         // sample into pr.
         sh2 irp[8];
-        if (!jb->subpel) {
-          const int mx = sh.mvx[node], my = sh.mvy[node];
-          const uint8_t* __restrict__ rp = jb->ref;
-          const int xf = cx + tx * 4 + mx;  // first reference column of the tile
-          const int yf = cy + ty * 4 + my;  // and row
-          // A tile whose 4 x 4 reference samples lie inside the frame: per
-          // row the two dwords around its 4 samples (the last row's second
-          // dword inside the frame too), one v_alignbyte and two
-          // byte-to-16-bit v_perm_b32; row offsets (below 2^31) one stride
-          // apart.
-          const uint32_t o0 = (uint32_t)yf * (uint32_t)stride + (uint32_t)xf;
-          if (ref_aligned && xf >= 0 && xf + 3 < jb->w && yf >= 0 && yf + 3 < jb->h &&
-              ((o0 + 3u * (uint32_t)stride) & ~3u) + 8u <= frame_bytes) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const uint32_t o = o0 + (uint32_t)(q * stride);
-              const uint32_t* a = (const uint32_t*)(rp + (o & ~3u));
-              const uint32_t v = __builtin_amdgcn_alignbyte(a[1], a[0], o & 3u);
-              const us2 r0 = __builtin_bit_cast(us2, __builtin_amdgcn_perm(0u, v, 0x0c010c00u));
-              const us2 r1 = __builtin_bit_cast(us2, __builtin_amdgcn_perm(0u, v, 0x0c030c02u));
-              irp[2 * q] = __builtin_bit_cast(sh2, cp[2 * q] - r0);
-              irp[2 * q + 1] = __builtin_bit_cast(sh2, cp[2 * q + 1] - r1);
-            }
-          } else {
-            uint32_t yo[4], xo[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              yo[q] = (uint32_t)(clampi(yf + q, 0, jb->h - 1) * stride);
-              xo[q] = (uint32_t)clampi(xf + q, 0, jb->w - 1);
-            }
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-              const us2 r = {(unsigned short)rp[yo[m >> 1] + xo[2 * (m & 1)]],
-                             (unsigned short)rp[yo[m >> 1] + xo[2 * (m & 1) + 1]]};
-              irp[m] = __builtin_bit_cast(sh2, cp[m] - r);
-            }
-          }
+        if (!jb->subpel && sh.elig[node]) {
+          inter_rows(jb, cx + tx * 4 + sh.mvx[node], cy + ty * 4 + sh.mvy[node], cp, ref_aligned,
+                     frame_bytes, irp);
         } else {
 #pragma unroll
           for (int m = 0; m < 8; ++m) irp[m] = (sh2)(0);
@@ -878,6 +940,7 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
           sh.angj[node] = bj, sh.angd[node] = bd, sh.angm[node] = (uint8_t)bm;
       }
     }
+    }  // !SHARED
   }
   __syncthreads();
   if (angular && tid == 0 && sh.elig[0]) {
@@ -898,6 +961,15 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     if (node == 0) {
       for (int m = 0; m < 3; ++m)
         sh.satd[0][m] = sh.part0[0][m] + sh.part0[1][m] + sh.part0[2][m] + sh.part0[3][m];
+    }
+    if (SHARED) {
+      // Planar and DC SATDs of the job sharing this current frame.
+      const uint32_t* is = jb->intra_src + ((size_t)ctu * kNodes + node) * 2;
+      sh.satd[node][1] = is[0], sh.satd[node][2] = is[1];
+    } else if (own) {
+      uint32_t* io = jb->intra + ((size_t)ctu * kNodes + node) * 2;
+      const bool in = sh.kind[node] == 2;
+      io[0] = in ? sh.satd[node][1] : 0u, io[1] = in ? sh.satd[node][2] : 0u;
     }
   }
   __syncthreads();
@@ -1171,14 +1243,38 @@ __global__ __launch_bounds__(256) void search_kernel_d8(const JobDesc* jobs_, co
   search_persistent<8>(jobs_, items_, qo, counter, win, win_dwords_max);
 }
 
-template <bool ANG>
-__global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus) {
+// Job owning CTU `flat` of a leaf launch over the listed jobs (in lctu_start order).
+__device__ int find_ljob(cjob jobs, const int* list, int n, int flat) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[list[mid]].lctu_start <= flat) lo = mid;
+    else hi = mid - 1;
+  }
+  return list[lo];
+}
+
+// One workgroup per CTU of the launch: every job's CTUs (list null), or, when
+// jobs share intra SATDs, two launches with lists of their own: SHARED = false
+// over the jobs that take none (those whose SATDs are shared write them),
+// SHARED = true over the others.  Each launch deals its own CTUs evenly to the
+// XCDs.
+template <bool ANG, bool SHARED>
+__global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, const int* list,
+                                                   int n_jobs, int n_ctus) {
   __shared__ LeafShared sh;
   const cjob jobs = (cjob)jobs_;
   const int flat = xcd_contiguous_index();
   if (flat >= n_ctus) return;
-  const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
-  leaf_ctu<ANG>(jobs + j, flat - jobs[j].ctu_start, sh);
+  int j, ctu;
+  if (list) {
+    j = __builtin_amdgcn_readfirstlane(find_ljob(jobs, list, n_jobs, flat));
+    ctu = flat - jobs[j].lctu_start;
+  } else {
+    j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
+    ctu = flat - jobs[j].ctu_start;
+  }
+  leaf_ctu<ANG, SHARED>(jobs + j, ctu, sh);
 }
 
 hipError_t launch_store_job(const JobDesc& jb, JobDesc* dst, hipStream_t st) {
@@ -1253,11 +1349,23 @@ hipError_t launch_search(const JobDesc* jobs, const uint2* items, const QueueOff
 }
 
 hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, bool angular,
+                       const int* llist, int n_ljobs0, int n_lctus0, int n_lctus1,
                        hipStream_t st) {
-  if (angular)
-    hipLaunchKernelGGL(leaf_kernel<true>, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus);
-  else
-    hipLaunchKernelGGL(leaf_kernel<false>, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus);
+  const int* l0 = llist;
+  const int nj0 = llist ? n_ljobs0 : n_jobs, nc0 = llist ? n_lctus0 : n_ctus;
+  if (nc0 > 0) {
+    if (angular)
+      hipLaunchKernelGGL((leaf_kernel<true, false>), dim3(nc0), dim3(256), 0, st, jobs, l0, nj0,
+                         nc0);
+    else
+      hipLaunchKernelGGL((leaf_kernel<false, false>), dim3(nc0), dim3(256), 0, st, jobs, l0, nj0,
+                         nc0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (!llist || n_lctus1 <= 0) return hipSuccess;
+  hipLaunchKernelGGL((leaf_kernel<false, true>), dim3(n_lctus1), dim3(256), 0, st, jobs,
+                     llist + n_ljobs0, n_jobs - n_ljobs0, n_lctus1);
   return hipGetLastError();
 }
 

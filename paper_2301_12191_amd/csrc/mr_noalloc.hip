@@ -144,7 +144,7 @@ extern "C" int mr_ctu_search_noalloc(const mr_frame* cur, const mr_frame* ref,
   bind_scratch(P, base + head + qbytes + dbytes);
   if (e == hipSuccess) e = launch_store_job(P.jobs[0], jobs_d, st);
   if (e == hipSuccess)
-    e = launch_plan(P, jobs_d, nullptr, PlanLists{nullptr, nullptr, nullptr}, counter, st,
+    e = launch_plan(P, jobs_d, nullptr, PlanLists{nullptr, nullptr, nullptr, nullptr}, counter, st,
                     nullptr);
   return e == hipSuccess ? MR_OK : MR_EHIP;
 }

@@ -289,10 +289,11 @@ size_t device_lds_max() {
   return cached[dev];
 }
 
-// Two frame descriptors of the same picture memory and geometry.
-static bool same_frame(const mr_frame* a, const mr_frame* b) {
-  return a->luma == b->luma && a->width == b->width && a->height == b->height &&
-         a->stride == b->stride;
+// A frame's identity for sharing work between jobs of a batch: its memory and
+// geometry (plus, for padded references, the margins).
+using FrameKey = std::tuple<const uint8_t*, int, int, int, int, int>;
+static FrameKey frame_key(const mr_frame* f, int mx = 0, int my = 0) {
+  return FrameKey{f->luma, f->width, f->height, f->stride, mx, my};
 }
 
 int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
@@ -342,6 +343,21 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
   P->job_off.assign(n_jobs, 0);
   P->cur_owner.assign(n_jobs, -1);
   P->pad_owner.assign(n_jobs, -1);
+  // Jobs with the same current frame and no angular modes share the first
+  // one's planar and DC SATDs (QP-independent); that one writes them for all.
+  P->intra_owner.assign(n_jobs, -1);
+  P->intra_owned.assign(n_jobs, 0);
+  P->any_shared_intra = false;
+  std::map<FrameKey, int> first_cur, first_intra, first_pad;
+  for (int j = 0; j < n_jobs; ++j) {
+    if (p[j]->angular) continue;
+    auto ins = first_intra.emplace(frame_key(cur[j]), j);
+    if (!ins.second) {
+      P->intra_owner[j] = ins.first->second;
+      P->intra_owned[ins.first->second] = 1;
+      P->any_shared_intra = true;
+    }
+  }
   P->items.clear();
   P->rlist.clear();
   P->slist.clear();
@@ -390,16 +406,15 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     P->job_off[j] = P->scratch_bytes;
     // Jobs that read the same current frame (e.g. one pair at several QPs)
     // share one packed copy of its CTUs.
-    P->cur_owner[j] = -1;
-    for (int i = 0; i < j; ++i)
-      if (P->cur_owner[i] < 0 && same_frame(cur[i], cur[j])) {
-        P->cur_owner[j] = i;
-        break;
-      }
+    {
+      auto ins = first_cur.emplace(frame_key(cur[j]), j);
+      P->cur_owner[j] = ins.second ? -1 : ins.first->second;
+    }
     jb.pack_cur = P->cur_owner[j] < 0 ? 1 : 0;
     P->scratch_bytes += (jb.pack_cur ? up256((size_t)n_ctus * 4096) : 0) +
                         up256((size_t)n_ctus * kNodes * 8) + up256((size_t)n_ctus * kNodes) +
-                        up256((size_t)n_ctus * 16);
+                        up256((size_t)n_ctus * 16) +
+                        (P->intra_owned[j] ? up256((size_t)n_ctus * kNodes * 8) : 0);
     P->n_ctus += n_ctus;
     jb.subpel = p[j]->subpel;
     jb.angular = p[j]->angular;
@@ -417,12 +432,8 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
       jb.pad_y = refine_pad_y(R);
       jb.pad_pitch = jb.w8 + 2 * jb.pad_x;
       // The same reference frame with the same margins (same R): one copy.
-      for (int i = 0; i < j; ++i)
-        if (P->pad_owner[i] < 0 && P->jobs[i].pad_pitch != 0 && same_frame(ref[i], ref[j]) &&
-            P->jobs[i].pad_x == jb.pad_x && P->jobs[i].pad_y == jb.pad_y) {
-          P->pad_owner[j] = i;
-          break;
-        }
+      auto ins = first_pad.emplace(frame_key(ref[j], jb.pad_x, jb.pad_y), j);
+      P->pad_owner[j] = ins.second ? -1 : ins.first->second;
       jb.pad_rows = P->pad_owner[j] < 0 ? 1 : 0;
       const int64_t pad_bytes = (int64_t)(jb.h8 + 2 * jb.pad_y) * jb.pad_pitch;
       if (jb.pad_rows) P->scratch_bytes += up256((size_t)pad_bytes);
@@ -491,6 +502,21 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
             jwork[j].push_back(Work{cost, (uint32_t)j, pack_item_y(row, sidx * jb.strip, b)});
           }
     }
+  }
+  // The two leaf launches of shared intra SATDs: jobs that take none, then the others.
+  P->llist.clear();
+  P->n_ljobs0 = P->n_lctus0 = P->n_lctus1 = 0;
+  if (P->any_shared_intra) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < n_jobs; ++j) {
+        if ((P->intra_owner[j] >= 0) != (pass == 1)) continue;
+        JobDesc& jb = P->jobs[j];
+        int& cnt = pass == 0 ? P->n_lctus0 : P->n_lctus1;
+        jb.lctu_start = cnt;
+        cnt += jb.ctus_w * jb.ctus_h;
+        P->llist.push_back(j);
+        if (pass == 0) P->n_ljobs0 += 1;
+      }
   }
   if (total_items > ((int64_t)1 << 30)) return MR_EINVAL;
   if (P->lds_bytes > device_lds_max()) return MR_EINVAL;  // a forced tile shape too large
@@ -562,6 +588,14 @@ void bind_scratch(Plan& P, uint8_t* base) {
     sp += up256((size_t)n_ctus * kNodes);
     jb.eligbits = (uint32_t*)sp;
     sp += up256((size_t)n_ctus * 16);
+    jb.intra = nullptr;
+    jb.intra_src = nullptr;
+    if (P.intra_owner[j] >= 0) {
+      jb.intra_src = P.jobs[P.intra_owner[j]].intra;  // owners come first
+    } else if (P.intra_owned[j]) {
+      jb.intra = (uint32_t*)sp;
+      sp += up256((size_t)n_ctus * kNodes * 8);
+    }
     jb.subres = nullptr;
     if (jb.subpel) {
       jb.subres = (uint32_t*)sp;
@@ -592,7 +626,10 @@ hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, con
   if (e == hipSuccess && P.n_sjobs > 0)
     e = launch_subpel(jobs_d, L.slist, P.n_sjobs, P.n_sctus, st);
   if (ev) profile_mark(ev, 3, st);
-  if (e == hipSuccess) e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, P.any_angular, st);
+  if (e == hipSuccess)
+    e = launch_leaf(jobs_d, P.n_jobs, P.n_ctus, P.any_angular,
+                    P.any_shared_intra ? L.llist : nullptr, P.n_ljobs0, P.n_lctus0, P.n_lctus1,
+                    st);
   if (ev) profile_mark(ev, 4, st);
   return e;
 }
@@ -667,7 +704,7 @@ int mr_ctu_search_seeded(const mr_frame* cur, const mr_frame* ref, const mr_sear
   const bool prof = profile_on() && profile_begin(&ev, st) == MR_OK;
   hipError_t e = launch_store_job(P.jobs[0], jobs_d, st);
   if (e == hipSuccess)
-    e = launch_plan(P, jobs_d, nullptr, PlanLists{nullptr, nullptr, nullptr}, counter, st,
+    e = launch_plan(P, jobs_d, nullptr, PlanLists{nullptr, nullptr, nullptr, nullptr}, counter, st,
                     prof ? &ev : nullptr);
   if (prof) profile_push(ev);
   const hipError_t ef = hipFreeAsync(scratch, st);

@@ -63,6 +63,16 @@ struct Plan {
   // or padded reference (pad_owner) it shares: same frame, size and stride (and
   // margins), or -1 for its own copy.
   std::vector<int> cur_owner, pad_owner;
+  // Per job, the earlier job whose intra SATDs it takes (same current frame,
+  // neither angular), or -1; any_shared_intra: some job takes them.
+  std::vector<int> intra_owner;
+  std::vector<char> intra_owned;  // 1: some job takes this job's intra SATDs
+  bool any_shared_intra = false;
+  // With shared intra SATDs, the leaf runs twice: over the jobs that take none
+  // (llist[0 .. n_ljobs0), n_lctus0 CTUs), then over those that do (the rest of
+  // llist, n_lctus1 CTUs); lctu_start numbers each job's CTUs in its launch.
+  std::vector<int> llist;
+  int n_ljobs0 = 0, n_lctus0 = 0, n_lctus1 = 0;
   size_t scratch_bytes = 0;           // per-job scratch total (curpack, keys, elig, refpad)
   // Seeded jobs (refinement) in rctu_start order, sub-pel jobs in sctu_start
   // order, jobs with a padded reference (seeded or sub-pel).
@@ -91,11 +101,12 @@ struct PlanLists {
   const int* rlist;
   const int* slist;
   const int* plist;
+  const int* llist;
 };
 // Device layout of a planned batch (job array, items, job lists, counter,
 // scratch), its upload, and the device job lists inside it.
 struct BatchLayout {
-  size_t jobs, items, rlist, slist, plist, counter, scratch, total;
+  size_t jobs, items, rlist, slist, plist, llist, counter, scratch, total;
 };
 BatchLayout batch_layout(const Plan& P);
 hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st);
@@ -116,7 +127,9 @@ hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* co
 hipError_t launch_search(const JobDesc* jobs, const uint2* items, const QueueOffsets& qoff,
                          int D, int strip, int n_wg, size_t lds_bytes, uint32_t* counter,
                          hipStream_t st);
+// Leaf over all jobs (llist null), or, with shared intra SATDs, its two launches.
 hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, bool angular,
+                       const int* llist, int n_ljobs0, int n_lctus0, int n_lctus1,
                        hipStream_t st);
 hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int max_rows,
                       hipStream_t st);

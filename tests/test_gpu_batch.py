@@ -71,8 +71,8 @@ def test_batch_mixed_jobs_equal_single_calls(mr):
 
 def test_jobs_sharing_frames_equal_single_calls(mr):
     """One frame pair at several QPs and search forms in one batch: the jobs share the packed
-    current CTUs, and those with equal margins the padded reference; each equals its own
-    launch."""
+    current CTUs and the intra SATDs, and those with equal margins the padded reference; each
+    equals its own launch."""
     import torch
     sc = synth.Scene(11, 360, 200, 6, 14, 2)
     cur = torch.from_numpy(sc.render(1)).cuda()
@@ -93,6 +93,14 @@ def test_jobs_sharing_frames_equal_single_calls(mr):
             dict(cur=cur, ref=ref, qp=32, search_range=24, seed=seed),    # other margins: own copy
             dict(cur=cur, ref=other, qp=27, search_range=16, seed=seed),  # other reference
             dict(cur=other, ref=cur, qp=30, search_range=16)]             # other current frame
+    # and a bounded job first: the jobs after it take its intra SATDs, also at nodes its
+    # bounds exclude
+    b2 = torch.zeros((25, 45, 2), dtype=torch.uint8)
+    b2[..., 0] = 2
+    b2[..., 1] = 3
+    jobs += [dict(cur=ref, ref=other, qp=30, search_range=16, bounds=b2.cuda()),
+             dict(cur=ref, ref=other, qp=22, search_range=16),
+             dict(cur=ref, ref=cur, qp=35, search_range=8, seed=seed)]
     outs = mr.mr_ctu_search_batch(jobs)
     torch.cuda.synchronize()
     for k, (j, o) in enumerate(zip(jobs, outs)):
