@@ -21,6 +21,14 @@ __device__ __forceinline__ int xcd_contiguous_index() {
   return xcd * q + min(xcd, rm) + k;
 }
 
+// m * num / den rounded to nearest, halves away from zero (|m| < 2^15,
+// 1 <= num <= 8192, 1 <= den <= 32768: every intermediate fits 32 bits).
+__device__ __forceinline__ int scale_round_dev(int m, int num, int den) {
+  const uint32_t a = (uint32_t)(m < 0 ? -m : m) * (uint32_t)num;
+  const int q = (int)((2u * a + (uint32_t)den) / (2u * (uint32_t)den));
+  return m < 0 ? -q : q;
+}
+
 // Z-order (Morton) position -> (x, y) for 6-bit indices.
 __device__ __forceinline__ int zx(int z) { return (z & 1) | ((z >> 1) & 2) | ((z >> 2) & 4); }
 __device__ __forceinline__ int zy(int z) { return ((z >> 1) & 1) | ((z >> 2) & 2) | ((z >> 3) & 4); }

@@ -114,6 +114,8 @@ struct JobDesc {
   const uint8_t* bounds;   // [U][V][2] or null
   uint8_t* elig;           // [ctus][85] 1 = node may be a leaf (inside and allowed)
   uint32_t* eligbits;      // [ctus][4] the same as a bit mask (bit n of word n / 32)
+  uint8_t* okbits;         // [ctus][85] bit 0: the node may split, bit 1: it may be a leaf
+                           // (the bounds rule; written by the prep kernel)
   // Seeded search (reference MV reuse with a refinement window); seed_mv null
   // means full search.
   const int16_t* seed_mv;  // [ceil(seed_h/8)][ceil(seed_w/8)][2] reference MVs
@@ -122,6 +124,8 @@ struct JobDesc {
   int32_t seed_qpel;       // 1: seed_mv in quarter-pel units
   int32_t rctu_start;      // first CTU of this job among the seeded jobs' CTUs
   uint8_t* rtab;           // refinement key tables (kRtabBytes), seeded jobs only
+  uint32_t* seedc;         // [ctus][85] search centre of each CU, seeded jobs only:
+                           // (uint16) dx | dy << 16 (written by the prep kernel)
   int32_t angular;         // 1: the leaf also scores the 33 angular intra modes
   // Intra SATDs shared by jobs of a batch with the same current frame (none of
   // them angular): the first such job's leaf writes, per node of every CTU,

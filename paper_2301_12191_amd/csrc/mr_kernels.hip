@@ -140,6 +140,7 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
     const int n = kCtu >> d, lx = local % (1 << d), ly = local / (1 << d);
     const int x0 = cx + lx * n, y0 = cy + ly * n;
     uint8_t e = 0;
+    bool split_ok = d < 3, leaf_ok = true;
     if (x0 + n <= jb->w8 && y0 + n <= jb->h8) {
       e = 1;
       if (jb->bounds) {
@@ -151,11 +152,26 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
             min_lo = min(min_lo, (int)b[0]);
             max_hi = max(max_hi, (int)b[1]);
           }
-        const bool split_ok = d < 3 && d < max_hi;
-        e = (d >= min_lo || !split_ok) ? 1 : 0;
+        split_ok = d < 3 && d < max_hi;
+        leaf_ok = d >= min_lo || !split_ok;
+        e = leaf_ok ? 1 : 0;
       }
     }
     jb->elig[(size_t)ctu * kNodes + tid] = e;
+    jb->okbits[(size_t)ctu * kNodes + tid] = (uint8_t)((split_ok ? 1 : 0) | (leaf_ok ? 2 : 0));
+    if (jb->seed_mv) {
+      // Seeded search centre: the reference MV of the unit co-located with the
+      // CU's centre, scaled to this picture and clamped so that the refinement
+      // window stays inside the search range.
+      const uint32_t sw = jb->seed_w, shh = jb->seed_h, W = jb->w, H = jb->h;
+      const uint32_t px = x0 + n / 2, py = y0 + n / 2;
+      const uint32_t xr = min(px * sw / W, sw - 1), yr = min(py * shh / H, shh - 1);
+      const int16_t* m = jb->seed_mv + 2 * ((yr >> 3) * ((sw + 7) >> 3) + (xr >> 3));
+      const int lim = jb->R - jb->seed_r, qs = 2 * jb->seed_qpel;  // quarter-pel: 4 units a pixel
+      const int cxm = clampi(scale_round_dev(m[0], W, sw << qs), -lim, lim);
+      const int cym = clampi(scale_round_dev(m[1], H, shh << qs), -lim, lim);
+      jb->seedc[(size_t)ctu * kNodes + tid] = (uint32_t)(cxm & 0xFFFF) | ((uint32_t)cym << 16);
+    }
     uint64_t key = kKeyNone;
     if (corner) {
       // The node's blocks are a Z-order run of 4^(3-d) blocks.
@@ -651,21 +667,9 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     }
     sh.satq[node] = sq;
     sh.mvx[node] = (int16_t)mx, sh.mvy[node] = (int16_t)my;
-    // bounds admissibility (same rule the prep kernel applied)
-    bool split_ok = d < 3, leaf_ok = true;
-    if (jb->bounds && sh.kind[node] == 2) {
-      const int uw = W8 >> 3;
-      int min_lo = 3, max_hi = 0;
-      for (int uy = y0 >> 3; uy < (y0 + n) >> 3; ++uy)
-        for (int ux = x0 >> 3; ux < (x0 + n) >> 3; ++ux) {
-          const uint8_t* b = jb->bounds + 2 * ((size_t)uy * uw + ux);
-          min_lo = min(min_lo, (int)b[0]);
-          max_hi = max(max_hi, (int)b[1]);
-        }
-      split_ok = d < 3 && d < max_hi;
-      leaf_ok = d >= min_lo || !split_ok;
-    }
-    sh.split_ok[node] = split_ok, sh.leaf_ok[node] = leaf_ok;
+    // bounds admissibility, as the prep kernel evaluated it
+    const uint8_t ok = jb->okbits[(size_t)ctu * kNodes + node];
+    sh.split_ok[node] = ok & 1, sh.leaf_ok[node] = (ok >> 1) & 1;
     // Neighbour samples after H.265 reference substitution.  In the
     // substitution's scan order (left column bottom to top, corner, top row
     // left to right; scan index k = 2n - off for the left column and k = off

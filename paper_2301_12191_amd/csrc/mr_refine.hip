@@ -17,14 +17,6 @@
 
 namespace mr {
 
-// m * num / den rounded to nearest, halves away from zero (|m| < 2^15,
-// 1 <= num <= 8192, 1 <= den <= 32768: every intermediate fits 32 bits).
-__device__ __forceinline__ int scale_round_dev(int m, int num, int den) {
-  const uint32_t a = (uint32_t)(m < 0 ? -m : m) * (uint32_t)num;
-  const int q = (int)((2u * a + (uint32_t)den) / (2u * (uint32_t)den));
-  return m < 0 ? -q : q;
-}
-
 // Signed Exp-Golomb length of v without a branch on the sign.
 __device__ __forceinline__ uint32_t se_len(int v) {
   const uint32_t k = 2u * (uint32_t)(v < 0 ? -v : v) - (v > 0 ? 1u : 0u);
@@ -141,26 +133,18 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   const int ctu_x = (ctu % jb->ctus_w) * kCtu, ctu_y = (ctu / jb->ctus_w) * kCtu;
   const int lx = bx >> sh3, ly = by >> sh3;
   const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
-  const int R = jb->R, r = jb->seed_r, lim = R - r;
+  const int R = jb->R, r = jb->seed_r;
   const int ncand = 2 * r + 1;
   const int rem = ncand - pass * NP;  // window columns left for this pass (uniform)
   if (rem <= 0) return;
   const int bh = (ncand + nband - 1) / nband;
   const int iy0 = band * bh, iy1 = min(ncand, iy0 + bh);
   if (iy0 >= iy1) return;
-  const int W = jb->w, H = jb->h;
-  // The eligibility flags, the reference MV at this lane's CU centre and the
-  // current block are loaded together: the wavefront's first global loads.
+  // The eligibility flags, the search centre of this lane's CU (scaled and
+  // clamped by the prep kernel) and the current block are loaded together:
+  // the wavefront's first global loads.
   const bool e = jb->elig[(size_t)ctu * kNodes + node] != 0;
-  const uint32_t sw = jb->seed_w, shh = jb->seed_h;
-  int16_t m0, m1;
-  {
-    const uint32_t px = ctu_x + lx * n + n / 2, py = ctu_y + ly * n + n / 2;
-    const uint32_t xr = min(px * sw / (uint32_t)W, sw - 1);
-    const uint32_t yr = min(py * shh / (uint32_t)H, shh - 1);
-    const int16_t* m = jb->seed_mv + 2 * ((yr >> 3) * ((sw + 7) >> 3) + (xr >> 3));
-    m0 = m[0], m1 = m[1];
-  }
+  const uint32_t cc = jb->seedc[(size_t)ctu * kNodes + node];
   uint32_t c[16];
   {
     const uint4* cp = (const uint4*)(jb->curpack + (size_t)ctu * 1024 + b * 16);
@@ -172,12 +156,9 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   }
   // Consume every load here, so that the compiler keeps them above the exit
   // test (one round of latency instead of three).
-  asm volatile("" ::"v"(m0), "v"(m1), "v"(c[0]), "v"(c[4]), "v"(c[8]), "v"(c[12]));
+  asm volatile("" ::"v"(cc), "v"(c[0]), "v"(c[4]), "v"(c[8]), "v"(c[12]));
   if (__ballot(e) == 0) return;  // no CU of this depth may be a leaf
-  // Search centre of this lane's CU (all products < 2^27).
-  const int qs = 2 * jb->seed_qpel;  // quarter-pel maps: 4 map units per pixel
-  const int cxm = clampi(scale_round_dev(m0, W, sw << qs), -lim, lim);
-  const int cym = clampi(scale_round_dev(m1, H, shh << qs), -lim, lim);
+  const int cxm = (int)(int16_t)(cc & 0xFFFFu), cym = (int)cc >> 16;  // within [r - R, R - r]
   // This lane's block (blocks outside the coded picture belong to CUs that are
   // not searched; their loads are kept inside the padded reference).
   const int X0 = min(ctu_x + 8 * bx, jb->w8 - 8), Y0 = min(ctu_y + 8 * by, jb->h8 - 8);
@@ -191,7 +172,14 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   const int shb = xs & 3;
   // Column key terms, one LDS slot per (position, lane): kept out of the
   // register file, which the ring of pre-shifted rows fills.
-  {
+  if (pass * NP + NP <= ncand) {  // uniform: every column of the pass is in the window
+    const uint32_t* kp = rk + (cxm - r + pass * NP + R);  // entries 0..2R
+    uint32_t kv[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) kv[k] = kp[k];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) Ks[k][b] = kv[k];
+  } else {
     // All loads first (indices clamped into the table), then the selects.
     uint32_t kv[NP];
 #pragma unroll
@@ -200,16 +188,20 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
     for (int k = 0; k < NP; ++k)  // window column pass NP + k (valid: 0..2r)
       Ks[k][b] = pass * NP + k < ncand ? kv[k] : 0x80000000u;
   }
-  const uint32_t* src = (const uint32_t*)(jb->refpad +
-                                          (size_t)(Y0 + cym - r + iy0 + jb->pad_y) * pitch +
-                                          (xs - shb));
-  const int dwp = pitch >> 2;
+  // Window row `row` of this lane: a 32-bit byte offset from the (uniform)
+  // padded reference, so that each load is one add and a scalar base.  Rows
+  // up to nrow + 7 are read (one past the last band row's ring refill), at
+  // most h8 + 2R + 8 < h8 + 2 pad_y padded rows.
+  const uint8_t* __restrict__ rp = jb->refpad;
+  const uint32_t pitch_u = (uint32_t)pitch;
+  const uint32_t off0 = (uint32_t)(Y0 + cym - r + iy0 + jb->pad_y) * pitch_u + (uint32_t)(xs - shb);
   uint64_t P[8][NQ + 1];
 #pragma unroll
   for (int row = 0; row < 8; ++row) {
+    const uint32_t* s = (const uint32_t*)(rp + (off0 + (uint32_t)row * pitch_u));
     uint32_t raw[NDW];
 #pragma unroll
-    for (int j = 0; j < NDW; ++j) raw[j] = src[row * dwp + j];
+    for (int j = 0; j < NDW; ++j) raw[j] = s[j];
     align_pairs<NQ>(raw, shb, P[row]);
   }
   const int nrow = iy1 - iy0;
@@ -227,11 +219,15 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
       // across steps multiplies the live registers.
       __builtin_amdgcn_sched_barrier(0);
       const int dy = cym - r + iy0 + t;
+      // The ring's next row, loaded unconditionally (also after the band's
+      // last row: in bounds, unused) so that the wait for the previous row's
+      // table entries need not also wait for it.
       uint32_t nxt[NDW];
       const bool more = t + 1 < nrow;
-      if (more) {
+      {
+        const uint32_t* s = (const uint32_t*)(rp + (off0 + (uint32_t)(t + 8) * pitch_u));
 #pragma unroll
-        for (int j = 0; j < NDW; ++j) nxt[j] = src[(t + 8) * dwp + j];
+        for (int j = 0; j < NDW; ++j) nxt[j] = s[j];
       }
       // Every position, also past the window in a partial last pass: its
       // samples are inside the padded reference and its key term is 2^31.

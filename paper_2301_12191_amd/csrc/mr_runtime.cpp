@@ -412,7 +412,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     }
     jb.pack_cur = P->cur_owner[j] < 0 ? 1 : 0;
     P->scratch_bytes += (jb.pack_cur ? up256((size_t)n_ctus * 4096) : 0) +
-                        up256((size_t)n_ctus * kNodes * 8) + up256((size_t)n_ctus * kNodes) +
+                        up256((size_t)n_ctus * kNodes * 8) + 2 * up256((size_t)n_ctus * kNodes) +
                         up256((size_t)n_ctus * 16) +
                         (P->intra_owned[j] ? up256((size_t)n_ctus * kNodes * 8) : 0);
     P->n_ctus += n_ctus;
@@ -443,7 +443,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
     if (seed_of(j)) {
       // Seeded: refinement around reference MVs instead of the full search.
       set_job_seed(jb, seed_of(j));
-      P->scratch_bytes += up256(kRtabBytes);
+      P->scratch_bytes += up256(kRtabBytes) + up256((size_t)n_ctus * kNodes * 4);  // + seedc
       jb.rctu_start = P->n_rctus;
       P->rlist.push_back(j);
       P->n_rjobs += 1;
@@ -588,6 +588,8 @@ void bind_scratch(Plan& P, uint8_t* base) {
     sp += up256((size_t)n_ctus * kNodes);
     jb.eligbits = (uint32_t*)sp;
     sp += up256((size_t)n_ctus * 16);
+    jb.okbits = sp;
+    sp += up256((size_t)n_ctus * kNodes);
     jb.intra = nullptr;
     jb.intra_src = nullptr;
     if (P.intra_owner[j] >= 0) {
@@ -602,9 +604,12 @@ void bind_scratch(Plan& P, uint8_t* base) {
       sp += up256((size_t)n_ctus * kNodes * 8);
     }
     jb.rtab = nullptr;
+    jb.seedc = nullptr;
     if (jb.seed_mv) {
       jb.rtab = sp;
       sp += up256(kRtabBytes);
+      jb.seedc = (uint32_t*)sp;
+      sp += up256((size_t)n_ctus * kNodes * 4);
     }
     jb.refpad = nullptr;
     if (jb.seed_mv || jb.subpel)
