@@ -81,16 +81,21 @@ PlanLists batch_lists(uint8_t* mem, const BatchLayout& L) {
 // host image of the head of the layout (they are contiguous, from offset 0 to
 // the counter).  A copy from pageable memory reads its source before it
 // returns, so the image may go out of scope.
-hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st) {
-  std::vector<uint8_t> img(L.counter, 0);
-  std::memcpy(img.data() + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs);
+void batch_image(const Plan& P, const BatchLayout& L, uint8_t* img) {
+  std::memset(img, 0, L.counter);
+  std::memcpy(img + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs);
   if (!P.items.empty())
-    std::memcpy(img.data() + L.items, P.items.data(), sizeof(uint2) * P.items.size());
+    std::memcpy(img + L.items, P.items.data(), sizeof(uint2) * P.items.size());
   const std::pair<const std::vector<int>*, size_t> lists[4] = {
       {&P.rlist, L.rlist}, {&P.slist, L.slist}, {&P.plist, L.plist}, {&P.llist, L.llist}};
   for (const auto& pl : lists)
     if (!pl.first->empty())
-      std::memcpy(img.data() + pl.second, pl.first->data(), sizeof(int) * pl.first->size());
+      std::memcpy(img + pl.second, pl.first->data(), sizeof(int) * pl.first->size());
+}
+
+hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st) {
+  std::vector<uint8_t> img(L.counter);
+  batch_image(P, L, img.data());
   return hipMemcpyAsync(mem, img.data(), img.size(), hipMemcpyHostToDevice, st);
 }
 

@@ -150,20 +150,26 @@ class GpuExecutor : public Executor {
   }
 
   int launch(const std::vector<SchedJob*>& jobs, void** handle) override {
-    hipStream_t st = streams_[next_++ & 1];
     const int n = (int)jobs.size();
-    // References whose batches still run (chain_on_launch): this batch waits
-    // for them on the device; on their own stream the order is given.
+    // References whose batches still run (chain_on_launch): this batch goes on
+    // the stream of the first of them, where the order is given; it waits for
+    // the others on the device.  A batch without running references takes the
+    // streams in turn.  (A wait between streams adds about 10 us between the
+    // reference's last kernel and the dependent's first.)
+    hipStream_t st = nullptr;
     {
-      std::vector<hipEvent_t> waits;
+      std::vector<const JobOut*> running;
       for (SchedJob* j : jobs) {
         if (!j->ref_job) continue;
         const JobOut* ro = (const JobOut*)ref_state_(j->ref_job);
         if (!ro) return MR_EDEPEND;
-        if (ro->batch && ro->batch_running && ro->stream != st &&
-            std::find(waits.begin(), waits.end(), ro->batch->ev) == waits.end())
-          waits.push_back(ro->batch->ev);
+        if (ro->batch && ro->batch_running) running.push_back(ro);
       }
+      st = running.empty() ? streams_[next_++ & 1] : running.front()->stream;
+      std::vector<hipEvent_t> waits;
+      for (const JobOut* ro : running)
+        if (ro->stream != st && std::find(waits.begin(), waits.end(), ro->batch->ev) == waits.end())
+          waits.push_back(ro->batch->ev);
       for (hipEvent_t ev : waits)
         if (hipStreamWaitEvent(st, ev, 0) != hipSuccess) return MR_EHIP;
     }
@@ -392,20 +398,21 @@ struct mr_ladder {
 
 static void ladder_loop(mr_ladder* l) {
   (void)hipSetDevice(l->ex->device());
-  // The loop sleeps 20 us between steps; with Linux's default 50 us timer slack
-  // each sleep would last about three times that.  1 us of slack for this thread.
+  // While work is queued or running the loop steps every 5 us, and a
+  // submission wakes it at once (it waits on cv_work, which the submit calls
+  // signal): a batch's completion is seen within a few us and a new frame's
+  // jobs are planned as soon as they arrive.  With Linux's default 50 us
+  // timer slack each wait would last ten times that; 1 us of slack for this
+  // thread.
   (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(l->mu);
   while (!l->stop.load()) {
     const int done = l->sched->step();
     if (done) l->cv_done.notify_all();
-    if (l->sched->idle()) {
+    if (l->sched->idle())
       l->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-    } else {
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
-      lk.lock();
-    }
+    else
+      l->cv_work.wait_for(lk, std::chrono::microseconds(5));
   }
   // Drain: wait for batches in flight so their outputs are complete.
   while (l->sched->batches_in_flight() > 0) {

@@ -252,8 +252,9 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
         best = K < best ? K : best;
       }
       pm = m;
-      pd = rd[m & ((1u << kRankBitsR) - 1)];
-      pu = ru[dy + R];
+      // 32-bit byte offsets from the (uniform) tables: one add per load.
+      pd = *(const uint64_t*)((const uint8_t*)rd + (m & ((1u << kRankBitsR) - 1)) * 8u);
+      pu = *(const uint64_t*)((const uint8_t*)ru + (uint32_t)(dy + R) * 8u);  // dy >= -R
       if (more) align_pairs<NQ>(nxt, shb, P[u]);
     }
   }

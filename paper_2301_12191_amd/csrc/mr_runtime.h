@@ -109,6 +109,9 @@ struct BatchLayout {
   size_t jobs, items, rlist, slist, plist, llist, counter, scratch, total;
 };
 BatchLayout batch_layout(const Plan& P);
+// The host image of [0, L.counter) of the layout: descriptors, items, lists
+// (zeros between them).
+void batch_image(const Plan& P, const BatchLayout& L, uint8_t* img);
 hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st);
 PlanLists batch_lists(uint8_t* mem, const BatchLayout& L);
 // prep -> [pad] -> [search] -> [refine] -> [subpel] -> leaf for a bound plan.
