@@ -59,14 +59,17 @@ namespace mr {
 // Device layout of a planned batch: job array, items, the seeded / sub-pel /
 // padded job lists, queue counter, then per-job scratch.
 BatchLayout batch_layout(const Plan& P) {
+  // Packed at 16 bytes so that the head of most batches fits one upload
+  // kernel's arguments; the counters start a 256-byte line.
+  auto up16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
   BatchLayout L;
   L.jobs = 0;
-  L.items = up256(sizeof(JobDesc) * P.n_jobs);
-  L.rlist = L.items + up256(sizeof(uint2) * P.items.size());
-  L.slist = L.rlist + up256(sizeof(int) * P.rlist.size());
-  L.plist = L.slist + up256(sizeof(int) * P.slist.size());
-  L.llist = L.plist + up256(sizeof(int) * P.plist.size());
-  L.counter = L.llist + up256(sizeof(int) * P.llist.size());
+  L.items = up16(sizeof(JobDesc) * P.n_jobs);
+  L.rlist = L.items + up16(sizeof(uint2) * P.items.size());
+  L.slist = L.rlist + up16(sizeof(int) * P.rlist.size());
+  L.plist = L.slist + up16(sizeof(int) * P.slist.size());
+  L.llist = L.plist + up16(sizeof(int) * P.plist.size());
+  L.counter = up256(L.llist + up16(sizeof(int) * P.llist.size()));
   L.scratch = L.counter + kCounterBytes;
   L.total = L.scratch + P.scratch_bytes;
   return L;
@@ -81,8 +84,8 @@ PlanLists batch_lists(uint8_t* mem, const BatchLayout& L) {
 // host image of the head of the layout (they are contiguous, from offset 0 to
 // the counter).  A copy from pageable memory reads its source before it
 // returns, so the image may go out of scope.
-void batch_image(const Plan& P, const BatchLayout& L, uint8_t* img) {
-  std::memset(img, 0, L.counter);
+void batch_image(const Plan& P, const BatchLayout& L, uint8_t* img, size_t bytes) {
+  std::memset(img, 0, bytes);
   std::memcpy(img + L.jobs, P.jobs.data(), sizeof(JobDesc) * P.n_jobs);
   if (!P.items.empty())
     std::memcpy(img + L.items, P.items.data(), sizeof(uint2) * P.items.size());
@@ -94,8 +97,16 @@ void batch_image(const Plan& P, const BatchLayout& L, uint8_t* img) {
 }
 
 hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st) {
+  // The image ends at the counters; of it only [0, end of the last list) is
+  // needed (the rest is alignment).
+  const size_t used = (L.llist + sizeof(int) * P.llist.size() + 3) & ~(size_t)3;
+  if (used <= kUploadMaxBytes) {
+    uint8_t img[kUploadMaxBytes];
+    batch_image(P, L, img, used);
+    return launch_upload(img, used, mem, st);
+  }
   std::vector<uint8_t> img(L.counter);
-  batch_image(P, L, img.data());
+  batch_image(P, L, img.data(), L.counter);
   return hipMemcpyAsync(mem, img.data(), img.size(), hipMemcpyHostToDevice, st);
 }
 

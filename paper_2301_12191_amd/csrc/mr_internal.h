@@ -35,6 +35,10 @@ __host__ __device__ inline int refine_pad_y(int R) { return R + 8; }
 // Within one window row, (SAD + (c >> 16)) * 2^9 + rank orders the candidates
 // as their 64-bit keys do, and the row minimum m decodes to the key
 // (m >> 9) * 2^33 + rd[m & 511] + ru[dy + R].
+// Largest batch head (descriptors, items, lists) uploaded as a kernel's
+// argument rather than by a copy from host memory.
+constexpr size_t kUploadMaxBytes = 3584;
+
 constexpr int kRtabSpan = 257;  // 2R + 1 for R <= 128
 constexpr int kRankBitsR = 9;
 constexpr size_t kRtabRk = 0;

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -1370,6 +1371,27 @@ hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, bool angular
   if (!llist || n_lctus1 <= 0) return hipSuccess;
   hipLaunchKernelGGL((leaf_kernel<false, true>), dim3(n_lctus1), dim3(256), 0, st, jobs,
                      llist + n_ljobs0, n_jobs - n_ljobs0, n_lctus1);
+  return hipGetLastError();
+}
+
+// A batch's descriptor image passed by value: the kernel copies it from its
+// arguments to device memory, one dword per thread.  In the stream's order, as
+// a kernel, it starts as soon as the previous kernel ends, where a copy from
+// host memory would first go through the copy engine (about 10 us).
+struct UploadImage {
+  uint32_t w[kUploadMaxBytes / 4];
+};
+
+__global__ __launch_bounds__(256) void upload_kernel(UploadImage img, uint32_t* dst, int n_words) {
+  for (int i = threadIdx.x; i < n_words; i += 256) dst[i] = img.w[i];
+}
+
+hipError_t launch_upload(const uint8_t* img, size_t bytes, uint8_t* dst, hipStream_t st) {
+  if (bytes > kUploadMaxBytes || (bytes & 3) != 0) return hipErrorInvalidValue;
+  UploadImage u;
+  std::memcpy(u.w, img, bytes);
+  hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(256), 0, st, u, (uint32_t*)dst,
+                     (int)(bytes / 4));
   return hipGetLastError();
 }
 

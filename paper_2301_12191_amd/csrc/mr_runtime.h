@@ -109,9 +109,9 @@ struct BatchLayout {
   size_t jobs, items, rlist, slist, plist, llist, counter, scratch, total;
 };
 BatchLayout batch_layout(const Plan& P);
-// The host image of [0, L.counter) of the layout: descriptors, items, lists
-// (zeros between them).
-void batch_image(const Plan& P, const BatchLayout& L, uint8_t* img);
+// The host image of [0, bytes) of the layout (bytes at least the end of the
+// last list, at most L.counter): descriptors, items, lists, zeros between them.
+void batch_image(const Plan& P, const BatchLayout& L, uint8_t* img, size_t bytes);
 hipError_t batch_upload(const Plan& P, uint8_t* mem, const BatchLayout& L, hipStream_t st);
 PlanLists batch_lists(uint8_t* mem, const BatchLayout& L);
 // prep -> [pad] -> [search] -> [refine] -> [subpel] -> leaf for a bound plan.
@@ -142,6 +142,9 @@ hipError_t launch_refine(const JobDesc* jobs, const int* rlist, int n_rjobs, int
                          int max_r, hipStream_t st);
 hipError_t launch_depth_bounds(const uint8_t* ref_depth, int ref_w, int ref_h, int dep_w,
                                int dep_h, int dlo, int dhi, uint8_t* out, hipStream_t st);
+// Copy of a host image of at most kUploadMaxBytes (a multiple of 4) to `dst`
+// by a kernel that takes it as its argument.
+hipError_t launch_upload(const uint8_t* img, size_t bytes, uint8_t* dst, hipStream_t st);
 // Depth bounds of several dependents (one launch per kMaxBoundsJobs of them).
 hipError_t launch_depth_bounds_batch(const BoundsJob* jobs, int n, hipStream_t st);
 int search_occupancy(int D, int strip, size_t lds_bytes);
