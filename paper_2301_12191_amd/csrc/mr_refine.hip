@@ -40,16 +40,21 @@ __device__ __forceinline__ void align_pairs(const uint32_t (&raw)[NQ + 3], int s
 // candidates, whose block SADs this lane holds as NQ packed quads (16-bit
 // fields k = positions 4q + k) and one 32-bit SAD (position 4 NQ).  The SADs
 // are first summed over aligned groups of 4^(3-d) lanes (d = 3: none; 2: quads;
-// 1: rows of 16; 0: the wavefront) with DPP adds; d is uniform.  For d >= 1
-// every lane of a group receives its sums; for d = 0 the lanes of the last row
-// (48..63) do: after the row sums, row 1 adds row 0 (row_bcast:15 into rows 1
-// and 3) and rows 2 and 3 add lane 31 (row_bcast:31).  A field holds an 8x8
-// SAD (<= 16320) and, after the quad level, a 16x16 SAD (<= 65280): below
-// 2^16, so 32-bit adds on two fields are exact.  Larger CUs are unpacked after
-// the quad level.
+// 1: rows of 16; 0: the wavefront) with DPP adds; d is uniform.  A field holds
+// an 8x8 SAD (<= 16320) and, after the quad level, a 16x16 SAD (<= 65280):
+// below 2^16, so 32-bit adds on two fields are exact.
+// For d <= 1, after the quad level the four lanes of a quad hold the same
+// sums, so they share the candidates out: lane k (= b & 3) takes positions
+// k + 4i (i < NQ) and, if k = 0, position 4 NQ (unpacked to 32 bits, one
+// select and one field extract each), with key terms Kl.  Lanes 4 apart hold
+// the same positions: rotations by 4 and 8 within the row add the row's
+// quads, and for d = 0 the lane-wise swaps of the row pairs and of the halves
+// add the rows.  The quad's minimum then covers every position.  Every lane of
+// a group ends with the group's minimum.
 template <int NQ>
 __device__ __forceinline__ uint32_t row_min_key(uint64_t (&aq)[NQ], uint32_t a8, int d,
-                                                const uint32_t (*Ks)[64], int b) {
+                                                const uint32_t (*Ks)[64], int b,
+                                                const uint32_t (&Kl)[NQ + 1]) {
   constexpr int NP = 4 * NQ + 1;
   uint32_t w[2 * NQ + 1];
 #pragma unroll
@@ -71,28 +76,42 @@ __device__ __forceinline__ uint32_t row_min_key(uint64_t (&aq)[NQ], uint32_t a8,
     }
     m = min(m, (w[2 * NQ] << kRankBitsR) + Ks[4 * NQ][b]);
   } else {
-    uint32_t acc[NP];
+    const bool first = (b & 3) == 0;
+    const uint32_t fsh = (uint32_t)(b & 1) * 16u;
+    uint32_t v[NQ + 1];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      acc[4 * q] = w[2 * q] & 0xFFFFu, acc[4 * q + 1] = w[2 * q] >> 16;
-      acc[4 * q + 2] = w[2 * q + 1] & 0xFFFFu, acc[4 * q + 3] = w[2 * q + 1] >> 16;
+    for (int i = 0; i < NQ; ++i) {
+      // The high dword of the pair for lanes with b & 2 (a lane mask constant):
+      // one v_cndmask (written out, so that the choice stays a select of two
+      // registers instead of an indexed array).
+      uint32_t x;
+      asm("v_cndmask_b32_e64 %0, %1, %2, %3"
+          : "=v"(x)
+          : "v"(w[2 * i]), "v"(w[2 * i + 1]), "s"(0xCCCCCCCCCCCCCCCCull));
+      v[i] = (x >> fsh) & 0xFFFFu;
     }
-    acc[4 * NQ] = w[2 * NQ];
+    v[NQ] = first ? w[2 * NQ] : 0u;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x141>(acc[k]);  // row_half_mirror
+    for (int i = 0; i <= NQ; ++i) v[i] = add_dpp<0x124>(v[i]);  // row_ror:4
 #pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = add_dpp<0x140>(acc[k]);  // row_mirror
+    for (int i = 0; i <= NQ; ++i) v[i] = add_dpp<0x128>(v[i]);  // row_ror:8
     if (d == 0) {
 #pragma unroll
-      for (int k = 0; k < NP; ++k)
-        acc[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)acc[k], 0x142, 0xA, 0xF, false);
+      for (int i = 0; i <= NQ; ++i) {
+        const auto s = __builtin_amdgcn_permlane16_swap(v[i], v[i], false, false);  // rows 0|1, 2|3
+        v[i] = s[0] + s[1];
+      }
 #pragma unroll
-      for (int k = 0; k < NP; ++k)
-        acc[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)acc[k], 0x143, 0xC, 0xF, false);
+      for (int i = 0; i <= NQ; ++i) {
+        const auto s = __builtin_amdgcn_permlane32_swap(v[i], v[i], false, false);  // halves
+        v[i] = s[0] + s[1];
+      }
     }
-    // SAD < 2^21: SAD * 2^9 + Ks stays below 2^32, also past the window.
+    // SAD < 2^21: SAD * 2^9 + Kl stays below 2^32, also past the window.
 #pragma unroll
-    for (int k = 0; k < NP; ++k) m = min(m, (acc[k] << kRankBitsR) + Ks[k][b]);
+    for (int i = 0; i <= NQ; ++i) m = min(m, (v[i] << kRankBitsR) + Kl[i]);
+    m = min(m, dpp_mov<0xB1, 0xF>(m, m));  // quad_perm [1,0,3,2]
+    m = min(m, dpp_mov<0x4E, 0xF>(m, m));  // quad_perm [2,3,0,1]
   }
   return m;
 }
@@ -188,6 +207,17 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
     for (int k = 0; k < NP; ++k)  // window column pass NP + k (valid: 0..2r)
       Ks[k][b] = pass * NP + k < ncand ? kv[k] : 0x80000000u;
   }
+  // For d <= 1, the key terms of this lane's share of the positions (this
+  // lane's own column of Ks; 2^31 for the slot that lanes k != 0 leave empty).
+  uint32_t Kl[NQ + 1];
+  if (d <= 1) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) Kl[i] = Ks[(b & 3) + 4 * i][b];
+    Kl[NQ] = (b & 3) == 0 ? Ks[4 * NQ][b] : 0x80000000u;
+  } else {
+#pragma unroll
+    for (int i = 0; i <= NQ; ++i) Kl[i] = 0;
+  }
   // Window row `row` of this lane: a 32-bit byte offset from the (uniform)
   // padded reference, so that each load is one add and a scalar base.  Rows
   // up to nrow + 7 are read (one past the last band row's ring refill), at
@@ -246,7 +276,7 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
         a8 = __builtin_amdgcn_sad_u8(c[2 * row], (uint32_t)P[sl][NQ], a8);
         a8 = __builtin_amdgcn_sad_u8(c[2 * row + 1], (uint32_t)(P[sl][NQ] >> 32), a8);
       }
-      const uint32_t m = row_min_key<NQ>(aq, a8, d, Ks, b);
+      const uint32_t m = row_min_key<NQ>(aq, a8, d, Ks, b, Kl);
       {
         const uint64_t K = ((uint64_t)(pm >> kRankBitsR) << 33) + pd + pu;
         best = K < best ? K : best;
