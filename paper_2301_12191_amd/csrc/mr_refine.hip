@@ -36,7 +36,7 @@ __device__ __forceinline__ void align_pairs(const uint32_t (&raw)[NQ + 3], int s
   for (int q = 0; q <= NQ; ++q) P[q] = ((uint64_t)e[q + 1] << 32) | e[q];
 }
 
-// The minimum 32-bit key SAD * 2^9 + Ks[k] over a window row's NP = 4 NQ + 1
+// The minimum 32-bit key SAD * 2^9 + Kr[k] over a window row's NP = 4 NQ + 1
 // candidates, whose block SADs this lane holds as NQ packed quads (16-bit
 // fields k = positions 4q + k) and one 32-bit SAD (position 4 NQ).  The SADs
 // are first summed over aligned groups of 4^(3-d) lanes (d = 3: none; 2: quads;
@@ -53,7 +53,7 @@ __device__ __forceinline__ void align_pairs(const uint32_t (&raw)[NQ + 3], int s
 // a group ends with the group's minimum.
 template <int NQ>
 __device__ __forceinline__ uint32_t row_min_key(uint64_t (&aq)[NQ], uint32_t a8, int d,
-                                                const uint32_t (*Ks)[64], int b,
+                                                const uint32_t (&Kr)[4 * NQ + 1], int b,
                                                 const uint32_t (&Kl)[NQ + 1]) {
   constexpr int NP = 4 * NQ + 1;
   uint32_t w[2 * NQ + 1];
@@ -72,9 +72,9 @@ __device__ __forceinline__ uint32_t row_min_key(uint64_t (&aq)[NQ], uint32_t a8,
     for (int q = 0; q < NQ; ++q) {
       const uint64_t v = ((uint64_t)w[2 * q + 1] << 32) | w[2 * q];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) m = min(m, field_mad(v, k, 1u << kRankBitsR, Ks[4 * q + k][b]));
+      for (int k = 0; k < 4; ++k) m = min(m, field_mad(v, k, 1u << kRankBitsR, Kr[4 * q + k]));
     }
-    m = min(m, (w[2 * NQ] << kRankBitsR) + Ks[4 * NQ][b]);
+    m = min(m, (w[2 * NQ] << kRankBitsR) + Kr[4 * NQ]);
   } else {
     const bool first = (b & 3) == 0;
     const uint32_t fsh = (uint32_t)(b & 1) * 16u;
@@ -189,15 +189,17 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   // column at or left of it and its byte in that dword (0..3, per lane).
   const int xs = X0 + cxm - r + jb->pad_x + pass * NP;
   const int shb = xs & 3;
-  // Column key terms, one LDS slot per (position, lane): kept out of the
-  // register file, which the ring of pre-shifted rows fills.
+  // Column key terms of this lane's positions: in registers for the row minima
+  // (Kr), and in LDS (Ks), from where the lanes of a quad take their shares at
+  // d <= 1.
+  uint32_t Kr[NP];
   if (pass * NP + NP <= ncand) {  // uniform: every column of the pass is in the window
     const uint32_t* kp = rk + (cxm - r + pass * NP + R);  // entries 0..2R
     uint32_t kv[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) kv[k] = kp[k];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) Ks[k][b] = kv[k];
+    for (int k = 0; k < NP; ++k) Ks[k][b] = Kr[k] = kv[k];
   } else {
     // All loads first (indices clamped into the table), then the selects.
     uint32_t kv[NP];
@@ -205,7 +207,7 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
     for (int k = 0; k < NP; ++k) kv[k] = rk[min(cxm - r + pass * NP + k + R, 2 * R)];
 #pragma unroll
     for (int k = 0; k < NP; ++k)  // window column pass NP + k (valid: 0..2r)
-      Ks[k][b] = pass * NP + k < ncand ? kv[k] : 0x80000000u;
+      Ks[k][b] = Kr[k] = pass * NP + k < ncand ? kv[k] : 0x80000000u;
   }
   // For d <= 1, the key terms of this lane's share of the positions (this
   // lane's own column of Ks; 2^31 for the slot that lanes k != 0 leave empty).
@@ -238,6 +240,7 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
   uint64_t best = kKeyNone;
   // The previous row's minimum and its table entries.  Before the first row:
   // a key above every real one (< 2^54) and below kKeyNone.
+  uint32_t next_off = off0 + 8u * pitch_u;  // the ring's next row
   uint32_t pm = 0xFFFFFFFFu;
   uint64_t pd = 0, pu = 0;
   for (int g = 0; g < nrow; g += 8) {
@@ -255,7 +258,8 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
       uint32_t nxt[NDW];
       const bool more = t + 1 < nrow;
       {
-        const uint32_t* s = (const uint32_t*)(rp + (off0 + (uint32_t)(t + 8) * pitch_u));
+        const uint32_t* s = (const uint32_t*)(rp + next_off);
+        next_off += pitch_u;
 #pragma unroll
         for (int j = 0; j < NDW; ++j) nxt[j] = s[j];
       }
@@ -276,7 +280,7 @@ __device__ void refine_wave(cjob jb, int ctu, int d, int pass, int band, int nba
         a8 = __builtin_amdgcn_sad_u8(c[2 * row], (uint32_t)P[sl][NQ], a8);
         a8 = __builtin_amdgcn_sad_u8(c[2 * row + 1], (uint32_t)(P[sl][NQ] >> 32), a8);
       }
-      const uint32_t m = row_min_key<NQ>(aq, a8, d, Ks, b, Kl);
+      const uint32_t m = row_min_key<NQ>(aq, a8, d, Kr, b, Kl);
       {
         const uint64_t K = ((uint64_t)(pm >> kRankBitsR) << 33) + pd + pu;
         best = K < best ? K : best;
