@@ -41,6 +41,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sing
                       [--no-dag] [--no-serving] [--serve-seconds S]
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -190,11 +191,17 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
         for f in range(n_frames + 1):
             for i, r in enumerate(rungs):
                 lad.put_frame(stream, f, i, frames[(f, r["width"])])
+        # No collection of the client's garbage inside the timed region: a full collection
+        # of this process's objects takes milliseconds, comparable to several frames.
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         order = [(f, i) for f in range(1, n_frames + 1) for i in range(len(rungs))]
         groups = [order] if pipelined else [[x for x in order if x[0] == f]
                                             for f in range(1, n_frames + 1)]
+        group_ms = []
         for grp in groups:
+            tg = time.perf_counter()
             ids = dict(zip(lad.submit_many([(stream, f, i) for f, i in grp]), grp))
             done, idle, starts = 0, 0, []
             while done < len(ids):
@@ -217,7 +224,9 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
                     rel.append(c.job_id)
                 lad.release_many(rel)
             first_launch.append(min(starts))  # submission -> the group's first launch
+            group_ms.append(round((time.perf_counter() - tg) * 1e3, 3))
         t1 = time.perf_counter()
+        gc.enable()
         st = lad.stats()
         for i, c in held:
             j_dag[i] = int(lad.outputs(c)["cost"].sum().item())
@@ -227,7 +236,8 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
         host = {"batches": nb,
                 "host_ms_per_batch": round((st["host_launch_ms"] - st0["host_launch_ms"]) /
                                            max(1, nb), 4),
-                "submit_to_first_launch_ms": round(sorted(first_launch)[len(first_launch) // 2], 4)}
+                "submit_to_first_launch_ms": round(sorted(first_launch)[len(first_launch) // 2], 4),
+                "group_ms": group_ms}
         return (t1 - t0) * 1e3 / n_frames, j_dag, sorted(lat), host
 
     try:
