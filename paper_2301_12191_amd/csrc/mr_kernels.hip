@@ -135,6 +135,34 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
     }
   }
   if (corner) __syncthreads();
+  // Bounds of every node (min lo, max hi over its 8x8 units), bottom-up: one
+  // load per unit, then three levels of 2x2 in LDS (nodes in raster order per
+  // depth, at 0, 1, 5, 21).  Units outside the coded picture are neutral.
+  __shared__ uint8_t nlo[kNodes], nhi[kNodes];
+  const bool bounded = jb->bounds != nullptr;  // uniform
+  if (bounded) {
+    if (tid < 64) {
+      const int ux = (cx >> 3) + (tid & 7), uy = (cy >> 3) + (tid >> 3), uw = jb->w8 >> 3;
+      uint8_t lo = 3, hi = 0;
+      if (ux < uw && uy < (jb->h8 >> 3)) {
+        const uint8_t* b = jb->bounds + 2 * ((size_t)uy * uw + ux);
+        lo = b[0], hi = b[1];
+      }
+      nlo[21 + tid] = lo, nhi[21 + tid] = hi;
+    }
+#pragma unroll
+    for (int d = 2; d >= 0; --d) {
+      __syncthreads();
+      const int side = 1 << d, first = d == 0 ? 0 : d == 1 ? 1 : 5, child = d == 2 ? 21 : d == 1 ? 5 : 1;
+      if (tid < side * side) {
+        const int lx = tid % side, ly = tid / side, cs = 2 * side;
+        const int c0 = child + 2 * ly * cs + 2 * lx;
+        nlo[first + tid] = min(min(nlo[c0], nlo[c0 + 1]), min(nlo[c0 + cs], nlo[c0 + cs + 1]));
+        nhi[first + tid] = max(max(nhi[c0], nhi[c0 + 1]), max(nhi[c0 + cs], nhi[c0 + cs + 1]));
+      }
+    }
+    __syncthreads();
+  }
   if (tid < kNodes) {
     const int d = tid == 0 ? 0 : tid < 5 ? 1 : tid < 21 ? 2 : 3;
     const int local = tid - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
@@ -144,15 +172,8 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
     bool split_ok = d < 3, leaf_ok = true;
     if (x0 + n <= jb->w8 && y0 + n <= jb->h8) {
       e = 1;
-      if (jb->bounds) {
-        const int uw = jb->w8 >> 3;
-        int min_lo = 3, max_hi = 0;
-        for (int uy = y0 >> 3; uy < (y0 + n) >> 3; ++uy)
-          for (int ux = x0 >> 3; ux < (x0 + n) >> 3; ++ux) {
-            const uint8_t* b = jb->bounds + 2 * ((size_t)uy * uw + ux);
-            min_lo = min(min_lo, (int)b[0]);
-            max_hi = max(max_hi, (int)b[1]);
-          }
+      if (bounded) {
+        const int min_lo = nlo[tid], max_hi = nhi[tid];
         split_ok = d < 3 && d < max_hi;
         leaf_ok = d >= min_lo || !split_ok;
         e = leaf_ok ? 1 : 0;
