@@ -163,14 +163,19 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
     }
     __syncthreads();
   }
+  // Per node thread: its geometry and the bounds rule.
+  int d = 0, lx = 0, ly = 0, n = kCtu, x0 = cx, y0 = cy;
+  uint8_t e = 0;
+  bool split_ok = false, leaf_ok = true;
+  __shared__ uint8_t sok[kNodes];  // may split (a node crossing the picture edge must)
   if (tid < kNodes) {
-    const int d = tid == 0 ? 0 : tid < 5 ? 1 : tid < 21 ? 2 : 3;
+    d = tid == 0 ? 0 : tid < 5 ? 1 : tid < 21 ? 2 : 3;
     const int local = tid - (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21);
-    const int n = kCtu >> d, lx = local % (1 << d), ly = local / (1 << d);
-    const int x0 = cx + lx * n, y0 = cy + ly * n;
-    uint8_t e = 0;
-    bool split_ok = d < 3, leaf_ok = true;
-    if (x0 + n <= jb->w8 && y0 + n <= jb->h8) {
+    n = kCtu >> d, lx = local % (1 << d), ly = local / (1 << d);
+    x0 = cx + lx * n, y0 = cy + ly * n;
+    split_ok = d < 3;
+    const bool inside = x0 + n <= jb->w8 && y0 + n <= jb->h8;
+    if (inside) {
       e = 1;
       if (bounded) {
         const int min_lo = nlo[tid], max_hi = nhi[tid];
@@ -179,6 +184,21 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
         e = leaf_ok ? 1 : 0;
       }
     }
+    if (bounded) sok[tid] = inside ? (split_ok ? 1 : 0) : 1;
+  }
+  if (bounded) {
+    // A node is reached only if every ancestor may split: one below a node
+    // that may not is never part of the partition, so it is not eligible
+    // either (no search key, refinement or SATD for it).
+    __syncthreads();
+    if (tid < kNodes) {
+      for (int a = 0; a < d; ++a) {
+        const int base = a == 0 ? 0 : a == 1 ? 1 : 5;
+        if (!sok[base + (ly >> (d - a)) * (1 << a) + (lx >> (d - a))]) e = 0;
+      }
+    }
+  }
+  if (tid < kNodes) {
     jb->elig[(size_t)ctu * kNodes + tid] = e;
     jb->okbits[(size_t)ctu * kNodes + tid] = (uint8_t)((split_ok ? 1 : 0) | (leaf_ok ? 2 : 0));
     if (jb->seed_mv) {
@@ -1036,7 +1056,9 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       if (k == 1) {
         J = cj, Dd = cd, Rr = cr;
       } else if (k == 2) {
-        const bool split_ok = sh.split_ok[node], leaf_ok = sh.leaf_ok[node];
+        // An inside node that may be a leaf is eligible unless it cannot be
+        // reached (an ancestor may not split); then its value is never used.
+        const bool split_ok = sh.split_ok[node], leaf_ok = sh.leaf_ok[node] && sh.elig[node];
         const int flag = d < 3 ? 1 : 0;
         int64_t lj = INT64_MAX;
         if (leaf_ok) lj = sh.lj[node] + s * flag;
