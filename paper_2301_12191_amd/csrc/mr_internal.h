@@ -139,6 +139,9 @@ struct JobDesc {
   // only.
   uint32_t* intra;
   const uint32_t* intra_src;
+  uint64_t intra_users;    // bit k: job k of the batch takes this job's intra SATDs (bit 63:
+                           // job 63 or later does); the SATDs are computed for the nodes
+                           // eligible in this job or in one of them
   int32_t lctu_start;      // with shared intra SATDs: first CTU of this job among the
                            // CTUs of its leaf launch (jobs taking them, or the others)
   // Sub-pel refinement: per node {quarter-pel MV (qx | qy << 16), SATD}.

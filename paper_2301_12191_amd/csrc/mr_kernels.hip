@@ -543,6 +543,7 @@ struct LeafShared {
   uint8_t cur[64 * 64];
   int16_t refs[kRefTotal];
   int16_t mvx[kNodes], mvy[kNodes];  // integer-pel, or quarter-pel with sub-pel refinement
+  uint8_t need[kNodes];  // intra SATDs wanted by a job that takes this job's
   uint32_t satq[kNodes];             // sub-pel: SATD at the refined MV
   int32_t dc[kNodes];                // DC: sum of the n top and n left neighbours
   int16_t nx0[kNodes], ny0[kNodes];  // node origin in the picture
@@ -671,7 +672,7 @@ __device__ __forceinline__ void inter_rows(cjob jb, int xf, int yf, const us2 (&
 // batch with the same current frame (intra_src): no neighbours, and its inter
 // SATDs two depths at a time ((3, 2) and (1, 0)) in one packed transform.
 template <bool ANG, bool SHARED>
-__device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
+__device__ void leaf_ctu(cjob jobs, cjob jb, int ctu, LeafShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
   const int W8 = jb->w8, H8 = jb->h8;
@@ -696,6 +697,24 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     sh.kind[node] = (x0 >= W8 || y0 >= H8) ? 0 : ((x0 + n > W8 || y0 + n > H8) ? 1 : 2);
     const uint8_t e = jb->elig[(size_t)ctu * kNodes + node];
     sh.elig[node] = e;
+    // A job whose intra SATDs serve other jobs computes them for every inside
+    // node eligible in one of those (same current frame, so same CTU grid).
+    uint8_t nd = 0;
+    if (!SHARED && jb->intra && sh.kind[node] == 2) {
+      const uint64_t users = jb->intra_users;  // uniform
+      if (users >> 63) {
+        nd = 1;
+      } else {
+        for (uint64_t u = users; u; u &= u - 1) {
+          const uint32_t* eb = jobs[__builtin_ctzll(u)].eligbits + (size_t)ctu * 4;
+          if ((eb[node >> 5] >> (node & 31)) & 1u) {
+            nd = 1;
+            break;
+          }
+        }
+      }
+    }
+    sh.need[node] = nd;
     int mx = 0, my = 0;
     uint32_t sq = 0;
     if (e && jb->subpel) {
@@ -742,8 +761,8 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
   // closed form gives each one directly.
   const int stride = jb->stride;
   const bool angular = ANG && jb->angular != 0;  // uniform
-  // A job whose intra SATDs serve other jobs computes them for every node
-  // inside the picture, eligible here or not.
+  // A job whose intra SATDs serve other jobs computes them also for the nodes
+  // eligible in one of those (sh.need), and writes them.
   const bool own = !SHARED && jb->intra != nullptr;  // uniform
   // Planar and DC read p[-1][0..n] and p[0..n][-1] of a node at (x0, y0):
   // with x0, y0 >= 1, x0 + n <= W8 - 1 and y0 + n <= H8 - 1 all of them are
@@ -759,7 +778,7 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
     const int n = kCtu >> d, len = angular ? 4 * n + 1 : 2 * n + 2, tpn = 256 >> (2 * d);
     const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + (tid >> (8 - 2 * d));
     const int j = tid & (tpn - 1);
-    if (sh.elig[node] || (own && sh.kind[node] == 2)) {
+    if (sh.elig[node] || sh.need[node]) {
       const int x0 = sh.nx0[node], y0 = sh.ny0[node], a = sh.na[node], b = sh.nb[node];
       int16_t* R = sh.refs + ref_offset(node);
       int dcs = 0;
@@ -879,7 +898,7 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       const int lx = (tx * 4) >> lg, ly = (ty * 4) >> lg;
       const int node = (d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 5 : 21) + ly * (1 << d) + lx;
       uint32_t v0 = 0, v1 = 0, v2 = 0;
-      if (sh.elig[node] || (own && sh.kind[node] == 2)) {
+      if (sh.elig[node] || sh.need[node]) {
         // Inter residual (zero with sub-pel refinement: that SATD comes from
         // subres) in the low halves, planar residual in the high halves; both
         // first as pairs of a row's samples (irp, prp), then regrouped per
@@ -1014,7 +1033,7 @@ __device__ void leaf_ctu(cjob jb, int ctu, LeafShared& sh) {
       sh.satd[node][1] = is[0], sh.satd[node][2] = is[1];
     } else if (own) {
       uint32_t* io = jb->intra + ((size_t)ctu * kNodes + node) * 2;
-      const bool in = sh.kind[node] == 2;
+      const bool in = sh.need[node] != 0;  // the nodes the other jobs read
       io[0] = in ? sh.satd[node][1] : 0u, io[1] = in ? sh.satd[node][2] : 0u;
     }
   }
@@ -1322,7 +1341,7 @@ __global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, const i
     j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, flat));
     ctu = flat - jobs[j].ctu_start;
   }
-  leaf_ctu<ANG, SHARED>(jobs + j, ctu, sh);
+  leaf_ctu<ANG, SHARED>(jobs, jobs + j, ctu, sh);
 }
 
 hipError_t launch_store_job(const JobDesc& jb, JobDesc* dst, hipStream_t st) {

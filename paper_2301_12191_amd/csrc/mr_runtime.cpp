@@ -592,8 +592,11 @@ void bind_scratch(Plan& P, uint8_t* base) {
     sp += up256((size_t)n_ctus * kNodes);
     jb.intra = nullptr;
     jb.intra_src = nullptr;
+    jb.intra_users = 0;  // owners come first: set below by the jobs that take theirs
     if (P.intra_owner[j] >= 0) {
-      jb.intra_src = P.jobs[P.intra_owner[j]].intra;  // owners come first
+      JobDesc& ow = P.jobs[P.intra_owner[j]];
+      jb.intra_src = ow.intra;
+      ow.intra_users |= 1ull << std::min(j, 63);
     } else if (P.intra_owned[j]) {
       jb.intra = (uint32_t*)sp;
       sp += up256((size_t)n_ctus * kNodes * 8);
