@@ -200,9 +200,16 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
         groups = [order] if pipelined else [[x for x in order if x[0] == f]
                                             for f in range(1, n_frames + 1)]
         group_ms = []
-        for grp in groups:
+        # The group's jobs as the server takes them, built before the previous group ends;
+        # the previous group's last completions are released after this submission.
+        subs = [[(stream, f, i) for f, i in grp] for grp in groups]
+        pending = []
+        for g, grp in enumerate(groups):
             tg = time.perf_counter()
-            ids = dict(zip(lad.submit_many([(stream, f, i) for f, i in grp]), grp))
+            ids = dict(zip(lad.submit_many(subs[g]), grp))
+            if pending:
+                lad.release_many(pending)
+                pending = []
             done, idle, starts = 0, 0, []
             while done < len(ids):
                 got = lad.poll(64, 200000)
@@ -222,11 +229,15 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
                             held.append((i, c))
                             continue
                     rel.append(c.job_id)
-                lad.release_many(rel)
+                if done < len(ids):
+                    lad.release_many(rel)
+                else:
+                    pending = rel
             first_launch.append(min(starts))  # submission -> the group's first launch
             group_ms.append(round((time.perf_counter() - tg) * 1e3, 3))
         t1 = time.perf_counter()
         gc.enable()
+        lad.release_many(pending)
         st = lad.stats()
         for i, c in held:
             j_dag[i] = int(lad.outputs(c)["cost"].sum().item())
