@@ -112,6 +112,9 @@ struct JobDesc {
   int32_t pack_cur;        // 1: the prep kernel packs curpack; 0: another job of the
                            // batch with the same current frame does (shared copy)
   int32_t pad_rows;        // 1: the pad kernel copies refpad's rows; 0: shared copy
+  int32_t pad_row_start;   // first of this job's rows among the pad kernel's row blocks
+                           // (the padding jobs' rows in job-list order; a job that pads
+                           // nothing has the next padding job's start)
   uint64_t* keys;          // [ctus][85] arg-min keys J_me * 2^17 + candidate index
   const uint32_t* qtab;    // [steps][64 lanes][4D]
   const uint64_t* dtab;    // [steps][2048]

@@ -354,45 +354,52 @@ __device__ void build_refine_tables(cjob jb) {
   __syncthreads();
 }
 
-// Padded reference of every job that has one (seeded or sub-pel): jobs in y,
-// rows of each job's [h8 + 2 pad_y][pad_pitch] bytes grid-strided over blocks
-// 1.. in x, and 8-byte pieces of a row over the threads (pad_pitch is a
-// multiple of 8); a job whose reference another job of the batch pads (same
-// frame and margins) shares that copy.  Block 0 builds the seeded jobs' key
-// tables.
+// Padded reference of every job that has one (seeded or sub-pel): blocks
+// 0 .. n_pjobs - 1 build the seeded jobs' key tables; then one block per row of
+// each job's [h8 + 2 pad_y][pad_pitch] bytes, for the jobs that copy their
+// reference (a job whose reference another job of the batch pads, same frame
+// and margins, shares that copy and has no blocks), with 8-byte pieces of the
+// row over the threads (pad_pitch is a multiple of 8).
 __global__ __launch_bounds__(256) void pad_kernel(const JobDesc* jobs_, const int* plist,
                                                   int n_pjobs) {
-  for (int k = blockIdx.y; k < n_pjobs; k += gridDim.y) {
-    const cjob jb = (cjob)jobs_ + (plist ? plist[k] : 0);
-    if (blockIdx.x == 0) {  // the first block to start builds the key tables
-      if (jb->seed_mv) build_refine_tables(jb);
-      continue;
-    }
-    if (!jb->pad_rows) continue;  // another job of the batch pads the same frame
-    const int PY = jb->pad_y, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
-    const int pitch = jb->pad_pitch, rows = jb->h8 + 2 * PY, pieces = pitch >> 3;
-    const uint8_t* ref = jb->ref;
-    const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0);
-    for (int row = blockIdx.x - 1; row < rows; row += gridDim.x - 1) {
-      const uint8_t* rp = ref + (size_t)clampi(row - PY, 0, h - 1) * stride;
-      uint2* dst = (uint2*)(jb->refpad + (size_t)row * pitch);
-      for (int c = threadIdx.x; c < pieces; c += blockDim.x) {
-        uint32_t v[2];
+  const cjob jobs = (cjob)jobs_;
+  const int b = blockIdx.x;
+  if (b < n_pjobs) {  // the first blocks to start build the key tables
+    const cjob jb = jobs + (plist ? plist[b] : 0);
+    if (jb->seed_mv) build_refine_tables(jb);
+    return;
+  }
+  // Row block r: the padding job whose rows hold r (the last in list order
+  // whose first row is at most r: one that pads nothing has the next one's).
+  const int r = b - n_pjobs;
+  int lo = 0, hi = n_pjobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[plist ? plist[mid] : 0].pad_row_start <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  const cjob jb = jobs + (plist ? plist[lo] : 0);
+  const int PY = jb->pad_y, w = jb->w, h = jb->h, stride = jb->stride, P = jb->pad_x;
+  const int pitch = jb->pad_pitch, pieces = pitch >> 3, row = r - jb->pad_row_start;
+  const uint8_t* ref = jb->ref;
+  const bool dword_ok = ((stride & 3) == 0) && ((((uintptr_t)ref) & 3) == 0);
+  const uint8_t* rp = ref + (size_t)clampi(row - PY, 0, h - 1) * stride;
+  uint2* dst = (uint2*)(jb->refpad + (size_t)row * pitch);
+  for (int c = threadIdx.x; c < pieces; c += blockDim.x) {
+    uint32_t v[2];
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          const int x = 8 * c + 4 * half - P;
-          if (dword_ok && x >= 0 && x + 3 < w) {
-            v[half] = *(const uint32_t*)(rp + x);
-          } else {
-            uint32_t u = 0;
+    for (int half = 0; half < 2; ++half) {
+      const int x = 8 * c + 4 * half - P;
+      if (dword_ok && x >= 0 && x + 3 < w) {
+        v[half] = *(const uint32_t*)(rp + x);
+      } else {
+        uint32_t u = 0;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) u |= (uint32_t)rp[clampi(x + b, 0, w - 1)] << (8 * b);
-            v[half] = u;
-          }
-        }
-        dst[c] = make_uint2(v[0], v[1]);
+        for (int k = 0; k < 4; ++k) u |= (uint32_t)rp[clampi(x + k, 0, w - 1)] << (8 * k);
+        v[half] = u;
       }
     }
+    dst[c] = make_uint2(v[0], v[1]);
   }
 }
 
@@ -440,11 +447,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void re
   refine_body<2>(jobs_, rlist, n_rjobs, n_rctus);
 }
 
-hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int max_rows,
+hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int total_rows,
                       hipStream_t st) {
-  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)std::max(1, std::min(max_rows, 65534)) + 1,
-                                      (unsigned)std::min(n_pjobs, 65535)),
-                     dim3(256), 0, st, jobs, plist, n_pjobs);
+  if (n_pjobs < 1 || total_rows < 0 || (int64_t)n_pjobs + total_rows > INT32_MAX)
+    return hipErrorInvalidValue;
+  // One block per job (its key tables), then one per padded row of every job
+  // that copies its reference.
+  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)(n_pjobs + total_rows)), dim3(256), 0, st, jobs,
+                     plist, n_pjobs);
   return hipGetLastError();
 }
 

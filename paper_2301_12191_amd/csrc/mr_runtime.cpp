@@ -364,7 +364,7 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
   P->plist.clear();
   P->n_rjobs = P->n_rctus = P->max_r = 0;
   P->n_sjobs = P->n_sctus = 0;
-  P->max_pad_rows = 0;
+  P->pad_rows_total = 0;
   P->any_angular = false;
   P->n_ctus = 0;
   P->scratch_bytes = 0;
@@ -437,7 +437,8 @@ int make_plan(const mr_frame* const* cur, const mr_frame* const* ref,
       jb.pad_rows = P->pad_owner[j] < 0 ? 1 : 0;
       const int64_t pad_bytes = (int64_t)(jb.h8 + 2 * jb.pad_y) * jb.pad_pitch;
       if (jb.pad_rows) P->scratch_bytes += up256((size_t)pad_bytes);
-      P->max_pad_rows = std::max(P->max_pad_rows, jb.h8 + 2 * jb.pad_y);
+      jb.pad_row_start = P->pad_rows_total;
+      if (jb.pad_rows) P->pad_rows_total += jb.h8 + 2 * jb.pad_y;
       P->plist.push_back(j);
     }
     if (seed_of(j)) {
@@ -625,7 +626,7 @@ hipError_t launch_plan(const Plan& P, JobDesc* jobs_d, const uint2* items_d, con
   hipError_t e = launch_prep(jobs_d, P.n_jobs, P.n_ctus, counter, st);
   if (ev) profile_mark(ev, 1, st);
   if (e == hipSuccess && !P.plist.empty())
-    e = launch_pad(jobs_d, L.plist, (int)P.plist.size(), P.max_pad_rows, st);
+    e = launch_pad(jobs_d, L.plist, (int)P.plist.size(), P.pad_rows_total, st);
   if (e == hipSuccess && P.n_items > 0)
     e = launch_search(jobs_d, items_d, P.qoff, P.D, P.strip, P.n_wg, P.lds_bytes, counter, st);
   if (e == hipSuccess && P.n_rjobs > 0)

@@ -79,7 +79,7 @@ struct Plan {
   std::vector<int> rlist, slist, plist;
   int n_rjobs = 0, n_rctus = 0, max_r = 0;
   int n_sjobs = 0, n_sctus = 0;
-  int max_pad_rows = 0;  // rows of the largest padded reference
+  int pad_rows_total = 0;  // rows of all padded references the batch copies
   bool any_angular = false;  // some job scores the angular intra modes
   QueueOffsets qoff{};   // search items of each per-XCD queue
   // Input to make_plan: true leaves the jobs' key tables (qtab, dtab) null
@@ -134,7 +134,7 @@ hipError_t launch_search(const JobDesc* jobs, const uint2* items, const QueueOff
 hipError_t launch_leaf(const JobDesc* jobs, int n_jobs, int n_ctus, bool angular,
                        const int* llist, int n_ljobs0, int n_lctus0, int n_lctus1,
                        hipStream_t st);
-hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int max_rows,
+hipError_t launch_pad(const JobDesc* jobs, const int* plist, int n_pjobs, int total_rows,
                       hipStream_t st);
 hipError_t launch_subpel(const JobDesc* jobs, const int* slist, int n_sjobs, int n_sctus,
                          hipStream_t st);
