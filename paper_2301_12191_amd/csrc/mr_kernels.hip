@@ -698,23 +698,22 @@ __device__ void leaf_ctu(cjob jobs, cjob jb, int ctu, LeafShared& sh) {
     const uint8_t e = jb->elig[(size_t)ctu * kNodes + node];
     sh.elig[node] = e;
     // A job whose intra SATDs serve other jobs computes them for every inside
-    // node eligible in one of those (same current frame, so same CTU grid).
-    uint8_t nd = 0;
-    if (!SHARED && jb->intra && sh.kind[node] == 2) {
+    // node eligible in one of those (same current frame, so same CTU grid):
+    // the union of their eligibility masks, read with scalar loads.
+    uint32_t nw[3] = {0u, 0u, 0u};
+    if (!SHARED && jb->intra) {
       const uint64_t users = jb->intra_users;  // uniform
       if (users >> 63) {
-        nd = 1;
+        nw[0] = nw[1] = nw[2] = 0xFFFFFFFFu;
       } else {
         for (uint64_t u = users; u; u &= u - 1) {
-          const uint32_t* eb = jobs[__builtin_ctzll(u)].eligbits + (size_t)ctu * 4;
-          if ((eb[node >> 5] >> (node & 31)) & 1u) {
-            nd = 1;
-            break;
-          }
+          const sptr32 eb = (sptr32)(jobs[__builtin_ctzll(u)].eligbits + (size_t)ctu * 4);
+          nw[0] |= eb[0], nw[1] |= eb[1], nw[2] |= eb[2];
         }
       }
     }
-    sh.need[node] = nd;
+    const uint32_t word = node < 32 ? nw[0] : node < 64 ? nw[1] : nw[2];
+    sh.need[node] = sh.kind[node] == 2 && ((word >> (node & 31)) & 1u);
     int mx = 0, my = 0;
     uint32_t sq = 0;
     if (e && jb->subpel) {
@@ -1053,6 +1052,10 @@ __device__ void leaf_ctu(cjob jobs, cjob jb, int ctu, LeafShared& sh) {
     if (angular && sh.angj[node] < j)
       j = sh.angj[node], dd = sh.angd[node], rr = sh.angm[node] == 27 ? 4 : 7, m = sh.angm[node];
     sh.lj[node] = j, sh.ld[node] = dd, sh.lr[node] = rr, sh.mode[node] = m;
+  } else if (tid < kNodes) {
+    // Not eligible: below a node that may not split when it may still be a
+    // leaf by the bounds (its value is never used), so any finite value.
+    sh.lj[tid] = 0, sh.ld[tid] = 0, sh.lr[tid] = 0, sh.mode[tid] = 0;
   }
   __syncthreads();
   // Bottom-up decision, one depth level at a time.
@@ -1077,7 +1080,7 @@ __device__ void leaf_ctu(cjob jobs, cjob jb, int ctu, LeafShared& sh) {
       } else if (k == 2) {
         // An inside node that may be a leaf is eligible unless it cannot be
         // reached (an ancestor may not split); then its value is never used.
-        const bool split_ok = sh.split_ok[node], leaf_ok = sh.leaf_ok[node] && sh.elig[node];
+        const bool split_ok = sh.split_ok[node], leaf_ok = sh.leaf_ok[node];
         const int flag = d < 3 ? 1 : 0;
         int64_t lj = INT64_MAX;
         if (leaf_ok) lj = sh.lj[node] + s * flag;
@@ -1325,7 +1328,9 @@ __device__ int find_ljob(cjob jobs, const int* list, int n, int flat) {
 // jobs share intra SATDs, two launches with lists of their own: SHARED = false
 // over the jobs that take none (those whose SATDs are shared write them),
 // SHARED = true over the others.  Each launch deals its own CTUs evenly to the
-// XCDs.
+// XCDs.  At least four wavefronts per SIMD (at most 128 VGPRs): left free, the
+// compiler gives the angular form anything from 106 to 226 registers as the
+// code around it changes, and at 226 only two workgroups fit a CU.
 template <bool ANG, bool SHARED>
 __global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, const int* list,
                                                    int n_jobs, int n_ctus) {
