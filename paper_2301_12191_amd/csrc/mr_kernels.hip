@@ -77,7 +77,9 @@ __device__ __forceinline__ uint32_t set_lane(uint32_t v, uint32_t u, int l) {
 }
 
 // ---------------------------------------------------------------------------------- prep
-// One workgroup (256 threads) per CTU.
+// One workgroup of kPrepThreads threads per CTU: enough for its 85 nodes, and
+// small, so that many fit a CU (each is mostly load latency and barriers).
+constexpr int kPrepThreads = 128;
 __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
   const int tid = threadIdx.x;
   const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
@@ -89,7 +91,7 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
     __syncthreads();
   }
   // 64 blocks x 16 dwords (row r, half c of block bz at dword bz * 16 + 2r + c).
-  // Thread t reads dword t & 15 of CTU rows (t >> 4) + 16 i, i = 0..3, so a
+  // Thread t reads dword t & 15 of CTU rows (t >> 4) + 8 i, i = 0..7, so a
   // wavefront reads 4 whole CTU rows: plain dword loads when the frame is
   // dword-aligned and the CTU lies inside it, else clamped byte loads.  A job
   // that shares another job's packed copy only reads, for the corner SADs.
@@ -102,8 +104,8 @@ __device__ void prep_ctu(cjob jb, int ctu, uint32_t* csad) {
     const bool fast = ((jb->stride & 3) == 0) && ((((uintptr_t)jb->cur) & 3) == 0) &&
                       cx + 64 <= jb->w && cy + 64 <= jb->h;  // uniform
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ry = (tid >> 4) + 16 * i;
+    for (int i = 0; i < 64 / (kPrepThreads / 16); ++i) {
+      const int ry = (tid >> 4) + (kPrepThreads / 16) * i;
       uint32_t v;
       if (fast) {
         v = *(const uint32_t*)(jb->cur + (uint32_t)((cy + ry) * jb->stride + x0));
@@ -1179,7 +1181,7 @@ __global__ void store_job_kernel(JobDesc jb, JobDesc* dst) {
   if (threadIdx.x == 0) *dst = jb;
 }
 
-__global__ __launch_bounds__(256) void prep_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus,
+__global__ __launch_bounds__(kPrepThreads) void prep_kernel(const JobDesc* jobs_, int n_jobs, int n_ctus,
                                                    uint32_t* counter) {
   const cjob jobs = (cjob)jobs_;
   const int flat = xcd_contiguous_index();
@@ -1356,7 +1358,8 @@ hipError_t launch_store_job(const JobDesc& jb, JobDesc* dst, hipStream_t st) {
 
 hipError_t launch_prep(const JobDesc* jobs, int n_jobs, int n_ctus, uint32_t* counter,
                        hipStream_t st) {
-  hipLaunchKernelGGL(prep_kernel, dim3(n_ctus), dim3(256), 0, st, jobs, n_jobs, n_ctus, counter);
+  hipLaunchKernelGGL(prep_kernel, dim3(n_ctus), dim3(kPrepThreads), 0, st, jobs, n_jobs, n_ctus,
+                     counter);
   return hipGetLastError();
 }
 
