@@ -541,6 +541,10 @@ __device__ __forceinline__ int ref_offset(int node) {
 }
 constexpr int kRefTotal = 257 + 4 * 129 + 16 * 65 + 64 * 33;  // 3925
 
+// The angular arrays exist only in the angular form: without them the
+// workgroup's LDS is 19.4 KB, so 8 workgroups fit a CU's 160 KB (7 with them),
+// and a 2160p frame's 2040 CTUs run in one round.
+template <bool ANG>
 struct LeafShared {
   uint8_t cur[64 * 64];
   int16_t refs[kRefTotal];
@@ -561,10 +565,10 @@ struct LeafShared {
   uint8_t split_ok[kNodes], leaf_ok[kNodes];
   // Angular modes: per node the best (J, SATD, mode code); node 0's per-mode
   // SATDs arrive as per-wave partial sums.
-  int64_t angj[kNodes];
-  uint32_t angd[kNodes];
-  uint8_t angm[kNodes];
-  uint32_t ang0[4][33];
+  int64_t angj[ANG ? kNodes : 1];
+  uint32_t angd[ANG ? kNodes : 1];
+  uint8_t angm[ANG ? kNodes : 1];
+  uint32_t ang0[4][ANG ? 33 : 1];
 };
 
 // H.265 intraPredAngle of intra modes 2..34 (index = mode) and, for the
@@ -674,7 +678,7 @@ __device__ __forceinline__ void inter_rows(cjob jb, int xf, int yf, const us2 (&
 // batch with the same current frame (intra_src): no neighbours, and its inter
 // SATDs two depths at a time ((3, 2) and (1, 0)) in one packed transform.
 template <bool ANG, bool SHARED>
-__device__ void leaf_ctu(cjob jobs, cjob jb, int ctu, LeafShared& sh) {
+__device__ void leaf_ctu(cjob jobs, cjob jb, int ctu, LeafShared<ANG>& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cx = (ctu % jb->ctus_w) * kCtu, cy = (ctu / jb->ctus_w) * kCtu;
   const int W8 = jb->w8, H8 = jb->h8;
@@ -1336,7 +1340,7 @@ __device__ int find_ljob(cjob jobs, const int* list, int n, int flat) {
 template <bool ANG, bool SHARED>
 __global__ __launch_bounds__(256) void leaf_kernel(const JobDesc* jobs_, const int* list,
                                                    int n_jobs, int n_ctus) {
-  __shared__ LeafShared sh;
+  __shared__ LeafShared<ANG> sh;
   const cjob jobs = (cjob)jobs_;
   const int flat = xcd_contiguous_index();
   if (flat >= n_ctus) return;

@@ -18,11 +18,12 @@ from paper_2301_12191_amd import build as B
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# (source, kernel symbol pattern, max VGPRs, max scratch bytes per lane)
+# (source, kernel symbol pattern, max VGPRs, max scratch bytes per lane[, max LDS bytes])
 BUDGETS = [
     ("mr_kernels.hip", r"leaf_kernelILb1ELb0E", 128, 0),   # angular leaf: 4 waves/SIMD
-    ("mr_kernels.hip", r"leaf_kernelILb0ELb0E", 64, 0),    # leaf: 8 waves/SIMD
-    ("mr_kernels.hip", r"leaf_kernelILb0ELb1E", 64, 0),
+    # leaf: 8 waves/SIMD and 8 workgroups of 256 threads per CU (160 KB of LDS / 8)
+    ("mr_kernels.hip", r"leaf_kernelILb0ELb0E", 64, 0, 20480),
+    ("mr_kernels.hip", r"leaf_kernelILb0ELb1E", 64, 0, 20480),
     ("mr_kernels.hip", r"prep_kernel", 64, 0),
     ("mr_kernels.hip", r"search_kernel_d8", 256, 0),       # D = 8: 2 waves/SIMD
     ("mr_kernels.hip", r"search_kernelILi4E", 168, 0),     # D = 4: 3 waves/SIMD
@@ -46,8 +47,9 @@ def _metadata(src, tmp_path):
         name = re.search(r"\.name:\s+(\S+)", block)
         vgpr = re.search(r"\.vgpr_count:\s+(\d+)", block)
         priv = re.search(r"\.private_segment_fixed_size:\s+(\d+)", block)
-        if name and vgpr and priv:
-            kernels[name.group(1)] = (int(vgpr.group(1)), int(priv.group(1)))
+        lds = re.search(r"\.group_segment_fixed_size:\s+(\d+)", block)
+        if name and vgpr and priv and lds:
+            kernels[name.group(1)] = (int(vgpr.group(1)), int(priv.group(1)), int(lds.group(1)))
     return kernels
 
 
@@ -57,11 +59,11 @@ def test_kernel_register_budgets(tmp_path):
     for src in sorted({b[0] for b in BUDGETS}):
         meta[src] = _metadata(src, tmp_path)
     failures = []
-    for src, pat, max_vgpr, max_priv in BUDGETS:
+    for src, pat, max_vgpr, max_priv, *max_lds in BUDGETS:
         hits = [(k, v) for k, v in meta[src].items() if re.search(pat, k)]
         assert hits, f"{pat}: no kernel in {src}"
-        for k, (vgpr, priv) in hits:
-            if vgpr > max_vgpr or priv > max_priv:
+        for k, (vgpr, priv, lds) in hits:
+            if vgpr > max_vgpr or priv > max_priv or (max_lds and lds > max_lds[0]):
                 failures.append(f"{k}: {vgpr} VGPRs (budget {max_vgpr}), "
-                                f"{priv} scratch bytes (budget {max_priv})")
+                                f"{priv} scratch bytes (budget {max_priv}), {lds} LDS bytes")
     assert not failures, "\n".join(failures)
