@@ -392,18 +392,25 @@ __device__ void search_wave(cjob jb, int ctu, int band, int st_lo, int st_hi, co
         for (int j = 0; j < D; ++j) acq[j] = 0;
         const uint32_t *c0 = cb[2 * (sub & 1)], *c1 = cb[2 * (sub & 1) + 1],
                        *c2 = cb[2 * (sub & 1) + 2];
+        // The middle dword is loaded twice, once into each register pair
+        // ((d1:d0) and (d2:d1) must each be an aligned pair): a second LDS read
+        // instead of a v_mov per row.  c1b is c1 through an opaque zero, so
+        // that the two loads are not merged.
+        uint32_t zero = 0;
+        asm volatile("" : "+v"(zero));
+        const uint32_t* c1b = c1 + zero;
         const int r0 = 8 * (sub >> 1);
         // Window rows are loaded one row ahead of their use, so each row's LDS
         // latency overlaps the previous row's SADs.
-        uint32_t n0 = c0[r0], n1 = c1[r0], n2 = c2[r0];
+        uint32_t n0 = c0[r0], n1 = c1[r0], n1b = c1b[r0], n2 = c2[r0];
 #pragma unroll
         for (int w = 0; w < D + 7; ++w) {
-          const uint32_t d0 = n0, d1 = n1, d2 = n2;
+          const uint32_t d0 = n0, d1 = n1, d1b = n1b, d2 = n2;
           if (w + 1 < D + 7) {
-            n0 = c0[r0 + w + 1], n1 = c1[r0 + w + 1], n2 = c2[r0 + w + 1];
+            n0 = c0[r0 + w + 1], n1 = c1[r0 + w + 1], n1b = c1b[r0 + w + 1], n2 = c2[r0 + w + 1];
           }
           __builtin_amdgcn_sched_barrier(0);
-          const uint64_t p0 = ((uint64_t)d1 << 32) | d0, p1 = ((uint64_t)d2 << 32) | d1;
+          const uint64_t p0 = ((uint64_t)d1 << 32) | d0, p1 = ((uint64_t)d2 << 32) | d1b;
 #pragma unroll
           for (int j = 0; j < D; ++j) {
             const int r = w - j;
