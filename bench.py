@@ -202,7 +202,7 @@ def run_dag(mr, synth, torch, dev, n_frames=4):
         group_ms = []
         # The group's jobs as the server takes them, built before the previous group ends;
         # the previous group's last completions are released after this submission.
-        subs = [[(stream, f, i) for f, i in grp] for grp in groups]
+        subs = [lad.prepare([(stream, f, i) for f, i in grp]) for grp in groups]
         pending = []
         for g, grp in enumerate(groups):
             tg = time.perf_counter()

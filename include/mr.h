@@ -247,8 +247,9 @@ int mr_batch_destroy(mr_batch* b);
  * reference job fails, the dependent fails with MR_EDEPEND.  Submitting
  * a dependent whose reference job does not exist creates it (an implied job)
  * if the reference rung's frames are resident, else fails with MR_EDEPEND.
- * A request loop (one host thread, two device streams of default priority)
- * admits ready jobs in arrival order while their device footprint (scratch +
+ * A request loop (one host thread, two device streams of default priority;
+ * for 300 us after any activity it polls without sleeping, so it occupies a
+ * CPU core while jobs flow and sleeps once they stop) admits ready jobs in arrival order while their device footprint (scratch +
  * outputs + bounds) fits hbm_budget_bytes and fewer than max_inflight jobs
  * run, batches up to max_batch_jobs of them into one persistent search launch,
  * keeps up to four batches in flight, and releases dependents as references
@@ -257,7 +258,9 @@ int mr_batch_destroy(mr_batch* b);
  * are kept for reuse by later jobs of the same size, outside the admission
  * budget but capped at a quarter of it (at most 512 MiB; mr_ladder_stats
  * reports them), until mr_ladder_close; a device allocation that fails first
- * empties that cache and retries.  With reuse_mv, a dependent's search is
+ * empties that cache and retries.  Device memory comes from the server's own
+ * stream-ordered pool, which keeps up to hbm_budget_bytes mapped when blocks
+ * are freed (destroyed by mr_ladder_close).  With reuse_mv, a dependent's search is
  * also seeded with its reference job's MV map.  Each rung may carry
  * its own policy (own_policy), so that one configuration holds both
  * cross-resolution and same-resolution (multi-QP) edges, e.g. the
@@ -360,7 +363,8 @@ int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id);
 int mr_ladder_submit_many(mr_ladder* l, const mr_job* jobs, int32_t n, uint64_t* job_ids,
                           int32_t* n_submitted);
 /* Up to max completions, waiting up to timeout_us for the first one
- * (0 = do not wait).  MR_ETIMEOUT if none arrived. */
+ * (0 = do not wait; the first 300 us of a wait spin, the rest sleep).
+ * MR_ETIMEOUT if none arrived. */
 int mr_ladder_poll(mr_ladder* l, mr_completion* out, int32_t max, int32_t timeout_us,
                    int32_t* n_out);
 /* Cancel a job that has not been launched yet (waiting for its reference,

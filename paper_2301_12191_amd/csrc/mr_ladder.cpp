@@ -72,6 +72,23 @@ class GpuExecutor : public Executor {
     if (hipGetDevice(&device_) != hipSuccess) return MR_EHIP;
     for (auto& s : streams_)
       if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return MR_EHIP;
+    // The server's own stream-ordered pool, which keeps the memory it has
+    // mapped (up to the budget) when blocks are freed.  The device's default
+    // pool returns freed memory at every synchronisation, and mapping a large
+    // block anew takes ~150 us, inside a launch on the serving path.
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device_;
+    if (hipMemPoolCreate(&mp_, &props) != hipSuccess) {
+      mp_ = nullptr;
+      return MR_EHIP;
+    }
+    uint64_t keep = cfg_.budget_bytes;
+    if (hipMemPoolSetAttribute(mp_, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess)
+      return MR_EHIP;
     return MR_OK;
   }
 
@@ -87,6 +104,9 @@ class GpuExecutor : public Executor {
         (void)hipStreamDestroy(s);
       }
     for (hipEvent_t ev : events_) (void)hipEventDestroy(ev);
+    // Every block has been freed and its stream synchronised (the ladder frees
+    // the jobs' outputs before it deletes the executor).
+    if (mp_) (void)hipMemPoolDestroy(mp_);
   }
 
   int device() const { return device_; }
@@ -235,8 +255,10 @@ class GpuExecutor : public Executor {
     std::vector<const mr_search_params*> pp(n);
     std::vector<const mr_search_out*> po(n);
     for (int i = 0; i < n; ++i) pc[i] = &cur[i], pr[i] = &ref[i], pp[i] = &prm[i], po[i] = &outs[i];
+    // A batch of one job leaves its search items implicit (the kernel derives
+    // them from the job): less to plan and a smaller upload.
     Plan P;
-    int rc = make_plan(pc.data(), pr.data(), pp.data(), bnd.data(), po.data(), ps.data(), n, true,
+    int rc = make_plan(pc.data(), pr.data(), pp.data(), bnd.data(), po.data(), ps.data(), n, n > 1,
                        &P);
     if (rc != MR_OK) return rc;
     const BatchLayout L = batch_layout(P);
@@ -250,7 +272,8 @@ class GpuExecutor : public Executor {
     bind_scratch(P, mem + L.scratch);
     hipError_t e = batch_upload(P, mem, L, st);
     if (e == hipSuccess)
-      e = launch_plan(P, (JobDesc*)(mem + L.jobs), (const uint2*)(mem + L.items),
+      e = launch_plan(P, (JobDesc*)(mem + L.jobs),
+                      P.items.empty() ? nullptr : (const uint2*)(mem + L.items),
                       batch_lists(mem, L), (uint32_t*)(mem + L.counter), st, nullptr);
     hipEvent_t ev = nullptr;
     if (!events_.empty()) {
@@ -338,7 +361,7 @@ class GpuExecutor : public Executor {
   // and it is tried once more.
   bool alloc(uint8_t** p, size_t bytes, hipStream_t st) {
     ++allocs_;
-    if (hipMallocAsync((void**)p, bytes, st) == hipSuccess) return true;
+    if (hipMallocFromPoolAsync((void**)p, bytes, mp_, st) == hipSuccess) return true;
     (void)hipGetLastError();
     if (pool_.empty() && scratch_free_.empty()) return false;
     for (auto& kv : pool_) (void)hipFreeAsync(kv.second, st);
@@ -346,7 +369,7 @@ class GpuExecutor : public Executor {
     pool_.clear();
     scratch_free_.clear();
     pool_bytes_ = scratch_free_bytes_ = 0;
-    return hipMallocAsync((void**)p, bytes, st) == hipSuccess;
+    return hipMallocFromPoolAsync((void**)p, bytes, mp_, st) == hipSuccess;
   }
   // A cached scratch block of at least `bytes` (and at most twice that), or null.
   uint8_t* take_scratch(size_t bytes, size_t* got) {
@@ -368,6 +391,7 @@ class GpuExecutor : public Executor {
     return m;
   }
 
+  hipMemPool_t mp_ = nullptr;
   static constexpr size_t kPoolMaxBytes = size_t(512) << 20;
   std::multimap<size_t, uint8_t*> pool_;  // retired output blocks by size
   size_t pool_max_ = 0;  // cache cap (outputs and scratch): a quarter of the budget, <= 512 MiB
@@ -394,25 +418,55 @@ struct mr_ladder {
   std::thread worker;
   std::atomic<bool> stop{false};
   bool closed = false;
+  // Raised (under mu) by every call that may give the loop work (submissions,
+  // cancels, releases) and by the loop when it publishes completions: the
+  // spinning loop and pollers watch them without the lock.
+  std::atomic<uint64_t> work_seq{0}, done_seq{0};
 };
+
+// After any activity (a launch, a completion, a call that may give work) the
+// loop polls without sleeping for this long, and a poll call spins this long
+// for a completion before it blocks: a sleeping thread takes 10-20 us to wake,
+// which at a frame boundary (client sees the last completion, submits the next
+// frame, the loop launches it) is paid twice with the device idle.  Beyond the
+// window the loop sleeps in 5 us steps while batches run, 5 ms when idle.
+constexpr auto kSpinWindow = std::chrono::microseconds(300);
 
 static void ladder_loop(mr_ladder* l) {
   (void)hipSetDevice(l->ex->device());
-  // While work is queued or running the loop steps every 5 us, and a
-  // submission wakes it at once (it waits on cv_work, which the submit calls
-  // signal): a batch's completion is seen within a few us and a new frame's
-  // jobs are planned as soon as they arrive.  With Linux's default 50 us
-  // timer slack each wait would last ten times that; 1 us of slack for this
-  // thread.
+  // With Linux's default 50 us timer slack each 5 us wait would last ten times
+  // that; 1 us of slack for this thread.
   (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
+  using clock = std::chrono::steady_clock;
   std::unique_lock<std::mutex> lk(l->mu);
+  clock::time_point last_active = clock::now();
   while (!l->stop.load()) {
+    const uint64_t seen = l->work_seq.load(std::memory_order_acquire);
+    const int before = l->sched->batches_in_flight();
     const int done = l->sched->step();
-    if (done) l->cv_done.notify_all();
-    if (l->sched->idle())
-      l->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-    else
-      l->cv_work.wait_for(lk, std::chrono::microseconds(5));
+    if (done) {
+      l->done_seq.fetch_add(1, std::memory_order_release);
+      l->cv_done.notify_all();
+    }
+    const bool idle = l->sched->idle();
+    if (done || l->sched->batches_in_flight() != before) last_active = clock::now();
+    if (clock::now() - last_active < kSpinWindow) {
+      // Poll without sleeping, the lock released: until new work arrives, and
+      // while batches run for at most 2 us before the next step.
+      lk.unlock();
+      const clock::time_point until = clock::now() + std::chrono::microseconds(2);
+      while (!l->stop.load(std::memory_order_relaxed) &&
+             l->work_seq.load(std::memory_order_acquire) == seen) {
+        const clock::time_point t = clock::now();
+        if ((!idle && t >= until) || t - last_active >= kSpinWindow) break;
+        std::this_thread::yield();
+      }
+      lk.lock();
+    } else {
+      l->cv_work.wait_for(lk, idle ? std::chrono::microseconds(5000) : std::chrono::microseconds(5),
+                          [&] { return l->stop.load() || l->work_seq.load() != seen; });
+    }
+    if (l->work_seq.load(std::memory_order_acquire) != seen) last_active = clock::now();
   }
   // Drain: wait for batches in flight so their outputs are complete.
   while (l->sched->batches_in_flight() > 0) {
@@ -511,7 +565,10 @@ int mr_ladder_submit(mr_ladder* l, const mr_job* job, uint64_t* job_id) {
   std::lock_guard<std::mutex> lk(l->mu);
   if (l->closed) return MR_ESTATE;
   const int rc = l->sched->submit(job->stream_id, job->frame_idx, job->rung, job_id);
-  if (rc == MR_OK) l->cv_work.notify_all();
+  if (rc == MR_OK) {
+    l->work_seq.fetch_add(1, std::memory_order_release);
+    l->cv_work.notify_all();
+  }
   return rc;
 }
 
@@ -526,7 +583,10 @@ int mr_ladder_submit_many(mr_ladder* l, const mr_job* jobs, int32_t n, uint64_t*
     rc = l->sched->submit(jobs[i].stream_id, jobs[i].frame_idx, jobs[i].rung, &job_ids[i]);
     if (rc == MR_OK) ++*n_submitted;
   }
-  if (*n_submitted > 0) l->cv_work.notify_all();
+  if (*n_submitted > 0) {
+    l->work_seq.fetch_add(1, std::memory_order_release);
+    l->cv_work.notify_all();
+  }
   return rc;
 }
 
@@ -537,8 +597,20 @@ int mr_ladder_poll(mr_ladder* l, mr_completion* out, int32_t max, int32_t timeou
   std::unique_lock<std::mutex> lk(l->mu);
   std::vector<uint64_t> ids = l->sched->take_completions(max);
   if (ids.empty() && timeout_us > 0) {
-    const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(timeout_us);
-    while (ids.empty() && std::chrono::steady_clock::now() < until) {
+    using clock = std::chrono::steady_clock;
+    const clock::time_point until = clock::now() + std::chrono::microseconds(timeout_us);
+    // Spin first, the lock released, for a completion published within the
+    // spin window (done_seq is read under the lock, after the empty take).
+    const clock::time_point spin_until = std::min(until, clock::now() + kSpinWindow);
+    while (ids.empty() && clock::now() < spin_until) {
+      const uint64_t seen = l->done_seq.load(std::memory_order_acquire);
+      lk.unlock();
+      while (l->done_seq.load(std::memory_order_acquire) == seen && clock::now() < spin_until)
+        std::this_thread::yield();
+      lk.lock();
+      ids = l->sched->take_completions(max);
+    }
+    while (ids.empty() && clock::now() < until) {
       l->cv_done.wait_until(lk, until);
       ids = l->sched->take_completions(max);
     }
@@ -564,26 +636,34 @@ int mr_ladder_cancel(mr_ladder* l, uint64_t job_id) {
   if (!l) return MR_EINVAL;
   std::lock_guard<std::mutex> lk(l->mu);
   const int rc = l->sched->cancel(job_id);
-  if (rc == MR_OK) l->cv_done.notify_all();
+  if (rc == MR_OK) {
+    l->done_seq.fetch_add(1, std::memory_order_release);
+    l->work_seq.fetch_add(1, std::memory_order_release);  // its budget may admit others
+    l->cv_done.notify_all();
+  }
   return rc;
 }
 
 int mr_ladder_release(mr_ladder* l, uint64_t job_id) {
   if (!l) return MR_EINVAL;
   std::lock_guard<std::mutex> lk(l->mu);
-  return l->sched->release(job_id);
+  const int rc = l->sched->release(job_id);
+  if (rc == MR_OK) l->work_seq.fetch_add(1, std::memory_order_release);  // freed budget
+  return rc;
 }
 
 int mr_ladder_release_many(mr_ladder* l, const uint64_t* ids, int32_t n, int32_t* n_released) {
   if (n_released) *n_released = 0;
   if (!l || n < 0 || (n > 0 && !ids)) return MR_EINVAL;
   std::lock_guard<std::mutex> lk(l->mu);
-  for (int32_t i = 0; i < n; ++i) {
-    const int rc = l->sched->release(ids[i]);
-    if (rc != MR_OK) return rc;
-    if (n_released) *n_released = i + 1;
+  int rc = MR_OK;
+  int32_t i = 0;
+  for (; i < n && rc == MR_OK; ++i) {
+    rc = l->sched->release(ids[i]);
+    if (rc == MR_OK && n_released) *n_released = i + 1;
   }
-  return MR_OK;
+  if (n > 0) l->work_seq.fetch_add(1, std::memory_order_release);  // freed budget
+  return rc;
 }
 
 int mr_ladder_get_stats(mr_ladder* l, mr_ladder_stats* out) {

@@ -465,6 +465,14 @@ def _tensor_view(ptr, shape, dtype, device):
     return torch.as_tensor(_Holder(), device=device).view(dtype).view(shape)
 
 
+class _PreparedJobs:
+    """A submission's argument array (see Ladder.prepare)."""
+    __slots__ = ("arr", "n")
+
+    def __init__(self, arr, n):
+        self.arr, self.n = arr, n
+
+
 class Ladder:
     """mr_ladder_* handle: continuous-batching server of ladder frame-pair jobs."""
 
@@ -525,12 +533,24 @@ class Ladder:
             raise MRError(rc, "mr_ladder_submit")
         return jid.value
 
-    def submit_many(self, jobs) -> list:
-        """jobs: (stream_id, frame_idx, rung) tuples, submitted together in order. On a refusal
-        raises MRError whose `submitted` holds the ids of the jobs accepted before it."""
+    @staticmethod
+    def prepare(jobs):
+        """The argument array of a later submit_many, built ahead of time (a client that
+        submits the next frame's jobs the moment the last one completes builds them before)."""
         jobs = list(jobs)
-        n = len(jobs)
-        arr = (mr_job * max(n, 1))(*[mr_job(s, f, r) for s, f, r in jobs])
+        return _PreparedJobs((mr_job * max(len(jobs), 1))(*[mr_job(s, f, r) for s, f, r in jobs]),
+                             len(jobs))
+
+    def submit_many(self, jobs) -> list:
+        """jobs: (stream_id, frame_idx, rung) tuples, or the result of prepare(), submitted
+        together in order. On a refusal raises MRError whose `submitted` holds the ids of the
+        jobs accepted before it."""
+        if isinstance(jobs, _PreparedJobs):
+            arr, n = jobs.arr, jobs.n
+        else:
+            jobs = list(jobs)
+            n = len(jobs)
+            arr = (mr_job * max(n, 1))(*[mr_job(s, f, r) for s, f, r in jobs])
         ids = (ctypes.c_uint64 * max(n, 1))()
         done = ctypes.c_int32()
         rc = _ladder_lib().mr_ladder_submit_many(self._h, arr, n, ids, ctypes.byref(done))
