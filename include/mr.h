@@ -255,9 +255,10 @@ int mr_batch_destroy(mr_batch* b);
  * keeps up to four batches in flight, and releases dependents as references
  * are launched (continuous batching).  Done reference jobs stay resident for later
  * dependents until their memory is needed.  The output blocks of finished jobs
- * are kept for reuse by later jobs of the same size, outside the admission
- * budget but capped at a quarter of it (at most 512 MiB; mr_ladder_stats
- * reports them), until mr_ladder_close; a device allocation that fails first
+ * are kept for reuse by later jobs of the same size, and finished batches'
+ * scratch for later batches, outside the admission budget but each capped at
+ * a quarter of it (at most 512 MiB; mr_ladder_stats reports them), until
+ * mr_ladder_close; a device allocation that fails first
  * empties that cache and retries.  Device memory comes from the server's own
  * stream-ordered pool, which keeps up to hbm_budget_bytes mapped when blocks
  * are freed (destroyed by mr_ladder_close).  With reuse_mv, a dependent's search is
@@ -326,7 +327,7 @@ typedef struct {
   double ctus_per_s;                      /* ctus_done / (last done - first start) */
   uint64_t bytes_in_use, peak_bytes;      /* footprint of admitted jobs (the budget's) */
   int64_t cancelled, timed_out;           /* of the failed ones */
-  uint64_t cached_bytes;                  /* retired output blocks kept for reuse */
+  uint64_t cached_bytes;                  /* retired output and scratch blocks kept */
   double host_launch_ms;                  /* server thread's time in batch launches
                                              (plan, allocation, upload, kernel launches) */
   int64_t device_allocs;                  /* device allocations made by the server

@@ -314,7 +314,7 @@ class GpuExecutor : public Executor {
     for (SchedJob* j : jobs)
       if (j->exec_state) ((JobOut*)j->exec_state)->batch_running = false;
     // The batch has finished on the device: its scratch may serve the next one.
-    if (pool_bytes_ + scratch_free_bytes_ + b->scratch_bytes <= pool_max_) {
+    if (scratch_free_bytes_ + b->scratch_bytes <= pool_max_) {
       scratch_free_.emplace(b->scratch_bytes, b->scratch);
       scratch_free_bytes_ += b->scratch_bytes;
     } else {
@@ -334,7 +334,7 @@ class GpuExecutor : public Executor {
     JobOut* o = (JobOut*)j.exec_state;
     if (!o) return;
     if (j.state == kDone && !o->batch_running &&
-        pool_bytes_ + scratch_free_bytes_ + o->bytes <= pool_max_) {
+        pool_bytes_ + o->bytes <= pool_max_) {
       pool_.emplace(o->bytes, o->mem);
       pool_bytes_ += o->bytes;
     } else {
@@ -394,7 +394,10 @@ class GpuExecutor : public Executor {
   hipMemPool_t mp_ = nullptr;
   static constexpr size_t kPoolMaxBytes = size_t(512) << 20;
   std::multimap<size_t, uint8_t*> pool_;  // retired output blocks by size
-  size_t pool_max_ = 0;  // cache cap (outputs and scratch): a quarter of the budget, <= 512 MiB
+  // Cap of each cache (outputs, scratch): a quarter of the budget, <= 512 MiB.
+  // Separate caps, so that a pipelined run's large batch scratch does not
+  // crowd the outputs of its many jobs out of theirs.
+  size_t pool_max_ = 0;
   size_t pool_bytes_ = 0;
   std::multimap<size_t, uint8_t*> scratch_free_;  // scratch of finished batches by size
   size_t scratch_free_bytes_ = 0;
