@@ -347,7 +347,9 @@ int mr_ladder_put_frame(mr_ladder* l, int32_t stream_id, int32_t frame_idx, int3
  * (all rungs), so that a long-running server's frame table holds the frames
  * still in use; the caller may then reuse or free that memory once the jobs
  * that read those frames have completed.  A job submitted earlier whose frames
- * are dropped before it starts completes with MR_EDEPEND.
+ * are dropped before it starts completes with MR_EDEPEND.  Done reference jobs
+ * of the stream's frames up to before_frame, which no later dependent can use,
+ * stop staying resident: once released their output blocks are freed.
  * Errors: MR_EINVAL (null ladder, negative stream id). */
 int mr_ladder_drop_frames(mr_ladder* l, int32_t stream_id, int32_t before_frame);
 /* Errors: MR_EINVAL (ids, frames not resident), MR_EDEPEND, MR_EAGAIN (queue

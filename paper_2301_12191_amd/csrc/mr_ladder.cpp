@@ -560,6 +560,8 @@ int mr_ladder_drop_frames(mr_ladder* l, int32_t stream_id, int32_t before_frame)
   if (!l || stream_id < 0) return MR_EINVAL;
   std::lock_guard<std::mutex> lk(l->mu);  // not between the scheduler's check and a launch
   l->ex->drop_frames(stream_id, before_frame);
+  l->sched->frames_dropped(stream_id, before_frame);  // their resident references are freed
+  l->work_seq.fetch_add(1, std::memory_order_release);
   return MR_OK;
 }
 

@@ -96,7 +96,7 @@ void Scheduler::maybe_free(SchedJob& j) {
   // a stream that moves forward keeps the references of its last frames only,
   // and the older ones' blocks serve the next frames' jobs; clients that
   // revisit the last frames still find theirs.
-  if (j.state == kDone && is_reference_rung(cfg_, j.rung) && !superseded(j)) return;
+  if (j.state == kDone && is_reference_rung(cfg_, j.rung) && !j.stale && !superseded(j)) return;
   ex_->free_job(j);
   j.exec_state = nullptr;
   if (j.admitted) st_.bytes_in_use -= j.footprint, j.admitted = false;
@@ -118,6 +118,21 @@ void Scheduler::retire_finished() {
     auto lt = latest_.find(std::make_tuple(j.stream, j.frame, j.rung));
     if (lt != latest_.end() && lt->second == id) latest_.erase(lt);
     jobs_.erase(it);
+  }
+}
+
+void Scheduler::frames_dropped(int stream, int before_frame) {
+  std::vector<SchedJob*> old;
+  for (auto it = latest_.lower_bound(std::make_tuple(stream, 0, 0));
+       it != latest_.end() && std::get<0>(it->first) == stream &&
+       std::get<1>(it->first) <= before_frame;
+       ++it) {
+    auto jt = jobs_.find(it->second);
+    if (jt != jobs_.end()) old.push_back(jt->second.get());
+  }
+  for (SchedJob* r : old) {
+    r->stale = true;
+    maybe_free(*r);
   }
 }
 

@@ -52,6 +52,7 @@ struct SchedJob {
   JobState state = kQueued;
   int status = 0;
   bool implied = false;            // created by the server for a dependent
+  bool stale = false;              // its frames were dropped: serves no later dependent
   bool released = false;           // caller released the outputs
   bool handed_out = false;         // completion taken by take_completions
   uint64_t ref_job = 0;            // job whose depth map bounds this one (0 none)
@@ -120,6 +121,11 @@ class Scheduler {
   size_t jobs_known() const { return jobs_.size(); }
   // Free the outputs of every job still holding them (server shutdown).
   void free_all();
+  // The client dropped the frames of `stream` before `before_frame`: done
+  // reference jobs of frames up to `before_frame` can serve no later
+  // dependent (one needs its frame and the previous one) and stop staying
+  // resident.
+  void frames_dropped(int stream, int before_frame);
 
  private:
   struct Batch {

@@ -320,6 +320,31 @@ static void test_dropped_frames_fail_alone() {
   CHECK(s.submit(0, 2, 0, &a) == MR_EINVAL);  // not resident any more
 }
 
+// Dropping a stream's frames frees its resident references that no later
+// dependent can use (frames up to the drop point), and only those.
+static void test_dropped_frames_free_references() {
+  FakeExec ex;
+  ex.fp = {{0, 1}, {1, 1}, {2, 1}};
+  add_frames(ex, 0, 5, 3);
+  Scheduler s(ladder_cfg(1 << 20), &ex);
+  for (int f = 3; f <= 4; ++f) {
+    uint64_t a = 0;
+    CHECK(s.submit(0, f, 0, &a) == MR_OK);
+    run_until_idle(s, ex);
+    for (uint64_t id : s.take_completions(100)) CHECK(s.release(id) == MR_OK);
+    s.step();
+  }
+  CHECK(ex.freed == 0 && s.jobs_known() == 2);  // both references resident
+  s.frames_dropped(0, 3);  // frames 0..2 go: frame 3's reference can serve nobody
+  s.step();
+  CHECK(ex.freed == 1 && s.jobs_known() == 1);
+  uint64_t d = 0;
+  CHECK(s.submit(0, 4, 1, &d) == MR_OK);  // frame 4's reference still serves
+  CHECK(s.stats().implied == 0);
+  run_until_idle(s, ex);
+  CHECK(s.job(d)->state == kDone && s.job(d)->status == MR_OK);
+}
+
 // chain_on_launch: a dependent launches in the batch after its reference's,
 // in the same step, while that batch still runs; a reference that then fails
 // takes the already-launched dependent with it.
@@ -493,6 +518,7 @@ int main() {
   test_finished_jobs_are_forgotten();
   test_dropped_frames_fail_alone();
   test_superseded_references_freed();
+  test_dropped_frames_free_references();
   if (g_fail) {
     std::fprintf(stderr, "%d checks failed\n", g_fail);
     return 1;
